@@ -1,0 +1,275 @@
+"""Surrogate-form oracle (numpy, FP64) -- TEST INFRASTRUCTURE ONLY.
+
+Follows the paper's ANN model (Sec. 3.2):
+* network input  x(t) = {T, p, F(Y(t))} with the Box-Cox transform F;
+* network output the change of the mass fractions over one time step, here
+  taken in Box-Cox space, u* = F(Y(t+dt)) - F(Y(t));
+* inputs and outputs z-score normalised with training-set statistics;
+* hidden layers 1600, 800, 400 with GELU; Adam; L1 loss (Eq. Loss).
+
+Box-Cox (Box & Cox 1964): F(x) = (x^lambda - 1)/lambda with lambda = 0.1,
+which maps mass fractions in [0, 1] to [-1/lambda, 0]; negative mass
+fractions are clamped to 0 first.
+
+Rounding emulation: ``prec="bf16"`` rounds every layer's input activations and
+weights to bfloat16 (round to nearest even) and keeps everything else in FP64;
+``prec="fp8"`` additionally quantises the hidden-to-hidden layers' operands to
+OCP FP8 E4M3 (saturating, round to nearest even) with per-tensor scales
+amax/448.  The GPU accumulates in FP32, so results agree to accumulation
+rounding, not bitwise.
+
+The post-processing (inverse Box-Cox, weighted least-squares projection onto
+element conservation, clipping, residual and out-of-distribution flags,
+enthalpy Newton for T, reaction rates) is not in the paper; it is this
+project's reading of how the ANN output becomes a full chemistry step.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+from scipy.special import erf
+
+from . import OracleMech, mixture_enthalpy, thermo, RGAS
+
+LAMBDA = 0.1
+HIDDEN = (1600, 800, 400)
+
+# ----------------------------------------------------------------- rounding
+
+
+def round_bf16(x):
+    """Round FP64 values to the nearest bfloat16 (ties to even), returned as FP64.
+    First rounds to FP32 (round to nearest even), then to BF16 -- the GPU path
+    holds FP32 values when it converts."""
+    f = np.asarray(x, dtype=np.float64).astype(np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    lsb = (u >> 16) & 1
+    r = (u + 0x7FFF + lsb) >> 16
+    nan = np.isnan(f)
+    r = np.where(nan, (u >> 16) | 0x40, r)
+    out = (r.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+    return out
+
+
+def round_e4m3(x):
+    """Round to OCP FP8 E4M3 (e4m3fn: max 448, no infinities), saturating,
+    round to nearest even, via the exact grid of representable values."""
+    x = np.asarray(x, dtype=np.float64)
+    a = np.minimum(np.abs(x), 448.0)
+    e = np.floor(np.log2(np.maximum(a, 2.0 ** -9)))
+    e = np.maximum(e, -6.0)              # subnormals share the 2^-6 binade spacing
+    q = 2.0 ** (e - 3.0)                  # 3 mantissa bits
+    m = a / q
+    r = np.floor(m)
+    frac = m - r
+    up = (frac > 0.5) | ((frac == 0.5) & (np.mod(r, 2.0) == 1.0))
+    r = r + up
+    v = np.minimum(r * q, 448.0)
+    return np.where(np.isnan(x), np.nan, np.sign(x) * v)
+
+
+# ------------------------------------------------------------ transforms
+
+
+def boxcox(Y, lam=LAMBDA):
+    return (np.power(np.maximum(Y, 0.0), lam) - 1.0) / lam
+
+
+def inv_boxcox(z, lam=LAMBDA):
+    b = 1.0 + lam * z
+    return np.where(b > 0.0, np.power(np.maximum(b, 0.0), 1.0 / lam), 0.0)
+
+
+def gelu(x):
+    return 0.5 * x * (1.0 + erf(x / math.sqrt(2.0)))
+
+
+def gelu_grad(x):
+    return 0.5 * (1.0 + erf(x / math.sqrt(2.0))) + x * np.exp(-0.5 * x * x) / math.sqrt(2 * math.pi)
+
+
+def features(T, p, Y, lam=LAMBDA):
+    """Raw network features [T, p, F(Y_1..K)] as rows: shape [K+2, N]."""
+    return np.vstack([np.atleast_2d(T), np.atleast_2d(p), boxcox(Y, lam)])
+
+
+def targets(Y0, Y1, lam=LAMBDA):
+    """u* = F(Y(t+dt)) - F(Y(t)), shape [K, N]."""
+    return boxcox(Y1, lam) - boxcox(Y0, lam)
+
+
+def zstats(A):
+    """Training-set mean and standard deviation per row (features x samples),
+    with a zero spread replaced by 1."""
+    mu = A.mean(axis=1)
+    sd = A.std(axis=1)
+    sd = np.where(sd < 1e-12 * np.abs(mu) + 1e-30, 1.0, sd)
+    return mu, sd
+
+
+# ------------------------------------------------------------------- MLP
+
+
+def init_params(sizes, seed):
+    """W_l ~ U(+-1/sqrt(fan_in)), b_l ~ U(+-1/sqrt(fan_in)); W_l is [out, in]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    params = []
+    for fi, fo in zip(sizes[:-1], sizes[1:]):
+        bound = 1.0 / math.sqrt(fi)
+        W = rng.uniform(-bound, bound, (fo, fi))
+        b = rng.uniform(-bound, bound, fo)
+        params.append((W, b))
+    return params
+
+
+def _q(x, prec, layer, nlayers, scale=None):
+    if prec == "fp64":
+        return x
+    if prec == "fp8" and 0 < layer < nlayers - 1:
+        return round_e4m3(x / scale) * scale
+    return round_bf16(x)
+
+
+def forward(params, X, prec="fp64", fp8_scales=None, keep=False):
+    """X: [N, in] normalised inputs.  Returns the [N, out] output (and the
+    pre-activations / layer inputs when keep=True).  fp8_scales: per hidden
+    layer l (1..L-2) a pair (act_scale, weight_scale)."""
+    L = len(params)
+    h = X
+    zs, hs = [], []
+    for l, (W, b) in enumerate(params):
+        if prec == "fp8" and 0 < l < L - 1:
+            sa, sw = fp8_scales[l]
+            hq = round_e4m3(h / sa) * sa
+            Wq = round_e4m3(W / sw) * sw
+        else:
+            hq = _q(h, prec, l, L)
+            Wq = _q(W, prec, l, L)
+        hs.append(hq)
+        z = hq @ Wq.T + b
+        zs.append(z)
+        h = gelu(z) if l < L - 1 else z
+    if keep:
+        return h, zs, hs
+    return h
+
+
+def l1_loss(u, target):
+    return np.mean(np.abs(u - target))
+
+
+def backward(params, X, target, prec="fp64"):
+    """Gradients of the L1 loss (mean over samples and outputs) with respect
+    to every W_l, b_l.  dL/du = sign(u - u*)/(N * n_out), sign(0) = 0.  With
+    prec="bf16" the backward operands are rounded where the GPU rounds them:
+    the layer inputs (as in forward), the weights, and each layer's incoming
+    gradient dZ before it is multiplied."""
+    L = len(params)
+    u, zs, hs = forward(params, X, prec=prec, keep=True)
+    N, nout = u.shape
+    g = np.sign(u - target) / (N * nout)
+    grads = [None] * L
+    for l in range(L - 1, -1, -1):
+        W, _ = params[l]
+        gq = round_bf16(g) if prec != "fp64" else g
+        dW = gq.T @ hs[l]
+        db = g.sum(axis=0)
+        grads[l] = (dW, db)
+        if l > 0:
+            Wq = round_bf16(W) if prec != "fp64" else W
+            dh = gq @ Wq
+            g = dh * gelu_grad(zs[l - 1])
+    return grads, l1_loss(u, target)
+
+
+def adam_update(params, grads, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """Adam (Kingma & Ba 2015, Algorithm 1) with bias correction; t >= 1.
+    Returns new (params, m, v)."""
+    new_p, new_m, new_v = [], [], []
+    for (W, b), (gW, gb), (mW, mb), (vW, vb) in zip(params, grads, m, v):
+        out = []
+        for th, g, mm, vv in ((W, gW, mW, vW), (b, gb, mb, vb)):
+            mm = beta1 * mm + (1 - beta1) * g
+            vv = beta2 * vv + (1 - beta2) * g * g
+            mh = mm / (1 - beta1 ** t)
+            vh = vv / (1 - beta2 ** t)
+            th = th - lr * mh / (np.sqrt(vh) + eps)
+            out.append((th, mm, vv))
+        new_p.append((out[0][0], out[1][0]))
+        new_m.append((out[0][1], out[1][1]))
+        new_v.append((out[0][2], out[1][2]))
+    return new_p, new_m, new_v
+
+
+# ------------------------------------------------------------------- post
+
+
+def element_mass_matrix(mech):
+    """M[e, k] = (atoms of e in k) * A_e / W_k: element-e mass per unit Y_k."""
+    return mech.comp.T.astype(np.float64) * mech.awt[:, None] / mech.W[None, :]
+
+
+def project(mech, Y0, Yp, floor=1e-10):
+    """Weighted least-squares projection of Yp ([K, N]) onto the element
+    conservation constraints M Y = M Y0, with weights D = diag(Yp + floor):
+    Y = Yp + D M^T (M D M^T)^-1 (M Y0 - M Yp)."""
+    M = element_mass_matrix(mech)
+    out = np.empty_like(Yp)
+    for i in range(Yp.shape[1]):
+        d = np.maximum(Yp[:, i], 0.0) + floor
+        A = (M * d[None, :]) @ M.T
+        r = M @ Y0[:, i] - M @ Yp[:, i]
+        lam = np.linalg.solve(A, r)
+        out[:, i] = Yp[:, i] + d * (M.T @ lam)
+    return out
+
+
+def temperature_newton(om: OracleMech, T0, Y0, Y, tol=1e-9, maxit=20):
+    """Solve h(T, Y) = h(T0, Y0) for T by Newton from T0 (FP64)."""
+    T = np.array(T0, dtype=np.float64).copy()
+    for i in range(T.size):
+        h0 = mixture_enthalpy(om, T0[i], Y0[:, i])
+        t = T0[i]
+        for _ in range(maxit):
+            cpR, _, _ = thermo(om, t)
+            cp = float(np.sum(Y[:, i] * RGAS * cpR / om.mech.W))
+            dT = (mixture_enthalpy(om, t, Y[:, i]) - h0) / cp
+            t = t - dT
+            if abs(dT) < tol * t:
+                break
+        T[i] = t
+    return T
+
+
+def density(mech, T, p, Y):
+    S = (Y / mech.W[:, None]).sum(axis=0)
+    return p / (RGAS * T * S)
+
+
+def ood_flags(feat, lo, hi, margin=0.05):
+    """feat: raw features [F, N]; lo/hi: training-set range per feature."""
+    span = hi - lo
+    tol = np.where(span > 0, margin * span, 1e-6 * np.maximum(np.abs(hi), 1e-30))
+    bad = (feat < (lo - tol)[:, None]) | (feat > (hi + tol)[:, None])
+    return bad.any(axis=0)
+
+
+def post(om: OracleMech, T0, p, Y0, u_z, mu_out, sd_out, dt, lo=None, hi=None,
+         residual_tol=1e-6, margin=0.05, lam=LAMBDA):
+    """From the z-space network output u_z ([K, N]) to (T, Y, RR, flags)."""
+    mech = om.mech
+    du = u_z * sd_out[:, None] + mu_out[:, None]
+    Yp = inv_boxcox(boxcox(Y0, lam) + du, lam)
+    Y = project(mech, Y0, Yp)
+    Y = np.maximum(Y, 0.0)
+    M = element_mass_matrix(mech)
+    res = np.abs(M @ Y - M @ Y0).max(axis=0)
+    flags = np.zeros(T0.size, dtype=np.uint8)
+    if lo is not None:
+        flags |= np.where(ood_flags(features(T0, p, Y0, lam), lo, hi, margin), 1, 0).astype(np.uint8)
+    flags |= np.where(res > residual_tol, 2, 0).astype(np.uint8)
+    T = temperature_newton(om, T0, Y0, Y)
+    rho0 = density(mech, T0, p, Y0)
+    RR = rho0[None, :] * (Y - Y0) / dt
+    return dict(T=T, Y=Y, RR=RR, flags=flags, residual=res, Yp=Yp)
