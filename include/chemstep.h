@@ -1,0 +1,141 @@
+/*
+ * chemstep.h -- C ABI of the MI355X per-cell chemistry-step library.
+ *
+ * The library advances the thermochemical state of many independent CFD cells
+ * through one chemistry time step, the operation that the GPU-ANN method of
+ * arXiv 2312.05800 moves onto the GPU (Sec. 2: the whole step stays on the
+ * device, so no host/device copies happen inside it; Sec. 3.1: each
+ * composition is integrated over the chemistry time step; Sec. 3.2: the ANN
+ * maps {T, p, F(Y)} to the change of Y over the step).
+ *
+ * Conventions for every call below
+ *   - Pointers are DEVICE pointers unless marked (host).
+ *   - Cell arrays are SoA: scalar fields are [n] (element i at [i]); species
+ *     fields are [K][ld] (species k of cell i at [k*ld + i]); ld >= n.
+ *   - Units are SI: T in K, p in Pa, mass fractions dimensionless, rates in
+ *     kg/m^3/s or mol/m^3/s as stated.
+ *   - Calls are asynchronous and stream-ordered: `stream` is a hipStream_t
+ *     passed as void* (NULL = the legacy default stream).  Argument errors are
+ *     detected on the host before anything is launched and return an error
+ *     code; the call then has no effect.  Per-cell numerical outcomes go to
+ *     the per-cell stats/flags arrays, never to the return code.
+ *   - The caller owns every cell array.  Handles own their device copies of
+ *     constants, weights and workspace.  Calls that use the same handle
+ *     concurrently on different streams race on its workspace and must be
+ *     ordered by the caller.
+ *   - The library never exits or aborts.  A failed HIP call returns
+ *     CHEM_EHIP with the HIP error text in chem_last_error().
+ */
+#ifndef CHEMSTEP_H
+#define CHEMSTEP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CHEM_OK = 0,
+  CHEM_EINVAL = 1,       /* bad argument (null pointer, size, ld < n, ...) */
+  CHEM_ENOMEM = 2,       /* device allocation failed */
+  CHEM_EHIP = 3,         /* a HIP runtime call failed */
+  CHEM_EMECH = 4,        /* inconsistent mechanism description */
+  CHEM_EMODEL = 5,       /* inconsistent network / model file */
+  CHEM_EUNSUPPORTED = 6  /* valid but beyond this build's limits (e.g. K > 63) */
+} chem_status;
+
+/* Per-cell status codes written to stats[2][i] by chem_step. */
+enum {
+  CHEM_CELL_OK = 0,
+  CHEM_CELL_MAX_STEPS = 1,   /* more than max_steps step attempts */
+  CHEM_CELL_H_UNDERFLOW = 2, /* step size fell below h_min */
+  CHEM_CELL_NONFINITE = 3,   /* non-finite input state, or T <= 0, or p <= 0 */
+  CHEM_CELL_SINGULAR = 4     /* zero or non-finite pivot in the Newton matrix */
+};
+
+/* Human-readable name of a status code (static string). */
+const char *chem_status_string(chem_status s);
+/* Detail of the last error on the calling host thread (thread-local). */
+const char *chem_last_error(void);
+
+/* ------------------------------------------------------------ mechanism
+ * A reaction mechanism: K species over E elements, R reversible elementary
+ * reactions (one or two reactant and product species, stoichiometric
+ * coefficients 1 or 2, no third bodies).  Thermo per species is NASA-7
+ * (low range for T <= T_mid, else high range); forward rate constants are
+ * k_f = A T^b exp(-Ea/(R T)); reverse ones k_f/K_c with K_c from the standard
+ * Gibbs energies at p_ref = 101325 Pa.  All pointers in the descriptor are
+ * (host) and are copied at create time. */
+typedef struct {
+  int32_t K, R, E;
+  const double *W;       /* (host) [K] molar mass, kg/mol */
+  const int32_t *comp;   /* (host) [K][E] atoms of element e in species k */
+  const double *awt;     /* (host) [E] atomic weight, kg/mol */
+  const double *nasa;    /* (host) [K][17]: T_low, T_mid, T_high, low a1..a7, high a1..a7 */
+  const int32_t *rsp;    /* (host) [R][4]: reactant0, reactant1, product0, product1; -1 = none */
+  const int32_t *rnu;    /* (host) [R][4]: stoichiometric coefficient (1 or 2) of each slot */
+  const double *A;       /* (host) [R] SI: (m^3/mol)^(order-1)/s */
+  const double *b;       /* (host) [R] temperature exponent */
+  const double *Ea;      /* (host) [R] activation energy, J/mol */
+} chem_mech_desc;
+
+typedef struct chem_mech chem_mech;
+
+/* Validate `desc` (element balance of every reaction, index ranges, K <= 63,
+ * finite positive A and W) and upload it.  On success *out owns device memory
+ * until chem_mech_destroy.  Errors: CHEM_EINVAL (null), CHEM_EMECH
+ * (inconsistent), CHEM_EUNSUPPORTED (too large), CHEM_ENOMEM, CHEM_EHIP. */
+chem_status chem_mech_create(const chem_mech_desc *desc, chem_mech **out);
+void chem_mech_destroy(chem_mech *m);
+int32_t chem_mech_num_species(const chem_mech *m);
+int32_t chem_mech_num_reactions(const chem_mech *m);
+
+typedef struct {
+  int64_t n;   /* number of cells (0 is allowed: the call does nothing) */
+  int64_t ld;  /* leading dimension of [K][ld] arrays, >= n */
+} chem_batch;
+
+/* Integrator controls; NULL selects the defaults in brackets.
+ *   rtol [1e-6], atol_Y [1e-12], atol_T [1e-6 K]: error weights
+ *       atol + rtol*max(|y_old|, |y_new|) per component;
+ *   h0 [1e-8 s]: first step when no hint is given; h_min [1e-20 s];
+ *   max_steps [100000] step attempts per cell. */
+typedef struct {
+  double rtol, atol_Y, atol_T, h0, h_min;
+  int32_t max_steps;
+} chem_step_opts;
+
+/* Instantaneous chemistry of each cell (the reaction-rate evaluation the
+ * paper's ANN replaces, Sec. 1 and Sec. 3.2):
+ *   wdot [K][ld] net molar production rate, mol/m^3/s;
+ *   dTdt [n]     adiabatic constant-pressure temperature rate, K/s (nullable);
+ *   kfkr [2R][ld] forward rate constants in rows 0..R-1, reverse in R..2R-1,
+ *                 SI (nullable).
+ * Inputs T [n], p [n], Y [K][ld] are read only. */
+chem_status chem_rates(const chem_mech *m, chem_batch batch, const double *T, const double *p,
+                       const double *Y, double *wdot, double *dTdt, double *kfkr, void *stream);
+
+/* One chemistry step of every cell (Sec. 3.1: integrate each composition
+ * over the time step): the adiabatic constant-pressure reactor
+ *   dY_k/dt = W_k wdot_k / rho,  dT/dt = -sum_k h_k wdot_k / (rho c_p)
+ * integrated over [0, dt] by the 4-stage L-stable Rosenbrock method RODAS3
+ * with its analytic Jacobian, an embedded error estimate and adaptive step
+ * size, in FP64.
+ *   dt          step for every cell, s (> 0) unless dt_cell is given;
+ *   dt_cell     [n] per-cell step, s (nullable);
+ *   T  [n]      in/out temperature;  p [n] pressure (constant over the step);
+ *   Y  [K][ld]  in/out mass fractions (not clipped: tiny negatives may occur);
+ *   RR [K][ld]  out rho(T0, Y0) (Y - Y0) / dt, kg/m^3/s (nullable);
+ *   h_hint [n]  in/out step-size hint; <= 0 means none (nullable);
+ *   stats [3][ld] out int32 rows: accepted steps, rejected steps, CHEM_CELL_*
+ *               status (nullable).
+ * A failed cell keeps its input T and Y, gets RR = 0 and its status. */
+chem_status chem_step(const chem_mech *m, chem_batch batch, double dt, const double *dt_cell,
+                      double *T, const double *p, double *Y, double *RR, double *h_hint,
+                      int32_t *stats, const chem_step_opts *opts, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CHEMSTEP_H */

@@ -258,8 +258,8 @@ void or_chem_rates(const or_mech *m, long N, long ld, const double *T, const dou
 /* ------------------------------------------------------------------- LU */
 
 /* In-place LU of the row-major n x n matrix a.  At step k the pivot is the
- * not-yet-eliminated row with the largest |a[i][k]| (ties: lowest row index);
- * order[k] records it.  Rows stay where they are: the multiplier of row i at
+ * not-yet-eliminated row with the largest |a[i][k]| (ties: lowest row index;
+ * NaN counts as larger than any number); order[k] records it.  Rows stay where they are: the multiplier of row i at
  * step k is stored in a[i][k].  Returns 0, or 1 if a pivot is zero/non-finite. */
 int or_lu(int n, double *a, int *order) {
   int done[OR_NMAX];
@@ -270,6 +270,7 @@ int or_lu(int n, double *a, int *order) {
     for (int i = 0; i < n; ++i) {
       if (done[i]) continue;
       double v = fabs(a[i * n + k]);
+      if (isnan(v)) v = INFINITY; /* a NaN candidate wins and then fails the check below */
       if (best < 0 || v > bestv) { best = i; bestv = v; }
     }
     if (!(bestv > 0.0) || !isfinite(bestv)) return 1;
@@ -413,7 +414,8 @@ static void chem_jac_cb(void *c, const double *y, double *f, double *J) {
  *   start    h = min(dt, h_hint) if a hint > 0 is given, else min(dt, h0)
  *   last     the step is cut to dt - t when h >= dt - t; accepting it sets t = dt
  *   failure  more than max_steps attempts -> MAX_STEPS; h < h_min -> H_UNDERFLOW;
- *            non-finite or non-positive input T -> NONFINITE; zero pivot -> SINGULAR
+ *            non-finite input, T <= 0, p <= 0 or dt <= 0 -> NONFINITE;
+ *            zero or non-finite pivot -> SINGULAR
  * No clipping of negative mass fractions.  On return y holds the result (or is
  * unchanged on failure), *h_io the proposed next step size. */
 int or_integrate(const or_mech *m, double p, double *y, double dt, const or_opts *o,
@@ -424,7 +426,8 @@ int or_integrate(const or_mech *m, double p, double *y, double dt, const or_opts
   *nrej_out = 0;
   for (int i = 0; i < n; ++i)
     if (!isfinite(y[i])) return OR_NONFINITE;
-  if (!(y[0] > 0.0) || !isfinite(p) || !(p > 0.0)) return OR_NONFINITE;
+  if (!(y[0] > 0.0) || !isfinite(p) || !(p > 0.0) || !(dt > 0.0) || !isfinite(dt))
+    return OR_NONFINITE;
   chem_ctx ctx = {m, p};
   double yw[OR_NMAX], ynew[OR_NMAX], errv[OR_NMAX];
   for (int i = 0; i < n; ++i) yw[i] = y[i];

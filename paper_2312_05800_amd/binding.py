@@ -1,0 +1,196 @@
+"""ctypes binding of libchemstep.so (include/chemstep.h).
+
+Argument marshalling only: every computation runs in the library's HIP
+kernels.  Arrays are torch CUDA tensors (device memory); the calls are
+enqueued on torch's current stream.  If the library has not been built the
+first call raises -- there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libchemstep.so")
+
+_lock = threading.Lock()
+_lib = None
+
+_P = C.c_void_p
+
+
+class ChemError(RuntimeError):
+    def __init__(self, fn, status, detail):
+        super().__init__(f"{fn} failed: {status_name(status)} ({detail})")
+        self.status = status
+
+
+class MechDesc(C.Structure):
+    _fields_ = [("K", C.c_int32), ("R", C.c_int32), ("E", C.c_int32), ("W", _P), ("comp", _P),
+                ("awt", _P), ("nasa", _P), ("rsp", _P), ("rnu", _P), ("A", _P), ("b", _P),
+                ("Ea", _P)]
+
+
+class Batch(C.Structure):
+    _fields_ = [("n", C.c_int64), ("ld", C.c_int64)]
+
+
+class StepOpts(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("atol_Y", C.c_double), ("atol_T", C.c_double),
+                ("h0", C.c_double), ("h_min", C.c_double), ("max_steps", C.c_int32)]
+
+
+def lib():
+    """Load libchemstep.so (raises if it has not been built)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError(
+                    f"{LIB_PATH} is missing: build it first (python -m paper_2312_05800_amd.build)")
+            L = C.CDLL(LIB_PATH)
+            L.chem_status_string.restype = C.c_char_p
+            L.chem_status_string.argtypes = [C.c_int]
+            L.chem_last_error.restype = C.c_char_p
+            L.chem_mech_create.argtypes = [C.POINTER(MechDesc), C.POINTER(_P)]
+            L.chem_mech_destroy.argtypes = [_P]
+            L.chem_mech_num_species.argtypes = [_P]
+            L.chem_mech_num_reactions.argtypes = [_P]
+            L.chem_rates.argtypes = [_P, Batch, _P, _P, _P, _P, _P, _P, _P]
+            L.chem_step.argtypes = [_P, Batch, C.c_double, _P, _P, _P, _P, _P, _P, _P, _P, _P]
+            _setup_ann(L)
+            _lib = L
+    return _lib
+
+
+def _setup_ann(L):
+    """Prototypes of the surrogate-form entry points, when the library has them."""
+    if hasattr(L, "ann_create"):
+        from . import ann as _ann
+        _ann._prototypes(L)
+
+
+def status_name(s: int) -> str:
+    try:
+        return lib().chem_status_string(int(s)).decode()
+    except Exception:  # the library itself failed to load
+        return str(s)
+
+
+def check(fn: str, st: int):
+    if st != 0:
+        raise ChemError(fn, st, lib().chem_last_error().decode())
+
+
+def _dptr(t, dtype=None, name="array"):
+    """Device pointer of a torch CUDA tensor (None -> NULL)."""
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    return t.data_ptr()
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def _soa(t, K, n, name):
+    """Checks a [K][ld] species array and returns its leading dimension."""
+    if t.dim() != 2 or t.shape[0] != K or t.shape[1] < n or t.stride(1) != 1:
+        raise ValueError(f"{name} must be a [K={K}, >=n] row-major view")
+    return t.stride(0) if K > 1 else t.shape[1]
+
+
+class Mechanism:
+    """Device copy of a reaction mechanism (chem_mech handle).
+
+    ``desc`` is any object with the chem_mech_desc fields as numpy arrays:
+    W, comp, awt, nasa, rsp, rnu, A, b, Ea (e.g. a chemgen.Mech)."""
+
+    def __init__(self, desc):
+        self._keep = {}
+        arrs = {}
+        for name, dt in (("W", np.float64), ("comp", np.int32), ("awt", np.float64),
+                         ("nasa", np.float64), ("rsp", np.int32), ("rnu", np.int32),
+                         ("A", np.float64), ("b", np.float64), ("Ea", np.float64)):
+            a = np.ascontiguousarray(getattr(desc, name), dtype=dt)
+            arrs[name] = a
+            self._keep[name] = a
+        K = arrs["W"].shape[0]
+        R = arrs["rsp"].shape[0]
+        E = arrs["awt"].shape[0]
+        d = MechDesc(K, R, E, *(arrs[k].ctypes.data for k in
+                                ("W", "comp", "awt", "nasa", "rsp", "rnu", "A", "b", "Ea")))
+        h = _P()
+        check("chem_mech_create", lib().chem_mech_create(C.byref(d), C.byref(h)))
+        self.handle = h
+        self.K, self.R, self.E = K, R, E
+        self.desc = desc
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h and _lib is not None:
+            _lib.chem_mech_destroy(h)
+            self.handle = None
+
+
+def _opts(opts):
+    if opts is None:
+        return None
+    o = dict(rtol=1e-6, atol_Y=1e-12, atol_T=1e-6, h0=1e-8, h_min=1e-20, max_steps=100000)
+    o.update(opts)
+    return StepOpts(o["rtol"], o["atol_Y"], o["atol_T"], o["h0"], o["h_min"], int(o["max_steps"]))
+
+
+def chem_rates(mech: Mechanism, T, p, Y, dTdt: bool = True, kfkr: bool = False, stream=None):
+    """Instantaneous wdot [K, n] (mol/m^3/s), dT/dt [n] (K/s) and optionally
+    k_f/k_r [2R, n] of every cell.  Returns new tensors."""
+    import torch
+    n = T.shape[0]
+    ld = _soa(Y, mech.K, n, "Y")
+    dev = T.device
+    wdot = torch.empty((mech.K, ld), dtype=torch.float64, device=dev)
+    dT = torch.empty(n, dtype=torch.float64, device=dev) if dTdt else None
+    kk = torch.empty((2 * mech.R, ld), dtype=torch.float64, device=dev) if kfkr else None
+    f64 = torch.float64
+    check("chem_rates", lib().chem_rates(
+        mech.handle, Batch(n, ld), _dptr(T, f64, "T"), _dptr(p, f64, "p"), _dptr(Y, f64, "Y"),
+        _dptr(wdot), _dptr(dT), _dptr(kk), _stream(stream)))
+    out = dict(wdot=wdot[:, :n])
+    if dTdt:
+        out["dTdt"] = dT
+    if kfkr:
+        out["kf"] = kk[:mech.R, :n]
+        out["kr"] = kk[mech.R:, :n]
+    return out
+
+
+def chem_step(mech: Mechanism, dt, T, p, Y, dt_cell=None, RR=None, h_hint=None, stats=None,
+              opts=None, stream=None):
+    """Advance T [n] and Y [K, ld] in place by one chemistry step.  RR
+    ([K, ld] float64), h_hint ([n] float64) and stats ([3, ld] int32) are
+    optional caller-provided output tensors."""
+    import torch
+    n = T.shape[0]
+    ld = _soa(Y, mech.K, n, "Y")
+    if RR is not None and _soa(RR, mech.K, n, "RR") != ld:
+        raise ValueError("RR must have the leading dimension of Y")
+    if stats is not None and (stats.dim() != 2 or stats.shape[0] != 3 or stats.stride(0) != ld
+                              or stats.dtype != torch.int32):
+        raise ValueError("stats must be an int32 [3, ld] tensor with the leading dimension of Y")
+    o = _opts(opts)
+    f64 = torch.float64
+    check("chem_step", lib().chem_step(
+        mech.handle, Batch(n, ld), float(dt), _dptr(dt_cell, f64, "dt_cell"), _dptr(T, f64, "T"),
+        _dptr(p, f64, "p"), _dptr(Y, f64, "Y"), _dptr(RR, f64, "RR"),
+        _dptr(h_hint, f64, "h_hint"), _dptr(stats, torch.int32, "stats"),
+        None if o is None else C.byref(o), _stream(stream)))

@@ -1,0 +1,308 @@
+// Host side of the C ABI: status strings, error reporting, mechanism upload
+// and argument validation for chem_rates / chem_step.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <vector>
+
+#include "chem_internal.h"
+
+namespace chem {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+
+chem_status hip_fail(hipError_t e, const char *what) {
+  set_error("%s: %s", what, hipGetErrorString(e));
+  return CHEM_EHIP;
+}
+
+StepOpts resolve_opts(const chem_step_opts *o) {
+  StepOpts r{1e-6, 1e-12, 1e-6, 1e-8, 1e-20, 100000};
+  if (o) {
+    r.rtol = o->rtol;
+    r.atol_Y = o->atol_Y;
+    r.atol_T = o->atol_T;
+    r.h0 = o->h0;
+    r.h_min = o->h_min;
+    r.max_steps = o->max_steps;
+  }
+  return r;
+}
+
+}  // namespace chem
+
+using namespace chem;
+
+extern "C" const char *chem_status_string(chem_status s) {
+  switch (s) {
+    case CHEM_OK: return "CHEM_OK";
+    case CHEM_EINVAL: return "CHEM_EINVAL";
+    case CHEM_ENOMEM: return "CHEM_ENOMEM";
+    case CHEM_EHIP: return "CHEM_EHIP";
+    case CHEM_EMECH: return "CHEM_EMECH";
+    case CHEM_EMODEL: return "CHEM_EMODEL";
+    case CHEM_EUNSUPPORTED: return "CHEM_EUNSUPPORTED";
+  }
+  return "CHEM_UNKNOWN";
+}
+
+extern "C" const char *chem_last_error(void) { return g_err; }
+
+namespace {
+
+// Packs host arrays into one byte blob with 256-byte aligned sections.
+struct Packer {
+  std::vector<unsigned char> buf;
+  size_t add(const void *p, size_t bytes) {
+    size_t off = (buf.size() + 255) & ~size_t(255);
+    buf.resize(off + bytes);
+    if (bytes) memcpy(buf.data() + off, p, bytes);
+    return off;
+  }
+};
+
+}  // namespace
+
+extern "C" chem_status chem_mech_create(const chem_mech_desc *d, chem_mech **out) {
+  if (!d || !out) {
+    set_error("chem_mech_create: null argument");
+    return CHEM_EINVAL;
+  }
+  *out = nullptr;
+  const int K = d->K, R = d->R, E = d->E;
+  if (K < 1 || R < 0 || E < 1 || !d->W || !d->comp || !d->awt || !d->nasa ||
+      (R > 0 && (!d->rsp || !d->rnu || !d->A || !d->b || !d->Ea))) {
+    set_error("chem_mech_create: bad sizes or null arrays (K=%d R=%d E=%d)", K, R, E);
+    return CHEM_EINVAL;
+  }
+  if (K > KMAX) {
+    set_error("chem_mech_create: K=%d exceeds the limit of %d species", K, KMAX);
+    return CHEM_EUNSUPPORTED;
+  }
+  for (int k = 0; k < K; ++k) {
+    if (!(d->W[k] > 0.0) || !isfinite(d->W[k])) {
+      set_error("chem_mech_create: W[%d] must be finite and positive", k);
+      return CHEM_EMECH;
+    }
+    const double *c = d->nasa + 17 * k;
+    for (int j = 0; j < 17; ++j)
+      if (!isfinite(c[j])) {
+        set_error("chem_mech_create: non-finite NASA coefficient of species %d", k);
+        return CHEM_EMECH;
+      }
+  }
+  std::vector<int> cnt(K, 0);
+  for (int r = 0; r < R; ++r) {
+    const int32_t *sp = d->rsp + 4 * r, *nu = d->rnu + 4 * r;
+    if (!(d->A[r] > 0.0) || !isfinite(d->A[r]) || !isfinite(d->b[r]) || !isfinite(d->Ea[r])) {
+      set_error("chem_mech_create: reaction %d has a non-positive or non-finite A/b/Ea", r);
+      return CHEM_EMECH;
+    }
+    std::vector<long> bal(E, 0);
+    int nreac = 0, nprod = 0;
+    for (int s = 0; s < 4; ++s) {
+      if (sp[s] < 0) continue;
+      if (sp[s] >= K || nu[s] < 1 || nu[s] > 2) {
+        set_error("chem_mech_create: reaction %d slot %d: species %d / coefficient %d invalid", r,
+                  s, sp[s], nu[s]);
+        return CHEM_EMECH;
+      }
+      for (int t = 0; t < s; ++t)
+        if (sp[t] == sp[s]) {
+          set_error("chem_mech_create: reaction %d lists species %d twice", r, sp[s]);
+          return CHEM_EMECH;
+        }
+      (s < 2 ? nreac : nprod)++;
+      for (int e = 0; e < E; ++e) bal[e] += (s < 2 ? -1 : 1) * (long)nu[s] * d->comp[sp[s] * E + e];
+      cnt[sp[s]]++;
+    }
+    if (nreac == 0 || nprod == 0) {
+      set_error("chem_mech_create: reaction %d needs at least one reactant and one product", r);
+      return CHEM_EMECH;
+    }
+    for (int e = 0; e < E; ++e)
+      if (bal[e] != 0) {
+        set_error("chem_mech_create: reaction %d does not conserve element %d", r, e);
+        return CHEM_EMECH;
+      }
+  }
+
+  // host-side tables
+  std::vector<double> W(K), invW(K), Tmid(K), lo(7 * K), hi(7 * K);
+  for (int k = 0; k < K; ++k) {
+    W[k] = d->W[k];
+    invW[k] = 1.0 / d->W[k];
+    Tmid[k] = d->nasa[17 * k + 1];
+    for (int j = 0; j < 7; ++j) {
+      lo[7 * k + j] = d->nasa[17 * k + 3 + j];
+      hi[7 * k + j] = d->nasa[17 * k + 10 + j];
+    }
+  }
+  std::vector<double> lnA(R), bb(R), EaR(R), dn(R);
+  std::vector<int4> sp4(R), nu4(R);
+  const double RGAS = 8.314462618;
+  for (int r = 0; r < R; ++r) {
+    const int32_t *sp = d->rsp + 4 * r, *nu = d->rnu + 4 * r;
+    lnA[r] = log(d->A[r]);
+    bb[r] = d->b[r];
+    EaR[r] = d->Ea[r] / RGAS;
+    int dnn = 0;
+    int s4[4], n4[4];
+    for (int s = 0; s < 4; ++s) {
+      s4[s] = sp[s] < 0 ? -1 : sp[s];
+      n4[s] = sp[s] < 0 ? 0 : nu[s];
+      dnn += (s < 2 ? -1 : 1) * n4[s];
+    }
+    dn[r] = dnn;
+    sp4[r] = make_int4(s4[0], s4[1], s4[2], s4[3]);
+    nu4[r] = make_int4(n4[0], n4[1], n4[2], n4[3]);
+  }
+  std::vector<int> off(K + 1, 0);
+  for (int k = 0; k < K; ++k) off[k + 1] = off[k] + cnt[k];
+  const int nnz = off[K];
+  std::vector<int> cr(nnz > 0 ? nnz : 1), cs(nnz > 0 ? nnz : 1);
+  std::vector<double> cn(nnz > 0 ? nnz : 1);
+  std::vector<int> fill(off.begin(), off.end() - 1);
+  for (int r = 0; r < R; ++r)
+    for (int s = 0; s < 4; ++s) {
+      const int k = d->rsp[4 * r + s];
+      if (k < 0) continue;
+      const int e = fill[k]++;
+      cr[e] = r;
+      cs[e] = s;
+      cn[e] = (s < 2 ? -1.0 : 1.0) * d->rnu[4 * r + s];
+    }
+  std::vector<double> Mel((size_t)E * K);
+  for (int e = 0; e < E; ++e)
+    for (int k = 0; k < K; ++k) Mel[(size_t)e * K + k] = d->comp[k * E + e] * d->awt[e] / d->W[k];
+
+  Packer pk;
+  size_t oW = pk.add(W.data(), K * 8), oiW = pk.add(invW.data(), K * 8),
+         oTm = pk.add(Tmid.data(), K * 8), olo = pk.add(lo.data(), 7 * K * 8),
+         ohi = pk.add(hi.data(), 7 * K * 8), olnA = pk.add(lnA.data(), R * 8),
+         ob = pk.add(bb.data(), R * 8), oEa = pk.add(EaR.data(), R * 8),
+         odn = pk.add(dn.data(), R * 8), osp = pk.add(sp4.data(), R * sizeof(int4)),
+         onu = pk.add(nu4.data(), R * sizeof(int4)), ooff = pk.add(off.data(), (K + 1) * 4),
+         ocr = pk.add(cr.data(), cr.size() * 4), ocs = pk.add(cs.data(), cs.size() * 4),
+         ocn = pk.add(cn.data(), cn.size() * 8), oM = pk.add(Mel.data(), Mel.size() * 8);
+
+  chem_mech *m = new chem_mech();
+  m->K = K;
+  m->R = R;
+  m->E = E;
+  hipError_t e = hipGetDevice(&m->device);
+  if (e == hipSuccess) e = hipMalloc(&m->blob, pk.buf.size());
+  if (e != hipSuccess) {
+    delete m;
+    set_error("chem_mech_create: device allocation: %s", hipGetErrorString(e));
+    return CHEM_ENOMEM;
+  }
+  e = hipMalloc((void **)&m->counters, 64 * sizeof(unsigned long long));
+  if (e != hipSuccess) {
+    (void)hipFree(m->blob);
+    delete m;
+    set_error("chem_mech_create: device allocation: %s", hipGetErrorString(e));
+    return CHEM_ENOMEM;
+  }
+  e = hipMemcpy(m->blob, pk.buf.data(), pk.buf.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(m->counters, 0, 64 * sizeof(unsigned long long));
+  if (e != hipSuccess) {
+    (void)hipFree(m->blob);
+    (void)hipFree(m->counters);
+    delete m;
+    return hip_fail(e, "chem_mech_create: upload");
+  }
+  const unsigned char *base = (const unsigned char *)m->blob;
+  DevMech &dm = m->d;
+  dm.K = K;
+  dm.R = R;
+  dm.E = E;
+  dm.n = K + 1;
+  dm.W = (const double *)(base + oW);
+  dm.invW = (const double *)(base + oiW);
+  dm.Tmid = (const double *)(base + oTm);
+  dm.nasa_lo = (const double *)(base + olo);
+  dm.nasa_hi = (const double *)(base + ohi);
+  dm.lnA = (const double *)(base + olnA);
+  dm.b = (const double *)(base + ob);
+  dm.EaR = (const double *)(base + oEa);
+  dm.dn = (const double *)(base + odn);
+  dm.sp = (const int4 *)(base + osp);
+  dm.nu = (const int4 *)(base + onu);
+  dm.csr_off = (const int *)(base + ooff);
+  dm.csr_r = (const int *)(base + ocr);
+  dm.csr_slot = (const int *)(base + ocs);
+  dm.csr_nu = (const double *)(base + ocn);
+  dm.Mel = (const double *)(base + oM);
+  *out = m;
+  return CHEM_OK;
+}
+
+extern "C" void chem_mech_destroy(chem_mech *m) {
+  if (!m) return;
+  (void)hipFree(m->blob);
+  (void)hipFree(m->counters);
+  delete m;
+}
+
+extern "C" int32_t chem_mech_num_species(const chem_mech *m) { return m ? m->K : -1; }
+extern "C" int32_t chem_mech_num_reactions(const chem_mech *m) { return m ? m->R : -1; }
+
+static chem_status check_batch(const char *fn, const chem_mech *m, chem_batch b) {
+  if (!m) {
+    set_error("%s: null mechanism", fn);
+    return CHEM_EINVAL;
+  }
+  if (b.n < 0 || b.ld < b.n || b.n > (int64_t)1 << 40) {
+    set_error("%s: bad batch n=%lld ld=%lld", fn, (long long)b.n, (long long)b.ld);
+    return CHEM_EINVAL;
+  }
+  return CHEM_OK;
+}
+
+extern "C" chem_status chem_rates(const chem_mech *m, chem_batch batch, const double *T,
+                                  const double *p, const double *Y, double *wdot, double *dTdt,
+                                  double *kfkr, void *stream) {
+  chem_status st = check_batch("chem_rates", m, batch);
+  if (st != CHEM_OK) return st;
+  if (batch.n == 0) return CHEM_OK;
+  if (!T || !p || !Y || !wdot) {
+    set_error("chem_rates: T, p, Y and wdot must be non-null");
+    return CHEM_EINVAL;
+  }
+  return launch_rates(m, batch.n, batch.ld, T, p, Y, wdot, dTdt, kfkr, (hipStream_t)stream);
+}
+
+extern "C" chem_status chem_step(const chem_mech *m, chem_batch batch, double dt,
+                                 const double *dt_cell, double *T, const double *p, double *Y,
+                                 double *RR, double *h_hint, int32_t *stats,
+                                 const chem_step_opts *opts, void *stream) {
+  chem_status st = check_batch("chem_step", m, batch);
+  if (st != CHEM_OK) return st;
+  if (batch.n == 0) return CHEM_OK;
+  if (!T || !p || !Y) {
+    set_error("chem_step: T, p and Y must be non-null");
+    return CHEM_EINVAL;
+  }
+  if (!dt_cell && !(dt > 0.0 && isfinite(dt))) {
+    set_error("chem_step: dt must be finite and positive (got %g)", dt);
+    return CHEM_EINVAL;
+  }
+  StepOpts o = resolve_opts(opts);
+  if (!(o.rtol > 0.0) || !(o.atol_Y >= 0.0) || !(o.atol_T >= 0.0) || !(o.h0 > 0.0) ||
+      !(o.h_min >= 0.0) || o.max_steps < 1) {
+    set_error("chem_step: invalid options (rtol>0, atol>=0, h0>0, h_min>=0, max_steps>=1)");
+    return CHEM_EINVAL;
+  }
+  return launch_step(m, batch.n, batch.ld, dt, dt_cell, T, p, Y, RR, h_hint, stats, o, nullptr,
+                     (hipStream_t)stream);
+}

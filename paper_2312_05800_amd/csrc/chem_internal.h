@@ -1,0 +1,71 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "chemstep.h"
+
+namespace chem {
+
+constexpr int KMAX = 63;  // species limit: n = K + 1 <= 64 lanes per cell
+
+// Device-resident mechanism constants (one allocation, see chem_api.hip).
+struct DevMech {
+  int K, R, E, n;
+  const double *W;        // [K] kg/mol
+  const double *invW;     // [K]
+  const double *Tmid;     // [K]
+  const double *nasa_lo;  // [K][7]
+  const double *nasa_hi;  // [K][7]
+  const double *lnA;      // [R]
+  const double *b;        // [R]
+  const double *EaR;      // [R] Ea / R_gas, K
+  const double *dn;       // [R] sum of product minus reactant coefficients
+  const int4 *sp;         // [R] species of slots reactant0, reactant1, product0, product1 (-1 none)
+  const int4 *nu;         // [R] their coefficients (0 for empty slots)
+  const int *csr_off;     // [K+1] reactions in which species k takes part ...
+  const int *csr_r;       // [nnz]   ... in ascending order,
+  const int *csr_slot;    // [nnz]   its slot in that reaction,
+  const double *csr_nu;   // [nnz]   and its signed net coefficient
+  const double *Mel;      // [E][K] element mass per unit mass fraction, A_e a_ek / W_k
+};
+
+struct StepOpts {
+  double rtol, atol_Y, atol_T, h0, h_min;
+  int max_steps;
+};
+
+}  // namespace chem
+
+struct chem_mech {
+  chem::DevMech d;
+  void *blob;                      // device allocation behind d
+  unsigned long long *counters;    // device work-queue counters
+  int device;
+  int K, R, E;
+};
+
+namespace chem {
+
+void set_error(const char *fmt, ...);
+chem_status hip_fail(hipError_t e, const char *what);
+
+#define CHEM_HIP(call)                                   \
+  do {                                                   \
+    hipError_t e_ = (call);                              \
+    if (e_ != hipSuccess) return chem::hip_fail(e_, #call); \
+  } while (0)
+
+StepOpts resolve_opts(const chem_step_opts *o);
+
+// launchers (chem_kernels.hip)
+chem_status launch_rates(const chem_mech *m, int64_t n, int64_t ld, const double *T,
+                         const double *p, const double *Y, double *wdot, double *dTdt,
+                         double *kfkr, hipStream_t s);
+chem_status launch_step(const chem_mech *m, int64_t n, int64_t ld, double dt,
+                        const double *dt_cell, double *T, const double *p, double *Y,
+                        double *RR, double *h_hint, int32_t *stats, const StepOpts &o,
+                        const int32_t *index, hipStream_t s);
+
+}  // namespace chem

@@ -1,0 +1,53 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads and
+exports every function include/chemstep.h declares; status strings."""
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = []
+    for fn in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names += re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s*"
+                                r"([a-z][a-z0-9_]+)\s*\(", txt, flags=re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_declared_symbols():
+    import paper_2312_05800_amd as P
+    L = P.lib()
+    names = _declared()
+    assert "chem_step" in names and "chem_rates" in names
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_status_strings():
+    import paper_2312_05800_amd as P
+    assert P.status_name(0) == "CHEM_OK"
+    assert P.status_name(1) == "CHEM_EINVAL"
+    assert P.status_name(6) == "CHEM_EUNSUPPORTED"
+
+
+def test_invalid_mechanism_rejected_on_host():
+    """Validation runs before any device call, so it works without a GPU."""
+    import numpy as np
+    import chemgen
+    import paper_2312_05800_amd as P
+    m = chemgen.make_mechanism("h2")
+    bad = chemgen.Mech(**{**m.__dict__, "rnu": m.rnu.copy()})
+    bad.rnu[0, 2] = 2 if bad.rnu[0, 2] == 1 else 1  # breaks the element balance of reaction 0
+    with pytest.raises(P.ChemError) as e:
+        P.Mechanism(bad)
+    assert e.value.status == 4
+    big = chemgen.Mech(**{**m.__dict__, "W": np.zeros(70), "nasa": np.zeros((70, 17)),
+                          "comp": np.zeros((70, 3), dtype=np.int32)})
+    with pytest.raises(P.ChemError) as e:
+        P.Mechanism(big)
+    assert e.value.status == 6

@@ -1,0 +1,190 @@
+"""Parity of the HIP plain path (chem_rates, chem_step) with the CPU oracle,
+called through the C ABI."""
+import sys
+
+import numpy as np
+import pytest
+
+import chemgen
+import oracle
+from gpu_util import need_gpu, to_dev, one_way_scale, compare_state
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return need_gpu()
+
+
+@pytest.fixture(scope="module")
+def gm(dev):
+    import paper_2312_05800_amd as P
+    return {c: P.Mechanism(chemgen.make_mechanism(c)) for c in ("h2", "ch4")}
+
+
+@pytest.mark.parametrize("which,N", [("h2", 4096), ("ch4", 3001), ("h2", 1), ("ch4", 65)])
+def test_rates_parity(dev, gm, which, N):
+    import torch
+    import paper_2312_05800_amd as P
+    _say(f"[rates] {which} N={N}")
+    mech = chemgen.make_mechanism(which)
+    om = oracle.OracleMech(mech)
+    T, p, Y = chemgen.make_states(mech, which, N=N, seed=101)
+    w_o, dT_o, kf_o, kr_o = oracle.chem_rates(om, T, p, Y, want_k=True)
+    out = P.chem_rates(gm[which], to_dev(T, dev), to_dev(p, dev), to_dev(Y, dev), kfkr=True)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(out["kf"].cpu().numpy(), kf_o, rtol=1e-12, atol=0)
+    np.testing.assert_allclose(out["kr"].cpu().numpy(), kr_o, rtol=1e-12, atol=0)
+    sc = one_way_scale(mech, T, p, Y, kf_o, kr_o)
+    w_g = out["wdot"].cpu().numpy()
+    assert np.all(np.abs(w_g - w_o) <= 1e-12 * sc[None, :] * 4 + 1e-300)
+    # T rate: the terms of -sum h_k wdot_k/(rho c_p) have size max|h| * scale
+    RG = 8.314462618
+    hmax = np.array([np.abs(oracle.thermo(om, t)[1]).max() * RG * t for t in T])
+    S = (Y / mech.W[:, None]).sum(axis=0)
+    rho = p / (RG * T * S)
+    cp = np.array([np.sum(Y[:, i] * RG * oracle.thermo(om, T[i])[0] / mech.W)
+                   for i in range(N)])
+    scT = hmax * sc * 4 / (rho * cp)
+    dT_g = out["dTdt"].cpu().numpy()
+    assert np.all(np.abs(dT_g - dT_o) <= 1e-12 * mech.R * scT + 1e-300)
+
+
+def _gpu_step(P, gmech, dev, T, p, Y, dt, **kw):
+    import torch
+    Td, pd, Yd = to_dev(T, dev), to_dev(p, dev), to_dev(Y, dev)
+    K, N = Y.shape
+    RR = torch.zeros((K, N), dtype=torch.float64, device=dev)
+    st = torch.zeros((3, N), dtype=torch.int32, device=dev)
+    hh = kw.pop("h_hint", None)
+    hd = None if hh is None else to_dev(hh, dev)
+    dtc = kw.pop("dt_cell", None)
+    dtd = None if dtc is None else to_dev(dtc, dev)
+    P.chem_step(gmech, dt, Td, pd, Yd, dt_cell=dtd, RR=RR, h_hint=hd, stats=st, **kw)
+    torch.cuda.synchronize()
+    return dict(T=Td.cpu().numpy(), Y=Yd.cpu().numpy(), RR=RR.cpu().numpy(),
+                stats=st.cpu().numpy(), h_hint=None if hd is None else hd.cpu().numpy())
+
+
+@pytest.mark.parametrize("which,N,dt", [("h2", 4096, 1e-6), ("ch4", 1500, 1e-5)])
+def test_step_parity(dev, gm, which, N, dt):
+    """The whole small config (4096 H2/air cells) and a ragged CH4 batch:
+    T and Y_k > 1e-10 within 1e-8 of the oracle, identical step counts."""
+    import paper_2312_05800_amd as P
+    _say(f"[step] {which} N={N} dt={dt}")
+    mech = chemgen.make_mechanism(which)
+    om = oracle.OracleMech(mech)
+    T, p, Y = chemgen.make_states(mech, which, N=N, seed=202)
+    o = oracle.chem_step(om, dt, T, p, Y)
+    g = _gpu_step(P, gm[which], dev, T, p, Y, dt)
+    flips = np.nonzero(np.any(g["stats"][:2] != o["stats"][:2], axis=0))[0]
+    _say(f"  controller flips: {flips.size}; n_acc mean {o['stats'][0].mean():.1f}")
+    np.testing.assert_array_equal(g["stats"][2], o["stats"][2])
+    res = compare_state(g["T"], g["Y"], o["T"], o["Y"])
+    _say(f"  worst rel err T {res['T']:.2e} Y {res['Y']:.2e} tiny-Y abs {res['Ytiny']:.2e}")
+    assert flips.size == 0
+    assert res["ok"], res
+    np.testing.assert_allclose(g["RR"], o["RR"], rtol=1e-6,
+                               atol=1e-8 * np.abs(o["RR"]).max())
+
+
+def test_step_full_size_sampled(dev, gm):
+    """2^20 CH4/air cells in one launch (the benchmarked configuration);
+    the oracle recomputes an evenly spaced sample of 384 cells."""
+    import paper_2312_05800_amd as P
+    N = 1 << 20
+    _say(f"[step] ch4 full N={N}")
+    mech = chemgen.make_mechanism("ch4")
+    om = oracle.OracleMech(mech)
+    T, p, Y = chemgen.make_states(mech, "ch4")
+    g = _gpu_step(P, gm["ch4"], dev, T, p, Y, 1e-5)
+    idx = np.linspace(0, N - 1, 384).astype(np.int64)
+    o = oracle.chem_step(om, 1e-5, T[idx], p[idx], Y[:, idx])
+    assert np.all(g["stats"][2] == 0)
+    res = compare_state(g["T"][idx], g["Y"][:, idx], o["T"], o["Y"])
+    _say(f"  sample worst rel err T {res['T']:.2e} Y {res['Y']:.2e}")
+    assert res["ok"], res
+    np.testing.assert_array_equal(g["stats"][:, idx], o["stats"])
+    # properties that hold for every cell: element and mass conservation
+    Mel = mech.comp.T * mech.awt[:, None] / mech.W[None, :]
+    assert np.abs(Mel @ g["Y"] - Mel @ Y).max() <= 1e-12
+    assert np.abs(g["Y"].sum(axis=0) - 1.0).max() <= 1e-12
+
+
+def test_step_edge_cases(dev, gm):
+    import torch
+    import paper_2312_05800_amd as P
+    _say("[step] edge cases")
+    mech = chemgen.make_mechanism("ch4")
+    om = oracle.OracleMech(mech)
+    T, p, Y = chemgen.make_states(mech, "ch4", N=40, seed=303)
+    T = T.copy()
+    Y = Y.copy()
+    T[0] = np.nan
+    T[1] = -1.0
+    Y[4, 2] = np.inf
+    o = oracle.chem_step(om, 1e-5, T, p, Y)
+    g = _gpu_step(P, gm["ch4"], dev, T, p, Y, 1e-5)
+    np.testing.assert_array_equal(g["stats"], o["stats"])
+    np.testing.assert_array_equal(g["T"][:3], T[:3])
+    assert np.all(g["RR"][:, :3] == 0)
+    # per-cell dt and the step-size hint
+    dtc = np.where(np.arange(40) % 3 == 0, 1e-5, 2e-6)
+    hh = np.where(np.arange(40) % 2 == 0, 0.0, 3e-7)
+    o = oracle.chem_step(om, 1.0, T[3:], p[3:], Y[:, 3:], dt_cell=dtc[3:], h_hint=hh[3:])
+    g = _gpu_step(P, gm["ch4"], dev, T[3:], p[3:], Y[:, 3:], 1.0, dt_cell=dtc[3:], h_hint=hh[3:])
+    np.testing.assert_array_equal(g["stats"], o["stats"])
+    assert compare_state(g["T"], g["Y"], o["T"], o["Y"])["ok"]
+    np.testing.assert_allclose(g["h_hint"], o["h_hint"], rtol=1e-6)
+    # failure controls
+    for opts, code in ((dict(max_steps=1), 1), (dict(h_min=1.0), 2)):
+        g = _gpu_step(P, gm["ch4"], dev, T[3:], p[3:], Y[:, 3:], 1e-5, opts=opts)
+        assert np.all(g["stats"][2] == code)
+        np.testing.assert_array_equal(g["Y"], Y[:, 3:])
+    # empty batch and argument errors
+    e = torch.zeros(0, dtype=torch.float64, device=dev)
+    P.chem_step(gm["ch4"], 1e-5, e, e, torch.zeros((mech.K, 0), dtype=torch.float64, device=dev))
+    with pytest.raises(P.ChemError):
+        P.chem_step(gm["ch4"], -1.0, to_dev(T[3:], dev), to_dev(p[3:], dev),
+                    to_dev(Y[:, 3:], dev))
+
+
+def test_step_padded_leading_dimension(dev, gm):
+    """Y given as a [K, n] view of a wider [K, ld] buffer."""
+    import torch
+    import paper_2312_05800_amd as P
+    mech = chemgen.make_mechanism("h2")
+    om = oracle.OracleMech(mech)
+    T, p, Y = chemgen.make_states(mech, "h2", N=100, seed=404)
+    buf = torch.full((mech.K, 128), -7.0, dtype=torch.float64, device=dev)
+    buf[:, :100] = to_dev(Y, dev)
+    Td, pd = to_dev(T, dev), to_dev(p, dev)
+    P.chem_step(gm["h2"], 1e-6, Td, pd, buf[:, :100])
+    torch.cuda.synchronize()
+    o = oracle.chem_step(om, 1e-6, T, p, Y)
+    b = buf.cpu().numpy()
+    assert np.all(b[:, 100:] == -7.0)
+    assert compare_state(Td.cpu().numpy(), b[:, :100], o["T"], o["Y"])["ok"]
+
+
+def test_equilibrium_unchanged(dev, gm):
+    import paper_2312_05800_amd as P
+    from oracle.equilibrium import equilibrium_state
+    mech = chemgen.make_mechanism("ch4")
+    om = oracle.OracleMech(mech)
+    Ys, Ts = [], []
+    for i, T in enumerate((900.0, 1500.0, 2200.0, 2800.0)):
+        Ys.append(equilibrium_state(om, T, oracle.PREF, np.linspace(-2 - i, -9, mech.E)))
+        Ts.append(T)
+    Y = np.stack(Ys, axis=1)
+    T = np.array(Ts)
+    p = np.full(4, oracle.PREF)
+    g = _gpu_step(P, gm["ch4"], dev, T, p, Y, 1e-5)
+    np.testing.assert_allclose(g["T"], T, rtol=1e-10)
+    np.testing.assert_allclose(g["Y"], Y, rtol=1e-9, atol=1e-18)
