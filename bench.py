@@ -1,0 +1,319 @@
+#!/usr/bin/env python3
+"""Chemistry cells/s of the BF16 ANN step and of the FP64 integrator step on
+one MI355X (2^20 cells of the 30-species / 150-reaction CH4/air mechanism,
+dt = 1e-5 s), at the error measured against the CPU oracle.
+
+One timed step = one ann_step call over all cells (network, post-processing
+and FP64 fallback of flagged cells), with the input state restored from a
+pristine device copy first.  The FP64 integrator (chem_step) is timed the
+same way for the ratio.  The network is trained first on this GPU by the
+library's own kernels (labels from chem_step on perturbed states) unless
+--model names a saved one.  Prints one JSON line on stdout; progress goes to
+stderr.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "chemistry cells/s per step: BF16 ANN vs FP64 stiff integrator, at stated error"
+PEAK_BF16 = 2500e12   # dense MFMA, FLOP/s
+PEAK_FP64 = 78.6e12   # vector FP64, FLOP/s
+HIDDEN = (1600, 800, 400)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def rodas3_flops_per_attempt(mech):
+    """Algorithmic FP64 operations of one attempted RODAS3 step of one cell
+    (adds, multiplies, divides, FMA = 2, each exp/log/pow/sqrt = 1), counted
+    from the algorithm: 3 right-hand sides, 1 Jacobian, 1 LU, 4 solves, stage
+    combinations and the error norm."""
+    K, R = mech.K, mech.R
+    n = K + 1
+    nnz = int((mech.rsp >= 0).sum())
+    rhs = 44 * K + 30 * R + 2 * nnz + 6 * K + 24
+    jac = 34 * K + 16 * R + 25 * nnz + 11 * K * K + n * n
+    lu = sum(2 * j * j + j for j in range(1, n)) + n
+    solve = 2 * n * n - n
+    return 3 * rhs + jac + lu + 4 * solve + 60 * n
+
+
+def mlp_flops_per_cell(K):
+    dims = [K + 2, *HIDDEN, K]
+    return sum(2 * a * b for a, b in zip(dims[:-1], dims[1:]))
+
+
+def train_model(P, mech, gm, dev, args):
+    """Generate labels with the FP64 GPU integrator and train the network."""
+    import numpy as np
+    import torch
+    import chemgen
+    K = mech.K
+    t0 = time.time()
+    cfg = dict(chemgen.STATE_CONFIGS["ch4_train"])
+    T, p, Y0 = chemgen.make_states(mech, cfg, N=args.train_cells)
+    Td, pd, Y0d = (torch.from_numpy(a).to(dev) for a in (T, p, Y0))
+    T1d, Y1d = Td.clone(), Y0d.clone()
+    st = torch.zeros((3, T.size), dtype=torch.int32, device=dev)
+    torch.cuda.synchronize()
+    tg = time.time()
+    P.chem_step(gm, 1e-5, T1d, pd, Y1d, stats=st)
+    torch.cuda.synchronize()
+    t_label = time.time() - tg
+    ok = (st[2] == 0)
+    nbad = int((~ok).sum().item())
+    keep = torch.nonzero(ok).flatten()
+    Td, pd, Y0d, Y1d = Td[keep].contiguous(), pd[keep].contiguous(), \
+        Y0d[:, keep].contiguous(), Y1d[:, keep].contiguous()
+    n = Td.shape[0]
+    log(f"[train] labels for {T.size} states in {t_label:.2f} s ({nbad} failed)")
+    m = P.AnnModel(K + 2, K, HIDDEN, seed=args.seed)
+    m.fit_norm(Td, pd, Y0d, Y1d, 0.1, 1e-5)
+    loss = torch.zeros(1, dtype=torch.float32, device=dev)
+    rng = np.random.default_rng(args.seed)
+    B = args.batch
+    perm = None
+    pos = n
+    hist = []
+    tt = time.time()
+    for it in range(args.train_steps):
+        if pos + B > n:
+            perm = torch.from_numpy(rng.permutation(n).astype(np.int64)).to(dev)
+            pos = 0
+        idx = perm[pos:pos + B]
+        pos += B
+        frac = it / max(1, args.train_steps - 1)
+        lr = 1e-5 + 0.5 * (args.lr - 1e-5) * (1 + math.cos(math.pi * frac))
+        m.train_step(Td, pd, Y0d, Y1d, loss, index=idx, lr=lr)
+        if it % 200 == 0 or it == args.train_steps - 1:
+            hist.append((it, float(loss.item())))
+            log(f"[train] step {it} lr {lr:.2e} loss {hist[-1][1]:.5f}")
+    torch.cuda.synchronize()
+    t_train = time.time() - tt
+    info = dict(states=int(T.size), label_seconds=round(t_label, 3), failed_labels=nbad,
+                steps=args.train_steps, batch=B, train_seconds=round(t_train, 2),
+                ms_per_train_step=round(1e3 * t_train / max(1, args.train_steps), 3),
+                loss_first=hist[0][1] if hist else None, loss_last=hist[-1][1] if hist else None,
+                total_seconds=round(time.time() - t0, 2))
+    if args.save_model:
+        m.save(args.save_model)
+    return m, info
+
+
+def timed_loop(run, restore, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        restore()
+        run()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        restore()
+        run()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t
+
+
+def nrmse_table(dY_model, dY_ref, Yref_mean, names):
+    """Range-normalised RMSE of Delta-Y per species; majors = mean Y >= 1e-3
+    with a non-zero range of the reference Delta-Y."""
+    import numpy as np
+    out = {}
+    for k, nm in enumerate(names):
+        rng_ = float(dY_ref[k].max() - dY_ref[k].min())
+        rmse = float(np.sqrt(np.mean((dY_model[k] - dY_ref[k]) ** 2)))
+        out[nm] = dict(nrmse=rmse / rng_ if rng_ > 0 else float("nan"), range=rng_,
+                       major=bool(Yref_mean[k] >= 1e-3 and rng_ > 0))
+    majors = [v["nrmse"] for v in out.values() if v["major"]]
+    return out, (max(majors) if majors else float("nan"))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--cells", type=int, default=1 << 20)
+    ap.add_argument("--fp64-steps", type=int, default=2)
+    ap.add_argument("--model", default=None, help="load a saved model instead of training")
+    ap.add_argument("--save-model", default=None)
+    ap.add_argument("--train-cells", type=int, default=1 << 21)
+    ap.add_argument("--train-steps", type=int, default=3000)
+    ap.add_argument("--batch", type=int, default=8192)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--seed", type=int, default=55)
+    ap.add_argument("--oracle-sample", type=int, default=2048)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the chemistry step has no inter-GPU exchange "
+              "and this build runs on a single MI355X; use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import chemgen
+    import paper_2312_05800_amd as P
+
+    dev = torch.device("cuda:0")
+    mech = chemgen.make_mechanism("ch4")
+    K = mech.K
+    gm = P.Mechanism(mech)
+    N = args.cells
+
+    if args.model and os.path.exists(args.model):
+        model = P.AnnModel.load(args.model)
+        train_info = dict(loaded=args.model)
+    else:
+        model, train_info = train_model(P, mech, gm, dev, args)
+
+    T, p, Y = chemgen.make_states(mech, "ch4", N=N)
+    T0d, pd, Y0d = (torch.from_numpy(a).to(dev) for a in (T, p, Y))
+    Td, Yd = T0d.clone(), Y0d.clone()
+    RR = torch.zeros((K, N), dtype=torch.float64, device=dev)
+    flags = torch.zeros(N, dtype=torch.uint8, device=dev)
+    nfb = torch.zeros(1, dtype=torch.int64, device=dev)
+
+    def restore():
+        Td.copy_(T0d)
+        Yd.copy_(Y0d)
+
+    # ---- BF16 ANN step (with FP64 fallback) ----
+    P.profile_enable(True)
+    P.profile_read()
+    t_ann = timed_loop(lambda: model.step(gm, 1e-5, Td, pd, Yd, RR=RR, flags=flags,
+                                          n_fallback=nfb),
+                       restore, args.steps, args.warmup)
+    prof_ann = P.profile_read()
+    ann_T, ann_Y = Td.cpu().numpy(), Yd.cpu().numpy()
+    n_fallback = int(nfb.item())
+    log(f"[ann] {args.steps} steps in {t_ann:.3f} s; fallback cells {n_fallback}")
+
+    # ---- FP64 integrator step ----
+    st = torch.zeros((3, N), dtype=torch.int32, device=dev)
+    t_fp64 = timed_loop(lambda: P.chem_step(gm, 1e-5, Td, pd, Yd, stats=st), restore,
+                        args.fp64_steps, 1)
+    prof_fp64 = P.profile_read()
+    P.profile_enable(False)
+    fp_T, fp_Y = Td.cpu().numpy(), Yd.cpu().numpy()
+    stats = st.cpu().numpy()
+    attempts = int(stats[0].sum() + stats[1].sum())
+    log(f"[fp64] {args.fp64_steps} steps in {t_fp64:.3f} s; attempts/cell "
+        f"{attempts / N:.2f}")
+
+    ann_cps = N * args.steps / t_ann
+    fp64_cps = N * args.fp64_steps / t_fp64
+
+    # ---- accuracy against the CPU oracle on an evenly spaced sample ----
+    import oracle
+    om = oracle.OracleMech(mech)
+    idx = np.linspace(0, N - 1, args.oracle_sample).astype(np.int64)
+    o = oracle.chem_step(om, 1e-5, T[idx], p[idx], Y[:, idx])
+    dY_ref = o["Y"] - Y[:, idx]
+    table, ann_major = nrmse_table(ann_Y[:, idx] - Y[:, idx], dY_ref, o["Y"].mean(axis=1),
+                                   mech.species)
+    _, frozen_major = nrmse_table(np.zeros_like(dY_ref), dY_ref, o["Y"].mean(axis=1),
+                                  mech.species)
+    # explicit Euler from the instantaneous rates (GPU chem_rates)
+    rates = P.chem_rates(gm, T0d, pd, Y0d)
+    w = rates["wdot"].cpu().numpy()[:, idx]
+    rho = p[idx] / (8.314462618 * T[idx] * (Y[:, idx] / mech.W[:, None]).sum(axis=0))
+    _, euler_major = nrmse_table(mech.W[:, None] * w / rho * 1e-5, dY_ref, o["Y"].mean(axis=1),
+                                 mech.species)
+    big = np.abs(o["Y"]) > 1e-10
+    fp_err = max(float(np.max(np.abs(fp_T[idx] - o["T"]) / o["T"])),
+                 float(np.max(np.abs(fp_Y[:, idx] - o["Y"])[big] / np.abs(o["Y"])[big])))
+    ann_Terr = float(np.sqrt(np.mean((ann_T[idx] - o["T"]) ** 2)))
+
+    # ---- roofline of the dominant kernels, from HIP events on their streams ----
+    def avg(prof, label):
+        c, tot = prof.get(label, (0, 0.0))
+        return (tot / c * 1e-3) if c else float("nan"), c
+    t_l2, c_l2 = avg(prof_ann, "mlp_l2")
+    chunk = min(N, 1 << 21)
+    l2_flops = 2.0 * HIDDEN[0] * HIDDEN[1] * chunk
+    ach_bf16 = l2_flops / t_l2
+    t_step, c_step = avg(prof_fp64, "chem_step")
+    fl_attempt = rodas3_flops_per_attempt(mech)
+    step_flops = fl_attempt * attempts
+    ach_fp64 = step_flops / t_step
+    kernels_ann = {k: dict(launches=v[0], avg_ms=round(v[1] / max(v[0], 1), 4))
+                   for k, v in prof_ann.items()}
+
+    # ---- CPU baseline: the oracle on a bounded sample of the same cells ----
+    nthr = oracle.max_threads()
+    probe_n = 256
+    pi = np.linspace(0, N - 1, probe_n).astype(np.int64)
+    tp = time.time()
+    oracle.chem_step(om, 1e-5, T[pi], p[pi], Y[:, pi])
+    tp = time.time() - tp
+    ns = int(min(N, max(probe_n, args.cpu_seconds / max(tp, 1e-6) * probe_n)))
+    si = np.linspace(0, N - 1, ns).astype(np.int64)
+    tc = time.time()
+    oracle.chem_step(om, 1e-5, T[si], p[si], Y[:, si])
+    tc = time.time() - tc
+    cpu_cps = ns / tc
+
+    out = {
+        "metric": METRIC,
+        "value": round(ann_cps, 1),
+        "unit": "cells/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * t_ann / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {
+            "workload": "stratified CH4/air, 30 species / 150 reactions, 2^20 cells, dt=1e-5 s; "
+                        "BF16 MLP 32-1600-800-400-30 with FP64 RODAS3 fallback",
+            "cells": N, "species": K, "reactions": mech.R, "dt": 1e-5,
+            "hidden": list(HIDDEN)},
+        "fp64": {"cells_per_s": round(fp64_cps, 1), "steps": args.fp64_steps,
+                 "ms_per_step": round(1e3 * t_fp64 / args.fp64_steps, 3),
+                 "attempts_per_cell": round(attempts / N, 3),
+                 "max_rel_err_vs_oracle": fp_err, "dtype": "f64"},
+        "speedup_ann_vs_fp64": round(ann_cps / fp64_cps, 2),
+        "accuracy": {"sample_cells": int(idx.size),
+                     "ann_nrmse_major_max": ann_major,
+                     "frozen_nrmse_major_max": frozen_major,
+                     "euler_nrmse_major_max": euler_major,
+                     "ann_T_rmse_K": ann_Terr,
+                     "fallback_cells": n_fallback,
+                     "per_species": {k: round(v["nrmse"], 5) for k, v in table.items()
+                                     if v["major"]}},
+        "roofline": {"kernel": "mlp_l2 (1600->800 BF16 GEMM, bias+GELU)", "bound": "mfma",
+                     "achieved": round(ach_bf16 / 1e12, 2), "peak": PEAK_BF16 / 1e12,
+                     "unit": "TFLOP/s", "frac": round(ach_bf16 / PEAK_BF16, 4),
+                     "traffic": None, "avg_ms": round(t_l2 * 1e3, 4), "launches": c_l2,
+                     "flops_per_launch": l2_flops},
+        "roofline_fp64": {"kernel": "k_step (RODAS3 persistent)", "bound": "alu",
+                          "achieved": round(ach_fp64 / 1e12, 3), "peak": PEAK_FP64 / 1e12,
+                          "unit": "TFLOP/s", "frac": round(ach_fp64 / PEAK_FP64, 4),
+                          "traffic": None, "avg_ms": round(t_step * 1e3, 3),
+                          "launches": c_step, "flops_per_attempt": fl_attempt,
+                          "attempts_per_launch": attempts},
+        "kernels_ann": kernels_ann,
+        "cpu_baseline": {"value": round(cpu_cps, 2), "unit": "cells/s", "cores": nthr,
+                         "kind": "oracle",
+                         "sample": f"{ns} evenly spaced cells of the 2^20-cell workload, "
+                                   f"FP64 RODAS3 oracle (plain C, OpenMP)"},
+        "training": train_info,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -135,6 +135,109 @@ chem_status chem_step(const chem_mech *m, chem_batch batch, double dt, const dou
                       double *T, const double *p, double *Y, double *RR, double *h_hint,
                       int32_t *stats, const chem_step_opts *opts, void *stream);
 
+/* ------------------------------------------------------------ surrogate
+ * The ANN of Sec. 3.2 that stands in for the integration: inputs
+ * x = {T, p, F(Y)} with the Box-Cox transform F(y) = (y^lambda - 1)/lambda
+ * (lambda = 0.1; negative y clamped to 0), z-score normalised with training
+ * statistics; three GELU hidden layers (1600, 800, 400 in the paper); a linear
+ * output u, the z-scored change Y(t+dt) - Y(t) of the mass fractions (the
+ * output is not transformed).  Hidden GEMMs run on
+ * BF16 MFMA with FP32 accumulation.  Trained with the L1 loss (Eq. Loss) and
+ * Adam on FP32 master weights. */
+typedef struct ann_model ann_model;
+
+typedef struct {
+  int32_t n_in;       /* K + 2 for a mechanism with K species */
+  int32_t n_out;      /* K */
+  int32_t hidden[3];  /* hidden widths */
+  int32_t prec;       /* 0 = BF16 everywhere (the only value this build accepts) */
+} ann_arch;
+
+/* Normalisation and validity statistics (all arrays host, copied). */
+typedef struct {
+  float lambda;          /* Box-Cox exponent */
+  double dt_model;       /* time step the network was trained for, s */
+  const float *mu_in, *sd_in;   /* [n_in] input z-score */
+  const float *lo, *hi;         /* [n_in] training range of the raw inputs (OOD test) */
+  const float *mu_out, *sd_out; /* [n_out] output z-score */
+} ann_norm;
+
+/* New network with weights and biases ~ U(-1/sqrt(fan_in), 1/sqrt(fan_in))
+ * from `seed`, zero Adam state, no statistics.  Owns device memory. */
+chem_status ann_create(const ann_arch *arch, uint64_t seed, ann_model **out);
+void ann_destroy(ann_model *m);
+/* Layer l in 0..3: W (host) [out][in] row-major FP32, b (host) [out]. */
+chem_status ann_set_layer(ann_model *m, int32_t layer, const float *W, const float *b);
+chem_status ann_get_layer(const ann_model *m, int32_t layer, float *W, float *b);
+/* Gradients of the loss from the last ann_train_step (host arrays as above). */
+chem_status ann_get_grad(const ann_model *m, int32_t layer, float *dW, float *db);
+chem_status ann_set_norm(ann_model *m, const ann_norm *norm);
+/* Host copies of the statistics; any pointer may be NULL. */
+chem_status ann_get_norm(const ann_model *m, float *mu_in, float *sd_in, float *lo, float *hi,
+                         float *mu_out, float *sd_out, float *lambda, double *dt_model);
+/* Statistics from a training set of n state pairs (Y1 = Y0 integrated over
+ * dt_model): mean and population standard deviation (a zero spread becomes 1)
+ * and range of every input feature and every target.  Synchronises `stream`. */
+chem_status ann_fit_norm(ann_model *m, chem_batch batch, const double *T, const double *p,
+                         const double *Y0, const double *Y1, float lambda, double dt_model,
+                         void *stream);
+/* Network output only: U [n][n_out] row-major FP32, z-space. */
+chem_status ann_forward(ann_model *m, chem_batch batch, const double *T, const double *p,
+                        const double *Y, float *U, void *stream);
+
+typedef struct {
+  float residual_tol;   /* [1e-6] max |element mass fraction change| allowed */
+  float ood_margin;     /* [0.05] widening of the training range, fraction of its span */
+  int32_t fallback;     /* [1] integrate flagged cells with chem_step */
+  float audit_fraction; /* reserved, must be 0 */
+} ann_step_opts;
+
+/* The surrogate chemistry step of every cell (the ANN replacing the
+ * reaction-rate integration, Sec. 1-2): Y' = Y0 + sd_out u + mu_out from
+ * the network, projected onto element conservation by weighted least
+ * squares (weights Y' + 1e-10), clipped at 0; T from h(T, Y) = h(T0, Y0) by
+ * FP64 Newton; RR = rho0 (Y - Y0)/dt.  A cell is flagged (flags [n], nullable)
+ * with bit 0 if an input lies outside the widened training range or dt
+ * differs from dt_model, bit 1 if the element residual exceeds residual_tol;
+ * flagged cells keep their input state and, with fallback on, are integrated
+ * by chem_step (fb_opts) on the same stream without a host round trip; bit 2
+ * marks a failed fallback.  n_fallback (device int64, nullable) receives the
+ * number of flagged cells.  Workspace grows on the first call with a larger n. */
+chem_status ann_step(ann_model *m, const chem_mech *mech, chem_batch batch, double dt, double *T,
+                     const double *p, double *Y, double *RR, uint8_t *flags,
+                     int64_t *n_fallback, const ann_step_opts *opts,
+                     const chem_step_opts *fb_opts, void *stream);
+
+typedef struct {
+  float lr, beta1, beta2, eps;
+} ann_train_opts;
+
+/* One optimisation step on a batch of B state pairs (B a multiple of 32):
+ * features and targets from T, p, Y0 and Y1 (Y0 integrated over dt_model),
+ * gathered through index (device int64 [B], nullable: cells 0..B-1 with ld);
+ * forward pass keeping activations; L1 loss (mean over samples and outputs)
+ * written to *loss (device float); backward pass (BF16 operands, FP32
+ * accumulation, deterministic bias reductions); Adam with bias correction on
+ * the FP32 master weights, refreshing the BF16 copies.  lr = 0 computes the
+ * gradients only (no update, step count unchanged). */
+chem_status ann_train_step(ann_model *m, chem_batch batch, const double *T, const double *p,
+                           const double *Y0, const double *Y1, const int64_t *index,
+                           const ann_train_opts *opts, float *loss, void *stream);
+int64_t ann_num_steps(const ann_model *m);
+/* Binary model file: architecture, statistics, master weights, Adam state. */
+chem_status ann_save(const ann_model *m, const char *path);
+chem_status ann_load(const char *path, ann_model **out);
+
+/* ---------------------------------------------------------- launch timing
+ * Instrumentation for measurement: when enabled, every kernel launch the
+ * library issues is bracketed by HIP events on its own stream.
+ * chem_profile_read synchronises on those events and returns, per launch
+ * label (host char[48]), the number of launches and their total duration in
+ * milliseconds since the previous read; returns the number of labels written
+ * (at most cap).  Off by default; costs two event records per launch. */
+void chem_profile_enable(int32_t on);
+int32_t chem_profile_read(char (*names)[48], int64_t *launches, double *total_ms, int32_t cap);
+
 #ifdef __cplusplus
 }
 #endif

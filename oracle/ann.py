@@ -2,8 +2,9 @@
 
 Follows the paper's ANN model (Sec. 3.2):
 * network input  x(t) = {T, p, F(Y(t))} with the Box-Cox transform F;
-* network output the change of the mass fractions over one time step, here
-  taken in Box-Cox space, u* = F(Y(t+dt)) - F(Y(t));
+* network output the change of the mass fractions over one time step,
+  u* = Y(t+dt) - Y(t), in physical mass-fraction units (only the inputs are
+  Box-Cox transformed);
 * inputs and outputs z-score normalised with training-set statistics;
 * hidden layers 1600, 800, 400 with GELU; Adam; L1 loss (Eq. Loss).
 
@@ -18,7 +19,7 @@ OCP FP8 E4M3 (saturating, round to nearest even) with per-tensor scales
 amax/448.  The GPU accumulates in FP32, so results agree to accumulation
 rounding, not bitwise.
 
-The post-processing (inverse Box-Cox, weighted least-squares projection onto
+The post-processing (de-normalisation, weighted least-squares projection onto
 element conservation, clipping, residual and out-of-distribution flags,
 enthalpy Newton for T, reaction rates) is not in the paper; it is this
 project's reading of how the ANN output becomes a full chemistry step.
@@ -95,8 +96,9 @@ def features(T, p, Y, lam=LAMBDA):
 
 
 def targets(Y0, Y1, lam=LAMBDA):
-    """u* = F(Y(t+dt)) - F(Y(t)), shape [K, N]."""
-    return boxcox(Y1, lam) - boxcox(Y0, lam)
+    """u* = Y(t+dt) - Y(t), shape [K, N] (lam unused: the output is not
+    transformed)."""
+    return Y1 - Y0
 
 
 def zstats(A):
@@ -260,7 +262,7 @@ def post(om: OracleMech, T0, p, Y0, u_z, mu_out, sd_out, dt, lo=None, hi=None,
     """From the z-space network output u_z ([K, N]) to (T, Y, RR, flags)."""
     mech = om.mech
     du = u_z * sd_out[:, None] + mu_out[:, None]
-    Yp = inv_boxcox(boxcox(Y0, lam) + du, lam)
+    Yp = Y0 + du
     Y = project(mech, Y0, Yp)
     Y = np.maximum(Y, 0.0)
     M = element_mass_matrix(mech)

@@ -1,0 +1,185 @@
+"""ctypes binding of the surrogate-form entry points (ann_* in
+include/chemstep.h).  Argument marshalling only."""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from .binding import Batch, StepOpts, _dptr, _opts, _soa, _stream, check, lib
+
+_P = C.c_void_p
+
+
+class Arch(C.Structure):
+    _fields_ = [("n_in", C.c_int32), ("n_out", C.c_int32), ("hidden", C.c_int32 * 3),
+                ("prec", C.c_int32)]
+
+
+class Norm(C.Structure):
+    _fields_ = [("lambda_", C.c_float), ("dt_model", C.c_double), ("mu_in", _P), ("sd_in", _P),
+                ("lo", _P), ("hi", _P), ("mu_out", _P), ("sd_out", _P)]
+
+
+class StepOptsANN(C.Structure):
+    _fields_ = [("residual_tol", C.c_float), ("ood_margin", C.c_float), ("fallback", C.c_int32),
+                ("audit_fraction", C.c_float)]
+
+
+class TrainOpts(C.Structure):
+    _fields_ = [("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float),
+                ("eps", C.c_float)]
+
+
+def _prototypes(L):
+    L.ann_create.argtypes = [C.POINTER(Arch), C.c_uint64, C.POINTER(_P)]
+    L.ann_destroy.argtypes = [_P]
+    L.ann_set_layer.argtypes = [_P, C.c_int32, _P, _P]
+    L.ann_get_layer.argtypes = [_P, C.c_int32, _P, _P]
+    L.ann_get_grad.argtypes = [_P, C.c_int32, _P, _P]
+    L.ann_set_norm.argtypes = [_P, C.POINTER(Norm)]
+    L.ann_get_norm.argtypes = [_P, _P, _P, _P, _P, _P, _P, _P, _P]
+    L.ann_fit_norm.argtypes = [_P, Batch, _P, _P, _P, _P, C.c_float, C.c_double, _P]
+    L.ann_forward.argtypes = [_P, Batch, _P, _P, _P, _P, _P]
+    L.ann_step.argtypes = [_P, _P, Batch, C.c_double, _P, _P, _P, _P, _P, _P, _P, _P, _P]
+    L.ann_train_step.argtypes = [_P, Batch, _P, _P, _P, _P, _P, _P, _P, _P]
+    L.ann_num_steps.argtypes = [_P]
+    L.ann_num_steps.restype = C.c_int64
+    L.ann_save.argtypes = [_P, C.c_char_p]
+    L.ann_load.argtypes = [C.c_char_p, C.POINTER(_P)]
+
+
+class AnnModel:
+    """Handle of a surrogate network (ann_model)."""
+
+    def __init__(self, n_in=None, n_out=None, hidden=(1600, 800, 400), seed=0, prec=0,
+                 _handle=None):
+        lib()
+        if _handle is not None:
+            self.handle = _handle
+        else:
+            a = Arch(int(n_in), int(n_out), (C.c_int32 * 3)(*hidden), int(prec))
+            h = _P()
+            check("ann_create", lib().ann_create(C.byref(a), C.c_uint64(seed), C.byref(h)))
+            self.handle = h
+        self._dims = None
+
+    @classmethod
+    def load(cls, path):
+        h = _P()
+        check("ann_load", lib().ann_load(str(path).encode(), C.byref(h)))
+        return cls(_handle=h)
+
+    def save(self, path):
+        check("ann_save", lib().ann_save(self.handle, str(path).encode()))
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            try:
+                lib().ann_destroy(h)
+            except Exception:
+                pass
+            self.handle = None
+
+    @property
+    def num_steps(self):
+        return int(lib().ann_num_steps(self.handle))
+
+    def _layer_shapes(self, dims):
+        return [(dims[i + 1], dims[i]) for i in range(4)]
+
+    def set_layer(self, layer, W, b):
+        W = np.ascontiguousarray(W, dtype=np.float32)
+        b = np.ascontiguousarray(b, dtype=np.float32)
+        check("ann_set_layer", lib().ann_set_layer(self.handle, int(layer), W.ctypes.data,
+                                                   b.ctypes.data))
+
+    def get_layer(self, layer, shape):
+        W = np.zeros(shape, dtype=np.float32)
+        b = np.zeros(shape[0], dtype=np.float32)
+        check("ann_get_layer", lib().ann_get_layer(self.handle, int(layer), W.ctypes.data,
+                                                   b.ctypes.data))
+        return W, b
+
+    def get_grad(self, layer, shape):
+        W = np.zeros(shape, dtype=np.float32)
+        b = np.zeros(shape[0], dtype=np.float32)
+        check("ann_get_grad", lib().ann_get_grad(self.handle, int(layer), W.ctypes.data,
+                                                 b.ctypes.data))
+        return W, b
+
+    def set_norm(self, lam, dt_model, mu_in, sd_in, lo, hi, mu_out, sd_out):
+        arrs = [np.ascontiguousarray(a, dtype=np.float32)
+                for a in (mu_in, sd_in, lo, hi, mu_out, sd_out)]
+        self._keep = arrs
+        n = Norm(float(lam), float(dt_model), *(a.ctypes.data for a in arrs))
+        check("ann_set_norm", lib().ann_set_norm(self.handle, C.byref(n)))
+
+    def get_norm(self, n_in, n_out):
+        out = dict(mu_in=np.zeros(n_in, np.float32), sd_in=np.zeros(n_in, np.float32),
+                   lo=np.zeros(n_in, np.float32), hi=np.zeros(n_in, np.float32),
+                   mu_out=np.zeros(n_out, np.float32), sd_out=np.zeros(n_out, np.float32))
+        lam = C.c_float()
+        dtm = C.c_double()
+        check("ann_get_norm", lib().ann_get_norm(
+            self.handle, *(out[k].ctypes.data for k in ("mu_in", "sd_in", "lo", "hi", "mu_out",
+                                                        "sd_out")), C.byref(lam), C.byref(dtm)))
+        out["lambda"] = lam.value
+        out["dt_model"] = dtm.value
+        return out
+
+    def fit_norm(self, T, p, Y0, Y1, lam=0.1, dt_model=1e-5, stream=None):
+        import torch
+        n = T.shape[0]
+        ld = _soa(Y0, Y0.shape[0], n, "Y0")
+        f64 = torch.float64
+        check("ann_fit_norm", lib().ann_fit_norm(
+            self.handle, Batch(n, ld), _dptr(T, f64, "T"), _dptr(p, f64, "p"),
+            _dptr(Y0, f64, "Y0"), _dptr(Y1, f64, "Y1"), float(lam), float(dt_model),
+            _stream(stream)))
+
+    def forward(self, T, p, Y, n_out, stream=None):
+        import torch
+        n = T.shape[0]
+        ld = _soa(Y, Y.shape[0], n, "Y")
+        U = torch.empty((n, n_out), dtype=torch.float32, device=T.device)
+        f64 = torch.float64
+        check("ann_forward", lib().ann_forward(
+            self.handle, Batch(n, ld), _dptr(T, f64, "T"), _dptr(p, f64, "p"),
+            _dptr(Y, f64, "Y"), _dptr(U), _stream(stream)))
+        return U
+
+    def step(self, mech, dt, T, p, Y, RR=None, flags=None, n_fallback=None, residual_tol=1e-6,
+             ood_margin=0.05, fallback=True, fb_opts=None, stream=None):
+        """Surrogate chemistry step, in place on T and Y.  RR ([K, ld] float64),
+        flags ([n] uint8) and n_fallback ([1] int64) are optional outputs."""
+        import torch
+        n = T.shape[0]
+        ld = _soa(Y, mech.K, n, "Y")
+        o = StepOptsANN(float(residual_tol), float(ood_margin), 1 if fallback else 0, 0.0)
+        fo = _opts(fb_opts)
+        f64 = torch.float64
+        check("ann_step", lib().ann_step(
+            self.handle, mech.handle, Batch(n, ld), float(dt), _dptr(T, f64, "T"),
+            _dptr(p, f64, "p"), _dptr(Y, f64, "Y"), _dptr(RR, f64, "RR"),
+            _dptr(flags, torch.uint8, "flags"), _dptr(n_fallback, torch.int64, "n_fallback"),
+            C.byref(o), None if fo is None else C.byref(fo), _stream(stream)))
+
+    def train_step(self, T, p, Y0, Y1, loss, index=None, B=None, lr=1e-3, beta1=0.9,
+                   beta2=0.999, eps=1e-8, stream=None):
+        """One Adam step on B pairs (cells index[0..B) of the [K, ld] arrays, or
+        the first B cells).  loss: device float32 [1] receiving the L1 loss."""
+        import torch
+        if index is not None:
+            B = index.shape[0]
+            ld = Y0.stride(0)
+        else:
+            B = T.shape[0] if B is None else B
+            ld = _soa(Y0, Y0.shape[0], B, "Y0")
+        o = TrainOpts(float(lr), float(beta1), float(beta2), float(eps))
+        f64 = torch.float64
+        check("ann_train_step", lib().ann_train_step(
+            self.handle, Batch(B, ld), _dptr(T, f64, "T"), _dptr(p, f64, "p"),
+            _dptr(Y0, f64, "Y0"), _dptr(Y1, f64, "Y1"), _dptr(index, torch.int64, "index"),
+            C.byref(o), _dptr(loss, torch.float32, "loss"), _stream(stream)))

@@ -61,6 +61,9 @@ def lib():
             L.chem_mech_num_reactions.argtypes = [_P]
             L.chem_rates.argtypes = [_P, Batch, _P, _P, _P, _P, _P, _P, _P]
             L.chem_step.argtypes = [_P, Batch, C.c_double, _P, _P, _P, _P, _P, _P, _P, _P, _P]
+            L.chem_profile_enable.argtypes = [C.c_int32]
+            L.chem_profile_read.argtypes = [_P, _P, _P, C.c_int32]
+            L.chem_profile_read.restype = C.c_int32
             _setup_ann(L)
             _lib = L
     return _lib
@@ -194,3 +197,18 @@ def chem_step(mech: Mechanism, dt, T, p, Y, dt_cell=None, RR=None, h_hint=None, 
         _dptr(p, f64, "p"), _dptr(Y, f64, "Y"), _dptr(RR, f64, "RR"),
         _dptr(h_hint, f64, "h_hint"), _dptr(stats, torch.int32, "stats"),
         None if o is None else C.byref(o), _stream(stream)))
+
+
+def profile_enable(on: bool = True):
+    """Bracket every library launch with HIP events on its own stream."""
+    lib().chem_profile_enable(1 if on else 0)
+
+
+def profile_read(cap: int = 64):
+    """{label: (launches, total_ms)} since the previous read (synchronises)."""
+    names = (C.c_char * 48 * cap)()
+    cnt = (C.c_int64 * cap)()
+    tot = (C.c_double * cap)()
+    n = lib().chem_profile_read(names, cnt, tot, cap)
+    return {bytes(names[i]).split(b"\0")[0].decode(): (int(cnt[i]), float(tot[i]))
+            for i in range(n)}

@@ -1,0 +1,862 @@
+// Host side of the surrogate (ANN) ABI: the model handle (weights, Adam
+// state, normalisation statistics, workspaces), inference with fallback to
+// the FP64 integrator, one training step, statistics fitting and save/load.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <vector>
+
+#include "ann_internal.h"
+
+using ann::u16;
+
+namespace {
+
+// Growable device workspace made of named sections.
+struct Workspace {
+  void *base = nullptr;
+  size_t bytes = 0;
+  int64_t cap = 0;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// splitmix64 (Steele, Lea & Flood 2014) for the seeded initial weights.
+struct SplitMix {
+  uint64_t s;
+  uint64_t next() {
+    uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  }
+  double uniform() { return (next() >> 11) * (1.0 / 9007199254740992.0); }
+};
+
+}  // namespace
+
+struct ann_model {
+  int device = 0;
+  int n_in = 0, n_out = 0, prec = 0;
+  ann::Layer L[ann::NLAYER];
+  float *Wm[ann::NLAYER] = {}, *bm[ann::NLAYER] = {};  // FP32 master parameters
+  u16 *Wb[ann::NLAYER] = {};                           // BF16 copies used by the GEMMs
+  float *mW[ann::NLAYER] = {}, *vW[ann::NLAYER] = {}, *mb[ann::NLAYER] = {},
+        *vb[ann::NLAYER] = {};
+  float *gW[ann::NLAYER] = {}, *gb[ann::NLAYER] = {};
+  void *params = nullptr;  // one allocation behind all of the above
+  int64_t step = 0;
+  bool has_norm = false;
+  ann::Norm nm{};
+  void *norm_buf = nullptr;
+  std::vector<float> h_mu_in, h_sd_in, h_lo, h_hi, h_mu_out, h_sd_out;
+  // inference workspace (per chunk of cells)
+  Workspace wi;
+  u16 *X = nullptr, *H[3] = {};
+  float *U = nullptr;
+  int32_t *fb_index = nullptr;  // fallback cell list (own allocation, fb_cap entries)
+  int64_t fb_cap = 0;
+  unsigned long long *fb_count = nullptr;
+  // training workspace (per batch)
+  Workspace wt;
+  u16 *tX = nullptr, *tH[3] = {}, *tGb[ann::NLAYER] = {};
+  float *tZ[3] = {}, *tU = nullptr, *tUt = nullptr, *tGf[ann::NLAYER] = {};
+  double *loss_part = nullptr;
+};
+
+using namespace chem;
+
+namespace {
+
+constexpr int64_t CHUNK = 1 << 21;  // cells per inference pass
+constexpr int LOSS_PARTS = 256;
+
+int pad32(int x) { return (x + 31) / 32 * 32; }
+
+size_t layer_elems(const ann::Layer &L) { return (size_t)L.doutp * L.dinp; }
+
+chem_status grow_infer(ann_model *m, int64_t n) {
+  const int64_t need = n < CHUNK ? n : CHUNK;
+  if (m->wi.cap >= need) return CHEM_OK;
+  const int64_t cap = need;
+  size_t off = 0;
+  auto sect = [&](size_t bytes) {
+    size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  const size_t oX = sect((size_t)cap * m->L[0].dinp * 2);
+  size_t oH[3];
+  for (int l = 0; l < 3; ++l) oH[l] = sect((size_t)cap * m->L[l].doutp * 2);
+  const size_t oU = sect((size_t)cap * m->n_out * 4);
+  const size_t oC = sect(64);
+  if (m->wi.base) (void)hipFree(m->wi.base);
+  m->wi.base = nullptr;
+  m->wi.cap = 0;
+  if (hipMalloc(&m->wi.base, off) != hipSuccess) {
+    set_error("ann: cannot allocate %zu bytes of inference workspace", off);
+    return CHEM_ENOMEM;
+  }
+  unsigned char *b = (unsigned char *)m->wi.base;
+  m->X = (u16 *)(b + oX);
+  for (int l = 0; l < 3; ++l) m->H[l] = (u16 *)(b + oH[l]);
+  m->U = (float *)(b + oU);
+  m->fb_count = (unsigned long long *)(b + oC);
+  m->wi.bytes = off;
+  m->wi.cap = cap;
+  return CHEM_OK;
+}
+
+chem_status grow_train(ann_model *m, int64_t B) {
+  if (m->wt.cap >= B) return CHEM_OK;
+  size_t off = 0;
+  auto sect = [&](size_t bytes) {
+    size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  const size_t oX = sect((size_t)B * m->L[0].dinp * 2);
+  size_t oH[3], oZ[3], oGb[4], oGf[4];
+  for (int l = 0; l < 3; ++l) {
+    oH[l] = sect((size_t)B * m->L[l].doutp * 2);
+    oZ[l] = sect((size_t)B * m->L[l].doutp * 4);
+  }
+  const size_t oU = sect((size_t)B * m->L[3].doutp * 4);
+  const size_t oUt = sect((size_t)B * m->L[3].doutp * 4);
+  for (int l = 0; l < 4; ++l) {
+    oGb[l] = sect((size_t)B * m->L[l].doutp * 2);
+    oGf[l] = sect((size_t)B * m->L[l].doutp * 4);
+  }
+  const size_t oL = sect(LOSS_PARTS * 8);
+  if (m->wt.base) (void)hipFree(m->wt.base);
+  m->wt.base = nullptr;
+  m->wt.cap = 0;
+  if (hipMalloc(&m->wt.base, off) != hipSuccess) {
+    set_error("ann: cannot allocate %zu bytes of training workspace", off);
+    return CHEM_ENOMEM;
+  }
+  unsigned char *b = (unsigned char *)m->wt.base;
+  m->tX = (u16 *)(b + oX);
+  for (int l = 0; l < 3; ++l) {
+    m->tH[l] = (u16 *)(b + oH[l]);
+    m->tZ[l] = (float *)(b + oZ[l]);
+  }
+  m->tU = (float *)(b + oU);
+  m->tUt = (float *)(b + oUt);
+  for (int l = 0; l < 4; ++l) {
+    m->tGb[l] = (u16 *)(b + oGb[l]);
+    m->tGf[l] = (float *)(b + oGf[l]);
+  }
+  m->loss_part = (double *)(b + oL);
+  m->wt.cap = B;
+  m->wt.bytes = off;
+  return CHEM_OK;
+}
+
+// Uploads logical [dout][din] FP32 weights into the padded device layout.
+chem_status upload_layer(ann_model *m, int l, const float *W, const float *b) {
+  const ann::Layer &L = m->L[l];
+  std::vector<float> Wp((size_t)L.doutp * L.dinp, 0.0f), bp(L.doutp, 0.0f);
+  for (int o = 0; o < L.dout; ++o) {
+    for (int i = 0; i < L.din; ++i) Wp[(size_t)o * L.dinp + i] = W[(size_t)o * L.din + i];
+    bp[o] = b[o];
+  }
+  CHEM_HIP(hipMemcpy(m->Wm[l], Wp.data(), Wp.size() * 4, hipMemcpyHostToDevice));
+  CHEM_HIP(hipMemcpy(m->bm[l], bp.data(), bp.size() * 4, hipMemcpyHostToDevice));
+  chem_status st = ann::to_bf16((int64_t)Wp.size(), m->Wm[l], m->Wb[l], nullptr);
+  if (st != CHEM_OK) return st;
+  CHEM_HIP(hipDeviceSynchronize());
+  return CHEM_OK;
+}
+
+chem_status download_pair(const ann_model *m, int l, const float *dW, const float *db, float *W,
+                          float *b) {
+  const ann::Layer &L = m->L[l];
+  std::vector<float> Wp((size_t)L.doutp * L.dinp), bp(L.doutp);
+  CHEM_HIP(hipDeviceSynchronize());
+  CHEM_HIP(hipMemcpy(Wp.data(), dW, Wp.size() * 4, hipMemcpyDeviceToHost));
+  CHEM_HIP(hipMemcpy(bp.data(), db, bp.size() * 4, hipMemcpyDeviceToHost));
+  if (W)
+    for (int o = 0; o < L.dout; ++o)
+      for (int i = 0; i < L.din; ++i) W[(size_t)o * L.din + i] = Wp[(size_t)o * L.dinp + i];
+  if (b)
+    for (int o = 0; o < L.dout; ++o) b[o] = bp[o];
+  return CHEM_OK;
+}
+
+chem_status check_model(const char *fn, const ann_model *m) {
+  if (!m) {
+    set_error("%s: null model", fn);
+    return CHEM_EINVAL;
+  }
+  return CHEM_OK;
+}
+
+chem_status upload_norm(ann_model *m) {
+  const int ni = m->n_in, no = m->n_out;
+  if (!m->norm_buf) {
+    CHEM_HIP(hipMalloc(&m->norm_buf, (size_t)(4 * ni + 2 * no) * 4));
+    float *f = (float *)m->norm_buf;
+    m->nm.mu_in = f;
+    m->nm.sd_in = f + ni;
+    m->nm.lo = f + 2 * ni;
+    m->nm.hi = f + 3 * ni;
+    m->nm.mu_out = f + 4 * ni;
+    m->nm.sd_out = f + 4 * ni + no;
+  }
+  std::vector<float> all;
+  for (auto *v : {&m->h_mu_in, &m->h_sd_in, &m->h_lo, &m->h_hi, &m->h_mu_out, &m->h_sd_out})
+    all.insert(all.end(), v->begin(), v->end());
+  CHEM_HIP(hipMemcpy(m->norm_buf, all.data(), all.size() * 4, hipMemcpyHostToDevice));
+  m->has_norm = true;
+  return CHEM_OK;
+}
+
+}  // namespace
+
+extern "C" chem_status ann_create(const ann_arch *arch, uint64_t seed, ann_model **out) {
+  if (!arch || !out) {
+    set_error("ann_create: null argument");
+    return CHEM_EINVAL;
+  }
+  *out = nullptr;
+  if (arch->n_in < 1 || arch->n_out < 1 || arch->n_in > 96 || arch->n_out > 96) {
+    set_error("ann_create: n_in/n_out must be in 1..96 (got %d, %d)", arch->n_in, arch->n_out);
+    return CHEM_EINVAL;
+  }
+  for (int i = 0; i < 3; ++i)
+    if (arch->hidden[i] < 1 || arch->hidden[i] > 8192) {
+      set_error("ann_create: hidden sizes must be in 1..8192");
+      return CHEM_EINVAL;
+    }
+  if (arch->prec != 0) {
+    set_error("ann_create: only BF16 hidden layers (prec 0) are available in this build");
+    return CHEM_EUNSUPPORTED;
+  }
+  ann_model *m = new ann_model();
+  m->n_in = arch->n_in;
+  m->n_out = arch->n_out;
+  m->prec = arch->prec;
+  const int dims[5] = {arch->n_in, arch->hidden[0], arch->hidden[1], arch->hidden[2],
+                       arch->n_out};
+  for (int l = 0; l < 4; ++l) {
+    m->L[l].din = dims[l];
+    m->L[l].dout = dims[l + 1];
+    m->L[l].dinp = pad32(dims[l]);
+    m->L[l].doutp = pad32(dims[l + 1]);
+  }
+  size_t off = 0;
+  size_t oW[4], ob[4], oWb[4], omW[4], ovW[4], omb[4], ovb[4], ogW[4], ogb[4];
+  auto sect = [&](size_t bytes) {
+    size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  for (int l = 0; l < 4; ++l) {
+    const size_t e = layer_elems(m->L[l]), nb = m->L[l].doutp;
+    oW[l] = sect(e * 4);
+    ob[l] = sect(nb * 4);
+    oWb[l] = sect(e * 2);
+    omW[l] = sect(e * 4);
+    ovW[l] = sect(e * 4);
+    omb[l] = sect(nb * 4);
+    ovb[l] = sect(nb * 4);
+    ogW[l] = sect(e * 4);
+    ogb[l] = sect(nb * 4);
+  }
+  hipError_t e = hipGetDevice(&m->device);
+  if (e == hipSuccess) e = hipMalloc(&m->params, off);
+  if (e != hipSuccess) {
+    delete m;
+    set_error("ann_create: device allocation of %zu bytes failed", off);
+    return CHEM_ENOMEM;
+  }
+  e = hipMemset(m->params, 0, off);
+  if (e != hipSuccess) {
+    (void)hipFree(m->params);
+    delete m;
+    return hip_fail(e, "ann_create: hipMemset");
+  }
+  unsigned char *b = (unsigned char *)m->params;
+  for (int l = 0; l < 4; ++l) {
+    m->Wm[l] = (float *)(b + oW[l]);
+    m->bm[l] = (float *)(b + ob[l]);
+    m->Wb[l] = (u16 *)(b + oWb[l]);
+    m->mW[l] = (float *)(b + omW[l]);
+    m->vW[l] = (float *)(b + ovW[l]);
+    m->mb[l] = (float *)(b + omb[l]);
+    m->vb[l] = (float *)(b + ovb[l]);
+    m->gW[l] = (float *)(b + ogW[l]);
+    m->gb[l] = (float *)(b + ogb[l]);
+  }
+  // W, b ~ U(-1/sqrt(fan_in), +1/sqrt(fan_in))
+  SplitMix rng{seed};
+  for (int l = 0; l < 4; ++l) {
+    const ann::Layer &L = m->L[l];
+    const double bound = 1.0 / sqrt((double)L.din);
+    std::vector<float> W((size_t)L.dout * L.din), bb(L.dout);
+    for (auto &w : W) w = (float)((2.0 * rng.uniform() - 1.0) * bound);
+    for (auto &w : bb) w = (float)((2.0 * rng.uniform() - 1.0) * bound);
+    chem_status st = upload_layer(m, l, W.data(), bb.data());
+    if (st != CHEM_OK) {
+      ann_destroy(m);
+      return st;
+    }
+  }
+  *out = m;
+  return CHEM_OK;
+}
+
+extern "C" void ann_destroy(ann_model *m) {
+  if (!m) return;
+  (void)hipFree(m->params);
+  if (m->norm_buf) (void)hipFree(m->norm_buf);
+  if (m->wi.base) (void)hipFree(m->wi.base);
+  if (m->wt.base) (void)hipFree(m->wt.base);
+  if (m->fb_index) (void)hipFree(m->fb_index);
+  delete m;
+}
+
+extern "C" chem_status ann_set_layer(ann_model *m, int32_t layer, const float *W,
+                                     const float *b) {
+  chem_status st = check_model("ann_set_layer", m);
+  if (st != CHEM_OK) return st;
+  if (layer < 0 || layer >= ann::NLAYER || !W || !b) {
+    set_error("ann_set_layer: bad layer index or null array");
+    return CHEM_EINVAL;
+  }
+  return upload_layer(m, layer, W, b);
+}
+
+extern "C" chem_status ann_get_layer(const ann_model *m, int32_t layer, float *W, float *b) {
+  chem_status st = check_model("ann_get_layer", m);
+  if (st != CHEM_OK) return st;
+  if (layer < 0 || layer >= ann::NLAYER) {
+    set_error("ann_get_layer: bad layer index");
+    return CHEM_EINVAL;
+  }
+  return download_pair(m, layer, m->Wm[layer], m->bm[layer], W, b);
+}
+
+extern "C" chem_status ann_get_grad(const ann_model *m, int32_t layer, float *dW, float *db) {
+  chem_status st = check_model("ann_get_grad", m);
+  if (st != CHEM_OK) return st;
+  if (layer < 0 || layer >= ann::NLAYER) {
+    set_error("ann_get_grad: bad layer index");
+    return CHEM_EINVAL;
+  }
+  return download_pair(m, layer, m->gW[layer], m->gb[layer], dW, db);
+}
+
+extern "C" chem_status ann_set_norm(ann_model *m, const ann_norm *nm) {
+  chem_status st = check_model("ann_set_norm", m);
+  if (st != CHEM_OK) return st;
+  if (!nm || !nm->mu_in || !nm->sd_in || !nm->lo || !nm->hi || !nm->mu_out || !nm->sd_out ||
+      !(nm->lambda > 0.0f) || !(nm->dt_model > 0.0)) {
+    set_error("ann_set_norm: null array, lambda <= 0 or dt_model <= 0");
+    return CHEM_EINVAL;
+  }
+  for (int j = 0; j < m->n_in; ++j)
+    if (!(nm->sd_in[j] > 0.0f)) {
+      set_error("ann_set_norm: sd_in[%d] must be positive", j);
+      return CHEM_EINVAL;
+    }
+  for (int j = 0; j < m->n_out; ++j)
+    if (!(nm->sd_out[j] > 0.0f)) {
+      set_error("ann_set_norm: sd_out[%d] must be positive", j);
+      return CHEM_EINVAL;
+    }
+  m->nm.lambda = nm->lambda;
+  m->nm.dt_model = nm->dt_model;
+  m->h_mu_in.assign(nm->mu_in, nm->mu_in + m->n_in);
+  m->h_sd_in.assign(nm->sd_in, nm->sd_in + m->n_in);
+  m->h_lo.assign(nm->lo, nm->lo + m->n_in);
+  m->h_hi.assign(nm->hi, nm->hi + m->n_in);
+  m->h_mu_out.assign(nm->mu_out, nm->mu_out + m->n_out);
+  m->h_sd_out.assign(nm->sd_out, nm->sd_out + m->n_out);
+  return upload_norm(m);
+}
+
+extern "C" chem_status ann_get_norm(const ann_model *m, float *mu_in, float *sd_in, float *lo,
+                                    float *hi, float *mu_out, float *sd_out, float *lambda,
+                                    double *dt_model) {
+  chem_status st = check_model("ann_get_norm", m);
+  if (st != CHEM_OK) return st;
+  if (!m->has_norm) {
+    set_error("ann_get_norm: no statistics set");
+    return CHEM_EMODEL;
+  }
+  auto cp = [](const std::vector<float> &v, float *o) {
+    if (o) memcpy(o, v.data(), v.size() * 4);
+  };
+  cp(m->h_mu_in, mu_in);
+  cp(m->h_sd_in, sd_in);
+  cp(m->h_lo, lo);
+  cp(m->h_hi, hi);
+  cp(m->h_mu_out, mu_out);
+  cp(m->h_sd_out, sd_out);
+  if (lambda) *lambda = m->nm.lambda;
+  if (dt_model) *dt_model = m->nm.dt_model;
+  return CHEM_OK;
+}
+
+extern "C" chem_status ann_fit_norm(ann_model *m, chem_batch batch, const double *T,
+                                    const double *p, const double *Y0, const double *Y1,
+                                    float lambda, double dt_model, void *stream) {
+  chem_status st = check_model("ann_fit_norm", m);
+  if (st != CHEM_OK) return st;
+  const int K = m->n_out;
+  if (m->n_in != K + 2 || batch.n < 1 || batch.ld < batch.n || !T || !p || !Y0 || !Y1 ||
+      !(lambda > 0.0f) || !(dt_model > 0.0)) {
+    set_error("ann_fit_norm: needs n_in = n_out + 2, n >= 1, non-null arrays, lambda > 0");
+    return CHEM_EINVAL;
+  }
+  const int F = 2 * K + 2;
+  const int nblocks = 256;
+  double *part = nullptr;
+  CHEM_HIP(hipMalloc(&part, (size_t)nblocks * F * 4 * sizeof(double)));
+  ann::StatArgs a{batch.n, batch.ld, T, p, Y0, Y1, K, lambda, part, nblocks};
+  hipStream_t s = (hipStream_t)stream;
+  st = ann::stats_partial(a, s);
+  std::vector<double> h((size_t)nblocks * F * 4);
+  if (st == CHEM_OK) {
+    hipError_t e = hipMemcpyAsync(h.data(), part, h.size() * 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) st = hip_fail(e, "ann_fit_norm: read back");
+  }
+  (void)hipFree(part);
+  if (st != CHEM_OK) return st;
+  std::vector<float> mu(F), sd(F), lo(F), hi(F);
+  for (int f = 0; f < F; ++f) {
+    double s1 = 0, s2 = 0, mn = INFINITY, mx = -INFINITY;
+    for (int b = 0; b < nblocks; ++b) {
+      const double *o = &h[((size_t)b * F + f) * 4];
+      s1 += o[0];
+      s2 += o[1];
+      mn = fmin(mn, o[2]);
+      mx = fmax(mx, o[3]);
+    }
+    const double mean = s1 / batch.n;
+    const double var = fmax(s2 / batch.n - mean * mean, 0.0);
+    double sdv = sqrt(var);
+    if (sdv < 1e-12 * fabs(mean) + 1e-30) sdv = 1.0;
+    mu[f] = (float)mean;
+    sd[f] = (float)sdv;
+    lo[f] = (float)mn;
+    hi[f] = (float)mx;
+  }
+  m->nm.lambda = lambda;
+  m->nm.dt_model = dt_model;
+  m->h_mu_in.assign(mu.begin(), mu.begin() + K + 2);
+  m->h_sd_in.assign(sd.begin(), sd.begin() + K + 2);
+  m->h_lo.assign(lo.begin(), lo.begin() + K + 2);
+  m->h_hi.assign(hi.begin(), hi.begin() + K + 2);
+  m->h_mu_out.assign(mu.begin() + K + 2, mu.end());
+  m->h_sd_out.assign(sd.begin() + K + 2, sd.end());
+  return upload_norm(m);
+}
+
+namespace {
+
+// Network forward for n cells (n <= workspace capacity): features -> X ->
+// L1..L3 (bias + GELU, BF16) -> L4 (bias, FP32) -> U [n][n_out].
+chem_status forward_chunk(ann_model *m, int64_t n, int64_t ld, const double *T, const double *p,
+                          const double *Y, float *U, hipStream_t s) {
+  ann::FeatArgs fa{n, ld, T, p, Y, nullptr, m->n_out, m->L[0].dinp, m->nm.mu_in, m->nm.sd_in,
+                   m->nm.lambda, m->X};
+  chem_status st = ann::features(fa, s);
+  if (st != CHEM_OK) return st;
+  const u16 *in = m->X;
+  for (int l = 0; l < 4; ++l) {
+    const ann::Layer &L = m->L[l];
+    ann::GemmArgs g{};
+    g.M = (int)n;
+    g.K = L.dinp;
+    g.A = in;
+    g.lda = L.dinp;
+    g.B = m->Wb[l];
+    g.ldb = L.dinp;
+    g.bias = m->bm[l];
+    if (l < 3) {
+      g.N = L.doutp;
+      g.Cb = m->H[l];
+      g.ldcb = L.doutp;
+      static const char *lab[3] = {"mlp_l1", "mlp_l2", "mlp_l3"};
+      st = ann::gemm(g, true, true, ann::EPI_GELU, s, lab[l]);
+      in = m->H[l];
+    } else {
+      g.N = m->n_out;
+      g.Cf = U;
+      g.ldcf = m->n_out;
+      st = ann::gemm(g, true, true, ann::EPI_F32, s, "mlp_l4");
+    }
+    if (st != CHEM_OK) return st;
+  }
+  return CHEM_OK;
+}
+
+}  // namespace
+
+extern "C" chem_status ann_forward(ann_model *m, chem_batch batch, const double *T,
+                                   const double *p, const double *Y, float *U, void *stream) {
+  chem_status st = check_model("ann_forward", m);
+  if (st != CHEM_OK) return st;
+  if (!m->has_norm) {
+    set_error("ann_forward: normalisation statistics are not set");
+    return CHEM_EMODEL;
+  }
+  if (batch.n < 0 || batch.ld < batch.n || (batch.n > 0 && (!T || !p || !Y || !U))) {
+    set_error("ann_forward: bad batch or null array");
+    return CHEM_EINVAL;
+  }
+  if (m->n_in != m->n_out + 2) {
+    set_error("ann_forward: the network must have n_in = n_out + 2");
+    return CHEM_EMODEL;
+  }
+  if (batch.n == 0) return CHEM_OK;
+  st = grow_infer(m, batch.n);
+  if (st != CHEM_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  for (int64_t c0 = 0; c0 < batch.n; c0 += m->wi.cap) {
+    const int64_t nc = (batch.n - c0 < m->wi.cap) ? batch.n - c0 : m->wi.cap;
+    st = forward_chunk(m, nc, batch.ld, T + c0, p + c0, Y + c0, U + c0 * m->n_out, s);
+    if (st != CHEM_OK) return st;
+  }
+  return CHEM_OK;
+}
+
+namespace {
+__global__ void k_zero_counter(unsigned long long *c) {
+  if (threadIdx.x == 0) *c = 0ull;
+}
+__global__ void k_add_counter(const unsigned long long *c, int64_t *total, int first) {
+  if (threadIdx.x == 0) *total = (first ? 0 : *total) + (int64_t)*c;
+}
+}  // namespace
+
+extern "C" chem_status ann_step(ann_model *m, const chem_mech *mech, chem_batch batch, double dt,
+                                double *T, const double *p, double *Y, double *RR,
+                                uint8_t *flags, int64_t *n_fallback, const ann_step_opts *opts,
+                                const chem_step_opts *fb_opts, void *stream) {
+  chem_status st = check_model("ann_step", m);
+  if (st != CHEM_OK) return st;
+  if (!mech) {
+    set_error("ann_step: null mechanism");
+    return CHEM_EINVAL;
+  }
+  if (!m->has_norm) {
+    set_error("ann_step: normalisation statistics are not set");
+    return CHEM_EMODEL;
+  }
+  if (m->n_out != mech->K || m->n_in != mech->K + 2) {
+    set_error("ann_step: network has %d inputs / %d outputs, mechanism has K=%d", m->n_in,
+              m->n_out, mech->K);
+    return CHEM_EMODEL;
+  }
+  if (batch.n < 0 || batch.ld < batch.n || batch.n > INT32_MAX || !(dt > 0.0) || !isfinite(dt)) {
+    set_error("ann_step: bad batch or dt");
+    return CHEM_EINVAL;
+  }
+  if (batch.n == 0) return CHEM_OK;
+  if (!T || !p || !Y) {
+    set_error("ann_step: T, p and Y must be non-null");
+    return CHEM_EINVAL;
+  }
+  ann_step_opts o{1e-6f, 0.05f, 1, 0.0f};
+  if (opts) o = *opts;
+  if (!(o.residual_tol >= 0.0f) || !(o.ood_margin >= 0.0f)) {
+    set_error("ann_step: residual_tol and ood_margin must be >= 0");
+    return CHEM_EINVAL;
+  }
+  const StepOpts fo = resolve_opts(fb_opts);
+  st = grow_infer(m, batch.n);
+  if (st != CHEM_OK) return st;
+  if (o.fallback && m->fb_cap < batch.n) {
+    if (m->fb_index) (void)hipFree(m->fb_index);
+    m->fb_index = nullptr;
+    m->fb_cap = 0;
+    if (hipMalloc((void **)&m->fb_index, (size_t)batch.n * 4) != hipSuccess) {
+      set_error("ann_step: cannot allocate the fallback list");
+      return CHEM_ENOMEM;
+    }
+    m->fb_cap = batch.n;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, s, m->fb_count);
+  // a step other than the one the network was trained for: every cell falls back
+  const bool dt_mismatch = fabs(dt - m->nm.dt_model) > 1e-6 * m->nm.dt_model;
+  for (int64_t c0 = 0; c0 < batch.n; c0 += m->wi.cap) {
+    const int64_t nc = (batch.n - c0 < m->wi.cap) ? batch.n - c0 : m->wi.cap;
+    st = forward_chunk(m, nc, batch.ld, T + c0, p + c0, Y + c0, m->U, s);
+    if (st != CHEM_OK) return st;
+    ann::PostArgs pa{};
+    pa.n = nc;
+    pa.ld = batch.ld;
+    pa.dt = dt;
+    pa.T = T + c0;
+    pa.p = p + c0;
+    pa.Y = Y + c0;
+    pa.RR = RR ? RR + c0 : nullptr;
+    pa.flags = flags ? flags + c0 : nullptr;
+    pa.U = m->U;
+    pa.doutp = m->n_out;
+    pa.nm = m->nm;
+    pa.n_in = m->n_in;
+    pa.residual_tol = o.residual_tol;
+    pa.ood_margin = o.ood_margin;
+    pa.check_ood = 1;
+    pa.force_flag = dt_mismatch ? 1 : 0;
+    pa.fb_index = o.fallback ? m->fb_index : nullptr;
+    pa.fb_count = m->fb_count;
+    pa.index_base = c0;
+    st = ann::post(mech->d, pa, s);
+    if (st != CHEM_OK) return st;
+  }
+  if (o.fallback) {
+    st = launch_step(mech, batch.n, batch.ld, dt, nullptr, T, p, Y, RR, nullptr, nullptr, fo,
+                     m->fb_index, s, m->fb_count, flags);
+    if (st != CHEM_OK) return st;
+  }
+  if (n_fallback) hipLaunchKernelGGL(k_add_counter, dim3(1), dim3(64), 0, s, m->fb_count,
+                                     n_fallback, 1);
+  CHEM_HIP(hipGetLastError());
+  return CHEM_OK;
+}
+
+extern "C" chem_status ann_train_step(ann_model *m, chem_batch batch, const double *T,
+                                      const double *p, const double *Y0, const double *Y1,
+                                      const int64_t *index, const ann_train_opts *opts,
+                                      float *loss, void *stream) {
+  chem_status st = check_model("ann_train_step", m);
+  if (st != CHEM_OK) return st;
+  if (!m->has_norm) {
+    set_error("ann_train_step: normalisation statistics are not set");
+    return CHEM_EMODEL;
+  }
+  const int64_t B = batch.n;
+  if (B < 32 || B % 32 != 0 || B > (1 << 24) || (!index && batch.ld < B) || !T || !p || !Y0 ||
+      !Y1 || !loss || !opts) {
+    set_error("ann_train_step: batch must be a positive multiple of 32 (<= 2^24), arrays, "
+              "options and loss non-null");
+    return CHEM_EINVAL;
+  }
+  if (m->n_in != m->n_out + 2) {
+    set_error("ann_train_step: the network must have n_in = n_out + 2");
+    return CHEM_EMODEL;
+  }
+  st = grow_train(m, B);
+  if (st != CHEM_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const int K = m->n_out;
+  ann::FeatArgs fa{B, batch.ld, T, p, Y0, index, K, m->L[0].dinp, m->nm.mu_in, m->nm.sd_in,
+                   m->nm.lambda, m->tX};
+  if ((st = ann::features(fa, s)) != CHEM_OK) return st;
+  ann::TargetArgs ta{B, batch.ld, Y0, Y1, index, K, m->L[3].doutp, m->nm.mu_out, m->nm.sd_out,
+                     m->nm.lambda, m->tUt};
+  if ((st = ann::targets(ta, s)) != CHEM_OK) return st;
+  // forward, keeping pre-activations (FP32) and activations (BF16)
+  const u16 *in = m->tX;
+  for (int l = 0; l < 4; ++l) {
+    const ann::Layer &L = m->L[l];
+    ann::GemmArgs g{};
+    g.M = (int)B;
+    g.N = L.doutp;
+    g.K = L.dinp;
+    g.A = in;
+    g.lda = L.dinp;
+    g.B = m->Wb[l];
+    g.ldb = L.dinp;
+    g.bias = m->bm[l];
+    if (l < 3) {
+      g.Cb = m->tH[l];
+      g.ldcb = L.doutp;
+      g.Z = m->tZ[l];
+      g.ldz = L.doutp;
+      st = ann::gemm(g, true, true, ann::EPI_GELU, s, "train_fwd");
+      in = m->tH[l];
+    } else {
+      g.Cf = m->tU;
+      g.ldcf = L.doutp;
+      st = ann::gemm(g, true, true, ann::EPI_F32, s, "train_fwd");
+    }
+    if (st != CHEM_OK) return st;
+  }
+  st = ann::l1_grad(B, K, m->L[3].doutp, m->tU, m->tUt, m->tGb[3], m->tGf[3], m->loss_part,
+                    LOSS_PARTS, loss, s);
+  if (st != CHEM_OK) return st;
+  // backward: wgrad, bias grad, dgrad (through GELU') per layer
+  for (int l = 3; l >= 0; --l) {
+    const ann::Layer &L = m->L[l];
+    ann::GemmArgs w{};
+    w.M = L.doutp;
+    w.N = L.dinp;
+    w.K = (int)B;
+    w.A = m->tGb[l];
+    w.lda = L.doutp;
+    w.B = l > 0 ? m->tH[l - 1] : m->tX;
+    w.ldb = L.dinp;
+    w.Cf = m->gW[l];
+    w.ldcf = L.dinp;
+    if ((st = ann::gemm(w, false, false, ann::EPI_F32, s, "train_wgrad")) != CHEM_OK) return st;
+    if ((st = ann::colsum(B, L.doutp, m->tGf[l], L.doutp, m->gb[l], s)) != CHEM_OK) return st;
+    if (l > 0) {
+      const ann::Layer &P = m->L[l - 1];
+      ann::GemmArgs d{};
+      d.M = (int)B;
+      d.N = L.dinp;
+      d.K = L.doutp;
+      d.A = m->tGb[l];
+      d.lda = L.doutp;
+      d.B = m->Wb[l];
+      d.ldb = L.dinp;
+      d.Z = m->tZ[l - 1];
+      d.ldz = P.doutp;
+      d.Cb = m->tGb[l - 1];
+      d.ldcb = P.doutp;
+      d.Cf = m->tGf[l - 1];
+      d.ldcf = P.doutp;
+      if ((st = ann::gemm(d, true, false, ann::EPI_GELUGRAD, s, "train_dgrad")) != CHEM_OK)
+        return st;
+    }
+  }
+  if (opts->lr > 0.0f) {
+    m->step += 1;
+    const double bc1 = 1.0 - pow((double)opts->beta1, (double)m->step);
+    const double bc2 = 1.0 - pow((double)opts->beta2, (double)m->step);
+    for (int l = 0; l < 4; ++l) {
+      const ann::Layer &L = m->L[l];
+      st = ann::adam((int64_t)layer_elems(L), m->Wm[l], m->gW[l], m->mW[l], m->vW[l], m->Wb[l],
+                     opts->lr, opts->beta1, opts->beta2, opts->eps, (float)bc1, (float)bc2, s);
+      if (st != CHEM_OK) return st;
+      st = ann::adam(L.doutp, m->bm[l], m->gb[l], m->mb[l], m->vb[l], nullptr, opts->lr,
+                     opts->beta1, opts->beta2, opts->eps, (float)bc1, (float)bc2, s);
+      if (st != CHEM_OK) return st;
+    }
+  }
+  return CHEM_OK;
+}
+
+extern "C" int64_t ann_num_steps(const ann_model *m) { return m ? m->step : -1; }
+
+namespace {
+const char MAGIC[8] = {'C', 'H', 'E', 'M', 'A', 'N', 'N', '1'};
+
+bool wr(FILE *f, const void *p, size_t n) { return fwrite(p, 1, n, f) == n; }
+bool rd(FILE *f, void *p, size_t n) { return fread(p, 1, n, f) == n; }
+}  // namespace
+
+extern "C" chem_status ann_save(const ann_model *m, const char *path) {
+  chem_status st = check_model("ann_save", m);
+  if (st != CHEM_OK) return st;
+  if (!path) {
+    set_error("ann_save: null path");
+    return CHEM_EINVAL;
+  }
+  FILE *f = fopen(path, "wb");
+  if (!f) {
+    set_error("ann_save: cannot open %s", path);
+    return CHEM_EINVAL;
+  }
+  bool ok = wr(f, MAGIC, 8);
+  int32_t hdr[7] = {m->n_in, m->n_out, m->L[0].dout, m->L[1].dout, m->L[2].dout, m->prec,
+                    m->has_norm ? 1 : 0};
+  ok = ok && wr(f, hdr, sizeof(hdr)) && wr(f, &m->step, 8) && wr(f, &m->nm.lambda, 4) &&
+       wr(f, &m->nm.dt_model, 8);
+  if (m->has_norm)
+    for (auto *v : {&m->h_mu_in, &m->h_sd_in, &m->h_lo, &m->h_hi, &m->h_mu_out, &m->h_sd_out})
+      ok = ok && wr(f, v->data(), v->size() * 4);
+  for (int l = 0; l < 4 && ok; ++l) {
+    const ann::Layer &L = m->L[l];
+    std::vector<float> W((size_t)L.dout * L.din), b(L.dout);
+    const float *srcW[3] = {m->Wm[l], m->mW[l], m->vW[l]};
+    const float *srcb[3] = {m->bm[l], m->mb[l], m->vb[l]};
+    for (int q = 0; q < 3 && ok; ++q) {
+      st = download_pair(m, l, srcW[q], srcb[q], W.data(), b.data());
+      if (st != CHEM_OK) {
+        fclose(f);
+        return st;
+      }
+      ok = wr(f, W.data(), W.size() * 4) && wr(f, b.data(), b.size() * 4);
+    }
+  }
+  ok = (fclose(f) == 0) && ok;
+  if (!ok) {
+    set_error("ann_save: write to %s failed", path);
+    return CHEM_EINVAL;
+  }
+  return CHEM_OK;
+}
+
+extern "C" chem_status ann_load(const char *path, ann_model **out) {
+  if (!path || !out) {
+    set_error("ann_load: null argument");
+    return CHEM_EINVAL;
+  }
+  *out = nullptr;
+  FILE *f = fopen(path, "rb");
+  if (!f) {
+    set_error("ann_load: cannot open %s", path);
+    return CHEM_EINVAL;
+  }
+  char mg[8];
+  int32_t hdr[7];
+  int64_t step = 0;
+  float lambda = 0;
+  double dtm = 0;
+  bool ok = rd(f, mg, 8) && memcmp(mg, MAGIC, 8) == 0 && rd(f, hdr, sizeof(hdr)) &&
+            rd(f, &step, 8) && rd(f, &lambda, 4) && rd(f, &dtm, 8);
+  if (!ok) {
+    fclose(f);
+    set_error("ann_load: %s is not a model file", path);
+    return CHEM_EMODEL;
+  }
+  ann_arch arch{hdr[0], hdr[1], {hdr[2], hdr[3], hdr[4]}, hdr[5]};
+  ann_model *m = nullptr;
+  chem_status st = ann_create(&arch, 0, &m);
+  if (st != CHEM_OK) {
+    fclose(f);
+    return st;
+  }
+  if (hdr[6]) {
+    std::vector<float> v[6];
+    const int sz[6] = {m->n_in, m->n_in, m->n_in, m->n_in, m->n_out, m->n_out};
+    for (int q = 0; q < 6 && ok; ++q) {
+      v[q].resize(sz[q]);
+      ok = rd(f, v[q].data(), sz[q] * 4);
+    }
+    if (ok) {
+      ann_norm nn{lambda, dtm, v[0].data(), v[1].data(), v[2].data(), v[3].data(), v[4].data(),
+                  v[5].data()};
+      st = ann_set_norm(m, &nn);
+      ok = st == CHEM_OK;
+    }
+  }
+  for (int l = 0; l < 4 && ok; ++l) {
+    const ann::Layer &L = m->L[l];
+    std::vector<float> W((size_t)L.dout * L.din), b(L.dout);
+    float *dstW[3] = {m->Wm[l], m->mW[l], m->vW[l]};
+    float *dstb[3] = {m->bm[l], m->mb[l], m->vb[l]};
+    for (int q = 0; q < 3 && ok; ++q) {
+      ok = rd(f, W.data(), W.size() * 4) && rd(f, b.data(), b.size() * 4);
+      if (!ok) break;
+      std::vector<float> Wp((size_t)L.doutp * L.dinp, 0.0f), bp(L.doutp, 0.0f);
+      for (int o = 0; o < L.dout; ++o) {
+        for (int i = 0; i < L.din; ++i) Wp[(size_t)o * L.dinp + i] = W[(size_t)o * L.din + i];
+        bp[o] = b[o];
+      }
+      ok = hipMemcpy(dstW[q], Wp.data(), Wp.size() * 4, hipMemcpyHostToDevice) == hipSuccess &&
+           hipMemcpy(dstb[q], bp.data(), bp.size() * 4, hipMemcpyHostToDevice) == hipSuccess;
+    }
+    if (ok) ok = ann::to_bf16((int64_t)layer_elems(L), m->Wm[l], m->Wb[l], nullptr) == CHEM_OK;
+  }
+  fclose(f);
+  if (!ok || hipDeviceSynchronize() != hipSuccess) {
+    ann_destroy(m);
+    set_error("ann_load: %s is truncated or inconsistent", path);
+    return CHEM_EMODEL;
+  }
+  m->step = step;
+  *out = m;
+  return CHEM_OK;
+}

@@ -1,0 +1,111 @@
+// Internal declarations of the surrogate (ANN) path.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "chem_internal.h"
+
+namespace ann {
+
+typedef unsigned short u16;  // bfloat16 storage
+
+constexpr int NLAYER = 4;
+
+// Dense layer l maps din[l] -> dout[l]; stored dims are padded to a multiple
+// of 32 with zero weights and biases (padded units are exactly zero).
+struct Layer {
+  int din, dout;    // logical
+  int dinp, doutp;  // padded
+};
+
+struct Norm {
+  float lambda;
+  double dt_model;
+  float *mu_in, *sd_in, *lo, *hi;  // device [n_in]
+  float *mu_out, *sd_out;          // device [n_out]
+};
+
+enum { EPI_F32 = 0, EPI_GELU = 1, EPI_GELUGRAD = 2 };
+
+struct GemmArgs {
+  int M, N, K;
+  const u16 *A;
+  long lda;
+  const u16 *B;
+  long ldb;
+  const float *bias;
+  u16 *Cb;
+  long ldcb;
+  float *Cf;
+  long ldcf;
+  float *Z;
+  long ldz;
+};
+
+// C = epi(A * op(B)); AK: A is [M][K] row-major (else [K][M]); BK: B is [N][K]
+// row-major (else [K][N]).
+chem_status gemm(const GemmArgs &g, bool AK, bool BK, int epi, hipStream_t s,
+                 const char *label);
+
+struct FeatArgs {
+  int64_t n, ld;
+  const double *T, *p, *Y;
+  const int64_t *index;  // optional gather list
+  int K, dinp;
+  const float *mu, *sd;
+  float lambda;
+  u16 *X;  // [n][dinp] bf16
+};
+chem_status features(const FeatArgs &a, hipStream_t s);
+
+struct TargetArgs {
+  int64_t n, ld;
+  const double *Y0, *Y1;
+  const int64_t *index;
+  int K, doutp;
+  const float *mu, *sd;
+  float lambda;
+  float *U;  // [n][doutp] fp32
+};
+chem_status targets(const TargetArgs &a, hipStream_t s);
+
+chem_status l1_grad(int64_t n, int K, int doutp, const float *U, const float *Ut, u16 *Gb,
+                    float *Gf, double *loss_part, int nparts, float *loss, hipStream_t s);
+chem_status colsum(int64_t M, int N, const float *X, long ldx, float *out, hipStream_t s);
+chem_status adam(int64_t n, float *W, const float *g, float *m, float *v, u16 *Wb, float lr,
+                 float b1, float b2, float eps, float bc1, float bc2, hipStream_t s);
+chem_status to_bf16(int64_t n, const float *src, u16 *dst, hipStream_t s);
+
+struct PostArgs {
+  int64_t n, ld;
+  double dt;
+  double *T;
+  const double *p;
+  double *Y;
+  double *RR;
+  uint8_t *flags;
+  const float *U;  // [n][doutp] z-space outputs
+  int doutp;
+  Norm nm;
+  int n_in;
+  float residual_tol, ood_margin;
+  int check_ood;
+  int force_flag;                 // flag bits set on every cell
+  int32_t *fb_index;              // fallback list (cell indices index_base + i)
+  unsigned long long *fb_count;   // device counter
+  int64_t index_base;
+};
+chem_status post(const chem::DevMech &M, const PostArgs &a, hipStream_t s);
+
+struct StatArgs {
+  int64_t n, ld;
+  const double *T, *p, *Y0, *Y1;
+  int K;
+  float lambda;
+  double *part;  // [nblocks][F][4] sums, sums of squares, min, max
+  int nblocks;
+};
+chem_status stats_partial(const StatArgs &a, hipStream_t s);
+
+}  // namespace ann

@@ -1,0 +1,594 @@
+// Surrogate-form kernels for gfx950: BF16 MFMA GEMM with fused epilogues
+// (bias + GELU, GELU-derivative, FP32 out), the Box-Cox/z-score prologue, the
+// L1-loss gradient, deterministic column sums, Adam, and the per-cell
+// post-processing of the network output (de-normalisation, element-conserving
+// projection, clipping, residual and out-of-distribution flags, enthalpy
+// Newton for T, reaction rates).
+#include <math.h>
+
+#include "ann_internal.h"
+
+namespace ann {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr double RG = 8.314462618;
+
+// FP32 -> BF16, round to nearest even (NaN stays NaN).
+__device__ __forceinline__ u16 f2bf(float f) {
+  unsigned u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (u16)((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (u16)(u >> 16);
+}
+
+__device__ __forceinline__ float gelu(float x) {
+  return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f));
+}
+
+__device__ __forceinline__ float gelu_grad(float x) {
+  return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) +
+         x * expf(-0.5f * x * x) * 0.39894228040143268f;
+}
+
+__device__ __forceinline__ float boxcox(float y, float lam) {
+  return (powf(fmaxf(y, 0.0f), lam) - 1.0f) / lam;
+}
+
+// ------------------------------------------------------------------ GEMM
+// Block = WM x WN waves; each wave owns TM x TN tiles of 32x32 computed with
+// v_mfma_f32_32x32x16_bf16.  Operand tiles are staged through LDS in a
+// K-contiguous layout (double buffered); operands stored MN-contiguous in
+// global memory are transposed while being written to LDS.
+template <int WM, int WN, int TM, int TN, bool AK, bool BKC, int EPI>
+__global__ __launch_bounds__(WM *WN * 64) void k_gemm(GemmArgs g) {
+  constexpr int BM = WM * TM * 32, BN = WN * TN * 32, BK = 32, LK = BK + 8;
+  constexpr int NT = WM * WN * 64;
+  __shared__ __attribute__((aligned(16))) u16 As[2][BM * LK];
+  __shared__ __attribute__((aligned(16))) u16 Bs[2][BN * LK];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave % WM, wn = wave / WM;
+  const long m0 = (long)blockIdx.x * BM, n0 = (long)blockIdx.y * BN;
+  constexpr int ACH = BM * BK / 8, BCH = BN * BK / 8;
+  constexpr int APT = (ACH + NT - 1) / NT, BPT = (BCH + NT - 1) / NT;
+  uint4 ra[APT], rb[BPT];
+  f32x16 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < APT; ++i) {
+      const int c = tid + i * NT;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (c < ACH) {
+        if (AK) {
+          const int r = c / (BK / 8), kc = (c % (BK / 8)) * 8;
+          if (m0 + r < g.M) v = *(const uint4 *)(g.A + (m0 + r) * g.lda + k0 + kc);
+        } else {
+          const int kr = c / (BM / 8), mc = (c % (BM / 8)) * 8;
+          if (m0 + mc < g.M) v = *(const uint4 *)(g.A + (long)(k0 + kr) * g.lda + m0 + mc);
+        }
+      }
+      ra[i] = v;
+    }
+#pragma unroll
+    for (int i = 0; i < BPT; ++i) {
+      const int c = tid + i * NT;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (c < BCH) {
+        if (BKC) {
+          const int r = c / (BK / 8), kc = (c % (BK / 8)) * 8;
+          if (n0 + r < g.N) v = *(const uint4 *)(g.B + (n0 + r) * g.ldb + k0 + kc);
+        } else {
+          const int kr = c / (BN / 8), nc = (c % (BN / 8)) * 8;
+          if (n0 + nc < g.N) v = *(const uint4 *)(g.B + (long)(k0 + kr) * g.ldb + n0 + nc);
+        }
+      }
+      rb[i] = v;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < APT; ++i) {
+      const int c = tid + i * NT;
+      if (c < ACH) {
+        if (AK) {
+          const int r = c / (BK / 8), kc = (c % (BK / 8)) * 8;
+          *(uint4 *)&As[buf][r * LK + kc] = ra[i];
+        } else {
+          const int kr = c / (BM / 8), mc = (c % (BM / 8)) * 8;
+          const u16 *e = (const u16 *)&ra[i];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) As[buf][(mc + j) * LK + kr] = e[j];
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < BPT; ++i) {
+      const int c = tid + i * NT;
+      if (c < BCH) {
+        if (BKC) {
+          const int r = c / (BK / 8), kc = (c % (BK / 8)) * 8;
+          *(uint4 *)&Bs[buf][r * LK + kc] = rb[i];
+        } else {
+          const int kr = c / (BN / 8), nc = (c % (BN / 8)) * 8;
+          const u16 *e = (const u16 *)&rb[i];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) Bs[buf][(nc + j) * LK + kr] = e[j];
+        }
+      }
+    }
+  };
+  auto compute = [&](int buf) {
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 16) {
+      bf16x8 a[TM], b[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+        a[i] = *(const bf16x8 *)&As[buf][(wm * TM * 32 + i * 32 + (lane & 31)) * LK + kk +
+                                         8 * (lane >> 5)];
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+        b[j] = *(const bf16x8 *)&Bs[buf][(wn * TN * 32 + j * 32 + (lane & 31)) * LK + kk +
+                                         8 * (lane >> 5)];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+  };
+
+  const int nk = g.K / BK;
+  load(0);
+  store(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < nk) load((kt + 1) * BK);
+    compute(cur);
+    if (kt + 1 < nk) store(cur ^ 1);
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const long col = n0 + wn * TN * 32 + j * 32 + (lane & 31);
+      if (col >= g.N) continue;
+      const float bias = g.bias ? g.bias[col] : 0.0f;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const long row = m0 + wm * TM * 32 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        if (row >= g.M) continue;
+        const float v = acc[i][j][r];
+        if (EPI == EPI_F32) {
+          g.Cf[row * g.ldcf + col] = v + bias;
+        } else if (EPI == EPI_GELU) {
+          const float z = v + bias;
+          if (g.Z) g.Z[row * g.ldz + col] = z;
+          if (g.Cb) g.Cb[row * g.ldcb + col] = f2bf(gelu(z));
+          if (g.Cf) g.Cf[row * g.ldcf + col] = gelu(z);
+        } else {
+          const float d = v * gelu_grad(g.Z[row * g.ldz + col]);
+          if (g.Cb) g.Cb[row * g.ldcb + col] = f2bf(d);
+          if (g.Cf) g.Cf[row * g.ldcf + col] = d;
+        }
+      }
+    }
+}
+
+template <int WM, int WN, int TM, int TN>
+chem_status gemm_cfg(const GemmArgs &g, bool AK, bool BK, int epi, hipStream_t s) {
+  constexpr int BM = WM * TM * 32, BN = WN * TN * 32;
+  dim3 grid((unsigned)((g.M + BM - 1) / BM), (unsigned)((g.N + BN - 1) / BN));
+  dim3 block(WM * WN * 64);
+  if (AK && BK && epi == EPI_GELU)
+    hipLaunchKernelGGL((k_gemm<WM, WN, TM, TN, true, true, EPI_GELU>), grid, block, 0, s, g);
+  else if (AK && BK && epi == EPI_F32)
+    hipLaunchKernelGGL((k_gemm<WM, WN, TM, TN, true, true, EPI_F32>), grid, block, 0, s, g);
+  else if (AK && !BK && epi == EPI_GELUGRAD)
+    hipLaunchKernelGGL((k_gemm<WM, WN, TM, TN, true, false, EPI_GELUGRAD>), grid, block, 0, s,
+                       g);
+  else if (!AK && !BK && epi == EPI_F32)
+    hipLaunchKernelGGL((k_gemm<WM, WN, TM, TN, false, false, EPI_F32>), grid, block, 0, s, g);
+  else {
+    chem::set_error("gemm: unsupported layout/epilogue combination");
+    return CHEM_EUNSUPPORTED;
+  }
+  CHEM_HIP(hipGetLastError());
+  return CHEM_OK;
+}
+
+// ------------------------------------------------------------- prologue
+
+__global__ void k_features(FeatArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  const int64_t c = a.index ? a.index[i] : i;
+  u16 *out = a.X + i * a.dinp;
+  for (int j0 = 0; j0 < a.dinp; j0 += 8) {
+    u16 v[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int j = j0 + t;
+      float x = 0.0f;
+      bool real = true;
+      if (j == 0) x = (float)a.T[c];
+      else if (j == 1) x = (float)a.p[c];
+      else if (j < a.K + 2) x = boxcox((float)a.Y[(int64_t)(j - 2) * a.ld + c], a.lambda);
+      else real = false;
+      v[t] = real ? f2bf((x - a.mu[j]) / a.sd[j]) : (u16)0;
+    }
+    *(uint4 *)(out + j0) = *(const uint4 *)v;
+  }
+}
+
+__global__ void k_targets(TargetArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  const int64_t c = a.index ? a.index[i] : i;
+  float *out = a.U + i * a.doutp;
+  for (int k = 0; k < a.doutp; ++k) {
+    float v = 0.0f;
+    if (k < a.K) {
+      // the change of the mass fraction over the step (FP64 difference)
+      const double d = a.Y1[(int64_t)k * a.ld + c] - a.Y0[(int64_t)k * a.ld + c];
+      v = (float)((d - a.mu[k]) / a.sd[k]);
+    }
+    out[k] = v;
+  }
+}
+
+// ------------------------------------------------------------ training
+
+// g = sign(u - u*) / (n K) (sign(0) = 0) on the K real outputs, 0 on padding;
+// per-block partial sums of |u - u*| for the loss.
+__global__ void k_l1(int64_t n, int K, int doutp, const float *U, const float *Ut, u16 *Gb,
+                     float *Gf, double *part) {
+  __shared__ double red[256];
+  const double scale = 1.0 / ((double)n * K);
+  double s = 0.0;
+  const int64_t total = n * doutp;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int k = (int)(e % doutp);
+    float gv = 0.0f;
+    if (k < K) {
+      const float d = U[e] - Ut[e];
+      s += fabs((double)d);
+      gv = (float)(((d > 0.0f) - (d < 0.0f)) * scale);
+    }
+    Gb[e] = f2bf(gv);
+    Gf[e] = gv;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void k_loss_final(const double *part, int nparts, double scale, float *loss) {
+  if (threadIdx.x != 0) return;
+  double s = 0.0;
+  for (int i = 0; i < nparts; ++i) s += part[i];
+  *loss = (float)(s * scale);
+}
+
+// out[j] = sum over rows of X[:, j] (FP64 accumulation, fixed order).
+__global__ void k_colsum(int64_t M, int N, const float *X, long ldx, float *out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= N) return;
+  double s = 0.0;
+  for (int64_t m = 0; m < M; ++m) s += X[m * ldx + j];
+  out[j] = (float)s;
+}
+
+__global__ void k_adam(int64_t n, float *W, const float *g, float *m, float *v, u16 *Wb, float lr,
+                       float b1, float b2, float eps, float bc1, float bc2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * gi;
+  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  const float w = W[i] - lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+  W[i] = w;
+  if (Wb) Wb[i] = f2bf(w);
+}
+
+__global__ void k_to_bf16(int64_t n, const float *src, u16 *dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = f2bf(src[i]);
+}
+
+// ----------------------------------------------------------------- post
+
+// Mass fraction k of the network's new state (before projection):
+// Y' = Y0 + sd u + mu, de-normalised in FP32, added in FP64.
+__device__ __forceinline__ double ann_y(const PostArgs &a, int64_t i, int k, double y0) {
+  const float du = a.U[i * a.doutp + k] * a.nm.sd_out[k] + a.nm.mu_out[k];
+  return y0 + (double)du;
+}
+
+__device__ __forceinline__ void species_h_cp(const chem::DevMech &M, int k, double T, double &hRT,
+                                             double &cpR) {
+  const double *c = (T <= M.Tmid[k]) ? M.nasa_lo + 7 * k : M.nasa_hi + 7 * k;
+  const double T2 = T * T, T3 = T2 * T, T4 = T3 * T;
+  cpR = c[0] + c[1] * T + c[2] * T2 + c[3] * T3 + c[4] * T4;
+  hRT = c[0] + c[1] * T / 2.0 + c[2] * T2 / 3.0 + c[3] * T3 / 4.0 + c[4] * T4 / 5.0 + c[5] / T;
+}
+
+constexpr int EMAX = 8;
+
+__global__ void k_post(chem::DevMech M, PostArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  const int K = M.K, E = M.E;
+  const double T0 = a.T[i], p = a.p[i];
+  uint8_t flag = (uint8_t)a.force_flag;
+
+  // out of distribution: any input feature outside the widened training range
+  if (a.check_ood) {
+    for (int j = 0; j < a.n_in; ++j) {
+      float x;
+      if (j == 0) x = (float)T0;
+      else if (j == 1) x = (float)p;
+      else x = boxcox((float)a.Y[(int64_t)(j - 2) * a.ld + i], a.nm.lambda);
+      const float lo = a.nm.lo[j], hi = a.nm.hi[j], span = hi - lo;
+      const float tol = span > 0.0f ? a.ood_margin * span : 1e-6f * fmaxf(fabsf(hi), 1e-30f);
+      if (!(x >= lo - tol && x <= hi + tol)) flag |= 1;
+    }
+  }
+
+  // weighted least-squares projection onto M Y = M Y0, D = diag(Y' + 1e-10)
+  double A[EMAX][EMAX], r[EMAX], z0[EMAX];
+  for (int e = 0; e < E; ++e) {
+    r[e] = 0.0;
+    z0[e] = 0.0;
+    for (int f = 0; f < E; ++f) A[e][f] = 0.0;
+  }
+  double S0 = 0.0;
+  for (int k = 0; k < K; ++k) {
+    const double y0 = a.Y[(int64_t)k * a.ld + i];
+    const double yp = ann_y(a, i, k, y0);
+    const double d = fmax(yp, 0.0) + 1e-10;
+    S0 += y0 / M.W[k];
+    for (int e = 0; e < E; ++e) {
+      const double me = M.Mel[e * K + k];
+      r[e] += me * (y0 - yp);
+      z0[e] += me * y0;
+      for (int f = 0; f <= e; ++f) A[e][f] += me * d * M.Mel[f * K + k];
+    }
+  }
+  // Cholesky of the symmetric positive definite E x E matrix
+  double Lc[EMAX][EMAX], lam[EMAX];
+  bool ok = true;
+  for (int e = 0; e < E; ++e) {
+    for (int f = 0; f <= e; ++f) {
+      double s = A[e][f];
+      for (int q = 0; q < f; ++q) s -= Lc[e][q] * Lc[f][q];
+      if (e == f) {
+        if (!(s > 0.0)) ok = false;
+        Lc[e][e] = sqrt(fmax(s, 1e-300));
+      } else {
+        Lc[e][f] = s / Lc[f][f];
+      }
+    }
+  }
+  for (int e = 0; e < E; ++e) {
+    double s = r[e];
+    for (int q = 0; q < e; ++q) s -= Lc[e][q] * lam[q];
+    lam[e] = s / Lc[e][e];
+  }
+  for (int e = E - 1; e >= 0; --e) {
+    double s = lam[e];
+    for (int q = e + 1; q < E; ++q) s -= Lc[q][e] * lam[q];
+    lam[e] = s / Lc[e][e];
+  }
+  // projected, clipped state; its element residual
+  double z1[EMAX];
+  for (int e = 0; e < E; ++e) z1[e] = 0.0;
+  for (int k = 0; k < K; ++k) {
+    const double y0 = a.Y[(int64_t)k * a.ld + i];
+    const double yp = ann_y(a, i, k, y0);
+    double corr = 0.0;
+    for (int e = 0; e < E; ++e) corr += M.Mel[e * K + k] * lam[e];
+    const double y = fmax(yp + (fmax(yp, 0.0) + 1e-10) * corr, 0.0);
+    for (int e = 0; e < E; ++e) z1[e] += M.Mel[e * K + k] * y;
+  }
+  double res = 0.0;
+  for (int e = 0; e < E; ++e) res = fmax(res, fabs(z1[e] - z0[e]));
+  if (!ok || !(res <= (double)a.residual_tol)) flag |= 2;
+
+  if (flag == 0) {
+    // temperature from h(T, Y) = h(T0, Y0) by Newton in FP64
+    double h0 = 0.0;
+    for (int k = 0; k < K; ++k) {
+      double hRT, cpR;
+      species_h_cp(M, k, T0, hRT, cpR);
+      h0 += a.Y[(int64_t)k * a.ld + i] * RG * T0 * hRT / M.W[k];
+    }
+    double T = T0;
+    for (int it = 0; it < 20; ++it) {
+      double h = 0.0, cp = 0.0;
+      for (int k = 0; k < K; ++k) {
+        const double y0 = a.Y[(int64_t)k * a.ld + i];
+        const double yp = ann_y(a, i, k, y0);
+        double corr = 0.0;
+        for (int e = 0; e < E; ++e) corr += M.Mel[e * K + k] * lam[e];
+        const double y = fmax(yp + (fmax(yp, 0.0) + 1e-10) * corr, 0.0);
+        double hRT, cpR;
+        species_h_cp(M, k, T, hRT, cpR);
+        h += y * RG * T * hRT / M.W[k];
+        cp += y * RG * cpR / M.W[k];
+      }
+      const double dT = (h - h0) / cp;
+      T -= dT;
+      if (fabs(dT) < 1e-9 * T) break;
+    }
+    if (!isfinite(T) || !(T > 0.0)) flag |= 2;
+    if (flag == 0) {
+      const double rho0 = p / (RG * T0 * S0);
+      for (int k = 0; k < K; ++k) {
+        const double y0 = a.Y[(int64_t)k * a.ld + i];
+        const double yp = ann_y(a, i, k, y0);
+        double corr = 0.0;
+        for (int e = 0; e < E; ++e) corr += M.Mel[e * K + k] * lam[e];
+        const double y = fmax(yp + (fmax(yp, 0.0) + 1e-10) * corr, 0.0);
+        if (a.RR) a.RR[(int64_t)k * a.ld + i] = rho0 * (y - y0) / a.dt;
+        a.Y[(int64_t)k * a.ld + i] = y;
+      }
+      a.T[i] = T;
+    }
+  }
+  if (flag != 0 && a.RR)
+    for (int k = 0; k < K; ++k) a.RR[(int64_t)k * a.ld + i] = 0.0;
+  if (a.flags) a.flags[i] = flag;
+  if (flag != 0) {
+    const unsigned long long slot = atomicAdd(a.fb_count, 1ull);
+    if (a.fb_index) a.fb_index[slot] = (int32_t)(a.index_base + i);
+  }
+}
+
+// ---------------------------------------------------------- statistics
+
+// Partial statistics of the training features: block (b, f) covers feature f
+// over cells b, b + nblocks, ...  Features 0..K+1 are the network inputs
+// (T, p, F(Y0)), features K+2..2K+1 the targets Y1 - Y0.  FP64.
+__global__ void k_stats(StatArgs a) {
+  __shared__ double s1[256], s2[256], mn[256], mx[256];
+  const int f = blockIdx.y;
+  const int K = a.K;
+  double x1 = 0.0, x2 = 0.0, lo = INFINITY, hi = -INFINITY;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n;
+       i += (int64_t)a.nblocks * blockDim.x) {
+    double x;
+    if (f == 0) x = a.T[i];
+    else if (f == 1) x = a.p[i];
+    else if (f < K + 2) {
+      x = (double)boxcox((float)a.Y0[(int64_t)(f - 2) * a.ld + i], a.lambda);
+    } else {
+      const int k = f - K - 2;
+      x = a.Y1[(int64_t)k * a.ld + i] - a.Y0[(int64_t)k * a.ld + i];
+    }
+    x1 += x;
+    x2 += x * x;
+    lo = fmin(lo, x);
+    hi = fmax(hi, x);
+  }
+  const int t = threadIdx.x;
+  s1[t] = x1;
+  s2[t] = x2;
+  mn[t] = lo;
+  mx[t] = hi;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (t < off) {
+      s1[t] += s1[t + off];
+      s2[t] += s2[t + off];
+      mn[t] = fmin(mn[t], mn[t + off]);
+      mx[t] = fmax(mx[t], mx[t + off]);
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    double *o = a.part + ((int64_t)blockIdx.x * gridDim.y + f) * 4;
+    o[0] = s1[0];
+    o[1] = s2[0];
+    o[2] = mn[0];
+    o[3] = mx[0];
+  }
+}
+
+unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace
+
+chem_status gemm(const GemmArgs &g, bool AK, bool BK, int epi, hipStream_t s,
+                 const char *label) {
+  if (g.M <= 0 || g.N <= 0) return CHEM_OK;
+  chem::ProfScope prof(label, s);
+  if (g.K % 32 != 0 || (!AK && g.M % 8 != 0) || (!BK && g.N % 8 != 0)) {
+    chem::set_error("gemm: K must be a multiple of 32 and transposed dims multiples of 8");
+    return CHEM_EINVAL;
+  }
+  if (g.N <= 32) return gemm_cfg<4, 1, 1, 1>(g, AK, BK, epi, s);
+  return gemm_cfg<2, 2, 2, 2>(g, AK, BK, epi, s);
+}
+
+chem_status features(const FeatArgs &a, hipStream_t s) {
+  if (a.n <= 0) return CHEM_OK;
+  chem::ProfScope prof("ann_features", s);
+  hipLaunchKernelGGL(k_features, dim3(nblk(a.n, 256)), dim3(256), 0, s, a);
+  CHEM_HIP(hipGetLastError());
+  return CHEM_OK;
+}
+
+chem_status targets(const TargetArgs &a, hipStream_t s) {
+  if (a.n <= 0) return CHEM_OK;
+  hipLaunchKernelGGL(k_targets, dim3(nblk(a.n, 256)), dim3(256), 0, s, a);
+  CHEM_HIP(hipGetLastError());
+  return CHEM_OK;
+}
+
+chem_status l1_grad(int64_t n, int K, int doutp, const float *U, const float *Ut, u16 *Gb,
+                    float *Gf, double *loss_part, int nparts, float *loss, hipStream_t s) {
+  hipLaunchKernelGGL(k_l1, dim3(nparts), dim3(256), 0, s, n, K, doutp, U, Ut, Gb, Gf, loss_part);
+  hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, s, loss_part, nparts,
+                     1.0 / ((double)n * K), loss);
+  CHEM_HIP(hipGetLastError());
+  return CHEM_OK;
+}
+
+chem_status colsum(int64_t M, int N, const float *X, long ldx, float *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_colsum, dim3(nblk(N, 64)), dim3(64), 0, s, M, N, X, ldx, out);
+  CHEM_HIP(hipGetLastError());
+  return CHEM_OK;
+}
+
+chem_status adam(int64_t n, float *W, const float *g, float *m, float *v, u16 *Wb, float lr,
+                 float b1, float b2, float eps, float bc1, float bc2, hipStream_t s) {
+  hipLaunchKernelGGL(k_adam, dim3(nblk(n, 256)), dim3(256), 0, s, n, W, g, m, v, Wb, lr, b1, b2,
+                     eps, bc1, bc2);
+  CHEM_HIP(hipGetLastError());
+  return CHEM_OK;
+}
+
+chem_status to_bf16(int64_t n, const float *src, u16 *dst, hipStream_t s) {
+  hipLaunchKernelGGL(k_to_bf16, dim3(nblk(n, 256)), dim3(256), 0, s, n, src, dst);
+  CHEM_HIP(hipGetLastError());
+  return CHEM_OK;
+}
+
+chem_status post(const chem::DevMech &M, const PostArgs &a, hipStream_t s) {
+  if (a.n <= 0) return CHEM_OK;
+  if (M.E > EMAX) {
+    chem::set_error("ann_step: at most %d elements supported", EMAX);
+    return CHEM_EUNSUPPORTED;
+  }
+  chem::ProfScope prof("ann_post", s);
+  hipLaunchKernelGGL(k_post, dim3(nblk(a.n, 128)), dim3(128), 0, s, M, a);
+  CHEM_HIP(hipGetLastError());
+  return CHEM_OK;
+}
+
+chem_status stats_partial(const StatArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_stats, dim3(a.nblocks, 2 * a.K + 2), dim3(256), 0, s, a);
+  CHEM_HIP(hipGetLastError());
+  return CHEM_OK;
+}
+
+}  // namespace ann

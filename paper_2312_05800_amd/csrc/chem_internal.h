@@ -48,6 +48,22 @@ struct chem_mech {
 
 namespace chem {
 
+// Brackets the launches issued during its lifetime with HIP events on stream
+// s when launch timing is enabled (chem_profile_enable); no-op otherwise.
+class ProfScope {
+ public:
+  ProfScope(const char *label, hipStream_t s);
+  ~ProfScope();
+  ProfScope(const ProfScope &) = delete;
+  ProfScope &operator=(const ProfScope &) = delete;
+
+ private:
+  const char *label_;
+  hipStream_t s_;
+  void *a_ = nullptr, *b_ = nullptr;
+  bool on_ = false;
+};
+
 void set_error(const char *fmt, ...);
 chem_status hip_fail(hipError_t e, const char *what);
 
@@ -66,6 +82,7 @@ chem_status launch_rates(const chem_mech *m, int64_t n, int64_t ld, const double
 chem_status launch_step(const chem_mech *m, int64_t n, int64_t ld, double dt,
                         const double *dt_cell, double *T, const double *p, double *Y,
                         double *RR, double *h_hint, int32_t *stats, const StepOpts &o,
-                        const int32_t *index, hipStream_t s);
+                        const int32_t *index, hipStream_t s,
+                        const unsigned long long *n_dev = nullptr, uint8_t *flags = nullptr);
 
 }  // namespace chem

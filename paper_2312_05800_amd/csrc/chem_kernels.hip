@@ -329,6 +329,8 @@ struct StepArgs {
   const int32_t *index;  // optional cell index list (cell j of the call is index[j])
   StepOpts o;
   unsigned long long *counter;
+  const unsigned long long *n_dev;  // optional device-side cell count (overrides n)
+  uint8_t *flags;                    // optional: bit 4 set for cells that fail
 };
 
 __global__ void k_reset_counter(unsigned long long *c) {
@@ -385,12 +387,13 @@ __global__ __launch_bounds__(64) void k_step(DevMech M, StepArgs A) {
   double yl = 0.0, y0 = 0.0, p = 0.0, dt = 0.0, t = 0.0, h = 0.0, fac_max = 6.0, rho0 = 0.0;
   int nacc = 0, nrej = 0, status = CELL_OK;
 
+  const int64_t ncell = A.n_dev ? (int64_t)*A.n_dev : A.n;
   auto fetch = [&]() {
     unsigned long long c = 0;
     if (l == 0) c = atomicAdd(A.counter, 1ull);
     c = __shfl(c, 0, G);
     cell = (int64_t)c;
-    active = cell < A.n;
+    active = cell < ncell;
     if (!active) return;
     gcell = A.index ? (int64_t)A.index[cell] : cell;
     yl = 0.0;
@@ -431,6 +434,7 @@ __global__ __launch_bounds__(64) void k_step(DevMech M, StepArgs A) {
         A.stats[A.ld + gcell] = nrej;
         A.stats[2 * A.ld + gcell] = status;
       }
+      if (A.flags && !ok) A.flags[gcell] |= 4;
     }
   };
 
@@ -556,6 +560,7 @@ chem_status launch_rates(const chem_mech *m, int64_t N, int64_t ld, const double
                       : (G == 32 ? lds_bytes<32>(m->R, cpw) : lds_bytes<64>(m->R, cpw));
   chem_status st = check_lds(sh, nullptr);
   if (st != CHEM_OK) return st;
+  ProfScope prof("chem_rates", s);
   switch (G) {
     case 16:
       hipLaunchKernelGGL(k_rates<16>, dim3((unsigned)blocks), dim3(64), sh, s, m->d, N, ld, T, p,
@@ -577,8 +582,8 @@ chem_status launch_rates(const chem_mech *m, int64_t N, int64_t ld, const double
 chem_status launch_step(const chem_mech *m, int64_t N, int64_t ld, double dt,
                         const double *dt_cell, double *T, const double *p, double *Y, double *RR,
                         double *h_hint, int32_t *stats, const StepOpts &o, const int32_t *index,
-                        hipStream_t s) {
-  StepArgs A{N, ld, dt, dt_cell, T, p, Y, RR, h_hint, stats, index, o, m->counters};
+                        hipStream_t s, const unsigned long long *n_dev, uint8_t *flags) {
+  StepArgs A{N, ld, dt, dt_cell, T, p, Y, RR, h_hint, stats, index, o, m->counters, n_dev, flags};
   const int G = group_size(m->d.n);
   const int cpw = 64 / G;
   size_t sh = G == 16 ? lds_bytes<16>(m->R, cpw)
@@ -590,10 +595,12 @@ chem_status launch_step(const chem_mech *m, int64_t N, int64_t ld, double dt,
   int per_cu = (int)((160 * 1024) / (sh > 0 ? sh : 1));
   if (per_cu < 1) per_cu = 1;
   if (per_cu > 32) per_cu = 32;
-  int64_t want = (N + cpw - 1) / cpw;
+  int64_t want = (N + cpw - 1) / cpw;  // with n_dev, N is an upper bound
   int64_t blocks = (int64_t)cus * per_cu;
   if (blocks > want) blocks = want;
+  if (blocks < 1) return CHEM_OK;
   hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, m->counters);
+  ProfScope prof(index ? "chem_step_fallback" : "chem_step", s);
   switch (G) {
     case 16:
       hipLaunchKernelGGL(k_step<16>, dim3((unsigned)blocks), dim3(64), sh, s, m->d, A);

@@ -1,0 +1,263 @@
+"""Parity of the HIP surrogate path (forward GEMMs, gradients, Adam,
+statistics, post-processing, fallback) with the numpy oracle, through the
+C ABI."""
+import os
+import sys
+import tempfile
+
+import numpy as np
+import pytest
+
+import chemgen
+import oracle
+from oracle import ann as oann
+from gpu_util import need_gpu, to_dev, compare_state
+
+pytestmark = pytest.mark.gpu
+
+HID = (1600, 800, 400)
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return need_gpu()
+
+
+@pytest.fixture(scope="module")
+def mech():
+    return chemgen.make_mechanism("ch4")
+
+
+@pytest.fixture(scope="module")
+def data(mech):
+    """A small seeded training set: CH4/air states and their oracle step."""
+    om = oracle.OracleMech(mech)
+    T, p, Y0 = chemgen.make_states(mech, "ch4", N=1024, seed=505)
+    o = oracle.chem_step(om, 1e-5, T, p, Y0)
+    return dict(T=T, p=p, Y0=Y0, Y1=o["Y"], T1=o["T"])
+
+
+def _norm_from(data, lam=0.1):
+    feat = oann.features(data["T"], data["p"], data["Y0"], lam)
+    tgt = oann.targets(data["Y0"], data["Y1"], lam)
+    mi, si = oann.zstats(feat)
+    mo, so = oann.zstats(tgt)
+    return dict(mu_in=mi, sd_in=si, lo=feat.min(axis=1), hi=feat.max(axis=1), mu_out=mo,
+                sd_out=so)
+
+
+def _model(mech, params, nm, dt=1e-5):
+    import paper_2312_05800_amd as P
+    K = mech.K
+    m = P.AnnModel(K + 2, K, HID, seed=1)
+    for l, (W, b) in enumerate(params):
+        m.set_layer(l, W, b)
+    m.set_norm(0.1, dt, nm["mu_in"], nm["sd_in"], nm["lo"], nm["hi"], nm["mu_out"], nm["sd_out"])
+    return m
+
+
+def _f32(a):
+    return np.asarray(a, dtype=np.float32).astype(np.float64)
+
+
+def _oracle_inputs(nm, T, p, Y):
+    feat = oann.features(T, p, Y)
+    return ((feat - _f32(nm["mu_in"])[:, None]) / _f32(nm["sd_in"])[:, None]).T
+
+
+def _params32(params):
+    return [(_f32(W), _f32(b)) for W, b in params]
+
+
+@pytest.mark.parametrize("N", [3001, 64])
+def test_forward_parity(dev, mech, data, N):
+    import torch
+    _say(f"[ann forward] N={N}")
+    K = mech.K
+    params = oann.init_params([K + 2, *HID, K], seed=7)
+    nm = _norm_from(data)
+    m = _model(mech, params, nm)
+    T, p, Y = chemgen.make_states(mech, "ch4", N=N, seed=606)
+    U = m.forward(to_dev(T, dev), to_dev(p, dev), to_dev(Y, dev), K)
+    torch.cuda.synchronize()
+    Ug = U.cpu().numpy().astype(np.float64)
+    Uo = oann.forward(_params32(params), _oracle_inputs(nm, T, p, Y), prec="bf16")
+    err = np.abs(Ug - Uo)
+    _say(f"  max abs {err.max():.3e} rms {np.sqrt((err ** 2).mean()):.3e} |U| {np.abs(Uo).mean():.3f}")
+    assert err.max() <= 2e-2 and np.sqrt((err ** 2).mean()) <= 2e-3
+    # the BF16 emulation is the right reference: FP64 differs by more than the GPU does
+    e64 = np.abs(oann.forward(_params32(params), _oracle_inputs(nm, T, p, Y)) - Uo)
+    assert np.sqrt((err ** 2).mean()) < np.sqrt((e64 ** 2).mean())
+
+
+def test_forward_full_size_sampled(dev, mech, data):
+    import torch
+    N = 1 << 20
+    _say(f"[ann forward] full N={N}")
+    K = mech.K
+    params = oann.init_params([K + 2, *HID, K], seed=8)
+    nm = _norm_from(data)
+    m = _model(mech, params, nm)
+    T, p, Y = chemgen.make_states(mech, "ch4_eval")
+    U = m.forward(to_dev(T, dev), to_dev(p, dev), to_dev(Y, dev), K)
+    torch.cuda.synchronize()
+    idx = np.linspace(0, N - 1, 257).astype(np.int64)
+    Ug = U[torch.from_numpy(idx).to(dev)].cpu().numpy().astype(np.float64)
+    Uo = oann.forward(_params32(params), _oracle_inputs(nm, T[idx], p[idx], Y[:, idx]),
+                      prec="bf16")
+    err = np.abs(Ug - Uo)
+    assert err.max() <= 2e-2 and np.sqrt((err ** 2).mean()) <= 2e-3
+    assert torch.isfinite(U).all()
+
+
+def test_fit_norm(dev, mech, data):
+    import paper_2312_05800_amd as P
+    K = mech.K
+    m = P.AnnModel(K + 2, K, HID, seed=1)
+    m.fit_norm(to_dev(data["T"], dev), to_dev(data["p"], dev), to_dev(data["Y0"], dev),
+               to_dev(data["Y1"], dev), 0.1, 1e-5)
+    g = m.get_norm(K + 2, K)
+    o = _norm_from(data)
+    # GPU features use FP32 Box-Cox; statistics agree to FP32 feature rounding
+    for k in ("mu_in", "lo", "hi"):
+        np.testing.assert_allclose(g[k], o[k], rtol=2e-5, atol=2e-5)
+    np.testing.assert_allclose(g["sd_in"], o["sd_in"], rtol=1e-3)
+    np.testing.assert_allclose(g["mu_out"], o["mu_out"], rtol=1e-2, atol=1e-5)
+    np.testing.assert_allclose(g["sd_out"], o["sd_out"], rtol=1e-2, atol=1e-5)
+    assert g["sd_in"][1] == 1.0  # constant pressure: zero spread -> 1
+    assert g["lambda"] == pytest.approx(0.1) and g["dt_model"] == 1e-5
+
+
+def test_gradients_and_adam(dev, mech, data):
+    import torch
+    _say("[ann grads]")
+    K = mech.K
+    params = oann.init_params([K + 2, *HID, K], seed=9)
+    nm = _norm_from(data)
+    m = _model(mech, params, nm)
+    B = 256
+    T, p, Y0, Y1 = data["T"][:B], data["p"][:B], data["Y0"][:, :B], data["Y1"][:, :B]
+    loss = torch.zeros(1, dtype=torch.float32, device=dev)
+    args = [to_dev(a, dev) for a in (T, p, Y0, Y1)]
+    m.train_step(*args, loss, lr=0.0)
+    torch.cuda.synchronize()
+    X = _oracle_inputs(nm, T, p, Y0)
+    tgt = ((oann.targets(Y0, Y1) - _f32(nm["mu_out"])[:, None]) / _f32(nm["sd_out"])[:, None]).T
+    grads, loss_o = oann.backward(_params32(params), X, tgt, prec="bf16")
+    assert abs(loss.item() - loss_o) <= 1e-3 * loss_o
+    shapes = [(HID[0], K + 2), (HID[1], HID[0]), (HID[2], HID[1]), (K, HID[2])]
+    for l in range(4):
+        gW, gb = m.get_grad(l, shapes[l])
+        for a, b in ((gW, grads[l][0]), (gb, grads[l][1])):
+            rel = np.linalg.norm(a - b) / np.linalg.norm(b)
+            cos = float(np.sum(a * b) / (np.linalg.norm(a) * np.linalg.norm(b)))
+            _say(f"  layer {l} rel {rel:.2e} cos {cos:.6f}")
+            assert rel <= 1e-2 and cos >= 0.999
+    # one Adam step: the first step moves every weight by lr * g / (|g| + eps)
+    W0 = [m.get_layer(l, shapes[l]) for l in range(4)]
+    m.train_step(*args, loss, lr=1e-3)
+    torch.cuda.synchronize()
+    assert m.num_steps == 1
+    for l in range(4):
+        gW, gb = m.get_grad(l, shapes[l])
+        W1, b1 = m.get_layer(l, shapes[l])
+        for w0, w1, g in ((W0[l][0], W1, gW), (W0[l][1], b1, gb)):
+            ref = w0.astype(np.float64) - 1e-3 * g / (np.abs(g) + 1e-8)
+            np.testing.assert_allclose(w1, ref, rtol=1e-5, atol=2e-7)
+
+
+def test_post_and_fallback(dev, mech, data):
+    import torch
+    import paper_2312_05800_amd as P
+    _say("[ann post/fallback]")
+    K = mech.K
+    om = oracle.OracleMech(mech)
+    params = oann.init_params([K + 2, *HID, K], seed=10)
+    # scale the output layer down so that the step is a small perturbation
+    params[3] = (params[3][0] * 0.02, params[3][1] * 0.02)
+    nm = _norm_from(data)
+    m = _model(mech, params, nm)
+    gm = P.Mechanism(mech)
+    N = 700
+    T, p, Y = chemgen.make_states(mech, "ch4", N=N, seed=707)
+    Td, pd, Yd = to_dev(T, dev), to_dev(p, dev), to_dev(Y, dev)
+    U = m.forward(Td, pd, Yd, K).cpu().numpy().astype(np.float64)
+    # surrogate only (no fallback): compare with the oracle's post-processing
+    RR = torch.zeros((K, N), dtype=torch.float64, device=dev)
+    flags = torch.zeros(N, dtype=torch.uint8, device=dev)
+    nfb = torch.zeros(1, dtype=torch.int64, device=dev)
+    m.step(gm, 1e-5, Td, pd, Yd, RR=RR, flags=flags, n_fallback=nfb, fallback=False)
+    torch.cuda.synchronize()
+    o = oann.post(om, T, p, Y, U.T, _f32(nm["mu_out"]), _f32(nm["sd_out"]), 1e-5,
+                  lo=_f32(nm["lo"]), hi=_f32(nm["hi"]))
+    fg = flags.cpu().numpy()
+    near = (o["residual"] > 0.5e-6) & (o["residual"] < 2e-6)
+    agree = (fg == o["flags"]) | near
+    _say(f"  flagged gpu {np.count_nonzero(fg)} oracle {np.count_nonzero(o['flags'])} "
+         f"near-threshold {np.count_nonzero(near)}")
+    assert agree.all()
+    assert int(nfb.item()) == np.count_nonzero(fg)
+    ok = (fg == 0) & (o["flags"] == 0)
+    assert ok.sum() > N // 4
+    Yg, Tg, RRg = Yd.cpu().numpy(), Td.cpu().numpy(), RR.cpu().numpy()
+    big = np.abs(o["Y"]) > 1e-6
+    err = np.abs(Yg - o["Y"])[:, ok]
+    assert np.all(err <= 1e-5 * np.abs(o["Y"][:, ok]) + 1e-9)
+    np.testing.assert_allclose(Tg[ok], o["T"][ok], rtol=1e-6)
+    # flagged cells are untouched without fallback
+    np.testing.assert_array_equal(Yg[:, fg != 0], Y[:, fg != 0])
+    assert np.all(RRg[:, fg != 0] == 0)
+    del big
+    # everything flagged (dt differs from the training dt): fallback = chem_step
+    Td, pd, Yd = to_dev(T, dev), to_dev(p, dev), to_dev(Y, dev)
+    m.step(gm, 2e-6, Td, pd, Yd, RR=RR, flags=flags, n_fallback=nfb)
+    torch.cuda.synchronize()
+    assert int(nfb.item()) == N
+    assert np.all(flags.cpu().numpy() & 1)
+    oc = oracle.chem_step(om, 2e-6, T, p, Y)
+    res = compare_state(Td.cpu().numpy(), Yd.cpu().numpy(), oc["T"], oc["Y"])
+    assert res["ok"], res
+    np.testing.assert_allclose(RR.cpu().numpy(), oc["RR"], rtol=1e-6,
+                               atol=1e-8 * np.abs(oc["RR"]).max())
+
+
+def test_save_load_roundtrip(dev, mech, data):
+    import torch
+    import paper_2312_05800_amd as P
+    K = mech.K
+    params = oann.init_params([K + 2, *HID, K], seed=11)
+    m = _model(mech, params, _norm_from(data))
+    T, p, Y = chemgen.make_states(mech, "ch4", N=100, seed=808)
+    args = [to_dev(a, dev) for a in (T, p, Y)]
+    U1 = m.forward(*args, K)
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "m.bin")
+        m.save(path)
+        m2 = P.AnnModel.load(path)
+        U2 = m2.forward(*args, K)
+    torch.cuda.synchronize()
+    assert torch.equal(U1, U2)
+
+
+def test_training_reduces_loss(dev, mech, data):
+    import torch
+    import paper_2312_05800_amd as P
+    _say("[ann train]")
+    K = mech.K
+    m = P.AnnModel(K + 2, K, HID, seed=3)
+    dv = {k: to_dev(v, dev) for k, v in data.items()}
+    m.fit_norm(dv["T"], dv["p"], dv["Y0"], dv["Y1"], 0.1, 1e-5)
+    loss = torch.zeros(1, dtype=torch.float32, device=dev)
+    rng = np.random.default_rng(0)
+    losses = []
+    for it in range(60):
+        idx = torch.from_numpy(rng.permutation(1024)[:256].astype(np.int64)).to(dev)
+        m.train_step(dv["T"], dv["p"], dv["Y0"], dv["Y1"], loss, index=idx, lr=1e-3)
+        losses.append(loss.item())
+    _say(f"  loss {losses[0]:.4f} -> {losses[-1]:.4f}")
+    assert np.mean(losses[-10:]) < 0.6 * np.mean(losses[:5])
