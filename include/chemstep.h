@@ -135,6 +135,30 @@ chem_status chem_step(const chem_mech *m, chem_batch batch, double dt, const dou
                       double *T, const double *p, double *Y, double *RR, double *h_hint,
                       int32_t *stats, const chem_step_opts *opts, void *stream);
 
+/* One set of cells of an uneven batched workload. */
+typedef struct {
+  int64_t n;        /* cells in the set (0 allowed) */
+  int64_t ld;       /* leading dimension of the set's [K][ld] arrays, >= n */
+  double dt;        /* chemistry time step of the set, s (> 0) */
+  double *T;        /* [n] in/out */
+  const double *p;  /* [n] */
+  double *Y;        /* [K][ld] in/out */
+  double *RR;       /* [K][ld] out, nullable */
+  double *h_hint;   /* [n] in/out, nullable */
+  int32_t *stats;   /* [3][ld] out, nullable */
+} chem_set;
+
+/* chem_step over several independent cell sets with their own dt in one
+ * persistent launch: the cells of all sets share one work queue, so sets of
+ * very different size and stiffness keep every wavefront busy.  `sets` is a
+ * (host) array of n_sets descriptors whose pointers are device pointers; the
+ * table is copied to device memory owned by `m` on `stream`, and the call
+ * synchronises `stream` while it stages that copy (calls on the same handle
+ * must be ordered by the caller).  Results per cell are those of chem_step
+ * with the set's dt. */
+chem_status chem_step_sets(const chem_mech *m, int32_t n_sets, const chem_set *sets,
+                           const chem_step_opts *opts, void *stream);
+
 /* ------------------------------------------------------------ surrogate
  * The ANN of Sec. 3.2 that stands in for the integration: inputs
  * x = {T, p, F(Y)} with the Box-Cox transform F(y) = (y^lambda - 1)/lambda
@@ -224,7 +248,21 @@ chem_status ann_train_step(ann_model *m, chem_batch batch, const double *T, cons
                            const double *Y0, const double *Y1, const int64_t *index,
                            const ann_train_opts *opts, float *loss, void *stream);
 int64_t ann_num_steps(const ann_model *m);
-/* Binary model file: architecture, statistics, master weights, Adam state. */
+/* FP8 variant of inference: the two hidden-to-hidden layers run on OCP FP8
+ * E4M3 MFMA with per-tensor scales amax/448 -- activation scales from a BF16
+ * forward pass over the calibration cells (at most 2^21 of them), weight
+ * scales from the FP32 master weights; the first and last layers stay BF16.
+ * Switches inference (ann_forward, ann_step) to FP8; synchronises `stream`.
+ * A training step with lr > 0 switches back to BF16 (weights changed). */
+chem_status ann_quantize_fp8(ann_model *m, chem_batch calib, const double *T, const double *p,
+                             const double *Y, void *stream);
+/* 0 = BF16 inference, 1 = FP8 hidden layers (requires ann_quantize_fp8). */
+chem_status ann_set_precision(ann_model *m, int32_t prec);
+/* Scales of the FP8 layers (host [2] each): activation and weight scale of
+ * the 2nd and 3rd layer. */
+chem_status ann_get_fp8_scales(const ann_model *m, float *act, float *wgt);
+/* Binary model file: architecture, statistics, master weights, Adam state
+ * (not the FP8 copies: quantise again after loading). */
 chem_status ann_save(const ann_model *m, const char *path);
 chem_status ann_load(const char *path, ann_model **out);
 

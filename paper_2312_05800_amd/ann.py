@@ -45,6 +45,9 @@ def _prototypes(L):
     L.ann_train_step.argtypes = [_P, Batch, _P, _P, _P, _P, _P, _P, _P, _P]
     L.ann_num_steps.argtypes = [_P]
     L.ann_num_steps.restype = C.c_int64
+    L.ann_quantize_fp8.argtypes = [_P, Batch, _P, _P, _P, _P]
+    L.ann_set_precision.argtypes = [_P, C.c_int32]
+    L.ann_get_fp8_scales.argtypes = [_P, _P, _P]
     L.ann_save.argtypes = [_P, C.c_char_p]
     L.ann_load.argtypes = [C.c_char_p, C.POINTER(_P)]
 
@@ -128,6 +131,27 @@ class AnnModel:
         out["lambda"] = lam.value
         out["dt_model"] = dtm.value
         return out
+
+    def quantize_fp8(self, T, p, Y, stream=None):
+        """Calibrate per-tensor scales on these cells and switch the hidden
+        layers to FP8 E4M3."""
+        import torch
+        n = T.shape[0]
+        ld = _soa(Y, Y.shape[0], n, "Y")
+        f64 = torch.float64
+        check("ann_quantize_fp8", lib().ann_quantize_fp8(
+            self.handle, Batch(n, ld), _dptr(T, f64, "T"), _dptr(p, f64, "p"),
+            _dptr(Y, f64, "Y"), _stream(stream)))
+
+    def set_precision(self, prec):
+        check("ann_set_precision", lib().ann_set_precision(self.handle, int(prec)))
+
+    def fp8_scales(self):
+        a = np.zeros(2, np.float32)
+        w = np.zeros(2, np.float32)
+        check("ann_get_fp8_scales", lib().ann_get_fp8_scales(self.handle, a.ctypes.data,
+                                                             w.ctypes.data))
+        return a, w
 
     def fit_norm(self, T, p, Y0, Y1, lam=0.1, dt_model=1e-5, stream=None):
         import torch

@@ -38,6 +38,11 @@ class Batch(C.Structure):
     _fields_ = [("n", C.c_int64), ("ld", C.c_int64)]
 
 
+class ChemSet(C.Structure):
+    _fields_ = [("n", C.c_int64), ("ld", C.c_int64), ("dt", C.c_double), ("T", _P), ("p", _P),
+                ("Y", _P), ("RR", _P), ("h_hint", _P), ("stats", _P)]
+
+
 class StepOpts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("atol_Y", C.c_double), ("atol_T", C.c_double),
                 ("h0", C.c_double), ("h_min", C.c_double), ("max_steps", C.c_int32)]
@@ -61,6 +66,7 @@ def lib():
             L.chem_mech_num_reactions.argtypes = [_P]
             L.chem_rates.argtypes = [_P, Batch, _P, _P, _P, _P, _P, _P, _P]
             L.chem_step.argtypes = [_P, Batch, C.c_double, _P, _P, _P, _P, _P, _P, _P, _P, _P]
+            L.chem_step_sets.argtypes = [_P, C.c_int32, _P, _P, _P]
             L.chem_profile_enable.argtypes = [C.c_int32]
             L.chem_profile_read.argtypes = [_P, _P, _P, C.c_int32]
             L.chem_profile_read.restype = C.c_int32
@@ -108,6 +114,8 @@ def _stream(stream):
 
 def _soa(t, K, n, name):
     """Checks a [K][ld] species array and returns its leading dimension."""
+    if n == 0 and t.dim() == 2 and t.shape[0] == K:
+        return t.shape[1]
     if t.dim() != 2 or t.shape[0] != K or t.shape[1] < n or t.stride(1) != 1:
         raise ValueError(f"{name} must be a [K={K}, >=n] row-major view")
     return t.stride(0) if K > 1 else t.shape[1]
@@ -197,6 +205,26 @@ def chem_step(mech: Mechanism, dt, T, p, Y, dt_cell=None, RR=None, h_hint=None, 
         _dptr(p, f64, "p"), _dptr(Y, f64, "Y"), _dptr(RR, f64, "RR"),
         _dptr(h_hint, f64, "h_hint"), _dptr(stats, torch.int32, "stats"),
         None if o is None else C.byref(o), _stream(stream)))
+
+
+def chem_step_sets(mech: Mechanism, sets, opts=None, stream=None):
+    """chem_step over several cell sets in one launch.  ``sets``: sequence of
+    dicts with keys dt, T, p, Y and optionally RR, h_hint, stats (tensors as
+    in chem_step); updated in place."""
+    import torch
+    f64 = torch.float64
+    arr = (ChemSet * max(1, len(sets)))()
+    for i, st in enumerate(sets):
+        n = st["T"].shape[0]
+        ld = _soa(st["Y"], mech.K, n, "Y")
+        arr[i] = ChemSet(n, ld, float(st["dt"]), _dptr(st["T"], f64, "T"),
+                         _dptr(st["p"], f64, "p"), _dptr(st["Y"], f64, "Y"),
+                         _dptr(st.get("RR"), f64, "RR"), _dptr(st.get("h_hint"), f64, "h_hint"),
+                         _dptr(st.get("stats"), torch.int32, "stats"))
+    o = _opts(opts)
+    check("chem_step_sets", lib().chem_step_sets(mech.handle, len(sets), C.addressof(arr),
+                                                 None if o is None else C.byref(o),
+                                                 _stream(stream)))
 
 
 def profile_enable(on: bool = True):

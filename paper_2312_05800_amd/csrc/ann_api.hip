@@ -63,6 +63,14 @@ struct ann_model {
   u16 *tX = nullptr, *tH[3] = {}, *tGb[ann::NLAYER] = {};
   float *tZ[3] = {}, *tU = nullptr, *tUt = nullptr, *tGf[ann::NLAYER] = {};
   double *loss_part = nullptr;
+  // FP8 inference of the hidden-to-hidden layers (L2, L3)
+  bool fp8_ready = false, use_fp8 = false;
+  float sa[3] = {1, 1, 1}, sw[3] = {1, 1, 1};  // per-tensor scales of layers 1, 2
+  void *fp8_buf = nullptr;
+  uint8_t *Wq1 = nullptr, *Wq2 = nullptr;  // [N2p][1600], [416][832]-style padded E4M3
+  float *bq1 = nullptr;                    // layer-1 bias padded to N2p
+  int n2p = 0, k3p = 0;                    // padded widths (multiples of 64)
+  uint8_t *H1q = nullptr, *H2q = nullptr;  // inference workspace (E4M3 activations)
 };
 
 using namespace chem;
@@ -91,6 +99,9 @@ chem_status grow_infer(ann_model *m, int64_t n) {
   for (int l = 0; l < 3; ++l) oH[l] = sect((size_t)cap * m->L[l].doutp * 2);
   const size_t oU = sect((size_t)cap * m->n_out * 4);
   const size_t oC = sect(64);
+  const int n2p = (m->L[1].dout + 63) / 64 * 64;
+  const size_t oQ1 = sect((size_t)cap * m->L[1].dinp);
+  const size_t oQ2 = sect((size_t)cap * n2p);
   if (m->wi.base) (void)hipFree(m->wi.base);
   m->wi.base = nullptr;
   m->wi.cap = 0;
@@ -103,6 +114,8 @@ chem_status grow_infer(ann_model *m, int64_t n) {
   for (int l = 0; l < 3; ++l) m->H[l] = (u16 *)(b + oH[l]);
   m->U = (float *)(b + oU);
   m->fb_count = (unsigned long long *)(b + oC);
+  m->H1q = (uint8_t *)(b + oQ1);
+  m->H2q = (uint8_t *)(b + oQ2);
   m->wi.bytes = off;
   m->wi.cap = cap;
   return CHEM_OK;
@@ -310,6 +323,7 @@ extern "C" chem_status ann_create(const ann_arch *arch, uint64_t seed, ann_model
 
 extern "C" void ann_destroy(ann_model *m) {
   if (!m) return;
+  if (m->fp8_buf) (void)hipFree(m->fp8_buf);
   (void)hipFree(m->params);
   if (m->norm_buf) (void)hipFree(m->norm_buf);
   if (m->wi.base) (void)hipFree(m->wi.base);
@@ -467,6 +481,62 @@ chem_status forward_chunk(ann_model *m, int64_t n, int64_t ld, const double *T, 
                    m->nm.lambda, m->X};
   chem_status st = ann::features(fa, s);
   if (st != CHEM_OK) return st;
+  if (m->use_fp8) {
+    // L1 (BF16) -> E4M3 activations; L2, L3 on FP8 MFMA; L4 (BF16)
+    const ann::Layer &L0 = m->L[0], &L1 = m->L[1], &L2 = m->L[2], &L3 = m->L[3];
+    ann::GemmArgs g{};
+    g.M = (int)n;
+    g.N = L0.doutp;
+    g.K = L0.dinp;
+    g.A = m->X;
+    g.lda = L0.dinp;
+    g.B = m->Wb[0];
+    g.ldb = L0.dinp;
+    g.bias = m->bm[0];
+    g.Cq = m->H1q;
+    g.ldcq = L0.doutp;
+    g.qinv = 1.0f / m->sa[1];
+    if ((st = ann::gemm(g, true, true, ann::EPI_GELU_Q8, s, "mlp_l1")) != CHEM_OK) return st;
+    ann::GemmArgs h{};
+    h.M = (int)n;
+    h.N = m->n2p;
+    h.K = L1.dinp;
+    h.A8 = m->H1q;
+    h.lda = L1.dinp;
+    h.B8 = m->Wq1;
+    h.ldb = L1.dinp;
+    h.bias = m->bq1;
+    h.scale = m->sa[1] * m->sw[1];
+    h.Cq = m->H2q;
+    h.ldcq = m->n2p;
+    h.qinv = 1.0f / m->sa[2];
+    if ((st = ann::gemm8(h, ann::EPI_GELU_Q8, s, "mlp_l2_fp8")) != CHEM_OK) return st;
+    ann::GemmArgs q{};
+    q.M = (int)n;
+    q.N = L2.doutp;
+    q.K = m->k3p;
+    q.A8 = m->H2q;
+    q.lda = m->k3p;
+    q.B8 = m->Wq2;
+    q.ldb = m->k3p;
+    q.bias = m->bm[2];
+    q.scale = m->sa[2] * m->sw[2];
+    q.Cb = m->H[2];
+    q.ldcb = L2.doutp;
+    if ((st = ann::gemm8(q, ann::EPI_GELU, s, "mlp_l3_fp8")) != CHEM_OK) return st;
+    ann::GemmArgs o{};
+    o.M = (int)n;
+    o.N = m->n_out;
+    o.K = L3.dinp;
+    o.A = m->H[2];
+    o.lda = L3.dinp;
+    o.B = m->Wb[3];
+    o.ldb = L3.dinp;
+    o.bias = m->bm[3];
+    o.Cf = U;
+    o.ldcf = m->n_out;
+    return ann::gemm(o, true, true, ann::EPI_F32, s, "mlp_l4");
+  }
   const u16 *in = m->X;
   for (int l = 0; l < 4; ++l) {
     const ann::Layer &L = m->L[l];
@@ -649,6 +719,10 @@ extern "C" chem_status ann_train_step(ann_model *m, chem_batch batch, const doub
   if (st != CHEM_OK) return st;
   hipStream_t s = (hipStream_t)stream;
   const int K = m->n_out;
+  if (opts->lr > 0.0f) {  // the E4M3 weights no longer match: back to BF16 inference
+    m->fp8_ready = false;
+    m->use_fp8 = false;
+  }
   ann::FeatArgs fa{B, batch.ld, T, p, Y0, index, K, m->L[0].dinp, m->nm.mu_in, m->nm.sd_in,
                    m->nm.lambda, m->tX};
   if ((st = ann::features(fa, s)) != CHEM_OK) return st;
@@ -858,5 +932,119 @@ extern "C" chem_status ann_load(const char *path, ann_model **out) {
   }
   m->step = step;
   *out = m;
+  return CHEM_OK;
+}
+
+namespace {
+float reduce_amax(const std::vector<float> &p) {
+  float a = 0.0f;
+  for (float v : p) a = fmaxf(a, v);
+  return a;
+}
+}  // namespace
+
+extern "C" chem_status ann_quantize_fp8(ann_model *m, chem_batch calib, const double *T,
+                                        const double *p, const double *Y, void *stream) {
+  chem_status st = check_model("ann_quantize_fp8", m);
+  if (st != CHEM_OK) return st;
+  if (!m->has_norm || m->n_in != m->n_out + 2) {
+    set_error("ann_quantize_fp8: statistics not set or n_in != n_out + 2");
+    return CHEM_EMODEL;
+  }
+  if (calib.n < 1 || calib.ld < calib.n || !T || !p || !Y) {
+    set_error("ann_quantize_fp8: needs a non-empty calibration batch");
+    return CHEM_EINVAL;
+  }
+  if (m->L[1].dinp % 64 != 0) {
+    set_error("ann_quantize_fp8: the first hidden width must be a multiple of 64");
+    return CHEM_EUNSUPPORTED;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t n = calib.n < CHUNK ? calib.n : CHUNK;
+  if ((st = grow_infer(m, n)) != CHEM_OK) return st;
+  const bool prev = m->use_fp8;
+  m->use_fp8 = false;  // calibrate on the BF16 activations
+  st = forward_chunk(m, n, calib.ld, T, p, Y, m->U, s);
+  m->use_fp8 = prev;
+  if (st != CHEM_OK) return st;
+  m->n2p = (m->L[1].dout + 63) / 64 * 64;
+  m->k3p = m->n2p;
+  if (!m->fp8_buf) {
+    const size_t b1 = (size_t)m->n2p * m->L[1].dinp, b2 = (size_t)m->L[2].doutp * m->k3p;
+    const size_t off1 = align256(b1), off2 = off1 + align256(b2);
+    CHEM_HIP(hipMalloc(&m->fp8_buf, off2 + (size_t)m->n2p * 4 + 1024 * 4));
+    unsigned char *b = (unsigned char *)m->fp8_buf;
+    m->Wq1 = b;
+    m->Wq2 = b + off1;
+    m->bq1 = (float *)(b + off2);
+  }
+  float *part = m->bq1 + m->n2p;  // 1024 floats of scratch for the amax partials
+  const int NP = 256;
+  std::vector<float> h(NP);
+  float amax_v[4];
+  const void *srcs[4] = {m->H[0], m->H[1], m->Wm[1], m->Wm[2]};
+  const int64_t cnt[4] = {n * m->L[0].doutp, n * m->L[1].doutp,
+                          (int64_t)layer_elems(m->L[1]), (int64_t)layer_elems(m->L[2])};
+  for (int q = 0; q < 4; ++q) {
+    if ((st = ann::amax(cnt[q], srcs[q], q < 2, part, NP, s)) != CHEM_OK) return st;
+    hipError_t e = hipMemcpyAsync(h.data(), part, NP * 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "ann_quantize_fp8: amax read back");
+    amax_v[q] = reduce_amax(h);
+  }
+  auto sc = [](float a) { return a > 0.0f && isfinite(a) ? a / 448.0f : 1.0f; };
+  m->sa[1] = sc(amax_v[0]);
+  m->sa[2] = sc(amax_v[1]);
+  m->sw[1] = sc(amax_v[2]);
+  m->sw[2] = sc(amax_v[3]);
+  st = ann::quant_e4m3(m->Wm[1], m->L[1].dinp, m->L[1].dout, m->L[1].din, m->Wq1, m->n2p,
+                       m->L[1].dinp, 1.0f / m->sw[1], s);
+  if (st != CHEM_OK) return st;
+  st = ann::quant_e4m3(m->Wm[2], m->L[2].dinp, m->L[2].doutp, m->L[2].din, m->Wq2,
+                       m->L[2].doutp, m->k3p, 1.0f / m->sw[2], s);
+  if (st != CHEM_OK) return st;
+  CHEM_HIP(hipStreamSynchronize(s));
+  std::vector<float> hb(m->n2p, 0.0f);  // layer-1 bias, zero-padded to the FP8 width
+  CHEM_HIP(hipMemcpy(hb.data(), m->bm[1], (size_t)m->L[1].dout * 4, hipMemcpyDeviceToHost));
+  CHEM_HIP(hipMemcpy(m->bq1, hb.data(), hb.size() * 4, hipMemcpyHostToDevice));
+  m->fp8_ready = true;
+  m->use_fp8 = true;
+  return CHEM_OK;
+}
+
+extern "C" chem_status ann_set_precision(ann_model *m, int32_t prec) {
+  chem_status st = check_model("ann_set_precision", m);
+  if (st != CHEM_OK) return st;
+  if (prec == 0) {
+    m->use_fp8 = false;
+    return CHEM_OK;
+  }
+  if (prec == 1) {
+    if (!m->fp8_ready) {
+      set_error("ann_set_precision: call ann_quantize_fp8 first");
+      return CHEM_EMODEL;
+    }
+    m->use_fp8 = true;
+    return CHEM_OK;
+  }
+  set_error("ann_set_precision: prec must be 0 (BF16) or 1 (FP8 hidden layers)");
+  return CHEM_EINVAL;
+}
+
+extern "C" chem_status ann_get_fp8_scales(const ann_model *m, float *act, float *wgt) {
+  chem_status st = check_model("ann_get_fp8_scales", m);
+  if (st != CHEM_OK) return st;
+  if (!m->fp8_ready) {
+    set_error("ann_get_fp8_scales: not quantised");
+    return CHEM_EMODEL;
+  }
+  if (act) {
+    act[0] = m->sa[1];
+    act[1] = m->sa[2];
+  }
+  if (wgt) {
+    wgt[0] = m->sw[1];
+    wgt[1] = m->sw[2];
+  }
   return CHEM_OK;
 }

@@ -26,7 +26,7 @@ struct Norm {
   float *mu_out, *sd_out;          // device [n_out]
 };
 
-enum { EPI_F32 = 0, EPI_GELU = 1, EPI_GELUGRAD = 2 };
+enum { EPI_F32 = 0, EPI_GELU = 1, EPI_GELUGRAD = 2, EPI_GELU_Q8 = 3 };
 
 struct GemmArgs {
   int M, N, K;
@@ -41,12 +41,26 @@ struct GemmArgs {
   long ldcf;
   float *Z;
   long ldz;
+  // FP8 variants: operands A8 [M][K], B8 [N][K] (E4M3), output Cq (E4M3)
+  const uint8_t *A8;
+  const uint8_t *B8;
+  uint8_t *Cq;
+  long ldcq;
+  float scale;  // multiplies the accumulator before the bias (FP8 operands)
+  float qinv;   // 1/scale of the E4M3 output (EPI_GELU_Q8)
 };
 
 // C = epi(A * op(B)); AK: A is [M][K] row-major (else [K][M]); BK: B is [N][K]
 // row-major (else [K][N]).
 chem_status gemm(const GemmArgs &g, bool AK, bool BK, int epi, hipStream_t s,
                  const char *label);
+// E4M3 x E4M3 GEMM (both K-contiguous, K a multiple of 64), epi GELU or GELU_Q8.
+chem_status gemm8(const GemmArgs &g, int epi, hipStream_t s, const char *label);
+// max |x| over n BF16 (bf16 = true) or FP32 values, into part[0..nparts)
+chem_status amax(int64_t n, const void *x, bool bf16, float *part, int nparts, hipStream_t s);
+// dst [rows_p][cols_p] E4M3 = e4m3(src[r][c] * qinv) for r < rows, c < cols, else 0
+chem_status quant_e4m3(const float *src, long ld_src, int rows, int cols, uint8_t *dst,
+                       int rows_p, int cols_p, float qinv, hipStream_t s);
 
 struct FeatArgs {
   int64_t n, ld;

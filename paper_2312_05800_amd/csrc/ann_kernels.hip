@@ -33,6 +33,23 @@ __device__ __forceinline__ float gelu_grad(float x) {
          x * expf(-0.5f * x * x) * 0.39894228040143268f;
 }
 
+// FP32 -> OCP FP8 E4M3 (e4m3fn: no infinities, max 448), saturating, round to
+// nearest even.
+__device__ __forceinline__ uint8_t f2e4m3(float x) {
+  if (x != x) return 0x7f;
+  const unsigned sign = (__float_as_uint(x) >> 24) & 0x80u;
+  const float a = fminf(fabsf(x), 448.0f);
+  unsigned code;
+  if (a < 0.015625f) {  // below 2^-6: subnormals, spacing 2^-9 (8 -> smallest normal)
+    code = (unsigned)rintf(a * 512.0f);
+  } else {
+    unsigned u = __float_as_uint(a);
+    u += 0x7ffffu + ((u >> 20) & 1u);  // keep 3 mantissa bits, ties to even
+    code = ((((u >> 23) & 0xffu) - 120u) << 3) | ((u >> 20) & 7u);
+  }
+  return (uint8_t)(sign | code);
+}
+
 __device__ __forceinline__ float boxcox(float y, float lam) {
   return (powf(fmaxf(y, 0.0f), lam) - 1.0f) / lam;
 }
@@ -50,7 +67,16 @@ __global__ __launch_bounds__(WM *WN * 64) void k_gemm(GemmArgs g) {
   __shared__ __attribute__((aligned(16))) u16 Bs[2][BN * LK];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave % WM, wn = wave / WM;
-  const long m0 = (long)blockIdx.x * BM, n0 = (long)blockIdx.y * BN;
+  // Block order: the N-tiles of one M-tile are consecutive logical blocks on
+  // the same XCD (blocks are dealt round-robin over the 8 XCDs), so an
+  // activation tile is fetched from HBM once and reused from that XCD's L2.
+  const int ntn = (g.N + BN - 1) / BN;
+  const int ntm = (g.M + BM - 1) / BM;
+  const int total = ntn * ntm;
+  const int per_xcd = (total + 7) / 8;
+  const int logical = (int)(blockIdx.x % 8) * per_xcd + (int)(blockIdx.x / 8);
+  if (logical >= total) return;
+  const long m0 = (long)(logical / ntn) * BM, n0 = (long)(logical % ntn) * BN;
   constexpr int ACH = BM * BK / 8, BCH = BN * BK / 8;
   constexpr int APT = (ACH + NT - 1) / NT, BPT = (BCH + NT - 1) / NT;
   uint4 ra[APT], rb[BPT];
@@ -177,6 +203,8 @@ __global__ __launch_bounds__(WM *WN * 64) void k_gemm(GemmArgs g) {
           if (g.Z) g.Z[row * g.ldz + col] = z;
           if (g.Cb) g.Cb[row * g.ldcb + col] = f2bf(gelu(z));
           if (g.Cf) g.Cf[row * g.ldcf + col] = gelu(z);
+        } else if (EPI == EPI_GELU_Q8) {
+          g.Cq[row * g.ldcq + col] = f2e4m3(gelu(v + bias) * g.qinv);
         } else {
           const float d = v * gelu_grad(g.Z[row * g.ldz + col]);
           if (g.Cb) g.Cb[row * g.ldcb + col] = f2bf(d);
@@ -189,12 +217,15 @@ __global__ __launch_bounds__(WM *WN * 64) void k_gemm(GemmArgs g) {
 template <int WM, int WN, int TM, int TN>
 chem_status gemm_cfg(const GemmArgs &g, bool AK, bool BK, int epi, hipStream_t s) {
   constexpr int BM = WM * TM * 32, BN = WN * TN * 32;
-  dim3 grid((unsigned)((g.M + BM - 1) / BM), (unsigned)((g.N + BN - 1) / BN));
+  const long total = (long)((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
+  dim3 grid((unsigned)(((total + 7) / 8) * 8));
   dim3 block(WM * WN * 64);
   if (AK && BK && epi == EPI_GELU)
     hipLaunchKernelGGL((k_gemm<WM, WN, TM, TN, true, true, EPI_GELU>), grid, block, 0, s, g);
   else if (AK && BK && epi == EPI_F32)
     hipLaunchKernelGGL((k_gemm<WM, WN, TM, TN, true, true, EPI_F32>), grid, block, 0, s, g);
+  else if (AK && BK && epi == EPI_GELU_Q8)
+    hipLaunchKernelGGL((k_gemm<WM, WN, TM, TN, true, true, EPI_GELU_Q8>), grid, block, 0, s, g);
   else if (AK && !BK && epi == EPI_GELUGRAD)
     hipLaunchKernelGGL((k_gemm<WM, WN, TM, TN, true, false, EPI_GELUGRAD>), grid, block, 0, s,
                        g);
@@ -206,6 +237,151 @@ chem_status gemm_cfg(const GemmArgs &g, bool AK, bool BK, int epi, hipStream_t s
   }
   CHEM_HIP(hipGetLastError());
   return CHEM_OK;
+}
+
+// ------------------------------------------------------------ FP8 GEMM
+// E4M3 operands with v_mfma_scale_f32_32x32x64_f8f6f4 (block scales fixed at
+// 2^0), FP32 accumulation; the per-tensor scales multiply the accumulator in
+// the epilogue.  K-step 64; same tiling, staging and XCD-aware block order as
+// the BF16 kernel.  Fragment layout: lane l holds row l % 32 and the 32
+// consecutive k values 32 (l / 32) .. 32 (l / 32) + 31.
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+
+template <int WM, int WN, int TM, int TN, int EPI>
+__global__ __launch_bounds__(WM *WN * 64) void k_gemm8(GemmArgs g) {
+  constexpr int BM = WM * TM * 32, BN = WN * TN * 32, BK = 64, LK = BK + 16;
+  constexpr int NT = WM * WN * 64;
+  __shared__ __attribute__((aligned(16))) uint8_t As[2][BM * LK];
+  __shared__ __attribute__((aligned(16))) uint8_t Bs[2][BN * LK];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave % WM, wn = wave / WM;
+  const int ntn = (g.N + BN - 1) / BN;
+  const int ntm = (g.M + BM - 1) / BM;
+  const int total = ntn * ntm;
+  const int per_xcd = (total + 7) / 8;
+  const int logical = (int)(blockIdx.x % 8) * per_xcd + (int)(blockIdx.x / 8);
+  if (logical >= total) return;
+  const long m0 = (long)(logical / ntn) * BM, n0 = (long)(logical % ntn) * BN;
+  constexpr int ACH = BM * BK / 16, BCH = BN * BK / 16;
+  constexpr int APT = (ACH + NT - 1) / NT, BPT = (BCH + NT - 1) / NT;
+  uint4 ra[APT], rb[BPT];
+  f32x16 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < APT; ++i) {
+      const int c = tid + i * NT;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (c < ACH) {
+        const int r = c / (BK / 16), kc = (c % (BK / 16)) * 16;
+        if (m0 + r < g.M) v = *(const uint4 *)(g.A8 + (m0 + r) * g.lda + k0 + kc);
+      }
+      ra[i] = v;
+    }
+#pragma unroll
+    for (int i = 0; i < BPT; ++i) {
+      const int c = tid + i * NT;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (c < BCH) {
+        const int r = c / (BK / 16), kc = (c % (BK / 16)) * 16;
+        if (n0 + r < g.N) v = *(const uint4 *)(g.B8 + (n0 + r) * g.ldb + k0 + kc);
+      }
+      rb[i] = v;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < APT; ++i) {
+      const int c = tid + i * NT;
+      if (c < ACH) {
+        const int r = c / (BK / 16), kc = (c % (BK / 16)) * 16;
+        *(uint4 *)&As[buf][r * LK + kc] = ra[i];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < BPT; ++i) {
+      const int c = tid + i * NT;
+      if (c < BCH) {
+        const int r = c / (BK / 16), kc = (c % (BK / 16)) * 16;
+        *(uint4 *)&Bs[buf][r * LK + kc] = rb[i];
+      }
+    }
+  };
+  auto compute = [&](int buf) {
+    i32x8 a[TM], b[TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+      a[i] = *(const i32x8 *)&As[buf][(wm * TM * 32 + i * 32 + (lane & 31)) * LK +
+                                      32 * (lane >> 5)];
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+      b[j] = *(const i32x8 *)&Bs[buf][(wn * TN * 32 + j * 32 + (lane & 31)) * LK +
+                                      32 * (lane >> 5)];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a[i], b[j], acc[i][j], 0, 0,
+                                                                     0, 127, 0, 127);
+  };
+  const int nk = g.K / BK;
+  load(0);
+  store(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < nk) load((kt + 1) * BK);
+    compute(cur);
+    if (kt + 1 < nk) store(cur ^ 1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const long col = n0 + wn * TN * 32 + j * 32 + (lane & 31);
+      if (col >= g.N) continue;
+      const float bias = g.bias ? g.bias[col] : 0.0f;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const long row = m0 + wm * TM * 32 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        if (row >= g.M) continue;
+        const float h = gelu(acc[i][j][r] * g.scale + bias);
+        if (EPI == EPI_GELU_Q8) g.Cq[row * g.ldcq + col] = f2e4m3(h * g.qinv);
+        else g.Cb[row * g.ldcb + col] = f2bf(h);
+      }
+    }
+}
+
+__global__ void k_amax(int64_t n, const void *x, int bf16, float *part) {
+  __shared__ float red[256];
+  float m = 0.0f;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const float v = bf16 ? __uint_as_float((unsigned)((const u16 *)x)[i] << 16)
+                         : ((const float *)x)[i];
+    m = fmaxf(m, fabsf(v));
+  }
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + off]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void k_quant(const float *src, long ld_src, int rows, int cols, uint8_t *dst,
+                        int rows_p, int cols_p, float qinv) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)rows_p * cols_p) return;
+  const int r = (int)(i / cols_p), c = (int)(i % cols_p);
+  dst[i] = (r < rows && c < cols) ? f2e4m3(src[(int64_t)r * ld_src + c] * qinv) : (uint8_t)0;
 }
 
 // ------------------------------------------------------------- prologue
@@ -316,13 +492,6 @@ __global__ void k_to_bf16(int64_t n, const float *src, u16 *dst) {
 
 // ----------------------------------------------------------------- post
 
-// Mass fraction k of the network's new state (before projection):
-// Y' = Y0 + sd u + mu, de-normalised in FP32, added in FP64.
-__device__ __forceinline__ double ann_y(const PostArgs &a, int64_t i, int k, double y0) {
-  const float du = a.U[i * a.doutp + k] * a.nm.sd_out[k] + a.nm.mu_out[k];
-  return y0 + (double)du;
-}
-
 __device__ __forceinline__ void species_h_cp(const chem::DevMech &M, int k, double T, double &hRT,
                                              double &cpR) {
   const double *c = (T <= M.Tmid[k]) ? M.nasa_lo + 7 * k : M.nasa_hi + 7 * k;
@@ -333,107 +502,153 @@ __device__ __forceinline__ void species_h_cp(const chem::DevMech &M, int k, doub
 
 constexpr int EMAX = 8;
 
-__global__ void k_post(chem::DevMech M, PostArgs a) {
+// One thread per cell; the cell's mass fractions stay in registers (KP >= K
+// slots, EP >= E elements), so every pass reads global memory once.
+template <int KP, int EP>
+__global__ __launch_bounds__(128) void k_post(chem::DevMech M, PostArgs a) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
   const int K = M.K, E = M.E;
   const double T0 = a.T[i], p = a.p[i];
   uint8_t flag = (uint8_t)a.force_flag;
-
+  double y0[KP], yn[KP];
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    y0[k] = 0.0;
+    yn[k] = 0.0;
+    if (k < K) {
+      y0[k] = a.Y[(int64_t)k * a.ld + i];
+      const float du = a.U[i * a.doutp + k] * a.nm.sd_out[k] + a.nm.mu_out[k];
+      yn[k] = y0[k] + (double)du;  // Y' = Y0 + sd u + mu
+    }
+  }
   // out of distribution: any input feature outside the widened training range
   if (a.check_ood) {
-    for (int j = 0; j < a.n_in; ++j) {
-      float x;
-      if (j == 0) x = (float)T0;
-      else if (j == 1) x = (float)p;
-      else x = boxcox((float)a.Y[(int64_t)(j - 2) * a.ld + i], a.nm.lambda);
-      const float lo = a.nm.lo[j], hi = a.nm.hi[j], span = hi - lo;
-      const float tol = span > 0.0f ? a.ood_margin * span : 1e-6f * fmaxf(fabsf(hi), 1e-30f);
-      if (!(x >= lo - tol && x <= hi + tol)) flag |= 1;
-    }
-  }
-
-  // weighted least-squares projection onto M Y = M Y0, D = diag(Y' + 1e-10)
-  double A[EMAX][EMAX], r[EMAX], z0[EMAX];
-  for (int e = 0; e < E; ++e) {
-    r[e] = 0.0;
-    z0[e] = 0.0;
-    for (int f = 0; f < E; ++f) A[e][f] = 0.0;
-  }
-  double S0 = 0.0;
-  for (int k = 0; k < K; ++k) {
-    const double y0 = a.Y[(int64_t)k * a.ld + i];
-    const double yp = ann_y(a, i, k, y0);
-    const double d = fmax(yp, 0.0) + 1e-10;
-    S0 += y0 / M.W[k];
-    for (int e = 0; e < E; ++e) {
-      const double me = M.Mel[e * K + k];
-      r[e] += me * (y0 - yp);
-      z0[e] += me * y0;
-      for (int f = 0; f <= e; ++f) A[e][f] += me * d * M.Mel[f * K + k];
-    }
-  }
-  // Cholesky of the symmetric positive definite E x E matrix
-  double Lc[EMAX][EMAX], lam[EMAX];
-  bool ok = true;
-  for (int e = 0; e < E; ++e) {
-    for (int f = 0; f <= e; ++f) {
-      double s = A[e][f];
-      for (int q = 0; q < f; ++q) s -= Lc[e][q] * Lc[f][q];
-      if (e == f) {
-        if (!(s > 0.0)) ok = false;
-        Lc[e][e] = sqrt(fmax(s, 1e-300));
-      } else {
-        Lc[e][f] = s / Lc[f][f];
+#pragma unroll
+    for (int j = 0; j < KP + 2; ++j) {
+      if (j < K + 2) {
+        float x;
+        if (j == 0) x = (float)T0;
+        else if (j == 1) x = (float)p;
+        else x = boxcox((float)y0[j - 2], a.nm.lambda);
+        const float lo = a.nm.lo[j], hi = a.nm.hi[j], span = hi - lo;
+        const float tol = span > 0.0f ? a.ood_margin * span : 1e-6f * fmaxf(fabsf(hi), 1e-30f);
+        if (!(x >= lo - tol && x <= hi + tol)) flag |= 1;
       }
     }
   }
-  for (int e = 0; e < E; ++e) {
-    double s = r[e];
-    for (int q = 0; q < e; ++q) s -= Lc[e][q] * lam[q];
-    lam[e] = s / Lc[e][e];
+  // weighted least-squares projection onto M Y = M Y0, D = diag(max(Y',0) + 1e-10)
+  double A[EP][EP], r[EP], z0[EP];
+#pragma unroll
+  for (int e = 0; e < EP; ++e) {
+    r[e] = 0.0;
+    z0[e] = 0.0;
+#pragma unroll
+    for (int f = 0; f < EP; ++f) A[e][f] = 0.0;
   }
-  for (int e = E - 1; e >= 0; --e) {
-    double s = lam[e];
-    for (int q = e + 1; q < E; ++q) s -= Lc[q][e] * lam[q];
-    lam[e] = s / Lc[e][e];
+  double S0 = 0.0;
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    if (k < K) {
+      const double d = fmax(yn[k], 0.0) + 1e-10;
+      S0 += y0[k] * M.invW[k];
+#pragma unroll
+      for (int e = 0; e < EP; ++e) {
+        if (e < E) {
+          const double me = M.Mel[e * K + k];
+          r[e] += me * (y0[k] - yn[k]);
+          z0[e] += me * y0[k];
+#pragma unroll
+          for (int f = 0; f <= e; ++f) A[e][f] += me * d * M.Mel[f * K + k];
+        }
+      }
+    }
   }
-  // projected, clipped state; its element residual
-  double z1[EMAX];
-  for (int e = 0; e < E; ++e) z1[e] = 0.0;
-  for (int k = 0; k < K; ++k) {
-    const double y0 = a.Y[(int64_t)k * a.ld + i];
-    const double yp = ann_y(a, i, k, y0);
-    double corr = 0.0;
-    for (int e = 0; e < E; ++e) corr += M.Mel[e * K + k] * lam[e];
-    const double y = fmax(yp + (fmax(yp, 0.0) + 1e-10) * corr, 0.0);
-    for (int e = 0; e < E; ++e) z1[e] += M.Mel[e * K + k] * y;
+  double Lc[EP][EP], lam[EP];
+  bool ok = true;
+#pragma unroll
+  for (int e = 0; e < EP; ++e) {
+#pragma unroll
+    for (int f = 0; f <= e; ++f) {
+      if (e < E) {
+        double v = A[e][f];
+#pragma unroll
+        for (int q = 0; q < f; ++q) v -= Lc[e][q] * Lc[f][q];
+        if (e == f) {
+          if (!(v > 0.0)) ok = false;
+          Lc[e][e] = sqrt(fmax(v, 1e-300));
+        } else {
+          Lc[e][f] = v / Lc[f][f];
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < EP; ++e) {
+    lam[e] = 0.0;
+    if (e < E) {
+      double v = r[e];
+#pragma unroll
+      for (int q = 0; q < e; ++q) v -= Lc[e][q] * lam[q];
+      lam[e] = v / Lc[e][e];
+    }
+  }
+#pragma unroll
+  for (int e = EP - 1; e >= 0; --e) {
+    if (e < E) {
+      double v = lam[e];
+#pragma unroll
+      for (int q = e + 1; q < EP; ++q)
+        if (q < E) v -= Lc[q][e] * lam[q];
+      lam[e] = v / Lc[e][e];
+    }
+  }
+  // projected and clipped state, and its element residual
+  double z1[EP];
+#pragma unroll
+  for (int e = 0; e < EP; ++e) z1[e] = 0.0;
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    if (k < K) {
+      double corr = 0.0;
+#pragma unroll
+      for (int e = 0; e < EP; ++e)
+        if (e < E) corr += M.Mel[e * K + k] * lam[e];
+      const double y = fmax(yn[k] + (fmax(yn[k], 0.0) + 1e-10) * corr, 0.0);
+      yn[k] = y;
+#pragma unroll
+      for (int e = 0; e < EP; ++e)
+        if (e < E) z1[e] += M.Mel[e * K + k] * y;
+    }
   }
   double res = 0.0;
-  for (int e = 0; e < E; ++e) res = fmax(res, fabs(z1[e] - z0[e]));
+#pragma unroll
+  for (int e = 0; e < EP; ++e)
+    if (e < E) res = fmax(res, fabs(z1[e] - z0[e]));
   if (!ok || !(res <= (double)a.residual_tol)) flag |= 2;
 
   if (flag == 0) {
     // temperature from h(T, Y) = h(T0, Y0) by Newton in FP64
     double h0 = 0.0;
-    for (int k = 0; k < K; ++k) {
-      double hRT, cpR;
-      species_h_cp(M, k, T0, hRT, cpR);
-      h0 += a.Y[(int64_t)k * a.ld + i] * RG * T0 * hRT / M.W[k];
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+      if (k < K) {
+        double hRT, cpR;
+        species_h_cp(M, k, T0, hRT, cpR);
+        h0 += y0[k] * RG * T0 * hRT * M.invW[k];
+      }
     }
     double T = T0;
     for (int it = 0; it < 20; ++it) {
       double h = 0.0, cp = 0.0;
-      for (int k = 0; k < K; ++k) {
-        const double y0 = a.Y[(int64_t)k * a.ld + i];
-        const double yp = ann_y(a, i, k, y0);
-        double corr = 0.0;
-        for (int e = 0; e < E; ++e) corr += M.Mel[e * K + k] * lam[e];
-        const double y = fmax(yp + (fmax(yp, 0.0) + 1e-10) * corr, 0.0);
-        double hRT, cpR;
-        species_h_cp(M, k, T, hRT, cpR);
-        h += y * RG * T * hRT / M.W[k];
-        cp += y * RG * cpR / M.W[k];
+#pragma unroll
+      for (int k = 0; k < KP; ++k) {
+        if (k < K) {
+          double hRT, cpR;
+          species_h_cp(M, k, T, hRT, cpR);
+          h += yn[k] * RG * T * hRT * M.invW[k];
+          cp += yn[k] * RG * cpR * M.invW[k];
+        }
       }
       const double dT = (h - h0) / cp;
       T -= dT;
@@ -442,20 +657,22 @@ __global__ void k_post(chem::DevMech M, PostArgs a) {
     if (!isfinite(T) || !(T > 0.0)) flag |= 2;
     if (flag == 0) {
       const double rho0 = p / (RG * T0 * S0);
-      for (int k = 0; k < K; ++k) {
-        const double y0 = a.Y[(int64_t)k * a.ld + i];
-        const double yp = ann_y(a, i, k, y0);
-        double corr = 0.0;
-        for (int e = 0; e < E; ++e) corr += M.Mel[e * K + k] * lam[e];
-        const double y = fmax(yp + (fmax(yp, 0.0) + 1e-10) * corr, 0.0);
-        if (a.RR) a.RR[(int64_t)k * a.ld + i] = rho0 * (y - y0) / a.dt;
-        a.Y[(int64_t)k * a.ld + i] = y;
+      const double sc = rho0 / a.dt;
+#pragma unroll
+      for (int k = 0; k < KP; ++k) {
+        if (k < K) {
+          if (a.RR) a.RR[(int64_t)k * a.ld + i] = sc * (yn[k] - y0[k]);
+          a.Y[(int64_t)k * a.ld + i] = yn[k];
+        }
       }
       a.T[i] = T;
     }
   }
-  if (flag != 0 && a.RR)
-    for (int k = 0; k < K; ++k) a.RR[(int64_t)k * a.ld + i] = 0.0;
+  if (flag != 0 && a.RR) {
+#pragma unroll
+    for (int k = 0; k < KP; ++k)
+      if (k < K) a.RR[(int64_t)k * a.ld + i] = 0.0;
+  }
   if (a.flags) a.flags[i] = flag;
   if (flag != 0) {
     const unsigned long long slot = atomicAdd(a.fb_count, 1ull);
@@ -529,6 +746,43 @@ chem_status gemm(const GemmArgs &g, bool AK, bool BK, int epi, hipStream_t s,
   return gemm_cfg<2, 2, 2, 2>(g, AK, BK, epi, s);
 }
 
+chem_status gemm8(const GemmArgs &g, int epi, hipStream_t s, const char *label) {
+  if (g.M <= 0 || g.N <= 0) return CHEM_OK;
+  if (g.K % 64 != 0 || g.lda % 16 != 0 || g.ldb % 16 != 0) {
+    chem::set_error("gemm8: K and leading dimensions must be multiples of 64 / 16");
+    return CHEM_EINVAL;
+  }
+  chem::ProfScope prof(label, s);
+  constexpr int BM = 128, BN = 128;
+  const long total = (long)((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
+  dim3 grid((unsigned)(((total + 7) / 8) * 8)), block(256);
+  if (epi == EPI_GELU_Q8)
+    hipLaunchKernelGGL((k_gemm8<2, 2, 2, 2, EPI_GELU_Q8>), grid, block, 0, s, g);
+  else if (epi == EPI_GELU)
+    hipLaunchKernelGGL((k_gemm8<2, 2, 2, 2, EPI_GELU>), grid, block, 0, s, g);
+  else {
+    chem::set_error("gemm8: unsupported epilogue");
+    return CHEM_EUNSUPPORTED;
+  }
+  CHEM_HIP(hipGetLastError());
+  return CHEM_OK;
+}
+
+chem_status amax(int64_t n, const void *x, bool bf16, float *part, int nparts, hipStream_t s) {
+  hipLaunchKernelGGL(k_amax, dim3(nparts), dim3(256), 0, s, n, x, bf16 ? 1 : 0, part);
+  CHEM_HIP(hipGetLastError());
+  return CHEM_OK;
+}
+
+chem_status quant_e4m3(const float *src, long ld_src, int rows, int cols, uint8_t *dst,
+                       int rows_p, int cols_p, float qinv, hipStream_t s) {
+  const int64_t n = (int64_t)rows_p * cols_p;
+  hipLaunchKernelGGL(k_quant, dim3(nblk(n, 256)), dim3(256), 0, s, src, ld_src, rows, cols, dst,
+                     rows_p, cols_p, qinv);
+  CHEM_HIP(hipGetLastError());
+  return CHEM_OK;
+}
+
 chem_status features(const FeatArgs &a, hipStream_t s) {
   if (a.n <= 0) return CHEM_OK;
   chem::ProfScope prof("ann_features", s);
@@ -580,7 +834,15 @@ chem_status post(const chem::DevMech &M, const PostArgs &a, hipStream_t s) {
     return CHEM_EUNSUPPORTED;
   }
   chem::ProfScope prof("ann_post", s);
-  hipLaunchKernelGGL(k_post, dim3(nblk(a.n, 128)), dim3(128), 0, s, M, a);
+  const dim3 grid(nblk(a.n, 128)), block(128);
+  if (M.K <= 16 && M.E <= 4)
+    hipLaunchKernelGGL((k_post<16, 4>), grid, block, 0, s, M, a);
+  else if (M.K <= 32 && M.E <= 4)
+    hipLaunchKernelGGL((k_post<32, 4>), grid, block, 0, s, M, a);
+  else if (M.K <= 32)
+    hipLaunchKernelGGL((k_post<32, EMAX>), grid, block, 0, s, M, a);
+  else
+    hipLaunchKernelGGL((k_post<64, EMAX>), grid, block, 0, s, M, a);
   CHEM_HIP(hipGetLastError());
   return CHEM_OK;
 }

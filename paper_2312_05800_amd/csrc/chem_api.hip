@@ -5,6 +5,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
+#include <utility>
 #include <vector>
 
 #include "chem_internal.h"
@@ -185,6 +187,42 @@ extern "C" chem_status chem_mech_create(const chem_mech_desc *d, chem_mech **out
   for (int e = 0; e < E; ++e)
     for (int k = 0; k < K; ++k) Mel[(size_t)e * K + k] = d->comp[k * E + e] * d->awt[e] / d->W[k];
 
+  // thermo polynomials with the constant divisors folded in
+  std::vector<double> nh(7 * K), nhh(7 * K), ns(7 * K), nsh(7 * K);
+  for (int k = 0; k < K; ++k)
+    for (int r = 0; r < 2; ++r) {
+      const double *a = d->nasa + 17 * k + (r == 0 ? 3 : 10);
+      double *h = (r == 0 ? nh.data() : nhh.data()) + 7 * k;
+      double *e = (r == 0 ? ns.data() : nsh.data()) + 7 * k;
+      h[0] = a[0]; h[1] = a[1] / 2.0; h[2] = a[2] / 3.0; h[3] = a[3] / 4.0; h[4] = a[4] / 5.0;
+      h[5] = a[5]; h[6] = 0.0;
+      e[0] = a[0]; e[1] = a[1]; e[2] = a[2] / 2.0; e[3] = a[3] / 3.0; e[4] = a[4] / 4.0;
+      e[5] = a[6]; e[6] = 0.0;
+    }
+  // Jacobian pair lists: for species k, every (j, r) with r containing both
+  std::vector<int> poff(K + 1, 0), pcode;
+  for (int k = 0; k < K; ++k) {
+    std::vector<std::pair<long, int>> ent;
+    for (int e = off[k]; e < off[k + 1]; ++e) {
+      const int r = cr[e];
+      const int nuk = (int)cn[e];
+      for (int s2 = 0; s2 < 4; ++s2) {
+        const int j = d->rsp[4 * r + s2];
+        if (j < 0) continue;
+        const int code = r | (s2 << 16) | ((nuk + 8) << 20) | (j << 24);
+        ent.push_back({(long)j * 262144L + (long)r * 4 + s2, code});
+      }
+    }
+    std::sort(ent.begin(), ent.end());
+    for (auto &q : ent) pcode.push_back(q.second);
+    poff[k + 1] = (int)pcode.size();
+  }
+  if (pcode.empty()) pcode.push_back(0);
+  if (R >= 65536) {
+    set_error("chem_mech_create: at most 65535 reactions");
+    return CHEM_EUNSUPPORTED;
+  }
+
   Packer pk;
   size_t oW = pk.add(W.data(), K * 8), oiW = pk.add(invW.data(), K * 8),
          oTm = pk.add(Tmid.data(), K * 8), olo = pk.add(lo.data(), 7 * K * 8),
@@ -193,7 +231,10 @@ extern "C" chem_status chem_mech_create(const chem_mech_desc *d, chem_mech **out
          odn = pk.add(dn.data(), R * 8), osp = pk.add(sp4.data(), R * sizeof(int4)),
          onu = pk.add(nu4.data(), R * sizeof(int4)), ooff = pk.add(off.data(), (K + 1) * 4),
          ocr = pk.add(cr.data(), cr.size() * 4), ocs = pk.add(cs.data(), cs.size() * 4),
-         ocn = pk.add(cn.data(), cn.size() * 8), oM = pk.add(Mel.data(), Mel.size() * 8);
+         ocn = pk.add(cn.data(), cn.size() * 8), oM = pk.add(Mel.data(), Mel.size() * 8),
+         onh = pk.add(nh.data(), nh.size() * 8), onhh = pk.add(nhh.data(), nhh.size() * 8),
+         ons = pk.add(ns.data(), ns.size() * 8), onsh = pk.add(nsh.data(), nsh.size() * 8),
+         opo = pk.add(poff.data(), poff.size() * 4), opc = pk.add(pcode.data(), pcode.size() * 4);
 
   chem_mech *m = new chem_mech();
   m->K = K;
@@ -243,12 +284,19 @@ extern "C" chem_status chem_mech_create(const chem_mech_desc *d, chem_mech **out
   dm.csr_slot = (const int *)(base + ocs);
   dm.csr_nu = (const double *)(base + ocn);
   dm.Mel = (const double *)(base + oM);
+  dm.nasa_h = (const double *)(base + onh);
+  dm.nasa_hh = (const double *)(base + onhh);
+  dm.nasa_s = (const double *)(base + ons);
+  dm.nasa_sh = (const double *)(base + onsh);
+  dm.pair_off = (const int *)(base + opo);
+  dm.pair_code = (const int *)(base + opc);
   *out = m;
   return CHEM_OK;
 }
 
 extern "C" void chem_mech_destroy(chem_mech *m) {
   if (!m) return;
+  if (m->set_buf) (void)hipFree(m->set_buf);
   (void)hipFree(m->blob);
   (void)hipFree(m->counters);
   delete m;
@@ -305,4 +353,59 @@ extern "C" chem_status chem_step(const chem_mech *m, chem_batch batch, double dt
   }
   return launch_step(m, batch.n, batch.ld, dt, dt_cell, T, p, Y, RR, h_hint, stats, o, nullptr,
                      (hipStream_t)stream);
+}
+
+extern "C" chem_status chem_step_sets(const chem_mech *m, int32_t n_sets, const chem_set *sets,
+                                      const chem_step_opts *opts, void *stream) {
+  if (!m || n_sets < 0 || (n_sets > 0 && !sets)) {
+    set_error("chem_step_sets: null mechanism or set table");
+    return CHEM_EINVAL;
+  }
+  if (n_sets > (1 << 20)) {
+    set_error("chem_step_sets: at most 2^20 sets");
+    return CHEM_EINVAL;
+  }
+  StepOpts o = resolve_opts(opts);
+  if (!(o.rtol > 0.0) || !(o.atol_Y >= 0.0) || !(o.atol_T >= 0.0) || !(o.h0 > 0.0) ||
+      !(o.h_min >= 0.0) || o.max_steps < 1) {
+    set_error("chem_step_sets: invalid options");
+    return CHEM_EINVAL;
+  }
+  std::vector<int64_t> off(n_sets + 1, 0);
+  for (int s = 0; s < n_sets; ++s) {
+    const chem_set &c = sets[s];
+    if (c.n < 0 || c.ld < c.n || (c.n > 0 && (!c.T || !c.p || !c.Y)) ||
+        (c.n > 0 && !(c.dt > 0.0 && isfinite(c.dt)))) {
+      set_error("chem_step_sets: set %d has bad sizes, null arrays or dt", s);
+      return CHEM_EINVAL;
+    }
+    off[s + 1] = off[s] + c.n;
+  }
+  const int64_t total = off[n_sets];
+  if (total == 0) return CHEM_OK;
+  const size_t tb = (size_t)n_sets * sizeof(chem_set);
+  const size_t need = ((tb + 255) & ~size_t(255)) + off.size() * 8;
+  chem_mech *mm = const_cast<chem_mech *>(m);
+  if (mm->set_cap < need) {
+    if (mm->set_buf) (void)hipFree(mm->set_buf);
+    mm->set_buf = nullptr;
+    mm->set_cap = 0;
+    if (hipMalloc(&mm->set_buf, need) != hipSuccess) {
+      set_error("chem_step_sets: cannot allocate the set table");
+      return CHEM_ENOMEM;
+    }
+    mm->set_cap = need;
+  }
+  std::vector<unsigned char> host(need);
+  memcpy(host.data(), sets, tb);
+  memcpy(host.data() + ((tb + 255) & ~size_t(255)), off.data(), off.size() * 8);
+  hipStream_t st = (hipStream_t)stream;
+  CHEM_HIP(hipMemcpyAsync(mm->set_buf, host.data(), need, hipMemcpyHostToDevice, st));
+  // the pageable source must stay valid until the copy has been staged
+  CHEM_HIP(hipStreamSynchronize(st));
+  const chem_set *dsets = (const chem_set *)mm->set_buf;
+  const int64_t *doff =
+      (const int64_t *)((unsigned char *)mm->set_buf + ((tb + 255) & ~size_t(255)));
+  return launch_step(m, total, 0, 0.0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                     nullptr, o, nullptr, st, nullptr, nullptr, dsets, doff, n_sets);
 }

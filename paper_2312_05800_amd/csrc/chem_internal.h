@@ -29,7 +29,19 @@ struct DevMech {
   const int *csr_slot;    // [nnz]   its slot in that reaction,
   const double *csr_nu;   // [nnz]   and its signed net coefficient
   const double *Mel;      // [E][K] element mass per unit mass fraction, A_e a_ek / W_k
+  const double *nasa_h;   // [K][7] low-range h/RT polynomial: a1, a2/2, a3/3, a4/4, a5/5, a6, 0
+  const double *nasa_hh;  // [K][7] same for the high range
+  const double *nasa_s;   // [K][7] low-range s/R: a1, a2, a3/2, a4/3, a5/4, a7, 0
+  const double *nasa_sh;  // [K][7] same for the high range
+  const int *pair_off;    // [K+1] per species k: entries (species j, reaction r, slot of j,
+  const int *pair_code;   //   net coefficient of k) for every r containing k and every j
+                          //   in r, sorted by (j, r); code = r | slot<<16 | (nu+8)<<20 | j<<24
 };
+
+__host__ __device__ inline int pair_r(int c) { return c & 0xffff; }
+__host__ __device__ inline int pair_slot(int c) { return (c >> 16) & 0xf; }
+__host__ __device__ inline double pair_nu(int c) { return (double)(((c >> 20) & 0xf) - 8); }
+__host__ __device__ inline int pair_j(int c) { return (c >> 24) & 0x7f; }
 
 struct StepOpts {
   double rtol, atol_Y, atol_T, h0, h_min;
@@ -42,6 +54,8 @@ struct chem_mech {
   chem::DevMech d;
   void *blob;                      // device allocation behind d
   unsigned long long *counters;    // device work-queue counters
+  void *set_buf = nullptr;         // device copy of the last chem_step_sets table
+  size_t set_cap = 0;
   int device;
   int K, R, E;
 };
@@ -83,6 +97,8 @@ chem_status launch_step(const chem_mech *m, int64_t n, int64_t ld, double dt,
                         const double *dt_cell, double *T, const double *p, double *Y,
                         double *RR, double *h_hint, int32_t *stats, const StepOpts &o,
                         const int32_t *index, hipStream_t s,
-                        const unsigned long long *n_dev = nullptr, uint8_t *flags = nullptr);
+                        const unsigned long long *n_dev = nullptr, uint8_t *flags = nullptr,
+                        const chem_set *sets = nullptr, const int64_t *set_off = nullptr,
+                        int n_sets = 0);
 
 }  // namespace chem

@@ -19,6 +19,7 @@
 // not hold up the lanes of cheap ones.  The wave ends when the counter runs
 // past the last cell; every group reaches that exit.
 #include <math.h>
+#include <stdlib.h>
 
 #include "chem_internal.h"
 
@@ -37,6 +38,18 @@ constexpr double TC[4][4] = {{0, 0, 0, 0}, {4.0, 0, 0, 0}, {1.0, -1.0, 0, 0},
 constexpr bool TNEWF[4] = {true, false, true, true};
 constexpr double TM[4] = {2.0, 0.0, 1.0, 1.0};
 constexpr double TE[4] = {0.0, 0.0, 0.0, 1.0};
+
+// Tableau entries for a run-time stage index (selects, no memory access).
+__device__ __forceinline__ double TA_S(int s, int j) {
+  return s == 2 ? (j == 0 ? TA[2][0] : (j == 1 ? TA[2][1] : TA[2][2]))
+       : (s == 3 ? (j == 0 ? TA[3][0] : (j == 1 ? TA[3][1] : TA[3][2])) : 0.0);
+}
+__device__ __forceinline__ double TC_S(int s, int j) {
+  return s == 1 ? (j == 0 ? TC[1][0] : 0.0)
+       : (s == 2 ? (j == 0 ? TC[2][0] : (j == 1 ? TC[2][1] : 0.0))
+                 : (s == 3 ? (j == 0 ? TC[3][0] : (j == 1 ? TC[3][1] : TC[3][2])) : 0.0));
+}
+__device__ __forceinline__ bool TNEWF_S(int s) { return s == 2 || s == 3; }
 
 enum { CELL_OK = 0, CELL_MAX_STEPS = 1, CELL_H_UNDERFLOW = 2, CELL_NONFINITE = 3,
        CELL_SINGULAR = 4 };
@@ -65,24 +78,23 @@ __device__ __forceinline__ bool grp_any(bool b) {
   return v != 0;
 }
 
-// Per-group LDS scratch (doubles).
+// Per-group LDS scratch (doubles): concentrations, h/RT and g/RT of the
+// species, rates of progress, and the Jacobian / Newton matrix (n rows of
+// stride G + 1).  In chem_rates the matrix region holds k_f, k_r instead.
 template <int G>
 struct GLds {
-  double *C, *hs, *gs, *qs, *dHs, *kfs, *krs, *dqdTs, *J;
+  double *C, *hs, *gs, *qs, *J;
   __device__ GLds(double *base, int R) {
     C = base;
     hs = C + G;
     gs = hs + G;
     qs = gs + G;
-    dHs = qs + R;
-    kfs = dHs + R;
-    krs = kfs + R;
-    dqdTs = krs + R;
-    J = dqdTs + R;
+    J = qs + R;
   }
   static constexpr int JS = G + 1;  // row stride of J (odd, spreads banks)
   __host__ __device__ static size_t doubles(int R) {
-    return 3 * G + 5 * (size_t)R + (size_t)G * JS;
+    const size_t j = (size_t)G * JS, k = 2 * (size_t)R;
+    return 3 * G + (size_t)R + (j > k ? j : k);
   }
 };
 
@@ -92,34 +104,67 @@ __device__ __forceinline__ double slot_fac(int s, int nu, const double *C) {
   return nu == 2 ? c * c : c;
 }
 
+// Rate constants and one-way rates of progress of reaction r from the
+// species data in LDS: ln k_f = ln A + b ln T - E_a/(R T),
+// ln K_c = -dG/RT + dn ln(p_ref/RT), k_r = exp(ln k_f - ln K_c).
+struct Rxn {
+  int4 sp, nu;
+  double kf, kr, fwd, rev, dH, dn;
+};
+
+template <int G>
+__device__ __forceinline__ Rxn rxn_eval(const DevMech &M, const GLds<G> &L, int r, double lnT,
+                                        double invT, double lnPRT) {
+  Rxn x;
+  x.sp = M.sp[r];
+  x.nu = M.nu[r];
+  double dG = 0.0, dH = 0.0;
+  if (x.sp.x >= 0) { dG -= x.nu.x * L.gs[x.sp.x]; dH -= x.nu.x * L.hs[x.sp.x]; }
+  if (x.sp.y >= 0) { dG -= x.nu.y * L.gs[x.sp.y]; dH -= x.nu.y * L.hs[x.sp.y]; }
+  if (x.sp.z >= 0) { dG += x.nu.z * L.gs[x.sp.z]; dH += x.nu.z * L.hs[x.sp.z]; }
+  if (x.sp.w >= 0) { dG += x.nu.w * L.gs[x.sp.w]; dH += x.nu.w * L.hs[x.sp.w]; }
+  x.dH = dH;
+  x.dn = M.dn[r];
+  const double lnkf = M.lnA[r] + M.b[r] * lnT - M.EaR[r] * invT;
+  const double lnKc = -dG + x.dn * lnPRT;
+  x.kf = exp(lnkf);
+  x.kr = exp(lnkf - lnKc);
+  x.fwd = x.kf * slot_fac(x.sp.x, x.nu.x, L.C) * slot_fac(x.sp.y, x.nu.y, L.C);
+  x.rev = x.kr * slot_fac(x.sp.z, x.nu.z, L.C) * slot_fac(x.sp.w, x.nu.w, L.C);
+  return x;
+}
+
 // Right-hand side (and optionally the Jacobian) of one cell.  Lane l holds
 // y_l in yl.  On return lane l holds f_l; species lanes hold wdot_k in wdl.
-// With JAC, lane l < n holds row l of M = I*dg - J in m[0..G-1]; lanes >= n
-// hold identity rows.  With KOUT the rate constants stay in L.kfs / L.krs.
+// With JAC, LDS row l (l < n) of L.J holds row l of M = I*dg - J.  With KOUT
+// the rate constants are left in L.J (k_f at [r], k_r at [R + r]).
 template <int G, bool JAC, bool KOUT>
 __device__ __forceinline__ void eval_cell(const DevMech &M, const GLds<G> &L, int l, double p,
-                                          double yl, double &f, double &wdl, double (&m)[G],
-                                          double dg) {
+                                          double yl, double &f, double &wdl, double dg) {
   const int K = M.K, R = M.R, n = M.n;
   const double T = __shfl(yl, 0, G);
-  const double lnT = log(T);
+  const double lnT = log(T), invT = 1.0 / T;
   const bool isSp = (l >= 1) && (l <= K);
   const int k = isSp ? l - 1 : 0;
-  double cpR = 0.0, hRT = 0.0, sR = 0.0, dcpR = 0.0, Wk = 1.0, Yk = 0.0;
+  double cpR = 0.0, hRT = 0.0, sR = 0.0, dcpR = 0.0, Wk = 1.0, iWk = 1.0, Yk = 0.0;
   if (isSp) {
     Wk = M.W[k];
+    iWk = M.invW[k];
     Yk = yl;
-    const double *a = (T <= M.Tmid[k]) ? M.nasa_lo + 7 * k : M.nasa_hi + 7 * k;
-    const double T2 = T * T, T3 = T2 * T, T4 = T3 * T;
-    cpR = a[0] + a[1] * T + a[2] * T2 + a[3] * T3 + a[4] * T4;
-    hRT = a[0] + a[1] * T / 2.0 + a[2] * T2 / 3.0 + a[3] * T3 / 4.0 + a[4] * T4 / 5.0 + a[5] / T;
-    sR = a[0] * lnT + a[1] * T + a[2] * T2 / 2.0 + a[3] * T3 / 3.0 + a[4] * T4 / 4.0 + a[6];
-    if (JAC) dcpR = a[1] + 2.0 * a[2] * T + 3.0 * a[3] * T2 + 4.0 * a[4] * T3;
+    const bool lo = T <= M.Tmid[k];
+    const double *a = (lo ? M.nasa_lo : M.nasa_hi) + 7 * k;
+    const double *hc = (lo ? M.nasa_h : M.nasa_hh) + 7 * k;
+    const double *sc = (lo ? M.nasa_s : M.nasa_sh) + 7 * k;
+    cpR = a[0] + T * (a[1] + T * (a[2] + T * (a[3] + T * a[4])));
+    hRT = hc[0] + T * (hc[1] + T * (hc[2] + T * (hc[3] + T * hc[4]))) + hc[5] * invT;
+    sR = sc[0] * lnT + T * (sc[1] + T * (sc[2] + T * (sc[3] + T * sc[4]))) + sc[5];
+    if (JAC) dcpR = a[1] + T * (2.0 * a[2] + T * (3.0 * a[3] + T * (4.0 * a[4])));
   }
-  const double S = grp_sum<G>(Yk / Wk);
+  const double S = grp_sum<G>(Yk * iWk);
   const double rho = p / (RG * T * S);
-  const double Ck = rho * Yk / Wk;
-  const double cp = grp_sum<G>(Yk * RG * cpR / Wk);
+  const double irho = 1.0 / rho;
+  const double Ck = rho * Yk * iWk;
+  const double cp = grp_sum<G>(Yk * RG * cpR * iWk);
   if (isSp) {
     L.C[k] = Ck;
     L.hs[k] = hRT;
@@ -130,32 +175,16 @@ __device__ __forceinline__ void eval_cell(const DevMech &M, const GLds<G> &L, in
   const double lnPRT = log(PREF / (RG * T));
   double sumHq = 0.0;
   for (int r = l; r < R; r += G) {
-    const int4 sp = M.sp[r];
-    const int4 nu = M.nu[r];
-    double dG = 0.0, dH = 0.0;
-    if (sp.x >= 0) { dG -= nu.x * L.gs[sp.x]; dH -= nu.x * L.hs[sp.x]; }
-    if (sp.y >= 0) { dG -= nu.y * L.gs[sp.y]; dH -= nu.y * L.hs[sp.y]; }
-    if (sp.z >= 0) { dG += nu.z * L.gs[sp.z]; dH += nu.z * L.hs[sp.z]; }
-    if (sp.w >= 0) { dG += nu.w * L.gs[sp.w]; dH += nu.w * L.hs[sp.w]; }
-    const double dn = M.dn[r];
-    const double lnkf = M.lnA[r] + M.b[r] * lnT - M.EaR[r] / T;
-    const double lnKc = -dG + dn * lnPRT;
-    const double kf = exp(lnkf);
-    const double kr = exp(lnkf - lnKc);
-    const double fwd = kf * slot_fac(sp.x, nu.x, L.C) * slot_fac(sp.y, nu.y, L.C);
-    const double rev = kr * slot_fac(sp.z, nu.z, L.C) * slot_fac(sp.w, nu.w, L.C);
-    L.qs[r] = fwd - rev;
-    if (JAC || KOUT) {
-      L.kfs[r] = kf;
-      L.krs[r] = kr;
+    const Rxn x = rxn_eval<G>(M, L, r, lnT, invT, lnPRT);
+    L.qs[r] = x.fwd - x.rev;
+    if (KOUT) {
+      L.J[r] = x.kf;
+      L.J[R + r] = x.kr;
     }
     if (JAC) {
-      const double dlnkf = M.b[r] / T + M.EaR[r] / (T * T);
-      const double dlnKc = dH / T - dn / T;
-      const double dqdT = fwd * dlnkf - rev * (dlnkf - dlnKc);
-      L.dqdTs[r] = dqdT;
-      L.dHs[r] = dH;
-      sumHq += RG * T * dH * dqdT;
+      const double dlnkf = M.b[r] * invT + M.EaR[r] * invT * invT;
+      const double dlnKc = (x.dH - x.dn) * invT;
+      sumHq += RG * T * x.dH * (x.fwd * dlnkf - x.rev * (dlnkf - dlnKc));
     }
   }
   wave_sync();
@@ -167,12 +196,12 @@ __device__ __forceinline__ void eval_cell(const DevMech &M, const GLds<G> &L, in
   }
   wdl = wd;
   const double Q = grp_sum<G>(isSp ? RG * T * hRT * wd : 0.0);
-  const double fT = -Q / (rho * cp);
-  f = (l == 0) ? fT : (isSp ? Wk * wd / rho : 0.0);
+  const double fT = -Q * irho / cp;
+  f = (l == 0) ? fT : (isSp ? Wk * wd * irho : 0.0);
   if (!JAC) return;
 
   // ---- analytic Jacobian ----
-  const double dcpdT = grp_sum<G>(Yk * RG * dcpR / Wk);
+  const double dcpdT = grp_sum<G>(Yk * RG * dcpR * iWk);
   const double sumCpW = grp_sum<G>(isSp ? RG * cpR * wd : 0.0);
   const double sumHqT = grp_sum<G>(sumHq);
   double *Jrow = L.J + l * GLds<G>::JS;
@@ -181,55 +210,100 @@ __device__ __forceinline__ void eval_cell(const DevMech &M, const GLds<G> &L, in
   wave_sync();
   double dwdTC = 0.0, JwT = 0.0;
   if (isSp) {
-    // row k of d wdot / d C (scattered into LDS row l) and sum_r dH_r dq_r/dC_k
+    // row k of d wdot / d C, scattered into LDS row l, and sum_r dH_r dq_r/dC_k;
+    // each species lane evaluates the rate constants of its own reactions
     const int e1 = M.csr_off[k + 1];
     for (int e = M.csr_off[k]; e < e1; ++e) {
       const int r = M.csr_r[e];
       const double nuk = M.csr_nu[e];
       const int slot = M.csr_slot[e];
-      const int4 sp = M.sp[r];
-      const int4 nu = M.nu[r];
-      const double kf = L.kfs[r], kr = L.krs[r];
-      const double f0 = slot_fac(sp.x, nu.x, L.C), f1 = slot_fac(sp.y, nu.y, L.C);
-      const double f2 = slot_fac(sp.z, nu.z, L.C), f3 = slot_fac(sp.w, nu.w, L.C);
+      const Rxn x = rxn_eval<G>(M, L, r, lnT, invT, lnPRT);
+      const double f0 = slot_fac(x.sp.x, x.nu.x, L.C), f1 = slot_fac(x.sp.y, x.nu.y, L.C);
+      const double f2 = slot_fac(x.sp.z, x.nu.z, L.C), f3 = slot_fac(x.sp.w, x.nu.w, L.C);
       double dq0 = 0.0, dq1 = 0.0, dq2 = 0.0, dq3 = 0.0;
-      if (sp.x >= 0) dq0 = kf * (nu.x == 2 ? 2.0 * L.C[sp.x] : 1.0) * f1;
-      if (sp.y >= 0) dq1 = kf * f0 * (nu.y == 2 ? 2.0 * L.C[sp.y] : 1.0);
-      if (sp.z >= 0) dq2 = -kr * (nu.z == 2 ? 2.0 * L.C[sp.z] : 1.0) * f3;
-      if (sp.w >= 0) dq3 = -kr * f2 * (nu.w == 2 ? 2.0 * L.C[sp.w] : 1.0);
-      if (sp.x >= 0) Jrow[1 + sp.x] += nuk * dq0;
-      if (sp.y >= 0) Jrow[1 + sp.y] += nuk * dq1;
-      if (sp.z >= 0) Jrow[1 + sp.z] += nuk * dq2;
-      if (sp.w >= 0) Jrow[1 + sp.w] += nuk * dq3;
-      dwdTC += nuk * L.dqdTs[r];
+      if (x.sp.x >= 0) dq0 = x.kf * (x.nu.x == 2 ? 2.0 * L.C[x.sp.x] : 1.0) * f1;
+      if (x.sp.y >= 0) dq1 = x.kf * f0 * (x.nu.y == 2 ? 2.0 * L.C[x.sp.y] : 1.0);
+      if (x.sp.z >= 0) dq2 = -x.kr * (x.nu.z == 2 ? 2.0 * L.C[x.sp.z] : 1.0) * f3;
+      if (x.sp.w >= 0) dq3 = -x.kr * f2 * (x.nu.w == 2 ? 2.0 * L.C[x.sp.w] : 1.0);
+      if (x.sp.x >= 0) Jrow[1 + x.sp.x] += nuk * dq0;
+      if (x.sp.y >= 0) Jrow[1 + x.sp.y] += nuk * dq1;
+      if (x.sp.z >= 0) Jrow[1 + x.sp.z] += nuk * dq2;
+      if (x.sp.w >= 0) Jrow[1 + x.sp.w] += nuk * dq3;
+      // dq/dT at fixed C: d ln kf/dT = b/T + Ea/(R T^2), d ln Kc/dT = dH_r/(R T^2) - dn/T
+      const double dlnkf = M.b[r] * invT + M.EaR[r] * invT * invT;
+      const double dlnKc = (x.dH - x.dn) * invT;
+      dwdTC += nuk * (x.fwd * dlnkf - x.rev * (dlnkf - dlnKc));
       const double dqk = slot == 0 ? dq0 : (slot == 1 ? dq1 : (slot == 2 ? dq2 : dq3));
-      JwT += RG * T * L.dHs[r] * dqk;
+      JwT += RG * T * x.dH * dqk;
     }
   }
   double a = 0.0;
   if (isSp)
     for (int j = 0; j < K; ++j) a += Jrow[1 + j] * L.C[j];
   const double aT = grp_sum<G>(isSp ? JwT * Ck : 0.0);
+  const double irhocp = irho / cp;
   if (isSp) {
     // chain rule through C_j(rho(T, Y), Y): dC_j/dY_i = rho d_ij/W_j - C_j/(S W_i), dC_j/dT = -C_j/T
-    for (int i = 0; i < K; ++i) {
-      const double Wi = M.W[i];
-      Jrow[1 + i] = (Wk / rho) * ((rho * Jrow[1 + i] - a / S) / Wi) + Wk * wd / (rho * S * Wi);
-    }
-    Jrow[0] = (Wk / rho) * (dwdTC - a / T) + Wk * wd / (rho * T);
-    L.J[1 + k] = -((rho * JwT - aT / S) / Wk) / (rho * cp) -
-                 fT * (-1.0 / (S * Wk) + RG * cpR / (Wk * cp));
+    const double c2 = Wk * (wd - a) * irho / S;
+    for (int i = 0; i < K; ++i) Jrow[1 + i] = (Wk * Jrow[1 + i] + c2) * M.invW[i];
+    Jrow[0] = Wk * irho * (dwdTC + (wd - a) * invT);
+    L.J[1 + k] = -((rho * JwT - aT / S) * iWk) * irhocp - fT * (-iWk / S + RG * cpR * iWk / cp);
   }
-  if (l == 0)
-    L.J[0] = -(sumCpW + sumHqT - aT / T) / (rho * cp) - fT * (-1.0 / T + dcpdT / cp);
+  if (l == 0) L.J[0] = -(sumCpW + sumHqT - aT * invT) * irhocp - fT * (-invT + dcpdT / cp);
   wave_sync();
+  // the Newton matrix M = I/(gamma h) - J replaces J in place, row l by lane l
+  if (l < n)
+    for (int j = 0; j < n; ++j) Jrow[j] = ((j == l) ? dg : 0.0) - Jrow[j];
+  wave_sync();
+}
+
+// LU with partial pivoting of the n x n matrix held in LDS, row l owned by
+// lane l (stride JS).  Pivot of step k: the not-yet-eliminated row with the
+// largest |a_ik| (NaN counts as largest), ties to the lowest row.  Rows do not
+// move: lane l records the step at which it became pivot (mystep) and the
+// inverse of its diagonal; multipliers overwrite the eliminated entries.
+// Loops stay rolled (the matrix is addressed in LDS, not in registers), which
+// keeps the kernel inside the instruction cache.  Returns false for a zero or
+// non-finite pivot.
+template <int G>
+__device__ __forceinline__ bool lu_factor(double *A, int l, int n, int &mystep, double &invd) {
+  constexpr int JS = GLds<G>::JS;
+  double *row = A + l * JS;
+  bool done = (l >= n);
+  mystep = done ? l : -1;
+  invd = 1.0;
+  bool ok = true;
+  for (int k = 0; k < n; ++k) {
+    double v = done ? -1.0 : fabs(row[k]);
+    if (v != v) v = INFINITY;
+    int idx = l;
 #pragma unroll
-  for (int j = 0; j < G; ++j) {
-    double v = 0.0;
-    if (j < n && l < n) v = -Jrow[j];
-    m[j] = v + ((j == l) ? ((l < n) ? dg : 1.0) : 0.0);
+    for (int off = G / 2; off >= 1; off >>= 1) {
+      const double v2 = __shfl_xor(v, off, G);
+      const int i2 = __shfl_xor(idx, off, G);
+      if (v2 > v || (v2 == v && i2 < idx)) {
+        v = v2;
+        idx = i2;
+      }
+    }
+    const double *prow = A + idx * JS;
+    const double pv = prow[k];
+    if (!(fabs(pv) > 0.0) || !isfinite(pv)) ok = false;
+    const double inv = 1.0 / pv;
+    if (l == idx) {
+      done = true;
+      mystep = k;
+      invd = inv;
+    }
+    if (!done) {
+      const double mult = row[k] * inv;
+      row[k] = mult;
+#pragma unroll 4
+      for (int j = k + 1; j < n; ++j) row[j] = fma(-mult, prow[j], row[j]);
+    }
+    wave_sync();
   }
-  wave_sync();  // LDS J is reused by the next evaluation
+  return ok;
 }
 
 // Lane that holds pivot step k within the calling lane's group.
@@ -241,77 +315,23 @@ __device__ __forceinline__ int pivot_lane(int mystep, int k, int gbase) {
   return __ffsll((long long)gm) - 1;
 }
 
-// In-register LU with partial pivoting of the n x n matrix whose row l sits
-// in lane l (m[]).  Pivot of step k: the not-yet-eliminated row with the
-// largest |m_ik| (NaN counts as largest), ties to the lowest row.  Rows do not
-// move: lane l records the step at which it became pivot (mystep) and the
-// inverse of its diagonal.  Returns false for a zero or non-finite pivot.
+// Solve M x = b with the factors of lu_factor.  Lane l passes b_l, gets x_l.
 template <int G>
-__device__ __forceinline__ bool lu_factor(double (&m)[G], int l, int n, int &mystep,
-                                          double &invd) {
-  bool done = (l >= n);
-  mystep = done ? l : -1;
-  invd = 1.0;
-  bool ok = true;
-#pragma unroll
-  for (int k = 0; k < G; ++k) {
-    if (k < n) {
-      double v = done ? -1.0 : fabs(m[k]);
-      if (v != v) v = INFINITY;
-      int idx = l;
-#pragma unroll
-      for (int off = G / 2; off >= 1; off >>= 1) {
-        const double v2 = __shfl_xor(v, off, G);
-        const int i2 = __shfl_xor(idx, off, G);
-        if (v2 > v || (v2 == v && i2 < idx)) {
-          v = v2;
-          idx = i2;
-        }
-      }
-      const double pv = __shfl(m[k], idx, G);
-      if (!(fabs(pv) > 0.0) || !isfinite(pv)) ok = false;
-      const double inv = 1.0 / pv;
-      if (l == idx) {
-        done = true;
-        mystep = k;
-        invd = inv;
-      }
-      const bool upd = !done;
-      const double mult = m[k] * inv;
-      if (upd) m[k] = mult;
-#pragma unroll
-      for (int j = k + 1; j < G; ++j) {
-        if (j < n) {
-          const double pj = __shfl(m[j], idx, G);
-          if (upd) m[j] = fma(-mult, pj, m[j]);
-        }
-      }
-    }
-  }
-  return ok;
-}
-
-// Solve M x = b with the factors of lu_factor.  Lane l passes b_l and gets x_l.
-template <int G>
-__device__ __forceinline__ double lu_solve(const double (&m)[G], int l, int n, int mystep,
-                                           double invd, int gbase, double b) {
-#pragma unroll
-  for (int k = 0; k < G; ++k) {
-    if (k < n) {
-      const int src = pivot_lane<G>(mystep, k, gbase);
-      const double zk = __shfl(b, src, G);
-      if (mystep > k) b = fma(-m[k], zk, b);
-    }
+__device__ __forceinline__ double lu_solve(const double *A, int l, int n, int mystep, double invd,
+                                           int gbase, double b) {
+  constexpr int JS = GLds<G>::JS;
+  const double *row = A + l * JS;
+  for (int k = 0; k < n; ++k) {
+    const int src = pivot_lane<G>(mystep, k, gbase);
+    const double zk = __shfl(b, src, G);
+    if (mystep > k) b = fma(-row[k], zk, b);
   }
   double x = 0.0;
-#pragma unroll
-  for (int k = G - 1; k >= 0; --k) {
-    if (k < n) {
-      const int src = pivot_lane<G>(mystep, k, gbase);
-      const double xk = __shfl(b * invd, src, G);
-      if (mystep < k) b = fma(-m[k], xk, b);
-      if (l == k) x = xk;
-    }
+  for (int k = n - 1; k >= 0; --k) {
+    const int src = pivot_lane<G>(mystep, k, gbase);
+    const double xk = __shfl(b * invd, src, G);
+    if (mystep < k) b = fma(-row[k], xk, b);
+    if (l == k) x = xk;
   }
   return x;
 }
@@ -331,6 +351,21 @@ struct StepArgs {
   unsigned long long *counter;
   const unsigned long long *n_dev;  // optional device-side cell count (overrides n)
   uint8_t *flags;                    // optional: bit 4 set for cells that fail
+  const chem_set *sets;              // optional set table (device): queue index q is cell
+  const int64_t *set_off;            //   q - set_off[s] of the set s with set_off[s] <= q
+  int n_sets;
+};
+
+// Arrays of the cell a group is working on.
+struct CellRef {
+  double *T;
+  const double *p;
+  double *Y;
+  double *RR;
+  double *hh;
+  int32_t *stats;
+  int64_t ld, i;
+  double dt;
 };
 
 __global__ void k_reset_counter(unsigned long long *c) {
@@ -346,7 +381,6 @@ __global__ __launch_bounds__(64) void k_rates(DevMech M, int64_t N, int64_t ld, 
   const int lane = threadIdx.x;
   const int g = lane / G, l = lane % G;
   GLds<G> L(lds + g * GLds<G>::doubles(M.R), M.R);
-  double m[G];
   for (int64_t base = (int64_t)blockIdx.x * CPW; base < N; base += (int64_t)gridDim.x * CPW) {
     const int64_t cell = base + g;
     if (cell >= N) break;  // group-uniform
@@ -356,15 +390,15 @@ __global__ __launch_bounds__(64) void k_rates(DevMech M, int64_t N, int64_t ld, 
     const double pc = p[cell];
     double f, wd;
     if (kfkr)
-      eval_cell<G, false, true>(M, L, l, pc, yl, f, wd, m, 0.0);
+      eval_cell<G, false, true>(M, L, l, pc, yl, f, wd, 0.0);
     else
-      eval_cell<G, false, false>(M, L, l, pc, yl, f, wd, m, 0.0);
+      eval_cell<G, false, false>(M, L, l, pc, yl, f, wd, 0.0);
     if (l >= 1 && l <= M.K) wdot[(int64_t)(l - 1) * ld + cell] = wd;
     if (l == 0 && dTdt) dTdt[cell] = f;
     if (kfkr) {
       for (int r = l; r < M.R; r += G) {
-        kfkr[(int64_t)r * ld + cell] = L.kfs[r];
-        kfkr[(int64_t)(M.R + r) * ld + cell] = L.krs[r];
+        kfkr[(int64_t)r * ld + cell] = L.J[r];
+        kfkr[(int64_t)(M.R + r) * ld + cell] = L.J[M.R + r];
       }
     }
     wave_sync();
@@ -379,7 +413,6 @@ __global__ __launch_bounds__(64) void k_step(DevMech M, StepArgs A) {
   const int n = M.n;
   GLds<G> L(lds + g * GLds<G>::doubles(M.R), M.R);
   const StepOpts &o = A.o;
-  double m[G];
 
   // per-cell state (group-uniform scalars are replicated in every lane)
   int64_t cell = 0, gcell = 0;
@@ -388,6 +421,7 @@ __global__ __launch_bounds__(64) void k_step(DevMech M, StepArgs A) {
   int nacc = 0, nrej = 0, status = CELL_OK;
 
   const int64_t ncell = A.n_dev ? (int64_t)*A.n_dev : A.n;
+  CellRef cr{};
   auto fetch = [&]() {
     unsigned long long c = 0;
     if (l == 0) c = atomicAdd(A.counter, 1ull);
@@ -395,14 +429,29 @@ __global__ __launch_bounds__(64) void k_step(DevMech M, StepArgs A) {
     cell = (int64_t)c;
     active = cell < ncell;
     if (!active) return;
-    gcell = A.index ? (int64_t)A.index[cell] : cell;
+    if (A.n_sets > 0) {
+      int lo = 0, hi = A.n_sets;
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (A.set_off[mid] <= cell) lo = mid;
+        else hi = mid;
+      }
+      const chem_set &st = A.sets[lo];
+      cr = CellRef{st.T, st.p, st.Y, st.RR, st.h_hint, st.stats, st.ld, cell - A.set_off[lo],
+                   st.dt};
+    } else {
+      const int64_t gc = A.index ? (int64_t)A.index[cell] : cell;
+      cr = CellRef{A.T, A.p, A.Y, A.RR, A.h_hint, A.stats, A.ld, gc,
+                   A.dt_cell ? A.dt_cell[gc] : A.dt};
+    }
+    gcell = cr.i;
     yl = 0.0;
-    if (l == 0) yl = A.T[gcell];
-    else if (l < n) yl = A.Y[(int64_t)(l - 1) * A.ld + gcell];
+    if (l == 0) yl = cr.T[gcell];
+    else if (l < n) yl = cr.Y[(int64_t)(l - 1) * cr.ld + gcell];
     y0 = yl;
-    p = A.p[gcell];
-    dt = A.dt_cell ? A.dt_cell[gcell] : A.dt;
-    const double hh = A.h_hint ? A.h_hint[gcell] : 0.0;
+    p = cr.p[gcell];
+    dt = cr.dt;
+    const double hh = cr.hh ? cr.hh[gcell] : 0.0;
     h = (hh > 0.0) ? hh : o.h0;
     if (h > dt) h = dt;
     t = 0.0;
@@ -422,17 +471,17 @@ __global__ __launch_bounds__(64) void k_step(DevMech M, StepArgs A) {
   auto finish = [&]() {
     const bool ok = (status == CELL_OK);
     if (ok && l < n) {
-      if (l == 0) A.T[gcell] = yl;
-      else A.Y[(int64_t)(l - 1) * A.ld + gcell] = yl;
+      if (l == 0) cr.T[gcell] = yl;
+      else cr.Y[(int64_t)(l - 1) * cr.ld + gcell] = yl;
     }
-    if (A.RR && l >= 1 && l < n)
-      A.RR[(int64_t)(l - 1) * A.ld + gcell] = ok ? rho0 * (yl - y0) / dt : 0.0;
+    if (cr.RR && l >= 1 && l < n)
+      cr.RR[(int64_t)(l - 1) * cr.ld + gcell] = ok ? rho0 * (yl - y0) / dt : 0.0;
     if (l == 0) {
-      if (A.h_hint && ok) A.h_hint[gcell] = h;
-      if (A.stats) {
-        A.stats[gcell] = nacc;
-        A.stats[A.ld + gcell] = nrej;
-        A.stats[2 * A.ld + gcell] = status;
+      if (cr.hh && ok) cr.hh[gcell] = h;
+      if (cr.stats) {
+        cr.stats[gcell] = nacc;
+        cr.stats[cr.ld + gcell] = nrej;
+        cr.stats[2 * cr.ld + gcell] = status;
       }
       if (A.flags && !ok) A.flags[gcell] |= 4;
     }
@@ -462,34 +511,41 @@ __global__ __launch_bounds__(64) void k_step(DevMech M, StepArgs A) {
       if (!end) {
         // ---- one RODAS3 attempt of size h from yl ----
         double F, wd;
-        eval_cell<G, true, false>(M, L, l, p, yl, F, wd, m, 1.0 / (GAMMA * h));
+        eval_cell<G, true, false>(M, L, l, p, yl, F, wd, 1.0 / (GAMMA * h));
         int mystep;
         double invd;
-        const bool ok = lu_factor<G>(m, l, n, mystep, invd);
+        const bool ok = lu_factor<G>(L.J, l, n, mystep, invd);
         if (!ok) {
           status = CELL_SINGULAR;
           end = true;
         } else {
-          double Ks[4];
-#pragma unroll
+          // Stage loop kept rolled so that one copy of the right-hand side and
+          // of the triangular solve is emitted (the unrolled form overflows the
+          // instruction cache).  Terms with j >= s add exact zeros, so the
+          // sums equal the oracle's sums over j < s.
+          double K0 = 0.0, K1 = 0.0, K2 = 0.0, K3 = 0.0;
+#pragma nounroll
           for (int s = 0; s < 4; ++s) {
-            if (s > 0 && TNEWF[s]) {
-              double v = yl;
-#pragma unroll
-              for (int j = 0; j < s; ++j) v += TA[s][j] * Ks[j];
-              eval_cell<G, false, false>(M, L, l, p, v, F, wd, m, 0.0);
+            if (TNEWF_S(s)) {
+              const double v = yl + TA_S(s, 0) * K0 + TA_S(s, 1) * K1 + TA_S(s, 2) * K2;
+              eval_cell<G, false, false>(M, L, l, p, v, F, wd, 0.0);
             }
-            double c = 0.0;
-#pragma unroll
-            for (int j = 0; j < s; ++j) c += TC[s][j] * Ks[j];
-            Ks[s] = lu_solve<G>(m, l, n, mystep, invd, gbase, F + c / h);
+            const double c = TC_S(s, 0) * K0 + TC_S(s, 1) * K1 + TC_S(s, 2) * K2;
+            const double x = lu_solve<G>(L.J, l, n, mystep, invd, gbase, F + c / h);
+            K0 = (s == 0) ? x : K0;
+            K1 = (s == 1) ? x : K1;
+            K2 = (s == 2) ? x : K2;
+            K3 = (s == 3) ? x : K3;
           }
           double ynew = yl, errv = 0.0;
-#pragma unroll
-          for (int s = 0; s < 4; ++s) {
-            ynew += TM[s] * Ks[s];
-            errv += TE[s] * Ks[s];
-          }
+          ynew += TM[0] * K0;
+          errv += TE[0] * K0;
+          ynew += TM[1] * K1;
+          errv += TE[1] * K1;
+          ynew += TM[2] * K2;
+          errv += TE[2] * K2;
+          ynew += TM[3] * K3;
+          errv += TE[3] * K3;
           double r2 = 0.0;
           if (l < n) {
             const double atol = (l == 0) ? o.atol_T : o.atol_Y;
@@ -582,8 +638,10 @@ chem_status launch_rates(const chem_mech *m, int64_t N, int64_t ld, const double
 chem_status launch_step(const chem_mech *m, int64_t N, int64_t ld, double dt,
                         const double *dt_cell, double *T, const double *p, double *Y, double *RR,
                         double *h_hint, int32_t *stats, const StepOpts &o, const int32_t *index,
-                        hipStream_t s, const unsigned long long *n_dev, uint8_t *flags) {
-  StepArgs A{N, ld, dt, dt_cell, T, p, Y, RR, h_hint, stats, index, o, m->counters, n_dev, flags};
+                        hipStream_t s, const unsigned long long *n_dev, uint8_t *flags,
+                        const chem_set *sets, const int64_t *set_off, int n_sets) {
+  StepArgs A{N,       ld,    dt,          dt_cell, T,     p,    Y,       RR,     h_hint,
+             stats,   index, o,           m->counters, n_dev, flags, sets, set_off, n_sets};
   const int G = group_size(m->d.n);
   const int cpw = 64 / G;
   size_t sh = G == 16 ? lds_bytes<16>(m->R, cpw)
@@ -591,8 +649,13 @@ chem_status launch_step(const chem_mech *m, int64_t N, int64_t ld, double dt,
   int cus = 0;
   chem_status st = check_lds(sh, &cus);
   if (st != CHEM_OK) return st;
-  // persistent grid: enough single-wave blocks to fill every CU's LDS
+  // persistent grid: enough single-wave blocks to fill every CU's LDS, or the
+  // number of waves per CU given by CHEMSTEP_STEP_WAVES_PER_CU (tuning)
   int per_cu = (int)((160 * 1024) / (sh > 0 ? sh : 1));
+  if (const char *env = getenv("CHEMSTEP_STEP_WAVES_PER_CU")) {
+    const int v = atoi(env);
+    if (v > 0 && v < per_cu) per_cu = v;
+  }
   if (per_cu < 1) per_cu = 1;
   if (per_cu > 32) per_cu = 32;
   int64_t want = (N + cpw - 1) / cpw;  // with n_dev, N is an upper bound
@@ -600,7 +663,7 @@ chem_status launch_step(const chem_mech *m, int64_t N, int64_t ld, double dt,
   if (blocks > want) blocks = want;
   if (blocks < 1) return CHEM_OK;
   hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, m->counters);
-  ProfScope prof(index ? "chem_step_fallback" : "chem_step", s);
+  ProfScope prof(index ? "chem_step_fallback" : (sets ? "chem_step_sets" : "chem_step"), s);
   switch (G) {
     case 16:
       hipLaunchKernelGGL(k_step<16>, dim3((unsigned)blocks), dim3(64), sh, s, m->d, A);

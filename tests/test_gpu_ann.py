@@ -261,3 +261,42 @@ def test_training_reduces_loss(dev, mech, data):
         losses.append(loss.item())
     _say(f"  loss {losses[0]:.4f} -> {losses[-1]:.4f}")
     assert np.mean(losses[-10:]) < 0.6 * np.mean(losses[:5])
+
+
+def test_fp8_forward_parity(dev, mech, data):
+    """FP8 E4M3 hidden layers: the GPU's calibrated scales equal amax/448 of
+    the oracle's BF16 activations and weights, and the output matches the
+    oracle's FP8 emulation with those scales."""
+    import torch
+    _say("[ann fp8]")
+    K = mech.K
+    params = oann.init_params([K + 2, *HID, K], seed=12)
+    nm = _norm_from(data)
+    m = _model(mech, params, nm)
+    Tc, pc, Yc = chemgen.make_states(mech, "ch4", N=2048, seed=909)
+    m.quantize_fp8(to_dev(Tc, dev), to_dev(pc, dev), to_dev(Yc, dev))
+    sa, sw = m.fp8_scales()
+    p32 = _params32(params)
+    _, _, hs = oann.forward(p32, _oracle_inputs(nm, Tc, pc, Yc), prec="bf16", keep=True)
+    np.testing.assert_allclose(sa, [np.abs(hs[1]).max() / 448, np.abs(hs[2]).max() / 448],
+                               rtol=1e-3)
+    np.testing.assert_allclose(sw, [np.abs(p32[1][0]).max() / 448, np.abs(p32[2][0]).max() / 448],
+                               rtol=1e-6)
+    T, p, Y = chemgen.make_states(mech, "ch4", N=3001, seed=910)
+    U = m.forward(to_dev(T, dev), to_dev(p, dev), to_dev(Y, dev), K)
+    torch.cuda.synchronize()
+    Ug = U.cpu().numpy().astype(np.float64)
+    sc = {1: (float(sa[0]), float(sw[0])), 2: (float(sa[1]), float(sw[1]))}
+    X = _oracle_inputs(nm, T, p, Y)
+    Uo = oann.forward(p32, X, prec="fp8", fp8_scales=sc)
+    Ub = oann.forward(p32, X, prec="bf16")
+    err = np.abs(Ug - Uo)
+    e_fmt = np.abs(Uo - Ub)
+    _say(f"  fp8 max abs {err.max():.3e} rms {np.sqrt((err ** 2).mean()):.3e}; "
+         f"fp8-vs-bf16 rms {np.sqrt((e_fmt ** 2).mean()):.3e}")
+    assert np.sqrt((err ** 2).mean()) < 0.25 * np.sqrt((e_fmt ** 2).mean())
+    assert err.max() <= 5e-2
+    # back to BF16
+    m.set_precision(0)
+    U2 = m.forward(to_dev(T, dev), to_dev(p, dev), to_dev(Y, dev), K).cpu().numpy()
+    assert np.sqrt(((U2 - Ub) ** 2).mean()) <= 2e-3

@@ -188,3 +188,36 @@ def test_equilibrium_unchanged(dev, gm):
     g = _gpu_step(P, gm["ch4"], dev, T, p, Y, 1e-5)
     np.testing.assert_allclose(g["T"], T, rtol=1e-10)
     np.testing.assert_allclose(g["Y"], Y, rtol=1e-9, atol=1e-18)
+
+
+def test_step_sets_uneven(dev, gm):
+    """Several sets of different size and dt in one launch: each cell equals
+    the oracle's chem_step with its set's dt; empty sets are allowed."""
+    import torch
+    import paper_2312_05800_amd as P
+    _say("[step sets]")
+    mech = chemgen.make_mechanism("ch4")
+    om = oracle.OracleMech(mech)
+    sizes = [0, 1, 37, 300, 900]
+    dts = [1e-6, 3e-7, 1e-5, 2e-6, 4e-5]
+    sets, host = [], []
+    for i, (nc, dt) in enumerate(zip(sizes, dts)):
+        T, p, Y = chemgen.make_states(mech, dict(fuel="CH4", phi=(0.5, 1.3),
+                                                 T=("uniform", 300.0, 2500.0), N=nc),
+                                      seed=500 + i)
+        d = dict(dt=dt, T=to_dev(T, dev), p=to_dev(p, dev), Y=to_dev(Y, dev),
+                 RR=torch.zeros((mech.K, nc), dtype=torch.float64, device=dev),
+                 stats=torch.zeros((3, nc), dtype=torch.int32, device=dev))
+        sets.append(d)
+        host.append((T, p, Y, dt))
+    P.chem_step_sets(gm["ch4"], sets)
+    torch.cuda.synchronize()
+    for d, (T, p, Y, dt) in zip(sets, host):
+        if T.size == 0:
+            continue
+        o = oracle.chem_step(om, dt, T, p, Y)
+        np.testing.assert_array_equal(d["stats"].cpu().numpy(), o["stats"])
+        res = compare_state(d["T"].cpu().numpy(), d["Y"].cpu().numpy(), o["T"], o["Y"])
+        assert res["ok"], res
+        np.testing.assert_allclose(d["RR"].cpu().numpy(), o["RR"], rtol=1e-6,
+                                   atol=1e-8 * np.abs(o["RR"]).max())
