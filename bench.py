@@ -27,6 +27,8 @@ PEAK_BF16 = 2500e12   # dense MFMA, FLOP/s
 PEAK_FP64 = 78.6e12   # vector FP64, FLOP/s
 PEAK_FP8 = 5000e12    # dense MFMA, FLOP/s
 HIDDEN = (1600, 800, 400)
+COPY_PROBE_DOUBLES = 1 << 25   # 256 MiB read + 256 MiB written by one plain copy kernel
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
 def log(*a):
@@ -51,6 +53,42 @@ def rodas3_flops_per_attempt(mech):
 def mlp_flops_per_cell(K):
     dims = [K + 2, *HIDDEN, K]
     return sum(2 * a * b for a, b in zip(dims[:-1], dims[1:]))
+
+
+def source_digest(paths):
+    """sha256 over the named kernel sources (relative to the repository)."""
+    import hashlib
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(label):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 counter
+    summary, or None when the kernel sources changed since the counters were
+    taken (or none were taken)."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    e = t.get("kernels", {}).get(label)
+    if not e or source_digest(e["sources"]) != e["sha256"]:
+        return None
+    return e["hbm_bytes_per_launch"]
+
+
+def copy_probe(dev):
+    """One plain device copy of known size (torch elementwise kernel), the
+    calibration point for the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    src = torch.ones(COPY_PROBE_DOUBLES, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    del src, dst
 
 
 def train_model(P, mech, gm, dev, args):
@@ -235,6 +273,8 @@ def main():
     fp64_cps = N * args.fp64_steps / t_fp64
 
     # ---- accuracy against the CPU oracle on an evenly spaced sample ----
+    copy_probe(dev)
+
     import oracle
     om = oracle.OracleMech(mech)
     idx = np.linspace(0, N - 1, args.oracle_sample).astype(np.int64)
@@ -265,6 +305,8 @@ def main():
     t_l2, c_l2 = avg(prof_ann, "mlp_l2")
     chunk = min(N, 1 << 21)
     l2_flops = 2.0 * HIDDEN[0] * HIDDEN[1] * chunk
+    # H1 in and H2 out (BF16), W2 and b2 once
+    l2_bytes = 2 * chunk * (HIDDEN[0] + HIDDEN[1]) + 2 * HIDDEN[0] * HIDDEN[1] + 4 * HIDDEN[1]
     ach_bf16 = l2_flops / t_l2
     t_step, c_step = avg(prof_fp64, "chem_step")
     fl_attempt = rodas3_flops_per_attempt(mech)
@@ -339,12 +381,14 @@ def main():
         "roofline": {"kernel": "mlp_l2 (1600->800 BF16 GEMM, bias+GELU)", "bound": "mfma",
                      "achieved": round(ach_bf16 / 1e12, 2), "peak": PEAK_BF16 / 1e12,
                      "unit": "TFLOP/s", "frac": round(ach_bf16 / PEAK_BF16, 4),
-                     "traffic": None, "avg_ms": round(t_l2 * 1e3, 4), "launches": c_l2,
-                     "flops_per_launch": l2_flops},
+                     "traffic": measured_traffic("mlp_l2"), "avg_ms": round(t_l2 * 1e3, 4),
+                     "launches": c_l2, "flops_per_launch": l2_flops,
+                     "algorithmic_bytes_per_launch": l2_bytes},
         "roofline_fp64": {"kernel": "k_step (RODAS3 persistent)", "bound": "alu",
                           "achieved": round(ach_fp64 / 1e12, 3), "peak": PEAK_FP64 / 1e12,
                           "unit": "TFLOP/s", "frac": round(ach_fp64 / PEAK_FP64, 4),
-                          "traffic": None, "avg_ms": round(t_step * 1e3, 3),
+                          "traffic": measured_traffic("chem_step"),
+                          "avg_ms": round(t_step * 1e3, 3),
                           "launches": c_step, "flops_per_attempt": fl_attempt,
                           "attempts_per_launch": attempts},
         "kernels_ann": kernels_ann,
