@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "ann_internal.h"
@@ -63,6 +64,8 @@ struct ann_model {
   u16 *tX = nullptr, *tH[3] = {}, *tGb[ann::NLAYER] = {};
   float *tZ[3] = {}, *tU = nullptr, *tUt = nullptr, *tGf[ann::NLAYER] = {};
   double *loss_part = nullptr;
+  double *col_part = nullptr;  // [COLSUM_PARTS][max dout] bias-gradient partials
+  float *wg_part = nullptr;    // split-K partial weight gradients
   // FP8 inference of the hidden-to-hidden layers (L2, L3)
   bool fp8_ready = false, use_fp8 = false;
   float sa[3] = {1, 1, 1}, sw[3] = {1, 1, 1};  // per-tensor scales of layers 1, 2
@@ -121,6 +124,16 @@ chem_status grow_infer(ann_model *m, int64_t n) {
   return CHEM_OK;
 }
 
+// Split-K factor of a weight-gradient GEMM (M x N output, K = batch rows): a
+// power of two that brings the launch to about 1024 blocks of 128 x 128, while
+// every split keeps a multiple of 32 rows.
+int wgrad_splits(int M, int N, int64_t K) {
+  const long tiles = (long)((M + 127) / 128) * ((N + 127) / 128);
+  int S = 1;
+  while (tiles * S < 1024 && S < 16 && K % (64L * S) == 0) S *= 2;
+  return S;
+}
+
 chem_status grow_train(ann_model *m, int64_t B) {
   if (m->wt.cap >= B) return CHEM_OK;
   size_t off = 0;
@@ -142,6 +155,16 @@ chem_status grow_train(ann_model *m, int64_t B) {
     oGf[l] = sect((size_t)B * m->L[l].doutp * 4);
   }
   const size_t oL = sect(LOSS_PARTS * 8);
+  size_t col_n = 0, wg_n = 0;
+  for (int l = 0; l < 4; ++l) {
+    const ann::Layer &L = m->L[l];
+    col_n = std::max(col_n, (size_t)ann::COLSUM_PARTS * L.doutp);
+    // the largest split any batch size can select (K = 2^30 divides by all)
+    const int S = wgrad_splits(L.doutp, L.dinp, 1L << 30);
+    if (S > 1) wg_n = std::max(wg_n, (size_t)S * L.doutp * L.dinp);
+  }
+  const size_t oC = sect(col_n * 8);
+  const size_t oW = sect(wg_n * 4);
   if (m->wt.base) (void)hipFree(m->wt.base);
   m->wt.base = nullptr;
   m->wt.cap = 0;
@@ -162,6 +185,8 @@ chem_status grow_train(ann_model *m, int64_t B) {
     m->tGf[l] = (float *)(b + oGf[l]);
   }
   m->loss_part = (double *)(b + oL);
+  m->col_part = (double *)(b + oC);
+  m->wg_part = (float *)(b + oW);
   m->wt.cap = B;
   m->wt.bytes = off;
   return CHEM_OK;
@@ -770,10 +795,17 @@ extern "C" chem_status ann_train_step(ann_model *m, chem_batch batch, const doub
     w.lda = L.doutp;
     w.B = l > 0 ? m->tH[l - 1] : m->tX;
     w.ldb = L.dinp;
-    w.Cf = m->gW[l];
     w.ldcf = L.dinp;
+    const int S = wgrad_splits(L.doutp, L.dinp, B);
+    const long wn = (long)L.doutp * L.dinp;
+    w.Cf = S > 1 ? m->wg_part : m->gW[l];
+    w.ksplit = S;
+    w.split_stride = wn;
     if ((st = ann::gemm(w, false, false, ann::EPI_F32, s, "train_wgrad")) != CHEM_OK) return st;
-    if ((st = ann::colsum(B, L.doutp, m->tGf[l], L.doutp, m->gb[l], s)) != CHEM_OK) return st;
+    if (S > 1 && (st = ann::sum_splits(wn, S, m->wg_part, wn, m->gW[l], s)) != CHEM_OK)
+      return st;
+    if ((st = ann::colsum(B, L.doutp, m->tGf[l], L.doutp, m->gb[l], m->col_part, s)) != CHEM_OK)
+      return st;
     if (l > 0) {
       const ann::Layer &P = m->L[l - 1];
       ann::GemmArgs d{};

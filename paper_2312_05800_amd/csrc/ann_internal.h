@@ -48,6 +48,10 @@ struct GemmArgs {
   long ldcq;
   float scale;  // multiplies the accumulator before the bias (FP8 operands)
   float qinv;   // 1/scale of the E4M3 output (EPI_GELU_Q8)
+  // split-K (EPI_F32 without bias only): K is cut into ksplit equal ranges,
+  // range s writes its partial product to Cf + s * split_stride
+  int ksplit;
+  long split_stride;
 };
 
 // C = epi(A * op(B)); AK: A is [M][K] row-major (else [K][M]); BK: B is [N][K]
@@ -86,7 +90,13 @@ chem_status targets(const TargetArgs &a, hipStream_t s);
 
 chem_status l1_grad(int64_t n, int K, int doutp, const float *U, const float *Ut, u16 *Gb,
                     float *Gf, double *loss_part, int nparts, float *loss, hipStream_t s);
-chem_status colsum(int64_t M, int N, const float *X, long ldx, float *out, hipStream_t s);
+// out[j] = sum over the M rows of X[:, j]; part: COLSUM_PARTS * N doubles
+constexpr int COLSUM_PARTS = 64;
+chem_status colsum(int64_t M, int N, const float *X, long ldx, float *out, double *part,
+                   hipStream_t s);
+// out[i] = sum_{s < S} part[s * stride + i], in order of s
+chem_status sum_splits(int64_t n, int S, const float *part, long stride, float *out,
+                       hipStream_t s);
 chem_status adam(int64_t n, float *W, const float *g, float *m, float *v, u16 *Wb, float lr,
                  float b1, float b2, float eps, float bc1, float bc2, hipStream_t s);
 chem_status to_bf16(int64_t n, const float *src, u16 *dst, hipStream_t s);

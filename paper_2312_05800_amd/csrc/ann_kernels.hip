@@ -13,6 +13,8 @@ namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 
 constexpr double RG = 8.314462618;
 
@@ -24,13 +26,27 @@ __device__ __forceinline__ u16 f2bf(float f) {
   return (u16)(u >> 16);
 }
 
+// erf(x) by the rational approximation of Abramowitz & Stegun 7.1.26
+// (|error| <= 1.5e-7), with the hardware reciprocal and base-2 exponential:
+// well inside the BF16 rounding of the activations it feeds.
+__device__ __forceinline__ float erf_as(float x) {
+  const float a = fabsf(x);
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, a, 1.0f));
+  const float poly =
+      t * fmaf(t, fmaf(t, fmaf(t, fmaf(t, 1.061405429f, -1.453152027f), 1.421413741f),
+                       -0.284496736f),
+               0.254829592f);
+  const float y = 1.0f - poly * __builtin_amdgcn_exp2f(-a * a * 1.4426950408889634f);
+  return copysignf(y, x);
+}
+
 __device__ __forceinline__ float gelu(float x) {
-  return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f));
+  return 0.5f * x * (1.0f + erf_as(x * 0.70710678118654752f));
 }
 
 __device__ __forceinline__ float gelu_grad(float x) {
-  return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) +
-         x * expf(-0.5f * x * x) * 0.39894228040143268f;
+  return 0.5f * (1.0f + erf_as(x * 0.70710678118654752f)) +
+         x * __builtin_amdgcn_exp2f(-0.5f * x * x * 1.4426950408889634f) * 0.39894228040143268f;
 }
 
 // FP32 -> OCP FP8 E4M3 (e4m3fn: no infinities, max 448), saturating, round to
@@ -77,6 +93,9 @@ __global__ __launch_bounds__(WM *WN * 64) void k_gemm(GemmArgs g) {
   const int logical = (int)(blockIdx.x % 8) * per_xcd + (int)(blockIdx.x / 8);
   if (logical >= total) return;
   const long m0 = (long)(logical / ntn) * BM, n0 = (long)(logical % ntn) * BN;
+  // split-K range of this block (blockIdx.y); the whole K when not split
+  const int kper = g.ksplit > 1 ? g.K / g.ksplit : g.K;
+  const int kbase = (int)blockIdx.y * kper;
   constexpr int ACH = BM * BK / 8, BCH = BN * BK / 8;
   constexpr int APT = (ACH + NT - 1) / NT, BPT = (BCH + NT - 1) / NT;
   uint4 ra[APT], rb[BPT];
@@ -172,18 +191,19 @@ __global__ __launch_bounds__(WM *WN * 64) void k_gemm(GemmArgs g) {
     }
   };
 
-  const int nk = g.K / BK;
-  load(0);
+  const int nk = kper / BK;
+  load(kbase);
   store(0);
   __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
     const int cur = kt & 1;
-    if (kt + 1 < nk) load((kt + 1) * BK);
+    if (kt + 1 < nk) load(kbase + (kt + 1) * BK);
     compute(cur);
     if (kt + 1 < nk) store(cur ^ 1);
     __syncthreads();
   }
 
+  float *const Cf = (EPI == EPI_F32 && g.ksplit > 1) ? g.Cf + blockIdx.y * g.split_stride : g.Cf;
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -197,7 +217,7 @@ __global__ __launch_bounds__(WM *WN * 64) void k_gemm(GemmArgs g) {
         if (row >= g.M) continue;
         const float v = acc[i][j][r];
         if (EPI == EPI_F32) {
-          g.Cf[row * g.ldcf + col] = v + bias;
+          Cf[row * g.ldcf + col] = v + bias;
         } else if (EPI == EPI_GELU) {
           const float z = v + bias;
           if (g.Z) g.Z[row * g.ldz + col] = z;
@@ -214,11 +234,194 @@ __global__ __launch_bounds__(WM *WN * 64) void k_gemm(GemmArgs g) {
     }
 }
 
+// ------------------------------------------------- forward-layer GEMM
+// Operand tiles are streamed into LDS by direct global->LDS loads
+// (global_load_lds_dwordx4: lane i's 16 bytes land at M0 + 16 i), so no
+// registers stage them.  A tile row holds 32 K values (64 bytes, four 16-byte
+// chunks); chunk c of row r is stored at position c ^ swz(r), which makes the
+// 16-lane phases of the 16-byte fragment reads hit distinct banks of the
+// 64-bank LDS (rows r..r+15 read one chunk each).
+__device__ __forceinline__ int swz(int r) { return (r >> 2) & 3; }
+
+// One direct load of 16 bytes per lane: wave-uniform 64-bit base in SGPRs, a
+// 32-bit per-lane byte offset, destination M0 = lds_addr (wave-uniform).
+// (M0 is listed as clobbered; the compiler sets it before each of its own uses.)
+#pragma clang diagnostic push
+#pragma clang diagnostic ignored "-Winline-asm"
+__device__ __forceinline__ void lds_dma16s(const void *sbase, unsigned voff, unsigned lds_addr) {
+  asm volatile("s_mov_b32 m0, %2\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, %1"
+               :
+               : "v"(voff), "s"(sbase), "s"(lds_addr)
+               : "memory", "m0");
+}
+#pragma clang diagnostic pop
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Forward-layer GEMM with 16x16 output tiles (v_mfma_f32_16x16x32_bf16, one
+// MFMA K-step per 32-wide stage), so the feature tile can be any multiple of
+// 16: BN = TN16 16 (e.g. 400 = 800 / 2), BM = WM TM16 16 cells, waves split
+// the cells.  Large tiles cut the bytes each block streams from L2 per flop
+// (BM BN / (BM + BN) flops per byte).  The K-steps stream through a ring of
+// STAGES LDS buffers: two are in flight while the waves multiply the third.
+// Each wave waits for its own loads of a stage (vmcnt) and a workgroup
+// barrier publishes all of them; rows past M or N are clamped to the last
+// valid row (their results are never stored).  K must be a multiple of 32.
+// Fragment: lane l holds row l % 16 and the 8 K values 8 (l / 16) ..; result:
+// lane l holds cell l % 16 and features 4 (l / 16) .. + 3 of its tile.
+template <int WM, int TM16, int TN16, int EPI>
+__global__ __launch_bounds__(WM * 64) void k_gemm_dma16(GemmArgs g) {
+  constexpr int BK = 32, STAGES = 3;
+  constexpr int BM = WM * TM16 * 16, BN = TN16 * 16, ROWS = BM + BN;
+  constexpr int NI = ROWS / 16;
+  constexpr int NPW = (NI + WM - 1) / WM;
+  constexpr int NMIN = NI / WM;
+  static_assert(BM % 16 == 0 && BN % 16 == 0, "tile rows must be multiples of 16");
+  __shared__ __attribute__((aligned(1024))) u16 S[STAGES * ROWS * BK];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int ntn = (g.N + BN - 1) / BN;
+  const int ntm = (g.M + BM - 1) / BM;
+  const int total = ntn * ntm;
+  const int per_xcd = (total + 7) / 8;
+  const int logical = (int)(blockIdx.x % 8) * per_xcd + (int)(blockIdx.x / 8);
+  if (logical >= total) return;
+  const long m0 = (long)(logical / ntn) * BM, n0 = (long)(logical % ntn) * BN;
+
+  // per-lane byte offsets of this wave's DMA rows within the tile (rows past
+  // M or N clamped to the last valid one) and the wave-uniform tile bases
+  const u16 *const sA = g.A + m0 * g.lda;
+  const u16 *const sB = g.B + n0 * g.ldb;
+  unsigned voff[NPW];
+#pragma unroll
+  for (int i = 0; i < NPW; ++i) {
+    const int gi = i * WM + wave;
+    const int row = gi * 16 + (lane >> 2);
+    const int chunk = (lane & 3) ^ swz(row);
+    unsigned o = 0;
+    if (gi < NI) {
+      if (row < BM) {
+        const long m = m0 + row < g.M ? m0 + row : g.M - 1;
+        o = (unsigned)(((m - m0) * g.lda + chunk * 8) * 2);
+      } else {
+        const long n = n0 + (row - BM) < g.N ? n0 + (row - BM) : g.N - 1;
+        o = (unsigned)(((n - n0) * g.ldb + chunk * 8) * 2);
+      }
+    }
+    voff[i] = o;
+  }
+  const unsigned lds0 =
+      (unsigned)(uintptr_t)(__attribute__((address_space(3))) u16 *)(S);
+  auto issue = [&](int stage, int kt) {
+#pragma unroll
+    for (int i = 0; i < NPW; ++i) {
+      const int gi = i * WM + wave;
+      if (gi < NI)
+        lds_dma16s((gi * 16 < BM ? sA : sB) + kt * BK, voff[i],
+                   lds0 + (unsigned)((stage * ROWS + gi * 16) * BK * 2));
+    }
+  };
+
+  f32x4 acc[TM16][TN16];
+#pragma unroll
+  for (int i = 0; i < TM16; ++i)
+#pragma unroll
+    for (int j = 0; j < TN16; ++j) acc[i][j] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
+
+  const int nk = g.K / BK;
+  const int cc = lane >> 4;
+  issue(0, 0);
+  if (nk > 1) issue(1, 1);
+  for (int kt = 0; kt < nk; ++kt) {
+    // this wave's loads of stage kt are done once at most the next stage's
+    // (NMIN or more instructions) remain; the barrier publishes every wave's
+    if (kt + 1 < nk)
+      asm volatile("s_waitcnt vmcnt(%0)\n\ts_barrier" : : "n"(NMIN) : "memory");
+    else
+      asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" : : : "memory");
+    // the ring slot of stage kt + 2 was last read in iteration kt - 1, which
+    // every wave finished before the barrier above
+    if (kt + 2 < nk) issue((kt + 2) % STAGES, kt + 2);
+    const u16 *T = S + (kt % STAGES) * ROWS * BK;
+    bf16x8 x[TM16];
+#pragma unroll
+    for (int i = 0; i < TM16; ++i) {
+      const int row = wave * TM16 * 16 + i * 16 + (lane & 15);
+      x[i] = *(const bf16x8 *)&T[row * BK + ((cc ^ swz(row)) * 8)];
+    }
+#pragma unroll
+    for (int j = 0; j < TN16; ++j) {
+      const int row = BM + j * 16 + (lane & 15);
+      const bf16x8 w = *(const bf16x8 *)&T[row * BK + ((cc ^ swz(row)) * 8)];
+#pragma unroll
+      for (int i = 0; i < TM16; ++i)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, x[i], acc[i][j], 0, 0, 0);
+    }
+  }
+
+  const int hf = 4 * (lane >> 4);
+#pragma unroll
+  for (int j = 0; j < TN16; ++j) {
+    if (n0 + j * 16 >= g.N) break;
+    const long col = n0 + j * 16 + hf;
+    float4 b = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (g.bias) b = *(const float4 *)(g.bias + col);
+#pragma unroll
+    for (int i = 0; i < TM16; ++i) {
+      const long row = m0 + wave * TM16 * 16 + i * 16 + (lane & 15);
+      if (row >= g.M) continue;
+      const float4 v = make_float4(acc[i][j][0] + b.x, acc[i][j][1] + b.y, acc[i][j][2] + b.z,
+                                   acc[i][j][3] + b.w);
+      if (EPI == EPI_F32) {
+        *(float4 *)(g.Cf + row * g.ldcf + col) = v;
+      } else if (EPI == EPI_GELU) {
+        if (g.Z) *(float4 *)(g.Z + row * g.ldz + col) = v;
+        const float4 h = make_float4(gelu(v.x), gelu(v.y), gelu(v.z), gelu(v.w));
+        if (g.Cb) {
+          const bf16x2 lo = __builtin_convertvector((f32x2){h.x, h.y}, bf16x2);
+          const bf16x2 hi = __builtin_convertvector((f32x2){h.z, h.w}, bf16x2);
+          uint2 o;
+          o.x = __builtin_bit_cast(unsigned, lo);
+          o.y = __builtin_bit_cast(unsigned, hi);
+          *(uint2 *)(g.Cb + row * g.ldcb + col) = o;
+        }
+        if (g.Cf) *(float4 *)(g.Cf + row * g.ldcf + col) = h;
+      } else if (EPI == EPI_GELU_Q8) {
+        const unsigned o = (unsigned)f2e4m3(gelu(v.x) * g.qinv) |
+                           ((unsigned)f2e4m3(gelu(v.y) * g.qinv) << 8) |
+                           ((unsigned)f2e4m3(gelu(v.z) * g.qinv) << 16) |
+                           ((unsigned)f2e4m3(gelu(v.w) * g.qinv) << 24);
+        *(unsigned *)(g.Cq + row * g.ldcq + col) = o;
+      }
+    }
+  }
+}
+
+template <int WM, int TM16, int TN16>
+chem_status gemm_dma16_cfg(const GemmArgs &g, int epi, hipStream_t s) {
+  constexpr int BM = WM * TM16 * 16, BN = TN16 * 16;
+  const long total = (long)((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
+  dim3 grid((unsigned)(((total + 7) / 8) * 8));
+  dim3 block(WM * 64);
+  if (epi == EPI_GELU)
+    hipLaunchKernelGGL((k_gemm_dma16<WM, TM16, TN16, EPI_GELU>), grid, block, 0, s, g);
+  else if (epi == EPI_F32)
+    hipLaunchKernelGGL((k_gemm_dma16<WM, TM16, TN16, EPI_F32>), grid, block, 0, s, g);
+  else if (epi == EPI_GELU_Q8)
+    hipLaunchKernelGGL((k_gemm_dma16<WM, TM16, TN16, EPI_GELU_Q8>), grid, block, 0, s, g);
+  else {
+    chem::set_error("gemm: unsupported epilogue for K-contiguous operands");
+    return CHEM_EUNSUPPORTED;
+  }
+  CHEM_HIP(hipGetLastError());
+  return CHEM_OK;
+}
+
 template <int WM, int WN, int TM, int TN>
 chem_status gemm_cfg(const GemmArgs &g, bool AK, bool BK, int epi, hipStream_t s) {
   constexpr int BM = WM * TM * 32, BN = WN * TN * 32;
   const long total = (long)((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
-  dim3 grid((unsigned)(((total + 7) / 8) * 8));
+  dim3 grid((unsigned)(((total + 7) / 8) * 8), g.ksplit > 1 ? g.ksplit : 1);
   dim3 block(WM * WN * 64);
   if (AK && BK && epi == EPI_GELU)
     hipLaunchKernelGGL((k_gemm<WM, WN, TM, TN, true, true, EPI_GELU>), grid, block, 0, s, g);
@@ -462,13 +665,33 @@ __global__ void k_loss_final(const double *part, int nparts, double scale, float
   *loss = (float)(s * scale);
 }
 
-// out[j] = sum over rows of X[:, j] (FP64 accumulation, fixed order).
-__global__ void k_colsum(int64_t M, int N, const float *X, long ldx, float *out) {
+// Column sums in two fixed-order passes (FP64 accumulation): block row q
+// sums rows [q M / P, (q + 1) M / P) of its columns into part[q][j]; the final
+// pass adds the P partials in order of q.
+__global__ void k_colsum_part(int64_t M, int N, const float *X, long ldx, double *part) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= N) return;
+  const int P = gridDim.y, q = blockIdx.y;
+  const int64_t m0 = M * q / P, m1 = M * (q + 1) / P;
+  double s = 0.0;
+  for (int64_t m = m0; m < m1; ++m) s += X[m * ldx + j];
+  part[(int64_t)q * N + j] = s;
+}
+
+__global__ void k_colsum_fin(int N, int P, const double *part, float *out) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= N) return;
   double s = 0.0;
-  for (int64_t m = 0; m < M; ++m) s += X[m * ldx + j];
+  for (int q = 0; q < P; ++q) s += part[(int64_t)q * N + j];
   out[j] = (float)s;
+}
+
+__global__ void k_sum_splits(int64_t n, int S, const float *part, long stride, float *out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float s = part[i];
+  for (int q = 1; q < S; ++q) s += part[(int64_t)q * stride + i];
+  out[i] = s;
 }
 
 __global__ void k_adam(int64_t n, float *W, const float *g, float *m, float *v, u16 *Wb, float lr,
@@ -742,6 +965,21 @@ chem_status gemm(const GemmArgs &g, bool AK, bool BK, int epi, hipStream_t s,
     chem::set_error("gemm: K must be a multiple of 32 and transposed dims multiples of 8");
     return CHEM_EINVAL;
   }
+  if (g.ksplit > 1 && (g.K % (32 * g.ksplit) != 0 || epi != EPI_F32 || g.bias)) {
+    chem::set_error("gemm: split-K needs K a multiple of 32 ksplit, FP32 output, no bias");
+    return CHEM_EINVAL;
+  }
+  if (AK && BK && epi != EPI_GELUGRAD && g.ksplit <= 1 && g.N % 16 == 0 && g.lda % 8 == 0 &&
+      g.ldb % 8 == 0 && g.ldcb % 4 == 0 && g.ldcf % 4 == 0 && g.ldz % 4 == 0 &&
+      g.ldcq % 4 == 0 && ((uintptr_t)g.A & 15) == 0 && ((uintptr_t)g.B & 15) == 0) {
+    // forward layers: 256 x 400 (or x 416) tiles through the direct-to-LDS
+    // ring when the launch still has at least two blocks per CU of work,
+    // 256 x 32 for the 32-wide output layer
+    const long mt = (g.M + 255) / 256;
+    if (g.N % 400 == 0 && mt * (g.N / 400) >= 512) return gemm_dma16_cfg<8, 2, 25>(g, epi, s);
+    if (g.N % 416 == 0 && mt * (g.N / 416) >= 512) return gemm_dma16_cfg<8, 2, 26>(g, epi, s);
+    if (g.N <= 32 && mt >= 512) return gemm_dma16_cfg<4, 4, 2>(g, epi, s);
+  }
   if (g.N <= 32) return gemm_cfg<4, 1, 1, 1>(g, AK, BK, epi, s);
   return gemm_cfg<2, 2, 2, 2>(g, AK, BK, epi, s);
 }
@@ -807,8 +1045,18 @@ chem_status l1_grad(int64_t n, int K, int doutp, const float *U, const float *Ut
   return CHEM_OK;
 }
 
-chem_status colsum(int64_t M, int N, const float *X, long ldx, float *out, hipStream_t s) {
-  hipLaunchKernelGGL(k_colsum, dim3(nblk(N, 64)), dim3(64), 0, s, M, N, X, ldx, out);
+chem_status colsum(int64_t M, int N, const float *X, long ldx, float *out, double *part,
+                   hipStream_t s) {
+  const int P = (int)(M < COLSUM_PARTS ? (M > 0 ? M : 1) : COLSUM_PARTS);
+  hipLaunchKernelGGL(k_colsum_part, dim3(nblk(N, 64), P), dim3(64), 0, s, M, N, X, ldx, part);
+  hipLaunchKernelGGL(k_colsum_fin, dim3(nblk(N, 256)), dim3(256), 0, s, N, P, part, out);
+  CHEM_HIP(hipGetLastError());
+  return CHEM_OK;
+}
+
+chem_status sum_splits(int64_t n, int S, const float *part, long stride, float *out,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_splits, dim3(nblk(n, 256)), dim3(256), 0, s, n, S, part, stride, out);
   CHEM_HIP(hipGetLastError());
   return CHEM_OK;
 }
