@@ -72,8 +72,9 @@ struct ann_model {
   void *fp8_buf = nullptr;
   uint8_t *Wq1 = nullptr, *Wq2 = nullptr;  // [N2p][1600], [416][832]-style padded E4M3
   float *bq1 = nullptr;                    // layer-1 bias padded to N2p
-  int n2p = 0, k3p = 0;                    // padded widths (multiples of 64)
+  int n2p = 0, k3p = 0, kq1 = 0;           // FP8 widths: L2 out (x32), L3 in / L2 in (x128)
   uint8_t *H1q = nullptr, *H2q = nullptr;  // inference workspace (E4M3 activations)
+  uint8_t *ood = nullptr;                  // per-cell out-of-distribution bits
 };
 
 using namespace chem;
@@ -86,6 +87,12 @@ constexpr int LOSS_PARTS = 256;
 int pad32(int x) { return (x + 31) / 32 * 32; }
 
 size_t layer_elems(const ann::Layer &L) { return (size_t)L.doutp * L.dinp; }
+
+// E4M3 layout: L2 reads H1q [cells][kq1] and Wq1 [n2p][kq1]; L3 reads H2q
+// [cells][k3p] and Wq2 [L3 outputs][k3p]; K widths padded to 128 with zeros.
+int fp8_n2p(const ann_model *m) { return (m->L[1].dout + 31) / 32 * 32; }
+int fp8_kq1(const ann_model *m) { return (m->L[1].dinp + 127) / 128 * 128; }
+int fp8_k3p(const ann_model *m) { return (fp8_n2p(m) + 127) / 128 * 128; }
 
 chem_status grow_infer(ann_model *m, int64_t n) {
   const int64_t need = n < CHUNK ? n : CHUNK;
@@ -100,11 +107,11 @@ chem_status grow_infer(ann_model *m, int64_t n) {
   const size_t oX = sect((size_t)cap * m->L[0].dinp * 2);
   size_t oH[3];
   for (int l = 0; l < 3; ++l) oH[l] = sect((size_t)cap * m->L[l].doutp * 2);
-  const size_t oU = sect((size_t)cap * m->n_out * 4);
+  const size_t oU = sect((size_t)cap * m->L[3].doutp * 4);
+  const size_t oO = sect((size_t)cap);
   const size_t oC = sect(64);
-  const int n2p = (m->L[1].dout + 63) / 64 * 64;
-  const size_t oQ1 = sect((size_t)cap * m->L[1].dinp);
-  const size_t oQ2 = sect((size_t)cap * n2p);
+  const size_t oQ1 = sect((size_t)cap * fp8_kq1(m));
+  const size_t oQ2 = sect((size_t)cap * fp8_k3p(m));
   if (m->wi.base) (void)hipFree(m->wi.base);
   m->wi.base = nullptr;
   m->wi.cap = 0;
@@ -116,9 +123,16 @@ chem_status grow_infer(ann_model *m, int64_t n) {
   m->X = (u16 *)(b + oX);
   for (int l = 0; l < 3; ++l) m->H[l] = (u16 *)(b + oH[l]);
   m->U = (float *)(b + oU);
+  m->ood = (uint8_t *)(b + oO);
   m->fb_count = (unsigned long long *)(b + oC);
   m->H1q = (uint8_t *)(b + oQ1);
   m->H2q = (uint8_t *)(b + oQ2);
+  // the E4M3 activation rows are padded to multiples of 128 bytes; the
+  // padding is never written and must read as zero
+  if (hipMemset(b + oQ1, 0, oQ2 - oQ1 + (size_t)cap * fp8_k3p(m)) != hipSuccess) {
+    set_error("ann: cannot clear the E4M3 activation workspace");
+    return CHEM_EHIP;
+  }
   m->wi.bytes = off;
   m->wi.cap = cap;
   return CHEM_OK;
@@ -499,11 +513,14 @@ extern "C" chem_status ann_fit_norm(ann_model *m, chem_batch batch, const double
 namespace {
 
 // Network forward for n cells (n <= workspace capacity): features -> X ->
-// L1..L3 (bias + GELU, BF16) -> L4 (bias, FP32) -> U [n][n_out].
+// L1..L3 (bias + GELU, BF16) -> L4 (bias, FP32) -> U [n][ldu] (ldu = n_out,
+// or the padded output width, whose extra columns come out zero).  With ood
+// non-null the out-of-distribution bit of every cell is written there.
 chem_status forward_chunk(ann_model *m, int64_t n, int64_t ld, const double *T, const double *p,
-                          const double *Y, float *U, hipStream_t s) {
+                          const double *Y, float *U, int ldu, uint8_t *ood, float ood_margin,
+                          hipStream_t s) {
   ann::FeatArgs fa{n, ld, T, p, Y, nullptr, m->n_out, m->L[0].dinp, m->nm.mu_in, m->nm.sd_in,
-                   m->nm.lambda, m->X};
+                   m->nm.lambda, m->X, ood, m->nm.lo, m->nm.hi, ood_margin};
   chem_status st = ann::features(fa, s);
   if (st != CHEM_OK) return st;
   if (m->use_fp8) {
@@ -519,21 +536,21 @@ chem_status forward_chunk(ann_model *m, int64_t n, int64_t ld, const double *T, 
     g.ldb = L0.dinp;
     g.bias = m->bm[0];
     g.Cq = m->H1q;
-    g.ldcq = L0.doutp;
+    g.ldcq = m->kq1;
     g.qinv = 1.0f / m->sa[1];
     if ((st = ann::gemm(g, true, true, ann::EPI_GELU_Q8, s, "mlp_l1")) != CHEM_OK) return st;
     ann::GemmArgs h{};
     h.M = (int)n;
     h.N = m->n2p;
-    h.K = L1.dinp;
+    h.K = m->kq1;
     h.A8 = m->H1q;
-    h.lda = L1.dinp;
+    h.lda = m->kq1;
     h.B8 = m->Wq1;
-    h.ldb = L1.dinp;
+    h.ldb = m->kq1;
     h.bias = m->bq1;
     h.scale = m->sa[1] * m->sw[1];
     h.Cq = m->H2q;
-    h.ldcq = m->n2p;
+    h.ldcq = m->k3p;
     h.qinv = 1.0f / m->sa[2];
     if ((st = ann::gemm8(h, ann::EPI_GELU_Q8, s, "mlp_l2_fp8")) != CHEM_OK) return st;
     ann::GemmArgs q{};
@@ -551,7 +568,7 @@ chem_status forward_chunk(ann_model *m, int64_t n, int64_t ld, const double *T, 
     if ((st = ann::gemm8(q, ann::EPI_GELU, s, "mlp_l3_fp8")) != CHEM_OK) return st;
     ann::GemmArgs o{};
     o.M = (int)n;
-    o.N = m->n_out;
+    o.N = ldu;
     o.K = L3.dinp;
     o.A = m->H[2];
     o.lda = L3.dinp;
@@ -559,7 +576,7 @@ chem_status forward_chunk(ann_model *m, int64_t n, int64_t ld, const double *T, 
     o.ldb = L3.dinp;
     o.bias = m->bm[3];
     o.Cf = U;
-    o.ldcf = m->n_out;
+    o.ldcf = ldu;
     return ann::gemm(o, true, true, ann::EPI_F32, s, "mlp_l4");
   }
   const u16 *in = m->X;
@@ -581,9 +598,9 @@ chem_status forward_chunk(ann_model *m, int64_t n, int64_t ld, const double *T, 
       st = ann::gemm(g, true, true, ann::EPI_GELU, s, lab[l]);
       in = m->H[l];
     } else {
-      g.N = m->n_out;
+      g.N = ldu;
       g.Cf = U;
-      g.ldcf = m->n_out;
+      g.ldcf = ldu;
       st = ann::gemm(g, true, true, ann::EPI_F32, s, "mlp_l4");
     }
     if (st != CHEM_OK) return st;
@@ -615,7 +632,8 @@ extern "C" chem_status ann_forward(ann_model *m, chem_batch batch, const double 
   hipStream_t s = (hipStream_t)stream;
   for (int64_t c0 = 0; c0 < batch.n; c0 += m->wi.cap) {
     const int64_t nc = (batch.n - c0 < m->wi.cap) ? batch.n - c0 : m->wi.cap;
-    st = forward_chunk(m, nc, batch.ld, T + c0, p + c0, Y + c0, U + c0 * m->n_out, s);
+    st = forward_chunk(m, nc, batch.ld, T + c0, p + c0, Y + c0, U + c0 * m->n_out, m->n_out,
+                       nullptr, 0.0f, s);
     if (st != CHEM_OK) return st;
   }
   return CHEM_OK;
@@ -683,7 +701,8 @@ extern "C" chem_status ann_step(ann_model *m, const chem_mech *mech, chem_batch 
   const bool dt_mismatch = fabs(dt - m->nm.dt_model) > 1e-6 * m->nm.dt_model;
   for (int64_t c0 = 0; c0 < batch.n; c0 += m->wi.cap) {
     const int64_t nc = (batch.n - c0 < m->wi.cap) ? batch.n - c0 : m->wi.cap;
-    st = forward_chunk(m, nc, batch.ld, T + c0, p + c0, Y + c0, m->U, s);
+    st = forward_chunk(m, nc, batch.ld, T + c0, p + c0, Y + c0, m->U, m->L[3].doutp, m->ood,
+                       o.ood_margin, s);
     if (st != CHEM_OK) return st;
     ann::PostArgs pa{};
     pa.n = nc;
@@ -695,12 +714,12 @@ extern "C" chem_status ann_step(ann_model *m, const chem_mech *mech, chem_batch 
     pa.RR = RR ? RR + c0 : nullptr;
     pa.flags = flags ? flags + c0 : nullptr;
     pa.U = m->U;
-    pa.doutp = m->n_out;
+    pa.doutp = m->L[3].doutp;
     pa.nm = m->nm;
     pa.n_in = m->n_in;
     pa.residual_tol = o.residual_tol;
     pa.ood_margin = o.ood_margin;
-    pa.check_ood = 1;
+    pa.ood = m->ood;
     pa.force_flag = dt_mismatch ? 1 : 0;
     pa.fb_index = o.fallback ? m->fb_index : nullptr;
     pa.fb_count = m->fb_count;
@@ -749,7 +768,7 @@ extern "C" chem_status ann_train_step(ann_model *m, chem_batch batch, const doub
     m->use_fp8 = false;
   }
   ann::FeatArgs fa{B, batch.ld, T, p, Y0, index, K, m->L[0].dinp, m->nm.mu_in, m->nm.sd_in,
-                   m->nm.lambda, m->tX};
+                   m->nm.lambda, m->tX, nullptr, nullptr, nullptr, 0.0f};
   if ((st = ann::features(fa, s)) != CHEM_OK) return st;
   ann::TargetArgs ta{B, batch.ld, Y0, Y1, index, K, m->L[3].doutp, m->nm.mu_out, m->nm.sd_out,
                      m->nm.lambda, m->tUt};
@@ -987,22 +1006,19 @@ extern "C" chem_status ann_quantize_fp8(ann_model *m, chem_batch calib, const do
     set_error("ann_quantize_fp8: needs a non-empty calibration batch");
     return CHEM_EINVAL;
   }
-  if (m->L[1].dinp % 64 != 0) {
-    set_error("ann_quantize_fp8: the first hidden width must be a multiple of 64");
-    return CHEM_EUNSUPPORTED;
-  }
   hipStream_t s = (hipStream_t)stream;
   const int64_t n = calib.n < CHUNK ? calib.n : CHUNK;
   if ((st = grow_infer(m, n)) != CHEM_OK) return st;
   const bool prev = m->use_fp8;
   m->use_fp8 = false;  // calibrate on the BF16 activations
-  st = forward_chunk(m, n, calib.ld, T, p, Y, m->U, s);
+  st = forward_chunk(m, n, calib.ld, T, p, Y, m->U, m->L[3].doutp, nullptr, 0.0f, s);
   m->use_fp8 = prev;
   if (st != CHEM_OK) return st;
-  m->n2p = (m->L[1].dout + 63) / 64 * 64;
-  m->k3p = m->n2p;
+  m->n2p = fp8_n2p(m);
+  m->k3p = fp8_k3p(m);
+  m->kq1 = fp8_kq1(m);
   if (!m->fp8_buf) {
-    const size_t b1 = (size_t)m->n2p * m->L[1].dinp, b2 = (size_t)m->L[2].doutp * m->k3p;
+    const size_t b1 = (size_t)m->n2p * m->kq1, b2 = (size_t)m->L[2].doutp * m->k3p;
     const size_t off1 = align256(b1), off2 = off1 + align256(b2);
     CHEM_HIP(hipMalloc(&m->fp8_buf, off2 + (size_t)m->n2p * 4 + 1024 * 4));
     unsigned char *b = (unsigned char *)m->fp8_buf;
@@ -1030,7 +1046,7 @@ extern "C" chem_status ann_quantize_fp8(ann_model *m, chem_batch calib, const do
   m->sw[1] = sc(amax_v[2]);
   m->sw[2] = sc(amax_v[3]);
   st = ann::quant_e4m3(m->Wm[1], m->L[1].dinp, m->L[1].dout, m->L[1].din, m->Wq1, m->n2p,
-                       m->L[1].dinp, 1.0f / m->sw[1], s);
+                       m->kq1, 1.0f / m->sw[1], s);
   if (st != CHEM_OK) return st;
   st = ann::quant_e4m3(m->Wm[2], m->L[2].dinp, m->L[2].doutp, m->L[2].din, m->Wq2,
                        m->L[2].doutp, m->k3p, 1.0f / m->sw[2], s);

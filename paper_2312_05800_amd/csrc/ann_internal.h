@@ -74,6 +74,11 @@ struct FeatArgs {
   const float *mu, *sd;
   float lambda;
   u16 *X;  // [n][dinp] bf16
+  // optional out-of-distribution test of the raw features against the
+  // training range widened by ood_margin of its span: ood[i] = 1 if outside
+  uint8_t *ood;
+  const float *lo, *hi;
+  float ood_margin;
 };
 chem_status features(const FeatArgs &a, hipStream_t s);
 
@@ -114,7 +119,7 @@ struct PostArgs {
   Norm nm;
   int n_in;
   float residual_tol, ood_margin;
-  int check_ood;
+  const uint8_t *ood;             // per-cell out-of-distribution bits (k_features), nullable
   int force_flag;                 // flag bits set on every cell
   int32_t *fb_index;              // fallback list (cell indices index_base + i)
   unsigned long long *fb_count;   // device counter

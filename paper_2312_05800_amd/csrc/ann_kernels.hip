@@ -66,9 +66,16 @@ __device__ __forceinline__ uint8_t f2e4m3(float x) {
   return (uint8_t)(sign | code);
 }
 
-__device__ __forceinline__ float boxcox(float y, float lam) {
-  return (powf(fmaxf(y, 0.0f), lam) - 1.0f) / lam;
+// Four values to packed E4M3 with the hardware conversion (round to nearest
+// even) after clamping to +-448: bit-identical to f2e4m3 for every finite
+// float (checked exhaustively on gfx950); a NaN input becomes -448.
+__device__ __forceinline__ unsigned e4m3x4(float a, float b, float c, float d) {
+  auto cl = [](float x) { return fminf(fmaxf(x, -448.0f), 448.0f); };
+  int r = __builtin_amdgcn_cvt_pk_fp8_f32(cl(a), cl(b), 0, false);
+  r = __builtin_amdgcn_cvt_pk_fp8_f32(cl(c), cl(d), r, true);
+  return (unsigned)r;
 }
+
 
 // ------------------------------------------------------------------ GEMM
 // Block = WM x WN waves; each wave owns TM x TN tiles of 32x32 computed with
@@ -387,11 +394,9 @@ __global__ __launch_bounds__(WM * 64) void k_gemm_dma16(GemmArgs g) {
         }
         if (g.Cf) *(float4 *)(g.Cf + row * g.ldcf + col) = h;
       } else if (EPI == EPI_GELU_Q8) {
-        const unsigned o = (unsigned)f2e4m3(gelu(v.x) * g.qinv) |
-                           ((unsigned)f2e4m3(gelu(v.y) * g.qinv) << 8) |
-                           ((unsigned)f2e4m3(gelu(v.z) * g.qinv) << 16) |
-                           ((unsigned)f2e4m3(gelu(v.w) * g.qinv) << 24);
-        *(unsigned *)(g.Cq + row * g.ldcq + col) = o;
+        *(unsigned *)(g.Cq + row * g.ldcq + col) =
+            e4m3x4(gelu(v.x) * g.qinv, gelu(v.y) * g.qinv, gelu(v.z) * g.qinv,
+                   gelu(v.w) * g.qinv);
       }
     }
   }
@@ -561,6 +566,150 @@ __global__ __launch_bounds__(WM *WN * 64) void k_gemm8(GemmArgs g) {
     }
 }
 
+// E4M3 x E4M3 forward GEMM on the direct-to-LDS ring: 16x16 output tiles with
+// v_mfma_scale_f32_16x16x128_f8f6f4 (block scales 2^0), one MFMA K-step per
+// 128-byte stage row.  A DMA instruction covers 8 rows of 128 bytes; chunk c
+// of row r sits at c ^ swz8(r), which keeps the 16-lane phases of the
+// fragment reads (rows r..r+15, one chunk each) on distinct banks.  K must be
+// a multiple of 128 (operands zero-padded by the caller).  Fragment: lane l
+// holds row l % 16 and the 32 K bytes 32 (l / 16) ..; the per-tensor scales
+// multiply the accumulator in the epilogue.
+__device__ __forceinline__ int swz8(int r) { return (r >> 1) & 7; }
+
+template <int WM, int TM16, int TN16, int EPI>
+__global__ __launch_bounds__(WM * 64) void k_gemm8_dma16(GemmArgs g) {
+  constexpr int BK = 128, STAGES = 3;
+  constexpr int BM = WM * TM16 * 16, BN = TN16 * 16, ROWS = BM + BN;
+  constexpr int NI = ROWS / 8;
+  constexpr int NPW = (NI + WM - 1) / WM;
+  constexpr int NMIN = NI / WM;
+  static_assert(BM % 16 == 0 && BN % 16 == 0, "tile rows must be multiples of 16");
+  __shared__ __attribute__((aligned(1024))) uint8_t S[STAGES * ROWS * BK];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int ntn = (g.N + BN - 1) / BN;
+  const int ntm = (g.M + BM - 1) / BM;
+  const int total = ntn * ntm;
+  const int per_xcd = (total + 7) / 8;
+  const int logical = (int)(blockIdx.x % 8) * per_xcd + (int)(blockIdx.x / 8);
+  if (logical >= total) return;
+  const long m0 = (long)(logical / ntn) * BM, n0 = (long)(logical % ntn) * BN;
+
+  const uint8_t *const sA = g.A8 + m0 * g.lda;
+  const uint8_t *const sB = g.B8 + n0 * g.ldb;
+  unsigned voff[NPW];
+#pragma unroll
+  for (int i = 0; i < NPW; ++i) {
+    const int gi = i * WM + wave;
+    const int row = gi * 8 + (lane >> 3);
+    const int chunk = (lane & 7) ^ swz8(row);
+    unsigned o = 0;
+    if (gi < NI) {
+      if (row < BM) {
+        const long m = m0 + row < g.M ? m0 + row : g.M - 1;
+        o = (unsigned)((m - m0) * g.lda + chunk * 16);
+      } else {
+        const long n = n0 + (row - BM) < g.N ? n0 + (row - BM) : g.N - 1;
+        o = (unsigned)((n - n0) * g.ldb + chunk * 16);
+      }
+    }
+    voff[i] = o;
+  }
+  const unsigned lds0 =
+      (unsigned)(uintptr_t)(__attribute__((address_space(3))) uint8_t *)(S);
+  auto issue = [&](int stage, int kt) {
+#pragma unroll
+    for (int i = 0; i < NPW; ++i) {
+      const int gi = i * WM + wave;
+      if (gi < NI)
+        lds_dma16s((gi * 8 < BM ? sA : sB) + kt * BK, voff[i],
+                   lds0 + (unsigned)((stage * ROWS + gi * 8) * BK));
+    }
+  };
+
+  f32x4 acc[TM16][TN16];
+#pragma unroll
+  for (int i = 0; i < TM16; ++i)
+#pragma unroll
+    for (int j = 0; j < TN16; ++j) acc[i][j] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
+
+  const int nk = g.K / BK;
+  const int c0 = 2 * (lane >> 4);
+  auto frag = [&](const uint8_t *T, int row) {
+    const uint4 lo = *(const uint4 *)&T[row * BK + ((c0 ^ swz8(row)) * 16)];
+    const uint4 hi = *(const uint4 *)&T[row * BK + (((c0 + 1) ^ swz8(row)) * 16)];
+    return (i32x8){(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w,
+                   (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+  };
+  issue(0, 0);
+  if (nk > 1) issue(1, 1);
+  for (int kt = 0; kt < nk; ++kt) {
+    if (kt + 1 < nk)
+      asm volatile("s_waitcnt vmcnt(%0)\n\ts_barrier" : : "n"(NMIN) : "memory");
+    else
+      asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" : : : "memory");
+    if (kt + 2 < nk) issue((kt + 2) % STAGES, kt + 2);
+    const uint8_t *T = S + (kt % STAGES) * ROWS * BK;
+    i32x8 x[TM16];
+#pragma unroll
+    for (int i = 0; i < TM16; ++i) x[i] = frag(T, wave * TM16 * 16 + i * 16 + (lane & 15));
+#pragma unroll
+    for (int j = 0; j < TN16; ++j) {
+      const i32x8 w = frag(T, BM + j * 16 + (lane & 15));
+#pragma unroll
+      for (int i = 0; i < TM16; ++i)
+        acc[i][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(w, x[i], acc[i][j], 0, 0,
+                                                                      0, 127, 0, 127);
+    }
+  }
+
+  const int hf = 4 * (lane >> 4);
+#pragma unroll
+  for (int j = 0; j < TN16; ++j) {
+    if (n0 + j * 16 >= g.N) break;
+    const long col = n0 + j * 16 + hf;
+    float4 b = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (g.bias) b = *(const float4 *)(g.bias + col);
+#pragma unroll
+    for (int i = 0; i < TM16; ++i) {
+      const long row = m0 + wave * TM16 * 16 + i * 16 + (lane & 15);
+      if (row >= g.M) continue;
+      const float4 h = make_float4(gelu(acc[i][j][0] * g.scale + b.x),
+                                   gelu(acc[i][j][1] * g.scale + b.y),
+                                   gelu(acc[i][j][2] * g.scale + b.z),
+                                   gelu(acc[i][j][3] * g.scale + b.w));
+      if (EPI == EPI_GELU_Q8) {
+        *(unsigned *)(g.Cq + row * g.ldcq + col) =
+            e4m3x4(h.x * g.qinv, h.y * g.qinv, h.z * g.qinv, h.w * g.qinv);
+      } else {
+        const bf16x2 lo = __builtin_convertvector((f32x2){h.x, h.y}, bf16x2);
+        const bf16x2 hi = __builtin_convertvector((f32x2){h.z, h.w}, bf16x2);
+        uint2 o;
+        o.x = __builtin_bit_cast(unsigned, lo);
+        o.y = __builtin_bit_cast(unsigned, hi);
+        *(uint2 *)(g.Cb + row * g.ldcb + col) = o;
+      }
+    }
+  }
+}
+
+template <int WM, int TM16, int TN16>
+chem_status gemm8_dma16_cfg(const GemmArgs &g, int epi, hipStream_t s) {
+  constexpr int BM = WM * TM16 * 16, BN = TN16 * 16;
+  const long total = (long)((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
+  dim3 grid((unsigned)(((total + 7) / 8) * 8)), block(WM * 64);
+  if (epi == EPI_GELU_Q8)
+    hipLaunchKernelGGL((k_gemm8_dma16<WM, TM16, TN16, EPI_GELU_Q8>), grid, block, 0, s, g);
+  else if (epi == EPI_GELU)
+    hipLaunchKernelGGL((k_gemm8_dma16<WM, TM16, TN16, EPI_GELU>), grid, block, 0, s, g);
+  else {
+    chem::set_error("gemm8: unsupported epilogue");
+    return CHEM_EUNSUPPORTED;
+  }
+  CHEM_HIP(hipGetLastError());
+  return CHEM_OK;
+}
+
 __global__ void k_amax(int64_t n, const void *x, int bf16, float *part) {
   __shared__ float red[256];
   float m = 0.0f;
@@ -589,26 +738,48 @@ __global__ void k_quant(const float *src, long ld_src, int rows, int cols, uint8
 
 // ------------------------------------------------------------- prologue
 
+// Box-Cox with the hardware base-2 logarithm and exponential (y <= 0, and
+// y below the FP32 normal range, give y^lambda = 0).
+__device__ __forceinline__ float boxcox_fast(float y, float lam) {
+  const float yl = y > 0.0f ? __builtin_amdgcn_exp2f(lam * __builtin_amdgcn_logf(y)) : 0.0f;
+  return (yl - 1.0f) / lam;
+}
+
+// One thread per cell: raw features (T, p, Box-Cox of Y), the optional
+// out-of-distribution bit, z-scored BF16 row of X.
 __global__ void k_features(FeatArgs a) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
   const int64_t c = a.index ? a.index[i] : i;
   u16 *out = a.X + i * a.dinp;
+  bool outside = false;
   for (int j0 = 0; j0 < a.dinp; j0 += 8) {
-    u16 v[8];
+    float z[8];
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
       const int j = j0 + t;
-      float x = 0.0f;
-      bool real = true;
-      if (j == 0) x = (float)a.T[c];
-      else if (j == 1) x = (float)a.p[c];
-      else if (j < a.K + 2) x = boxcox((float)a.Y[(int64_t)(j - 2) * a.ld + c], a.lambda);
-      else real = false;
-      v[t] = real ? f2bf((x - a.mu[j]) / a.sd[j]) : (u16)0;
+      z[t] = 0.0f;
+      if (j < a.K + 2) {
+        float x;
+        if (j == 0) x = (float)a.T[c];
+        else if (j == 1) x = (float)a.p[c];
+        else x = boxcox_fast((float)a.Y[(int64_t)(j - 2) * a.ld + c], a.lambda);
+        if (a.ood) {
+          const float lo = a.lo[j], hi = a.hi[j], span = hi - lo;
+          const float tol = span > 0.0f ? a.ood_margin * span : 1e-6f * fmaxf(fabsf(hi), 1e-30f);
+          if (!(x >= lo - tol && x <= hi + tol)) outside = true;
+        }
+        z[t] = (x - a.mu[j]) / a.sd[j];
+      }
     }
-    *(uint4 *)(out + j0) = *(const uint4 *)v;
+    uint4 o;
+    o.x = __builtin_bit_cast(unsigned, __builtin_convertvector((f32x2){z[0], z[1]}, bf16x2));
+    o.y = __builtin_bit_cast(unsigned, __builtin_convertvector((f32x2){z[2], z[3]}, bf16x2));
+    o.z = __builtin_bit_cast(unsigned, __builtin_convertvector((f32x2){z[4], z[5]}, bf16x2));
+    o.w = __builtin_bit_cast(unsigned, __builtin_convertvector((f32x2){z[6], z[7]}, bf16x2));
+    *(uint4 *)(out + j0) = o;
   }
+  if (a.ood) a.ood[i] = outside ? 1 : 0;
 }
 
 __global__ void k_targets(TargetArgs a) {
@@ -715,12 +886,33 @@ __global__ void k_to_bf16(int64_t n, const float *src, u16 *dst) {
 
 // ----------------------------------------------------------------- post
 
-__device__ __forceinline__ void species_h_cp(const chem::DevMech &M, int k, double T, double &hRT,
-                                             double &cpR) {
-  const double *c = (T <= M.Tmid[k]) ? M.nasa_lo + 7 * k : M.nasa_hi + 7 * k;
-  const double T2 = T * T, T3 = T2 * T, T4 = T3 * T;
-  cpR = c[0] + c[1] * T + c[2] * T2 + c[3] * T3 + c[4] * T4;
-  hRT = c[0] + c[1] * T / 2.0 + c[2] * T2 / 3.0 + c[3] * T3 / 4.0 + c[4] * T4 / 5.0 + c[5] / T;
+// c_p/R and h/RT of species k at T (Tp = T, T^2, T^3, T^4, 1/T): both
+// ranges' coefficients are wave-uniform loads, the range is chosen per lane;
+// h/RT uses the coefficients with the divisors folded in.
+__device__ __forceinline__ void species_h_cp(const chem::DevMech &M, int k, const double *Tp,
+                                             double &hRT, double &cpR) {
+  const bool low = Tp[0] <= M.Tmid[k];
+  double c[5], h[6];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    const double a = M.nasa_lo[7 * k + q], b = M.nasa_hi[7 * k + q];
+    c[q] = low ? a : b;
+  }
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    const double a = M.nasa_h[7 * k + q], b = M.nasa_hh[7 * k + q];
+    h[q] = low ? a : b;
+  }
+  cpR = c[0] + c[1] * Tp[0] + c[2] * Tp[1] + c[3] * Tp[2] + c[4] * Tp[3];
+  hRT = h[0] + h[1] * Tp[0] + h[2] * Tp[1] + h[3] * Tp[2] + h[4] * Tp[3] + h[5] * Tp[4];
+}
+
+__device__ __forceinline__ void tpowers(double T, double *Tp) {
+  Tp[0] = T;
+  Tp[1] = T * T;
+  Tp[2] = Tp[1] * T;
+  Tp[3] = Tp[2] * T;
+  Tp[4] = 1.0 / T;
 }
 
 constexpr int EMAX = 8;
@@ -735,31 +927,34 @@ __global__ __launch_bounds__(128) void k_post(chem::DevMech M, PostArgs a) {
   const double T0 = a.T[i], p = a.p[i];
   uint8_t flag = (uint8_t)a.force_flag;
   double y0[KP], yn[KP];
+  float u[KP];
+  if (a.doutp % 4 == 0) {
+#pragma unroll
+    for (int k = 0; k < KP; k += 4) {
+      float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      if (k < a.doutp) v = *(const float4 *)(a.U + i * a.doutp + k);
+      u[k] = v.x;
+      u[k + 1] = v.y;
+      u[k + 2] = v.z;
+      u[k + 3] = v.w;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < KP; ++k) u[k] = k < K ? a.U[i * a.doutp + k] : 0.0f;
+  }
 #pragma unroll
   for (int k = 0; k < KP; ++k) {
     y0[k] = 0.0;
     yn[k] = 0.0;
     if (k < K) {
       y0[k] = a.Y[(int64_t)k * a.ld + i];
-      const float du = a.U[i * a.doutp + k] * a.nm.sd_out[k] + a.nm.mu_out[k];
+      const float du = u[k] * a.nm.sd_out[k] + a.nm.mu_out[k];
       yn[k] = y0[k] + (double)du;  // Y' = Y0 + sd u + mu
     }
   }
   // out of distribution: any input feature outside the widened training range
-  if (a.check_ood) {
-#pragma unroll
-    for (int j = 0; j < KP + 2; ++j) {
-      if (j < K + 2) {
-        float x;
-        if (j == 0) x = (float)T0;
-        else if (j == 1) x = (float)p;
-        else x = boxcox((float)y0[j - 2], a.nm.lambda);
-        const float lo = a.nm.lo[j], hi = a.nm.hi[j], span = hi - lo;
-        const float tol = span > 0.0f ? a.ood_margin * span : 1e-6f * fmaxf(fabsf(hi), 1e-30f);
-        if (!(x >= lo - tol && x <= hi + tol)) flag |= 1;
-      }
-    }
-  }
+  // (tested by k_features on the same cells)
+  if (a.ood && a.ood[i]) flag |= 1;
   // weighted least-squares projection onto M Y = M Y0, D = diag(max(Y',0) + 1e-10)
   double A[EP][EP], r[EP], z0[EP];
 #pragma unroll
@@ -852,23 +1047,25 @@ __global__ __launch_bounds__(128) void k_post(chem::DevMech M, PostArgs a) {
 
   if (flag == 0) {
     // temperature from h(T, Y) = h(T0, Y0) by Newton in FP64
-    double h0 = 0.0;
+    double h0 = 0.0, Tp[5];
+    tpowers(T0, Tp);
 #pragma unroll
     for (int k = 0; k < KP; ++k) {
       if (k < K) {
         double hRT, cpR;
-        species_h_cp(M, k, T0, hRT, cpR);
+        species_h_cp(M, k, Tp, hRT, cpR);
         h0 += y0[k] * RG * T0 * hRT * M.invW[k];
       }
     }
     double T = T0;
     for (int it = 0; it < 20; ++it) {
       double h = 0.0, cp = 0.0;
+      tpowers(T, Tp);
 #pragma unroll
       for (int k = 0; k < KP; ++k) {
         if (k < K) {
           double hRT, cpR;
-          species_h_cp(M, k, T, hRT, cpR);
+          species_h_cp(M, k, Tp, hRT, cpR);
           h += yn[k] * RG * T * hRT * M.invW[k];
           cp += yn[k] * RG * cpR * M.invW[k];
         }
@@ -919,7 +1116,7 @@ __global__ void k_stats(StatArgs a) {
     if (f == 0) x = a.T[i];
     else if (f == 1) x = a.p[i];
     else if (f < K + 2) {
-      x = (double)boxcox((float)a.Y0[(int64_t)(f - 2) * a.ld + i], a.lambda);
+      x = (double)boxcox_fast((float)a.Y0[(int64_t)(f - 2) * a.ld + i], a.lambda);
     } else {
       const int k = f - K - 2;
       x = a.Y1[(int64_t)k * a.ld + i] - a.Y0[(int64_t)k * a.ld + i];
@@ -991,6 +1188,13 @@ chem_status gemm8(const GemmArgs &g, int epi, hipStream_t s, const char *label) 
     return CHEM_EINVAL;
   }
   chem::ProfScope prof(label, s);
+  if (g.K % 128 == 0 && g.N % 16 == 0 && ((uintptr_t)g.A8 & 15) == 0 &&
+      ((uintptr_t)g.B8 & 15) == 0 && g.ldcb % 4 == 0 && g.ldcq % 4 == 0) {
+    // 256 x 160 tiles (N a multiple of 160), else 128 x 208 (N of 208)
+    const long mt = (g.M + 255) / 256;
+    if (g.N % 160 == 0 && mt * (g.N / 160) >= 512) return gemm8_dma16_cfg<8, 2, 10>(g, epi, s);
+    if (g.N % 208 == 0 && mt * 2 * (g.N / 208) >= 512) return gemm8_dma16_cfg<8, 1, 13>(g, epi, s);
+  }
   constexpr int BM = 128, BN = 128;
   const long total = (long)((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
   dim3 grid((unsigned)(((total + 7) / 8) * 8)), block(256);
