@@ -590,6 +590,23 @@ chem_status forward_chunk(ann_model *m, int64_t n, int64_t ld, const double *T, 
     g.B = m->Wb[l];
     g.ldb = L.dinp;
     g.bias = m->bm[l];
+    if (l == 2) {
+      // the output layer rides in the epilogue of the last hidden layer when
+      // the tiling allows it (its activations then never reach HBM)
+      g.N = L.doutp;
+      g.B2 = m->Wb[3];
+      g.bias2 = m->bm[3];
+      g.N2 = m->L[3].doutp;
+      g.Cf = U;
+      g.ldcf = ldu;
+      if (ann::gemm_fuses_next(g)) return ann::gemm(g, true, true, ann::EPI_GELU_NEXT, s,
+                                                    "mlp_l3_l4");
+      g.B2 = nullptr;
+      g.bias2 = nullptr;
+      g.N2 = 0;
+      g.Cf = nullptr;
+      g.ldcf = 0;
+    }
     if (l < 3) {
       g.N = L.doutp;
       g.Cb = m->H[l];

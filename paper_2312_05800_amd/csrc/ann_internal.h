@@ -26,7 +26,7 @@ struct Norm {
   float *mu_out, *sd_out;          // device [n_out]
 };
 
-enum { EPI_F32 = 0, EPI_GELU = 1, EPI_GELUGRAD = 2, EPI_GELU_Q8 = 3 };
+enum { EPI_F32 = 0, EPI_GELU = 1, EPI_GELUGRAD = 2, EPI_GELU_Q8 = 3, EPI_GELU_NEXT = 4 };
 
 struct GemmArgs {
   int M, N, K;
@@ -52,12 +52,21 @@ struct GemmArgs {
   // range s writes its partial product to Cf + s * split_stride
   int ksplit;
   long split_stride;
+  // EPI_GELU_NEXT: the activations never leave the chip; the next (output)
+  // layer Cf[m][0..N2) = B2 [N2][N] * GELU(...)[m][:] + bias2 follows in the
+  // same kernel (N2 a multiple of 16, Cf row stride ldcf)
+  const u16 *B2;
+  const float *bias2;
+  int N2;
 };
 
 // C = epi(A * op(B)); AK: A is [M][K] row-major (else [K][M]); BK: B is [N][K]
 // row-major (else [K][N]).
 chem_status gemm(const GemmArgs &g, bool AK, bool BK, int epi, hipStream_t s,
                  const char *label);
+// Whether gemm() can run this forward layer with EPI_GELU_NEXT (the output
+// layer fused into its epilogue).
+bool gemm_fuses_next(const GemmArgs &g);
 // E4M3 x E4M3 GEMM (both K-contiguous, K a multiple of 64), epi GELU or GELU_Q8.
 chem_status gemm8(const GemmArgs &g, int epi, hipStream_t s, const char *label);
 // max |x| over n BF16 (bf16 = true) or FP32 values, into part[0..nparts)

@@ -264,6 +264,7 @@ __device__ __forceinline__ void lds_dma16s(const void *sbase, unsigned voff, uns
 #pragma clang diagnostic pop
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef short s16x4 __attribute__((ext_vector_type(4)));
 
 // Forward-layer GEMM with 16x16 output tiles (v_mfma_f32_16x16x32_bf16, one
 // MFMA K-step per 32-wide stage), so the feature tile can be any multiple of
@@ -276,14 +277,15 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 // valid row (their results are never stored).  K must be a multiple of 32.
 // Fragment: lane l holds row l % 16 and the 8 K values 8 (l / 16) ..; result:
 // lane l holds cell l % 16 and features 4 (l / 16) .. + 3 of its tile.
-template <int WM, int TM16, int TN16, int EPI>
+template <int WM, int TM16, int TN16, int EPI, int STAGES>
 __global__ __launch_bounds__(WM * 64) void k_gemm_dma16(GemmArgs g) {
-  constexpr int BK = 32, STAGES = 3;
+  constexpr int BK = 32;
   constexpr int BM = WM * TM16 * 16, BN = TN16 * 16, ROWS = BM + BN;
   constexpr int NI = ROWS / 16;
   constexpr int NPW = (NI + WM - 1) / WM;
   constexpr int NMIN = NI / WM;
   static_assert(BM % 16 == 0 && BN % 16 == 0, "tile rows must be multiples of 16");
+  static_assert(STAGES == 1 || STAGES == 3, "ring of 3 stages, or 1 for a single K-step");
   __shared__ __attribute__((aligned(1024))) u16 S[STAGES * ROWS * BK];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -337,18 +339,20 @@ __global__ __launch_bounds__(WM * 64) void k_gemm_dma16(GemmArgs g) {
 
   const int nk = g.K / BK;
   const int cc = lane >> 4;
+  // STAGES - 1 K-steps in flight ahead of the one being multiplied (a single
+  // stage serves layers with one K-step only)
   issue(0, 0);
-  if (nk > 1) issue(1, 1);
+  if (STAGES == 3 && nk > 1) issue(1, 1);
   for (int kt = 0; kt < nk; ++kt) {
     // this wave's loads of stage kt are done once at most the next stage's
     // (NMIN or more instructions) remain; the barrier publishes every wave's
-    if (kt + 1 < nk)
+    if (STAGES == 3 && kt + 1 < nk)
       asm volatile("s_waitcnt vmcnt(%0)\n\ts_barrier" : : "n"(NMIN) : "memory");
     else
       asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" : : : "memory");
-    // the ring slot of stage kt + 2 was last read in iteration kt - 1, which
-    // every wave finished before the barrier above
-    if (kt + 2 < nk) issue((kt + 2) % STAGES, kt + 2);
+    // STAGES = 3: the ring slot of stage kt + 2 was last read in iteration
+    // kt - 1, which every wave finished before the barrier above
+    if (STAGES == 3 && kt + 2 < nk) issue((kt + 2) % STAGES, kt + 2);
     const u16 *T = S + (kt % STAGES) * ROWS * BK;
     bf16x8 x[TM16];
 #pragma unroll
@@ -367,6 +371,69 @@ __global__ __launch_bounds__(WM * 64) void k_gemm_dma16(GemmArgs g) {
   }
 
   const int hf = 4 * (lane >> 4);
+  if constexpr (EPI == EPI_GELU_NEXT) {
+    // The block holds every feature of its cells (one N-tile, BN >= N): the
+    // GELU activations, rounded to BF16, are in the 16x16 C layout (lane l:
+    // cell l % 16, features 4 (l / 16) .. + 3 of tile j), which is exactly the
+    // B operand of v_mfma_f32_16x16x16_bf16 over the K-slice of tile j.  The
+    // output layer's weights [N2 = 32][BN] are staged in the (now idle) ring
+    // with rows padded by 4 elements (conflict-free 8-byte fragment reads).
+    constexpr int LW = BN + 4;
+    static_assert(BN % 16 == 0, "");
+    asm volatile("s_barrier" : : : "memory");  // every wave is done with the ring
+    u16 *Wl = S;
+    for (int c = tid; c < g.N2 * (BN / 4); c += WM * 64) {
+      const int r = c / (BN / 4), q = (c % (BN / 4)) * 4;
+      uint2 v = make_uint2(0, 0);
+      if (q < g.N) v = *(const uint2 *)(g.B2 + (long)r * g.N + q);
+      *(uint2 *)&Wl[r * LW + q] = v;
+    }
+    __syncthreads();
+    // one feature tile at a time: its activations feed both 16-wide output
+    // tiles and its accumulators die (keeps the register peak at the main
+    // loop's)
+    constexpr int TO = 2;  // output tiles (N2 = 32)
+    f32x4 u[TO][TM16];
+#pragma unroll
+    for (int o = 0; o < TO; ++o)
+#pragma unroll
+      for (int i = 0; i < TM16; ++i) u[o][i] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int j = 0; j < TN16; ++j) {
+      float4 b = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      if (j * 16 < g.N) b = *(const float4 *)(g.bias + j * 16 + hf);
+      s16x4 w[TO];
+#pragma unroll
+      for (int o = 0; o < TO; ++o)
+        w[o] = *(const s16x4 *)&Wl[(o * 16 + (lane & 15)) * LW + j * 16 + hf];
+#pragma unroll
+      for (int i = 0; i < TM16; ++i) {
+        const bf16x2 lo = __builtin_convertvector(
+            (f32x2){gelu(acc[i][j][0] + b.x), gelu(acc[i][j][1] + b.y)}, bf16x2);
+        const bf16x2 hi = __builtin_convertvector(
+            (f32x2){gelu(acc[i][j][2] + b.z), gelu(acc[i][j][3] + b.w)}, bf16x2);
+        const unsigned ul = __builtin_bit_cast(unsigned, lo), uh = __builtin_bit_cast(unsigned, hi);
+        const s16x4 h = (s16x4){(short)(ul & 0xffff), (short)(ul >> 16), (short)(uh & 0xffff),
+                                (short)(uh >> 16)};
+#pragma unroll
+        for (int o = 0; o < TO; ++o)
+          u[o][i] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w[o], h, u[o][i], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int o = 0; o < TO; ++o) {
+      const float4 b2 = *(const float4 *)(g.bias2 + o * 16 + hf);
+#pragma unroll
+      for (int i = 0; i < TM16; ++i) {
+        const long row = m0 + wave * TM16 * 16 + i * 16 + (lane & 15);
+        if (row < g.M)
+          *(float4 *)(g.Cf + row * g.ldcf + o * 16 + hf) =
+              make_float4(u[o][i][0] + b2.x, u[o][i][1] + b2.y, u[o][i][2] + b2.z,
+                          u[o][i][3] + b2.w);
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int j = 0; j < TN16; ++j) {
     if (n0 + j * 16 >= g.N) break;
@@ -402,18 +469,27 @@ __global__ __launch_bounds__(WM * 64) void k_gemm_dma16(GemmArgs g) {
   }
 }
 
-template <int WM, int TM16, int TN16>
+template <int WM, int TM16, int TN16, int STAGES = 3>
 chem_status gemm_dma16_cfg(const GemmArgs &g, int epi, hipStream_t s) {
   constexpr int BM = WM * TM16 * 16, BN = TN16 * 16;
+  if (STAGES == 1 && g.K != 32) {
+    chem::set_error("gemm: the single-stage tiling needs K = 32");
+    return CHEM_EUNSUPPORTED;
+  }
   const long total = (long)((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
   dim3 grid((unsigned)(((total + 7) / 8) * 8));
   dim3 block(WM * 64);
   if (epi == EPI_GELU)
-    hipLaunchKernelGGL((k_gemm_dma16<WM, TM16, TN16, EPI_GELU>), grid, block, 0, s, g);
+    hipLaunchKernelGGL((k_gemm_dma16<WM, TM16, TN16, EPI_GELU, STAGES>), grid, block, 0, s, g);
   else if (epi == EPI_F32)
-    hipLaunchKernelGGL((k_gemm_dma16<WM, TM16, TN16, EPI_F32>), grid, block, 0, s, g);
+    hipLaunchKernelGGL((k_gemm_dma16<WM, TM16, TN16, EPI_F32, STAGES>), grid, block, 0, s, g);
   else if (epi == EPI_GELU_Q8)
-    hipLaunchKernelGGL((k_gemm_dma16<WM, TM16, TN16, EPI_GELU_Q8>), grid, block, 0, s, g);
+    hipLaunchKernelGGL((k_gemm_dma16<WM, TM16, TN16, EPI_GELU_Q8, STAGES>), grid, block, 0, s,
+                       g);
+  else if (epi == EPI_GELU_NEXT && g.N <= BN && g.N2 == 32 &&
+           g.N2 * (BN + 4) <= STAGES * (BM + BN) * 32 && g.ldcf % 4 == 0)
+    hipLaunchKernelGGL((k_gemm_dma16<WM, TM16, TN16, EPI_GELU_NEXT, STAGES>), grid, block, 0, s,
+                       g);
   else {
     chem::set_error("gemm: unsupported epilogue for K-contiguous operands");
     return CHEM_EUNSUPPORTED;
@@ -1154,6 +1230,20 @@ unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 }  // namespace
 
+namespace {
+bool dma16_ok(const GemmArgs &g) {
+  return g.ksplit <= 1 && g.N % 16 == 0 && g.lda % 8 == 0 && g.ldb % 8 == 0 &&
+         g.ldcb % 4 == 0 && g.ldcf % 4 == 0 && g.ldz % 4 == 0 && g.ldcq % 4 == 0 &&
+         g.K % 32 == 0 && ((uintptr_t)g.A & 15) == 0 && ((uintptr_t)g.B & 15) == 0;
+}
+}  // namespace
+
+bool gemm_fuses_next(const GemmArgs &g) {
+  return dma16_ok(g) && g.N == 416 && (long)((g.M + 255) / 256) >= 512 && g.N2 == 32 &&
+         g.N2 <= g.ldcf && g.N2 * (416 + 4) <= 3 * (256 + 416) * 32 && g.B2 &&
+         g.bias && g.bias2 && ((uintptr_t)g.B2 & 7) == 0;
+}
+
 chem_status gemm(const GemmArgs &g, bool AK, bool BK, int epi, hipStream_t s,
                  const char *label) {
   if (g.M <= 0 || g.N <= 0) return CHEM_OK;
@@ -1166,13 +1256,21 @@ chem_status gemm(const GemmArgs &g, bool AK, bool BK, int epi, hipStream_t s,
     chem::set_error("gemm: split-K needs K a multiple of 32 ksplit, FP32 output, no bias");
     return CHEM_EINVAL;
   }
-  if (AK && BK && epi != EPI_GELUGRAD && g.ksplit <= 1 && g.N % 16 == 0 && g.lda % 8 == 0 &&
-      g.ldb % 8 == 0 && g.ldcb % 4 == 0 && g.ldcf % 4 == 0 && g.ldz % 4 == 0 &&
-      g.ldcq % 4 == 0 && ((uintptr_t)g.A & 15) == 0 && ((uintptr_t)g.B & 15) == 0) {
-    // forward layers: 256 x 400 (or x 416) tiles through the direct-to-LDS
-    // ring when the launch still has at least two blocks per CU of work,
-    // 256 x 32 for the 32-wide output layer
+  if (epi == EPI_GELU_NEXT) {
+    if (!AK || !BK || !gemm_fuses_next(g)) {
+      chem::set_error("gemm: the fused output layer needs the 256 x 416 tiling");
+      return CHEM_EUNSUPPORTED;
+    }
+    return gemm_dma16_cfg<8, 2, 26>(g, epi, s);
+  }
+  if (AK && BK && epi != EPI_GELUGRAD && dma16_ok(g)) {
+    // forward layers through the direct-to-LDS ring when the launch has at
+    // least two blocks per CU of work: K = 32 (first layer) in 64 x 320
+    // single-stage tiles; 256 x 400 (or x 416) tiles; 256 x 32 for the
+    // 32-wide output layer
     const long mt = (g.M + 255) / 256;
+    if (g.K == 32 && g.N % 320 == 0 && 4 * mt * (g.N / 320) >= 512)
+      return gemm_dma16_cfg<4, 1, 20, 1>(g, epi, s);
     if (g.N % 400 == 0 && mt * (g.N / 400) >= 512) return gemm_dma16_cfg<8, 2, 25>(g, epi, s);
     if (g.N % 416 == 0 && mt * (g.N / 416) >= 512) return gemm_dma16_cfg<8, 2, 26>(g, epi, s);
     if (g.N <= 32 && mt >= 512) return gemm_dma16_cfg<4, 4, 2>(g, epi, s);

@@ -300,3 +300,71 @@ def test_fp8_forward_parity(dev, mech, data):
     m.set_precision(0)
     U2 = m.forward(to_dev(T, dev), to_dev(p, dev), to_dev(Y, dev), K).cpu().numpy()
     assert np.sqrt(((U2 - Ub) ** 2).mean()) <= 2e-3
+
+
+def test_large_tile_paths_ragged(dev, mech, data):
+    """At a cell count that selects the 256-cell direct-to-LDS GEMM tiles and
+    leaves a ragged last tile (3 * 2^16 + 37 cells), BF16 and FP8 forward
+    passes match the oracle on sampled rows (the last 40 included), and
+    ann_step (padded 32-wide output layer, out-of-distribution bits from the
+    feature kernel) matches the oracle's post-processing of the same U."""
+    import torch
+    import paper_2312_05800_amd as P
+    K = mech.K
+    N = 3 * (1 << 16) + 37
+    _say(f"[ann large tiles] N={N}")
+    params = oann.init_params([K + 2, *HID, K], seed=13)
+    params[3] = (params[3][0] * 0.02, params[3][1] * 0.02)
+    nm = _norm_from(data)
+    m = _model(mech, params, nm)
+    p32 = _params32(params)
+    T, p, Y = chemgen.make_states(mech, "ch4", N=N, seed=911)
+    Td, pd, Yd = to_dev(T, dev), to_dev(p, dev), to_dev(Y, dev)
+    idx = np.unique(np.concatenate([np.linspace(0, N - 41, 200).astype(np.int64),
+                                    np.arange(N - 40, N)]))
+    it = torch.from_numpy(idx).to(dev)
+    X = _oracle_inputs(nm, T[idx], p[idx], Y[:, idx])
+    # BF16
+    U = m.forward(Td, pd, Yd, K)
+    torch.cuda.synchronize()
+    assert torch.isfinite(U).all()
+    Ug = U[it].cpu().numpy().astype(np.float64)
+    Uo = oann.forward(p32, X, prec="bf16")
+    err = np.abs(Ug - Uo)
+    _say(f"  bf16 max abs {err.max():.3e} rms {np.sqrt((err ** 2).mean()):.3e}")
+    assert err.max() <= 2e-2 and np.sqrt((err ** 2).mean()) <= 2e-3
+    # ann_step on the same cells (no fallback): oracle post of the GPU forward
+    RR = torch.zeros((K, N), dtype=torch.float64, device=dev)
+    flags = torch.zeros(N, dtype=torch.uint8, device=dev)
+    Ufull = U.cpu().numpy().astype(np.float64)
+    gm = P.Mechanism(mech)
+    m.step(gm, 1e-5, Td, pd, Yd, RR=RR, flags=flags, fallback=False)
+    torch.cuda.synchronize()
+    om = oracle.OracleMech(mech)
+    o = oann.post(om, T[idx], p[idx], Y[:, idx], Ufull[idx].T, _f32(nm["mu_out"]),
+                  _f32(nm["sd_out"]), 1e-5, lo=_f32(nm["lo"]), hi=_f32(nm["hi"]))
+    fg = flags[it].cpu().numpy()
+    near = (o["residual"] > 0.5e-6) & (o["residual"] < 2e-6)
+    assert ((fg == o["flags"]) | near).all()
+    ok = (fg == 0) & (o["flags"] == 0)
+    assert ok.sum() > len(idx) // 4
+    Yg = Yd[:, it].cpu().numpy()
+    assert np.all(np.abs(Yg - o["Y"])[:, ok] <= 1e-5 * np.abs(o["Y"][:, ok]) + 1e-9)
+    np.testing.assert_allclose(Td[it].cpu().numpy()[ok], o["T"][ok], rtol=1e-6)
+    del gm
+    # FP8 hidden layers on the same inputs (state restored)
+    Td, Yd = to_dev(T, dev), to_dev(Y, dev)
+    Tc, pc, Yc = chemgen.make_states(mech, "ch4", N=4096, seed=912)
+    m.quantize_fp8(to_dev(Tc, dev), to_dev(pc, dev), to_dev(Yc, dev))
+    sa, sw = m.fp8_scales()
+    U8 = m.forward(Td, pd, Yd, K)
+    torch.cuda.synchronize()
+    assert torch.isfinite(U8).all()
+    sc = {1: (float(sa[0]), float(sw[0])), 2: (float(sa[1]), float(sw[1]))}
+    Uo8 = oann.forward(p32, X, prec="fp8", fp8_scales=sc)
+    err8 = np.abs(U8[it].cpu().numpy().astype(np.float64) - Uo8)
+    e_fmt = np.abs(Uo8 - Uo)
+    _say(f"  fp8 max abs {err8.max():.3e} rms {np.sqrt((err8 ** 2).mean()):.3e}; "
+         f"fp8-vs-bf16 rms {np.sqrt((e_fmt ** 2).mean()):.3e}")
+    assert np.sqrt((err8 ** 2).mean()) < 0.25 * np.sqrt((e_fmt ** 2).mean())
+    assert err8.max() <= 5e-2
