@@ -390,7 +390,9 @@ def main():
                           "traffic": measured_traffic("chem_step"),
                           "avg_ms": round(t_step * 1e3, 3),
                           "launches": c_step, "flops_per_attempt": fl_attempt,
-                          "attempts_per_launch": attempts},
+                          "attempts_per_launch": attempts,
+                          # T, p, Y in; T, Y, stats out (FP64 SoA, int32 stats)
+                          "algorithmic_bytes_per_launch": N * (8 + 8 + 8 * K + 8 + 8 * K + 12)},
         "kernels_ann": kernels_ann,
         "fp8": fp8_out,
         "cpu_baseline": {"value": round(cpu_cps, 2), "unit": "cells/s", "cores": nthr,
