@@ -43,6 +43,8 @@ struct ann_model {
   ann::Layer L[ann::NLAYER];
   float *Wm[ann::NLAYER] = {}, *bm[ann::NLAYER] = {};  // FP32 master parameters
   u16 *Wb[ann::NLAYER] = {};                           // BF16 copies used by the GEMMs
+  u16 *Wt[ann::NLAYER] = {};     // K-blocked BF16 copies for the large-batch forward path
+  bool wt_stale = true;          // Wt behind Wb (set on every weight change)
   float *mW[ann::NLAYER] = {}, *vW[ann::NLAYER] = {}, *mb[ann::NLAYER] = {},
         *vb[ann::NLAYER] = {};
   float *gW[ann::NLAYER] = {}, *gb[ann::NLAYER] = {};
@@ -70,7 +72,8 @@ struct ann_model {
   bool fp8_ready = false, use_fp8 = false;
   float sa[3] = {1, 1, 1}, sw[3] = {1, 1, 1};  // per-tensor scales of layers 1, 2
   void *fp8_buf = nullptr;
-  uint8_t *Wq1 = nullptr, *Wq2 = nullptr;  // [N2p][1600], [416][832]-style padded E4M3
+  uint8_t *Wq1 = nullptr, *Wq2 = nullptr;  // [n2p][kq1], [L3 outputs][k3p] E4M3
+  uint8_t *Wq1t = nullptr, *Wq2t = nullptr;  // the same, K-blocked by 128 bytes
   float *bq1 = nullptr;                    // layer-1 bias padded to N2p
   int n2p = 0, k3p = 0, kq1 = 0;           // FP8 widths: L2 out (x32), L3 in / L2 in (x128)
   uint8_t *H1q = nullptr, *H2q = nullptr;  // inference workspace (E4M3 activations)
@@ -216,6 +219,7 @@ chem_status upload_layer(ann_model *m, int l, const float *W, const float *b) {
   }
   CHEM_HIP(hipMemcpy(m->Wm[l], Wp.data(), Wp.size() * 4, hipMemcpyHostToDevice));
   CHEM_HIP(hipMemcpy(m->bm[l], bp.data(), bp.size() * 4, hipMemcpyHostToDevice));
+  m->wt_stale = true;
   chem_status st = ann::to_bf16((int64_t)Wp.size(), m->Wm[l], m->Wb[l], nullptr);
   if (st != CHEM_OK) return st;
   CHEM_HIP(hipDeviceSynchronize());
@@ -299,7 +303,7 @@ extern "C" chem_status ann_create(const ann_arch *arch, uint64_t seed, ann_model
     m->L[l].doutp = pad32(dims[l + 1]);
   }
   size_t off = 0;
-  size_t oW[4], ob[4], oWb[4], omW[4], ovW[4], omb[4], ovb[4], ogW[4], ogb[4];
+  size_t oW[4], ob[4], oWb[4], oWt[4], omW[4], ovW[4], omb[4], ovb[4], ogW[4], ogb[4];
   auto sect = [&](size_t bytes) {
     size_t o = off;
     off = align256(off + bytes);
@@ -310,6 +314,7 @@ extern "C" chem_status ann_create(const ann_arch *arch, uint64_t seed, ann_model
     oW[l] = sect(e * 4);
     ob[l] = sect(nb * 4);
     oWb[l] = sect(e * 2);
+    oWt[l] = sect(e * 2);
     omW[l] = sect(e * 4);
     ovW[l] = sect(e * 4);
     omb[l] = sect(nb * 4);
@@ -335,6 +340,7 @@ extern "C" chem_status ann_create(const ann_arch *arch, uint64_t seed, ann_model
     m->Wm[l] = (float *)(b + oW[l]);
     m->bm[l] = (float *)(b + ob[l]);
     m->Wb[l] = (u16 *)(b + oWb[l]);
+    m->Wt[l] = (u16 *)(b + oWt[l]);
     m->mW[l] = (float *)(b + omW[l]);
     m->vW[l] = (float *)(b + ovW[l]);
     m->mb[l] = (float *)(b + omb[l]);
@@ -516,6 +522,16 @@ namespace {
 // L1..L3 (bias + GELU, BF16) -> L4 (bias, FP32) -> U [n][ldu] (ldu = n_out,
 // or the padded output width, whose extra columns come out zero).  With ood
 // non-null the out-of-distribution bit of every cell is written there.
+// Large batches of a network whose widths match the direct-to-LDS tilings run
+// every hidden layer on those kernels with K-blocked activations and weights
+// (rows of one 32-wide K-step contiguous in HBM; 128 bytes for E4M3).
+bool tiled_path(const ann_model *m, int64_t n) {
+  const ann::Layer &a = m->L[0], &b = m->L[1], &c = m->L[2];
+  if (n < (1 << 17) || a.dinp != 32 || a.doutp % 320 != 0) return false;
+  if (m->use_fp8) return m->n2p % 160 == 0 && c.doutp % 208 == 0;
+  return b.doutp % 400 == 0 && (c.doutp % 416 == 0 || c.doutp % 400 == 0);
+}
+
 chem_status forward_chunk(ann_model *m, int64_t n, int64_t ld, const double *T, const double *p,
                           const double *Y, float *U, int ldu, uint8_t *ood, float ood_margin,
                           hipStream_t s) {
@@ -523,9 +539,17 @@ chem_status forward_chunk(ann_model *m, int64_t n, int64_t ld, const double *T, 
                    m->nm.lambda, m->X, ood, m->nm.lo, m->nm.hi, ood_margin};
   chem_status st = ann::features(fa, s);
   if (st != CHEM_OK) return st;
+  const bool tl = tiled_path(m, n);
+  const long cap = (long)m->wi.cap;  // rows between K-blocks of the activations
+  if (tl && !m->use_fp8 && m->wt_stale) {
+    for (int l = 1; l <= 2; ++l)
+      if ((st = ann::tile_bf16(m->L[l].doutp, m->L[l].dinp, m->Wb[l], m->Wt[l], s)) != CHEM_OK)
+        return st;
+    m->wt_stale = false;
+  }
   if (m->use_fp8) {
     // L1 (BF16) -> E4M3 activations; L2, L3 on FP8 MFMA; L4 (BF16)
-    const ann::Layer &L0 = m->L[0], &L1 = m->L[1], &L2 = m->L[2], &L3 = m->L[3];
+    const ann::Layer &L0 = m->L[0], &L2 = m->L[2], &L3 = m->L[3];
     ann::GemmArgs g{};
     g.M = (int)n;
     g.N = L0.doutp;
@@ -536,7 +560,8 @@ chem_status forward_chunk(ann_model *m, int64_t n, int64_t ld, const double *T, 
     g.ldb = L0.dinp;
     g.bias = m->bm[0];
     g.Cq = m->H1q;
-    g.ldcq = m->kq1;
+    g.ldcq = tl ? cap * 128 : m->kq1;
+    g.tiled = tl ? ann::TILED_C : 0;
     g.qinv = 1.0f / m->sa[1];
     if ((st = ann::gemm(g, true, true, ann::EPI_GELU_Q8, s, "mlp_l1")) != CHEM_OK) return st;
     ann::GemmArgs h{};
@@ -544,27 +569,29 @@ chem_status forward_chunk(ann_model *m, int64_t n, int64_t ld, const double *T, 
     h.N = m->n2p;
     h.K = m->kq1;
     h.A8 = m->H1q;
-    h.lda = m->kq1;
-    h.B8 = m->Wq1;
-    h.ldb = m->kq1;
+    h.lda = tl ? cap * 128 : m->kq1;
+    h.B8 = tl ? m->Wq1t : m->Wq1;
+    h.ldb = tl ? (long)m->n2p * 128 : m->kq1;
     h.bias = m->bq1;
     h.scale = m->sa[1] * m->sw[1];
     h.Cq = m->H2q;
-    h.ldcq = m->k3p;
+    h.ldcq = tl ? cap * 128 : m->k3p;
     h.qinv = 1.0f / m->sa[2];
+    h.tiled = tl ? (ann::TILED_A | ann::TILED_B | ann::TILED_C) : 0;
     if ((st = ann::gemm8(h, ann::EPI_GELU_Q8, s, "mlp_l2_fp8")) != CHEM_OK) return st;
     ann::GemmArgs q{};
     q.M = (int)n;
     q.N = L2.doutp;
     q.K = m->k3p;
     q.A8 = m->H2q;
-    q.lda = m->k3p;
-    q.B8 = m->Wq2;
-    q.ldb = m->k3p;
+    q.lda = tl ? cap * 128 : m->k3p;
+    q.B8 = tl ? m->Wq2t : m->Wq2;
+    q.ldb = tl ? (long)L2.doutp * 128 : m->k3p;
     q.bias = m->bm[2];
     q.scale = m->sa[2] * m->sw[2];
     q.Cb = m->H[2];
     q.ldcb = L2.doutp;
+    q.tiled = tl ? (ann::TILED_A | ann::TILED_B) : 0;
     if ((st = ann::gemm8(q, ann::EPI_GELU, s, "mlp_l3_fp8")) != CHEM_OK) return st;
     ann::GemmArgs o{};
     o.M = (int)n;
@@ -580,16 +607,19 @@ chem_status forward_chunk(ann_model *m, int64_t n, int64_t ld, const double *T, 
     return ann::gemm(o, true, true, ann::EPI_F32, s, "mlp_l4");
   }
   const u16 *in = m->X;
+  bool in_tiled = false;  // X (K = 32) is one K-block either way
   for (int l = 0; l < 4; ++l) {
     const ann::Layer &L = m->L[l];
     ann::GemmArgs g{};
     g.M = (int)n;
     g.K = L.dinp;
     g.A = in;
-    g.lda = L.dinp;
-    g.B = m->Wb[l];
-    g.ldb = L.dinp;
+    g.lda = in_tiled ? cap * 32 : L.dinp;
+    const bool wt = tl && (l == 1 || l == 2);
+    g.B = wt ? m->Wt[l] : m->Wb[l];
+    g.ldb = wt ? (long)L.doutp * 32 : L.dinp;
     g.bias = m->bm[l];
+    g.tiled = (in_tiled ? ann::TILED_A : 0) | (wt ? ann::TILED_B : 0);
     if (l == 2) {
       // the output layer rides in the epilogue of the last hidden layer when
       // the tiling allows it (its activations then never reach HBM)
@@ -608,12 +638,17 @@ chem_status forward_chunk(ann_model *m, int64_t n, int64_t ld, const double *T, 
       g.ldcf = 0;
     }
     if (l < 3) {
+      // hidden activations K-blocked when the next layer reads them on the
+      // tiled path (L3's output feeds the 32-wide output layer row-major)
+      const bool ct = tl && l < 2;
       g.N = L.doutp;
       g.Cb = m->H[l];
-      g.ldcb = L.doutp;
+      g.ldcb = ct ? cap * 32 : L.doutp;
+      g.tiled |= ct ? ann::TILED_C : 0;
       static const char *lab[3] = {"mlp_l1", "mlp_l2", "mlp_l3"};
       st = ann::gemm(g, true, true, ann::EPI_GELU, s, lab[l]);
       in = m->H[l];
+      in_tiled = ct;
     } else {
       g.N = ldu;
       g.Cf = U;
@@ -864,6 +899,7 @@ extern "C" chem_status ann_train_step(ann_model *m, chem_batch batch, const doub
   }
   if (opts->lr > 0.0f) {
     m->step += 1;
+    m->wt_stale = true;
     const double bc1 = 1.0 - pow((double)opts->beta1, (double)m->step);
     const double bc2 = 1.0 - pow((double)opts->beta2, (double)m->step);
     for (int l = 0; l < 4; ++l) {
@@ -991,6 +1027,7 @@ extern "C" chem_status ann_load(const char *path, ann_model **out) {
            hipMemcpy(dstb[q], bp.data(), bp.size() * 4, hipMemcpyHostToDevice) == hipSuccess;
     }
     if (ok) ok = ann::to_bf16((int64_t)layer_elems(L), m->Wm[l], m->Wb[l], nullptr) == CHEM_OK;
+    m->wt_stale = true;
   }
   fclose(f);
   if (!ok || hipDeviceSynchronize() != hipSuccess) {
@@ -1037,11 +1074,14 @@ extern "C" chem_status ann_quantize_fp8(ann_model *m, chem_batch calib, const do
   if (!m->fp8_buf) {
     const size_t b1 = (size_t)m->n2p * m->kq1, b2 = (size_t)m->L[2].doutp * m->k3p;
     const size_t off1 = align256(b1), off2 = off1 + align256(b2);
-    CHEM_HIP(hipMalloc(&m->fp8_buf, off2 + (size_t)m->n2p * 4 + 1024 * 4));
+    const size_t off3 = off2 + align256(b1), off4 = off3 + align256(b2);
+    CHEM_HIP(hipMalloc(&m->fp8_buf, off4 + (size_t)m->n2p * 4 + 1024 * 4));
     unsigned char *b = (unsigned char *)m->fp8_buf;
     m->Wq1 = b;
     m->Wq2 = b + off1;
-    m->bq1 = (float *)(b + off2);
+    m->Wq1t = b + off2;
+    m->Wq2t = b + off3;
+    m->bq1 = (float *)(b + off4);
   }
   float *part = m->bq1 + m->n2p;  // 1024 floats of scratch for the amax partials
   const int NP = 256;
@@ -1068,6 +1108,8 @@ extern "C" chem_status ann_quantize_fp8(ann_model *m, chem_batch calib, const do
   st = ann::quant_e4m3(m->Wm[2], m->L[2].dinp, m->L[2].doutp, m->L[2].din, m->Wq2,
                        m->L[2].doutp, m->k3p, 1.0f / m->sw[2], s);
   if (st != CHEM_OK) return st;
+  if ((st = ann::tile_e4m3(m->n2p, m->kq1, m->Wq1, m->Wq1t, s)) != CHEM_OK) return st;
+  if ((st = ann::tile_e4m3(m->L[2].doutp, m->k3p, m->Wq2, m->Wq2t, s)) != CHEM_OK) return st;
   CHEM_HIP(hipStreamSynchronize(s));
   std::vector<float> hb(m->n2p, 0.0f);  // layer-1 bias, zero-padded to the FP8 width
   CHEM_HIP(hipMemcpy(hb.data(), m->bm[1], (size_t)m->L[1].dout * 4, hipMemcpyDeviceToHost));

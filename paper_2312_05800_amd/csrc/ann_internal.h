@@ -58,7 +58,14 @@ struct GemmArgs {
   const u16 *B2;
   const float *bias2;
   int N2;
+  // K-blocked operand layouts of the inference path (bits: 1 = A, 2 = B,
+  // 4 = the BF16 / E4M3 output): element (r, k) of a K-blocked matrix sits at
+  // (k / KB) ld + r KB + k % KB with KB = 32 elements (BF16) or 128 bytes
+  // (E4M3), so the rows of one K-step are contiguous; ld is then the stride
+  // between K-blocks.  Only the direct-to-LDS kernels accept it.
+  int tiled;
 };
+enum { TILED_A = 1, TILED_B = 2, TILED_C = 4 };
 
 // C = epi(A * op(B)); AK: A is [M][K] row-major (else [K][M]); BK: B is [N][K]
 // row-major (else [K][N]).
@@ -74,6 +81,8 @@ chem_status amax(int64_t n, const void *x, bool bf16, float *part, int nparts, h
 // dst [rows_p][cols_p] E4M3 = e4m3(src[r][c] * qinv) for r < rows, c < cols, else 0
 chem_status quant_e4m3(const float *src, long ld_src, int rows, int cols, uint8_t *dst,
                        int rows_p, int cols_p, float qinv, hipStream_t s);
+// dst [cols_p/128][rows_p][128] (E4M3) from the row-major E4M3 src [rows_p][cols_p]
+chem_status tile_e4m3(int rows_p, int cols_p, const uint8_t *src, uint8_t *dst, hipStream_t s);
 
 struct FeatArgs {
   int64_t n, ld;
@@ -114,6 +123,8 @@ chem_status sum_splits(int64_t n, int S, const float *part, long stride, float *
 chem_status adam(int64_t n, float *W, const float *g, float *m, float *v, u16 *Wb, float lr,
                  float b1, float b2, float eps, float bc1, float bc2, hipStream_t s);
 chem_status to_bf16(int64_t n, const float *src, u16 *dst, hipStream_t s);
+// dst [K/32][N][32] from src [N][K] (BF16, K a multiple of 32)
+chem_status tile_bf16(int N, int K, const u16 *src, u16 *dst, hipStream_t s);
 
 struct PostArgs {
   int64_t n, ld;

@@ -298,9 +298,12 @@ __global__ __launch_bounds__(WM * 64) void k_gemm_dma16(GemmArgs g) {
   const long m0 = (long)(logical / ntn) * BM, n0 = (long)(logical % ntn) * BN;
 
   // per-lane byte offsets of this wave's DMA rows within the tile (rows past
-  // M or N clamped to the last valid one) and the wave-uniform tile bases
-  const u16 *const sA = g.A + m0 * g.lda;
-  const u16 *const sB = g.B + n0 * g.ldb;
+  // M or N clamped to the last valid one) and the wave-uniform tile bases;
+  // a K-blocked operand keeps the tile's rows of one K-step contiguous
+  const bool ta = g.tiled & TILED_A, tb = g.tiled & TILED_B;
+  const u16 *const sA = g.A + m0 * (ta ? BK : g.lda);
+  const u16 *const sB = g.B + n0 * (tb ? BK : g.ldb);
+  const long kA = ta ? g.lda : BK, kB = tb ? g.ldb : BK;  // step between K-blocks
   unsigned voff[NPW];
 #pragma unroll
   for (int i = 0; i < NPW; ++i) {
@@ -311,10 +314,10 @@ __global__ __launch_bounds__(WM * 64) void k_gemm_dma16(GemmArgs g) {
     if (gi < NI) {
       if (row < BM) {
         const long m = m0 + row < g.M ? m0 + row : g.M - 1;
-        o = (unsigned)(((m - m0) * g.lda + chunk * 8) * 2);
+        o = (unsigned)(((m - m0) * (ta ? BK : g.lda) + chunk * 8) * 2);
       } else {
         const long n = n0 + (row - BM) < g.N ? n0 + (row - BM) : g.N - 1;
-        o = (unsigned)(((n - n0) * g.ldb + chunk * 8) * 2);
+        o = (unsigned)(((n - n0) * (tb ? BK : g.ldb) + chunk * 8) * 2);
       }
     }
     voff[i] = o;
@@ -326,7 +329,7 @@ __global__ __launch_bounds__(WM * 64) void k_gemm_dma16(GemmArgs g) {
     for (int i = 0; i < NPW; ++i) {
       const int gi = i * WM + wave;
       if (gi < NI)
-        lds_dma16s((gi * 16 < BM ? sA : sB) + kt * BK, voff[i],
+        lds_dma16s(gi * 16 < BM ? sA + kt * kA : sB + kt * kB, voff[i],
                    lds0 + (unsigned)((stage * ROWS + gi * 16) * BK * 2));
     }
   };
@@ -457,13 +460,16 @@ __global__ __launch_bounds__(WM * 64) void k_gemm_dma16(GemmArgs g) {
           uint2 o;
           o.x = __builtin_bit_cast(unsigned, lo);
           o.y = __builtin_bit_cast(unsigned, hi);
-          *(uint2 *)(g.Cb + row * g.ldcb + col) = o;
+          const long at = (g.tiled & TILED_C) ? (col / 32) * g.ldcb + row * 32 + col % 32
+                                              : row * g.ldcb + col;
+          *(uint2 *)(g.Cb + at) = o;
         }
         if (g.Cf) *(float4 *)(g.Cf + row * g.ldcf + col) = h;
       } else if (EPI == EPI_GELU_Q8) {
-        *(unsigned *)(g.Cq + row * g.ldcq + col) =
-            e4m3x4(gelu(v.x) * g.qinv, gelu(v.y) * g.qinv, gelu(v.z) * g.qinv,
-                   gelu(v.w) * g.qinv);
+        const long at = (g.tiled & TILED_C) ? (col / 128) * g.ldcq + row * 128 + col % 128
+                                            : row * g.ldcq + col;
+        *(unsigned *)(g.Cq + at) = e4m3x4(gelu(v.x) * g.qinv, gelu(v.y) * g.qinv,
+                                          gelu(v.z) * g.qinv, gelu(v.w) * g.qinv);
       }
     }
   }
@@ -671,8 +677,10 @@ __global__ __launch_bounds__(WM * 64) void k_gemm8_dma16(GemmArgs g) {
   if (logical >= total) return;
   const long m0 = (long)(logical / ntn) * BM, n0 = (long)(logical % ntn) * BN;
 
-  const uint8_t *const sA = g.A8 + m0 * g.lda;
-  const uint8_t *const sB = g.B8 + n0 * g.ldb;
+  const bool ta = g.tiled & TILED_A, tb = g.tiled & TILED_B;
+  const uint8_t *const sA = g.A8 + m0 * (ta ? BK : g.lda);
+  const uint8_t *const sB = g.B8 + n0 * (tb ? BK : g.ldb);
+  const long kA = ta ? g.lda : BK, kB = tb ? g.ldb : BK;  // step between K-blocks
   unsigned voff[NPW];
 #pragma unroll
   for (int i = 0; i < NPW; ++i) {
@@ -683,10 +691,10 @@ __global__ __launch_bounds__(WM * 64) void k_gemm8_dma16(GemmArgs g) {
     if (gi < NI) {
       if (row < BM) {
         const long m = m0 + row < g.M ? m0 + row : g.M - 1;
-        o = (unsigned)((m - m0) * g.lda + chunk * 16);
+        o = (unsigned)((m - m0) * (ta ? BK : g.lda) + chunk * 16);
       } else {
         const long n = n0 + (row - BM) < g.N ? n0 + (row - BM) : g.N - 1;
-        o = (unsigned)((n - n0) * g.ldb + chunk * 16);
+        o = (unsigned)((n - n0) * (tb ? BK : g.ldb) + chunk * 16);
       }
     }
     voff[i] = o;
@@ -698,7 +706,7 @@ __global__ __launch_bounds__(WM * 64) void k_gemm8_dma16(GemmArgs g) {
     for (int i = 0; i < NPW; ++i) {
       const int gi = i * WM + wave;
       if (gi < NI)
-        lds_dma16s((gi * 8 < BM ? sA : sB) + kt * BK, voff[i],
+        lds_dma16s(gi * 8 < BM ? sA + kt * kA : sB + kt * kB, voff[i],
                    lds0 + (unsigned)((stage * ROWS + gi * 8) * BK));
     }
   };
@@ -755,8 +763,9 @@ __global__ __launch_bounds__(WM * 64) void k_gemm8_dma16(GemmArgs g) {
                                    gelu(acc[i][j][2] * g.scale + b.z),
                                    gelu(acc[i][j][3] * g.scale + b.w));
       if (EPI == EPI_GELU_Q8) {
-        *(unsigned *)(g.Cq + row * g.ldcq + col) =
-            e4m3x4(h.x * g.qinv, h.y * g.qinv, h.z * g.qinv, h.w * g.qinv);
+        const long at = (g.tiled & TILED_C) ? (col / 128) * g.ldcq + row * 128 + col % 128
+                                            : row * g.ldcq + col;
+        *(unsigned *)(g.Cq + at) = e4m3x4(h.x * g.qinv, h.y * g.qinv, h.z * g.qinv, h.w * g.qinv);
       } else {
         const bf16x2 lo = __builtin_convertvector((f32x2){h.x, h.y}, bf16x2);
         const bf16x2 hi = __builtin_convertvector((f32x2){h.z, h.w}, bf16x2);
@@ -958,6 +967,16 @@ __global__ void k_adam(int64_t n, float *W, const float *g, float *m, float *v, 
 __global__ void k_to_bf16(int64_t n, const float *src, u16 *dst) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) dst[i] = f2bf(src[i]);
+}
+
+// K-blocked copy: element (r, k) of src [R][K] (KB-element blocks) to
+// dst[(k / KB) R KB + r KB + k % KB]; one thread per element.
+template <typename T, int KB>
+__global__ void k_tile(int R, int K, const T *src, T *dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)R * K) return;
+  const int r = (int)(i / K), k = (int)(i % K);
+  dst[(int64_t)(k / KB) * R * KB + (int64_t)r * KB + k % KB] = src[i];
 }
 
 // ----------------------------------------------------------------- post
@@ -1263,6 +1282,21 @@ chem_status gemm(const GemmArgs &g, bool AK, bool BK, int epi, hipStream_t s,
     }
     return gemm_dma16_cfg<8, 2, 26>(g, epi, s);
   }
+  if (g.tiled) {
+    // K-blocked operands exist only on the direct-to-LDS path, whose launch
+    // thresholds the caller has checked (ann_api: at least 2^17 cells)
+    const long mt = (g.M + 255) / 256;
+    if (!AK || !BK || epi == EPI_GELUGRAD || !dma16_ok(g) || (g.tiled & ~7)) {
+      chem::set_error("gemm: K-blocked operands need the direct-to-LDS tiling");
+      return CHEM_EUNSUPPORTED;
+    }
+    if (g.K == 32 && g.N % 320 == 0) return gemm_dma16_cfg<4, 1, 20, 1>(g, epi, s);
+    if (g.N % 400 == 0 && mt * (g.N / 400) >= 512) return gemm_dma16_cfg<8, 2, 25>(g, epi, s);
+    if (g.N % 416 == 0 && mt * (g.N / 416) >= 512) return gemm_dma16_cfg<8, 2, 26>(g, epi, s);
+    if (g.N <= 32 && mt >= 512) return gemm_dma16_cfg<4, 4, 2>(g, epi, s);
+    chem::set_error("gemm: no direct-to-LDS tiling for this K-blocked shape");
+    return CHEM_EUNSUPPORTED;
+  }
   if (AK && BK && epi != EPI_GELUGRAD && dma16_ok(g)) {
     // forward layers through the direct-to-LDS ring when the launch has at
     // least two blocks per CU of work: K = 32 (first layer) in 64 x 320
@@ -1292,6 +1326,10 @@ chem_status gemm8(const GemmArgs &g, int epi, hipStream_t s, const char *label) 
     const long mt = (g.M + 255) / 256;
     if (g.N % 160 == 0 && mt * (g.N / 160) >= 512) return gemm8_dma16_cfg<8, 2, 10>(g, epi, s);
     if (g.N % 208 == 0 && mt * 2 * (g.N / 208) >= 512) return gemm8_dma16_cfg<8, 1, 13>(g, epi, s);
+  }
+  if (g.tiled) {
+    chem::set_error("gemm8: K-blocked operands need the direct-to-LDS tiling");
+    return CHEM_EUNSUPPORTED;
   }
   constexpr int BM = 128, BN = 128;
   const long total = (long)((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
@@ -1343,6 +1381,28 @@ chem_status l1_grad(int64_t n, int K, int doutp, const float *U, const float *Ut
   hipLaunchKernelGGL(k_l1, dim3(nparts), dim3(256), 0, s, n, K, doutp, U, Ut, Gb, Gf, loss_part);
   hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, s, loss_part, nparts,
                      1.0 / ((double)n * K), loss);
+  CHEM_HIP(hipGetLastError());
+  return CHEM_OK;
+}
+
+chem_status tile_bf16(int N, int K, const u16 *src, u16 *dst, hipStream_t s) {
+  if (K % 32 != 0) {
+    chem::set_error("tile_bf16: K must be a multiple of 32");
+    return CHEM_EINVAL;
+  }
+  hipLaunchKernelGGL((k_tile<u16, 32>), dim3(nblk((int64_t)N * K, 256)), dim3(256), 0, s, N, K,
+                     src, dst);
+  CHEM_HIP(hipGetLastError());
+  return CHEM_OK;
+}
+
+chem_status tile_e4m3(int rows_p, int cols_p, const uint8_t *src, uint8_t *dst, hipStream_t s) {
+  if (cols_p % 128 != 0) {
+    chem::set_error("tile_e4m3: the padded width must be a multiple of 128");
+    return CHEM_EINVAL;
+  }
+  hipLaunchKernelGGL((k_tile<uint8_t, 128>), dim3(nblk((int64_t)rows_p * cols_p, 256)), dim3(256),
+                     0, s, rows_p, cols_p, src, dst);
   CHEM_HIP(hipGetLastError());
   return CHEM_OK;
 }
