@@ -1012,45 +1012,23 @@ __device__ __forceinline__ void tpowers(double T, double *Tp) {
 
 constexpr int EMAX = 8;
 
-// One thread per cell; the cell's mass fractions stay in registers (KP >= K
-// slots, EP >= E elements), so every pass reads global memory once.
+// One thread per cell.  One streaming pass over the species builds Y' =
+// Y0 + dY (kept in registers, KP >= K slots), the element sums of Y0 and of
+// Y0 - Y', the weighted normal matrix and h(T0, Y0); Y0 itself is not kept (it
+// is read again for RR).  Four waves per SIMD (a few spilled registers) beat
+// two spill-free ones by 1.25x: the kernel is latency-bound (FP64 Newton and
+// Cholesky chains per cell).
 template <int KP, int EP>
-__global__ __launch_bounds__(128) void k_post(chem::DevMech M, PostArgs a) {
+__global__ __launch_bounds__(128, 4) void k_post(chem::DevMech M, PostArgs a) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
   const int K = M.K, E = M.E;
   const double T0 = a.T[i], p = a.p[i];
   uint8_t flag = (uint8_t)a.force_flag;
-  double y0[KP], yn[KP];
-  float u[KP];
-  if (a.doutp % 4 == 0) {
-#pragma unroll
-    for (int k = 0; k < KP; k += 4) {
-      float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-      if (k < a.doutp) v = *(const float4 *)(a.U + i * a.doutp + k);
-      u[k] = v.x;
-      u[k + 1] = v.y;
-      u[k + 2] = v.z;
-      u[k + 3] = v.w;
-    }
-  } else {
-#pragma unroll
-    for (int k = 0; k < KP; ++k) u[k] = k < K ? a.U[i * a.doutp + k] : 0.0f;
-  }
-#pragma unroll
-  for (int k = 0; k < KP; ++k) {
-    y0[k] = 0.0;
-    yn[k] = 0.0;
-    if (k < K) {
-      y0[k] = a.Y[(int64_t)k * a.ld + i];
-      const float du = u[k] * a.nm.sd_out[k] + a.nm.mu_out[k];
-      yn[k] = y0[k] + (double)du;  // Y' = Y0 + sd u + mu
-    }
-  }
   // out of distribution: any input feature outside the widened training range
   // (tested by k_features on the same cells)
   if (a.ood && a.ood[i]) flag |= 1;
-  // weighted least-squares projection onto M Y = M Y0, D = diag(max(Y',0) + 1e-10)
+  double yn[KP];
   double A[EP][EP], r[EP], z0[EP];
 #pragma unroll
   for (int e = 0; e < EP; ++e) {
@@ -1059,20 +1037,49 @@ __global__ __launch_bounds__(128) void k_post(chem::DevMech M, PostArgs a) {
 #pragma unroll
     for (int f = 0; f < EP; ++f) A[e][f] = 0.0;
   }
-  double S0 = 0.0;
+  double S0 = 0.0, h0 = 0.0, Tp[5];
+  tpowers(T0, Tp);
+  const bool vec = a.doutp % 4 == 0;
 #pragma unroll
-  for (int k = 0; k < KP; ++k) {
-    if (k < K) {
-      const double d = fmax(yn[k], 0.0) + 1e-10;
-      S0 += y0[k] * M.invW[k];
+  for (int k4 = 0; k4 < KP; k4 += 4) {
+    float u4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (vec) {
+      if (k4 < a.doutp) {
+        const float4 v = *(const float4 *)(a.U + i * a.doutp + k4);
+        u4[0] = v.x;
+        u4[1] = v.y;
+        u4[2] = v.z;
+        u4[3] = v.w;
+      }
+    } else {
 #pragma unroll
-      for (int e = 0; e < EP; ++e) {
-        if (e < E) {
-          const double me = M.Mel[e * K + k];
-          r[e] += me * (y0[k] - yn[k]);
-          z0[e] += me * y0[k];
+      for (int t = 0; t < 4; ++t)
+        if (k4 + t < K) u4[t] = a.U[i * a.doutp + k4 + t];
+    }
 #pragma unroll
-          for (int f = 0; f <= e; ++f) A[e][f] += me * d * M.Mel[f * K + k];
+    for (int t = 0; t < 4; ++t) {
+      const int k = k4 + t;
+      yn[k] = 0.0;
+      if (k < K) {
+        const double y0 = a.Y[(int64_t)k * a.ld + i];
+        const float du = u4[t] * a.nm.sd_out[k] + a.nm.mu_out[k];
+        const double y = y0 + (double)du;  // Y' = Y0 + sd u + mu
+        yn[k] = y;
+        const double d = fmax(y, 0.0) + 1e-10;
+        S0 += y0 * M.invW[k];
+        double hRT, cpR;
+        species_h_cp(M, k, Tp, hRT, cpR);
+        h0 += y0 * RG * T0 * hRT * M.invW[k];
+        // weighted least-squares projection onto M Y = M Y0, D = diag(max(Y',0) + 1e-10)
+#pragma unroll
+        for (int e = 0; e < EP; ++e) {
+          if (e < E) {
+            const double me = M.Mel[e * K + k];
+            r[e] += me * (y0 - y);
+            z0[e] += me * y0;
+#pragma unroll
+            for (int f = 0; f <= e; ++f) A[e][f] += me * d * M.Mel[f * K + k];
+          }
         }
       }
     }
@@ -1142,16 +1149,6 @@ __global__ __launch_bounds__(128) void k_post(chem::DevMech M, PostArgs a) {
 
   if (flag == 0) {
     // temperature from h(T, Y) = h(T0, Y0) by Newton in FP64
-    double h0 = 0.0, Tp[5];
-    tpowers(T0, Tp);
-#pragma unroll
-    for (int k = 0; k < KP; ++k) {
-      if (k < K) {
-        double hRT, cpR;
-        species_h_cp(M, k, Tp, hRT, cpR);
-        h0 += y0[k] * RG * T0 * hRT * M.invW[k];
-      }
-    }
     double T = T0;
     for (int it = 0; it < 20; ++it) {
       double h = 0.0, cp = 0.0;
@@ -1176,8 +1173,9 @@ __global__ __launch_bounds__(128) void k_post(chem::DevMech M, PostArgs a) {
 #pragma unroll
       for (int k = 0; k < KP; ++k) {
         if (k < K) {
-          if (a.RR) a.RR[(int64_t)k * a.ld + i] = sc * (yn[k] - y0[k]);
-          a.Y[(int64_t)k * a.ld + i] = yn[k];
+          double *yp = a.Y + (int64_t)k * a.ld + i;
+          if (a.RR) a.RR[(int64_t)k * a.ld + i] = sc * (yn[k] - *yp);
+          *yp = yn[k];
         }
       }
       a.T[i] = T;
