@@ -46,8 +46,24 @@ __device__ __forceinline__ float erf_as(float x) {
   return copysignf(1.0f - __builtin_amdgcn_rcpf(q), x);
 }
 
+// GELU(x) = x Phi(x) = h + h erf(x / sqrt 2), h = x / 2, with the 7.1.28
+// coefficients pre-scaled by powers of 1/sqrt 2 (same approximation, one
+// multiply less).
 __device__ __forceinline__ float gelu(float x) {
-  return 0.5f * x * (1.0f + erf_as(x * 0.70710678118654752f));
+  const float a = fabsf(x);
+  float q = fmaf(a, fmaf(a, fmaf(a, fmaf(a, fmaf(a, fmaf(a, 5.382975e-06f, 4.889063564e-05f),
+                                                   3.8003575e-05f),
+                                          0.003277626324f),
+                                 0.02114100615f),
+                        0.04986734697f),
+               1.0f);
+  q *= q;
+  q *= q;
+  q *= q;
+  q *= q;
+  const float e = copysignf(1.0f - __builtin_amdgcn_rcpf(q), x);
+  const float h = 0.5f * x;
+  return fmaf(h, e, h);
 }
 
 __device__ __forceinline__ float gelu_grad(float x) {
@@ -302,6 +318,15 @@ __global__ __launch_bounds__(WM * 64) void k_gemm_dma16(GemmArgs g) {
   const int logical = (int)(blockIdx.x % 8) * per_xcd + (int)(blockIdx.x / 8);
   if (logical >= total) return;
   const long m0 = (long)(logical / ntn) * BM, n0 = (long)(logical % ntn) * BN;
+  // the tile's bias in LDS (published by the barrier below) so that the
+  // epilogue does not wait on global loads per feature tile
+  __shared__ __attribute__((aligned(16))) float bias_s[BN];
+  for (int c = tid; c < BN / 4; c += WM * 64) {
+    float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (g.bias && n0 + 4 * c < g.N) v = *(const float4 *)(g.bias + n0 + 4 * c);
+    *(float4 *)&bias_s[4 * c] = v;
+  }
+  __syncthreads();
 
   // per-lane byte offsets of this wave's DMA rows within the tile (rows past
   // M or N clamped to the last valid one) and the wave-uniform tile bases;
@@ -409,8 +434,7 @@ __global__ __launch_bounds__(WM * 64) void k_gemm_dma16(GemmArgs g) {
       for (int i = 0; i < TM16; ++i) u[o][i] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int j = 0; j < TN16; ++j) {
-      float4 b = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-      if (j * 16 < g.N) b = *(const float4 *)(g.bias + j * 16 + hf);
+      const float4 b = *(const float4 *)&bias_s[j * 16 + hf];
       s16x4 w[TO];
 #pragma unroll
       for (int o = 0; o < TO; ++o)
@@ -443,22 +467,32 @@ __global__ __launch_bounds__(WM * 64) void k_gemm_dma16(GemmArgs g) {
     }
     return;
   }
+  // per-lane row bases (the lane's cell and first feature) and wave-uniform
+  // offsets of each 16-feature tile
+  const bool tc = g.tiled & TILED_C;
+  long rb[TM16];
+  bool live[TM16];
+#pragma unroll
+  for (int i = 0; i < TM16; ++i) {
+    const long row = m0 + wave * TM16 * 16 + i * 16 + (lane & 15);
+    live[i] = row < g.M;
+    rb[i] = row;
+  }
 #pragma unroll
   for (int j = 0; j < TN16; ++j) {
-    if (n0 + j * 16 >= g.N) break;
-    const long col = n0 + j * 16 + hf;
-    float4 b = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    if (g.bias) b = *(const float4 *)(g.bias + col);
+    const long cj = n0 + j * 16;  // uniform
+    if (cj >= g.N) break;
+    const float4 b = *(const float4 *)&bias_s[j * 16 + hf];
 #pragma unroll
     for (int i = 0; i < TM16; ++i) {
-      const long row = m0 + wave * TM16 * 16 + i * 16 + (lane & 15);
-      if (row >= g.M) continue;
+      if (!live[i]) continue;
+      const long row = rb[i];
       const float4 v = make_float4(acc[i][j][0] + b.x, acc[i][j][1] + b.y, acc[i][j][2] + b.z,
                                    acc[i][j][3] + b.w);
       if (EPI == EPI_F32) {
-        *(float4 *)(g.Cf + row * g.ldcf + col) = v;
+        *(float4 *)(g.Cf + row * g.ldcf + hf + cj) = v;
       } else if (EPI == EPI_GELU) {
-        if (g.Z) *(float4 *)(g.Z + row * g.ldz + col) = v;
+        if (g.Z) *(float4 *)(g.Z + row * g.ldz + hf + cj) = v;
         const float4 h = make_float4(gelu(v.x), gelu(v.y), gelu(v.z), gelu(v.w));
         if (g.Cb) {
           const bf16x2 lo = __builtin_convertvector((f32x2){h.x, h.y}, bf16x2);
@@ -466,16 +500,16 @@ __global__ __launch_bounds__(WM * 64) void k_gemm_dma16(GemmArgs g) {
           uint2 o;
           o.x = __builtin_bit_cast(unsigned, lo);
           o.y = __builtin_bit_cast(unsigned, hi);
-          const long at = (g.tiled & TILED_C) ? (col / 32) * g.ldcb + row * 32 + col % 32
-                                              : row * g.ldcb + col;
-          *(uint2 *)(g.Cb + at) = o;
+          u16 *const at = tc ? g.Cb + (row * 32 + hf) + ((cj / 32) * g.ldcb + cj % 32)
+                             : g.Cb + (row * g.ldcb + hf) + cj;
+          *(uint2 *)at = o;
         }
-        if (g.Cf) *(float4 *)(g.Cf + row * g.ldcf + col) = h;
+        if (g.Cf) *(float4 *)(g.Cf + row * g.ldcf + hf + cj) = h;
       } else if (EPI == EPI_GELU_Q8) {
-        const long at = (g.tiled & TILED_C) ? (col / 128) * g.ldcq + row * 128 + col % 128
-                                            : row * g.ldcq + col;
-        *(unsigned *)(g.Cq + at) = e4m3x4(gelu(v.x) * g.qinv, gelu(v.y) * g.qinv,
-                                          gelu(v.z) * g.qinv, gelu(v.w) * g.qinv);
+        uint8_t *const at = tc ? g.Cq + (row * 128 + hf) + ((cj / 128) * g.ldcq + cj % 128)
+                               : g.Cq + (row * g.ldcq + hf) + cj;
+        *(unsigned *)at = e4m3x4(gelu(v.x) * g.qinv, gelu(v.y) * g.qinv, gelu(v.z) * g.qinv,
+                                 gelu(v.w) * g.qinv);
       }
     }
   }
@@ -682,6 +716,13 @@ __global__ __launch_bounds__(WM * 64) void k_gemm8_dma16(GemmArgs g) {
   const int logical = (int)(blockIdx.x % 8) * per_xcd + (int)(blockIdx.x / 8);
   if (logical >= total) return;
   const long m0 = (long)(logical / ntn) * BM, n0 = (long)(logical % ntn) * BN;
+  __shared__ __attribute__((aligned(16))) float bias_s[BN];  // as in k_gemm_dma16
+  for (int c = tid; c < BN / 4; c += WM * 64) {
+    float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (g.bias && n0 + 4 * c < g.N) v = *(const float4 *)(g.bias + n0 + 4 * c);
+    *(float4 *)&bias_s[4 * c] = v;
+  }
+  __syncthreads();
 
   const bool ta = g.tiled & TILED_A, tb = g.tiled & TILED_B;
   const uint8_t *const sA = g.A8 + m0 * (ta ? BK : g.lda);
@@ -758,8 +799,7 @@ __global__ __launch_bounds__(WM * 64) void k_gemm8_dma16(GemmArgs g) {
   for (int j = 0; j < TN16; ++j) {
     if (n0 + j * 16 >= g.N) break;
     const long col = n0 + j * 16 + hf;
-    float4 b = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    if (g.bias) b = *(const float4 *)(g.bias + col);
+    const float4 b = *(const float4 *)&bias_s[j * 16 + hf];
 #pragma unroll
     for (int i = 0; i < TM16; ++i) {
       const long row = m0 + wave * TM16 * 16 + i * 16 + (lane & 15);
