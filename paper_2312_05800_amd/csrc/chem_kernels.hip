@@ -84,16 +84,20 @@ __device__ __forceinline__ bool grp_any(bool b) {
 template <int G>
 struct GLds {
   double *C, *hs, *gs, *qs, *J;
-  __device__ GLds(double *base, int R) {
+  int js;  // row stride of J
+  __device__ GLds(double *base, int R, int n) {
     C = base;
     hs = C + G;
     gs = hs + G;
     qs = gs + G;
     J = qs + R;
+    js = stride(n);
   }
-  static constexpr int JS = G + 1;  // row stride of J (odd, spreads banks)
-  __host__ __device__ static size_t doubles(int R) {
-    const size_t j = (size_t)G * JS, k = 2 * (size_t)R;
+  // odd row stride (2 js banks apart: lanes reading one column hit distinct
+  // banks) and only the n rows of the n x n matrix
+  __host__ __device__ static int stride(int n) { return n | 1; }
+  __host__ __device__ static size_t doubles(int R, int n) {
+    const size_t j = (size_t)n * stride(n), k = 2 * (size_t)R;
     return 3 * G + (size_t)R + (j > k ? j : k);
   }
 };
@@ -204,7 +208,7 @@ __device__ __forceinline__ void eval_cell(const DevMech &M, const GLds<G> &L, in
   const double dcpdT = grp_sum<G>(Yk * RG * dcpR * iWk);
   const double sumCpW = grp_sum<G>(isSp ? RG * cpR * wd : 0.0);
   const double sumHqT = grp_sum<G>(sumHq);
-  double *Jrow = L.J + l * GLds<G>::JS;
+  double *Jrow = L.J + l * L.js;
   if (l < n)
     for (int j = 0; j < n; ++j) Jrow[j] = 0.0;
   wave_sync();
@@ -258,7 +262,7 @@ __device__ __forceinline__ void eval_cell(const DevMech &M, const GLds<G> &L, in
 }
 
 // LU with partial pivoting of the n x n matrix held in LDS, row l owned by
-// lane l (stride JS).  Pivot of step k: the not-yet-eliminated row with the
+// lane l (odd row stride).  Pivot of step k: the not-yet-eliminated row with the
 // largest |a_ik| (NaN counts as largest), ties to the lowest row.  Rows do not
 // move: lane l records the step at which it became pivot (mystep) and the
 // inverse of its diagonal; multipliers overwrite the eliminated entries.
@@ -267,7 +271,7 @@ __device__ __forceinline__ void eval_cell(const DevMech &M, const GLds<G> &L, in
 // non-finite pivot.
 template <int G>
 __device__ __forceinline__ bool lu_factor(double *A, int l, int n, int &mystep, double &invd) {
-  constexpr int JS = GLds<G>::JS;
+  const int JS = GLds<G>::stride(n);
   double *row = A + l * JS;
   bool done = (l >= n);
   mystep = done ? l : -1;
@@ -319,18 +323,19 @@ __device__ __forceinline__ int pivot_lane(int mystep, int k, int gbase) {
 template <int G>
 __device__ __forceinline__ double lu_solve(const double *A, int l, int n, int mystep, double invd,
                                            int gbase, double b) {
-  constexpr int JS = GLds<G>::JS;
+  const int JS = GLds<G>::stride(n);
   const double *row = A + l * JS;
+  const bool real = l < n;  // lanes past n own no row (none is stored for them)
   for (int k = 0; k < n; ++k) {
     const int src = pivot_lane<G>(mystep, k, gbase);
     const double zk = __shfl(b, src, G);
-    if (mystep > k) b = fma(-row[k], zk, b);
+    if (real && mystep > k) b = fma(-row[k], zk, b);
   }
   double x = 0.0;
   for (int k = n - 1; k >= 0; --k) {
     const int src = pivot_lane<G>(mystep, k, gbase);
     const double xk = __shfl(b * invd, src, G);
-    if (mystep < k) b = fma(-row[k], xk, b);
+    if (real && mystep < k) b = fma(-row[k], xk, b);
     if (l == k) x = xk;
   }
   return x;
@@ -380,7 +385,7 @@ __global__ __launch_bounds__(64) void k_rates(DevMech M, int64_t N, int64_t ld, 
   constexpr int CPW = 64 / G;
   const int lane = threadIdx.x;
   const int g = lane / G, l = lane % G;
-  GLds<G> L(lds + g * GLds<G>::doubles(M.R), M.R);
+  GLds<G> L(lds + g * GLds<G>::doubles(M.R, M.n), M.R, M.n);
   for (int64_t base = (int64_t)blockIdx.x * CPW; base < N; base += (int64_t)gridDim.x * CPW) {
     const int64_t cell = base + g;
     if (cell >= N) break;  // group-uniform
@@ -411,7 +416,7 @@ __global__ __launch_bounds__(64) void k_step(DevMech M, StepArgs A) {
   const int lane = threadIdx.x;
   const int g = lane / G, l = lane % G, gbase = g * G;
   const int n = M.n;
-  GLds<G> L(lds + g * GLds<G>::doubles(M.R), M.R);
+  GLds<G> L(lds + g * GLds<G>::doubles(M.R, M.n), M.R, M.n);
   const StepOpts &o = A.o;
 
   // per-cell state (group-uniform scalars are replicated in every lane)
@@ -582,8 +587,8 @@ __global__ __launch_bounds__(64) void k_step(DevMech M, StepArgs A) {
 }
 
 template <int G>
-size_t lds_bytes(int R, int cpw) {
-  return (size_t)cpw * GLds<G>::doubles(R) * sizeof(double);
+size_t lds_bytes(int R, int n, int cpw) {
+  return (size_t)cpw * GLds<G>::doubles(R, n) * sizeof(double);
 }
 
 int group_size(int n) { return n <= 16 ? 16 : (n <= 32 ? 32 : 64); }
@@ -612,8 +617,8 @@ chem_status launch_rates(const chem_mech *m, int64_t N, int64_t ld, const double
   const int cpw = 64 / G;
   int64_t blocks = (N + cpw - 1) / cpw;
   if (blocks > 65536) blocks = 65536;
-  size_t sh = G == 16 ? lds_bytes<16>(m->R, cpw)
-                      : (G == 32 ? lds_bytes<32>(m->R, cpw) : lds_bytes<64>(m->R, cpw));
+  size_t sh = G == 16 ? lds_bytes<16>(m->R, m->d.n, cpw)
+                      : (G == 32 ? lds_bytes<32>(m->R, m->d.n, cpw) : lds_bytes<64>(m->R, m->d.n, cpw));
   chem_status st = check_lds(sh, nullptr);
   if (st != CHEM_OK) return st;
   ProfScope prof("chem_rates", s);
@@ -644,8 +649,8 @@ chem_status launch_step(const chem_mech *m, int64_t N, int64_t ld, double dt,
              stats,   index, o,           m->counters, n_dev, flags, sets, set_off, n_sets};
   const int G = group_size(m->d.n);
   const int cpw = 64 / G;
-  size_t sh = G == 16 ? lds_bytes<16>(m->R, cpw)
-                      : (G == 32 ? lds_bytes<32>(m->R, cpw) : lds_bytes<64>(m->R, cpw));
+  size_t sh = G == 16 ? lds_bytes<16>(m->R, m->d.n, cpw)
+                      : (G == 32 ? lds_bytes<32>(m->R, m->d.n, cpw) : lds_bytes<64>(m->R, m->d.n, cpw));
   int cus = 0;
   chem_status st = check_lds(sh, &cus);
   if (st != CHEM_OK) return st;
