@@ -877,14 +877,20 @@ __device__ __forceinline__ float boxcox_fast(float y, float lam) {
 }
 
 // One thread per cell: raw features (T, p, Box-Cox of Y), the optional
-// out-of-distribution bit, z-scored BF16 row of X.
+// out-of-distribution bit, z-scored BF16 row of X.  DINP > 0 fixes the padded
+// width at compile time, so all of a cell's loads are issued before the first
+// one is used.
+template <int DINP>
 __global__ void k_features(FeatArgs a) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
+  const int dinp = DINP > 0 ? DINP : a.dinp;
   const int64_t c = a.index ? a.index[i] : i;
-  u16 *out = a.X + i * a.dinp;
+  u16 *out = a.X + i * dinp;
   bool outside = false;
-  for (int j0 = 0; j0 < a.dinp; j0 += 8) {
+#pragma unroll
+  for (int j0 = 0; j0 < (DINP > 0 ? DINP : 1 << 30); j0 += 8) {
+    if (DINP == 0 && j0 >= dinp) break;
     float z[8];
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
@@ -1239,6 +1245,7 @@ __global__ __launch_bounds__(128, 4) void k_post(chem::DevMech M, PostArgs a) {
   }
 }
 
+
 // ---------------------------------------------------------- statistics
 
 // Partial statistics of the training features: block (b, f) covers feature f
@@ -1408,7 +1415,10 @@ chem_status quant_e4m3(const float *src, long ld_src, int rows, int cols, uint8_
 chem_status features(const FeatArgs &a, hipStream_t s) {
   if (a.n <= 0) return CHEM_OK;
   chem::ProfScope prof("ann_features", s);
-  hipLaunchKernelGGL(k_features, dim3(nblk(a.n, 256)), dim3(256), 0, s, a);
+  if (a.dinp == 32)
+    hipLaunchKernelGGL(k_features<32>, dim3(nblk(a.n, 256)), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_features<0>, dim3(nblk(a.n, 256)), dim3(256), 0, s, a);
   CHEM_HIP(hipGetLastError());
   return CHEM_OK;
 }
