@@ -44,7 +44,8 @@ struct ann_model {
   float *Wm[ann::NLAYER] = {}, *bm[ann::NLAYER] = {};  // FP32 master parameters
   u16 *Wb[ann::NLAYER] = {};                           // BF16 copies used by the GEMMs
   u16 *Wt[ann::NLAYER] = {};     // K-blocked BF16 copies for the large-batch forward path
-  bool wt_stale = true;          // Wt behind Wb (set on every weight change)
+  u16 *W2p = nullptr;            // second layer K-blocked in the fused kernel's K order
+  bool wt_stale = true;          // Wt, W2p behind Wb (set on every weight change)
   float *mW[ann::NLAYER] = {}, *vW[ann::NLAYER] = {}, *mb[ann::NLAYER] = {},
         *vb[ann::NLAYER] = {};
   float *gW[ann::NLAYER] = {}, *gb[ann::NLAYER] = {};
@@ -309,6 +310,7 @@ extern "C" chem_status ann_create(const ann_arch *arch, uint64_t seed, ann_model
     off = align256(off + bytes);
     return o;
   };
+  const size_t oW2p = sect(layer_elems(m->L[1]) * 2);
   for (int l = 0; l < 4; ++l) {
     const size_t e = layer_elems(m->L[l]), nb = m->L[l].doutp;
     oW[l] = sect(e * 4);
@@ -336,6 +338,7 @@ extern "C" chem_status ann_create(const ann_arch *arch, uint64_t seed, ann_model
     return hip_fail(e, "ann_create: hipMemset");
   }
   unsigned char *b = (unsigned char *)m->params;
+  m->W2p = (u16 *)(b + oW2p);
   for (int l = 0; l < 4; ++l) {
     m->Wm[l] = (float *)(b + oW[l]);
     m->bm[l] = (float *)(b + ob[l]);
@@ -532,19 +535,25 @@ bool tiled_path(const ann_model *m, int64_t n) {
   return b.doutp % 400 == 0 && (c.doutp % 416 == 0 || c.doutp % 400 == 0);
 }
 
+// keep_h1: write the first two layers' activations row-major to H[0], H[1]
+// (no fused first two layers, no K-blocked layouts), for the FP8 calibration
+// that reads their first n rows
 chem_status forward_chunk(ann_model *m, int64_t n, int64_t ld, const double *T, const double *p,
                           const double *Y, float *U, int ldu, uint8_t *ood, float ood_margin,
-                          hipStream_t s) {
+                          hipStream_t s, bool keep_h1 = false) {
   ann::FeatArgs fa{n, ld, T, p, Y, nullptr, m->n_out, m->L[0].dinp, m->nm.mu_in, m->nm.sd_in,
                    m->nm.lambda, m->X, ood, m->nm.lo, m->nm.hi, ood_margin};
   chem_status st = ann::features(fa, s);
   if (st != CHEM_OK) return st;
-  const bool tl = tiled_path(m, n);
+  const bool tl = !keep_h1 && tiled_path(m, n);
   const long cap = (long)m->wi.cap;  // rows between K-blocks of the activations
-  if (tl && !m->use_fp8 && m->wt_stale) {
+  if (!m->use_fp8 && m->wt_stale) {
     for (int l = 1; l <= 2; ++l)
       if ((st = ann::tile_bf16(m->L[l].doutp, m->L[l].dinp, m->Wb[l], m->Wt[l], s)) != CHEM_OK)
         return st;
+    if ((st = ann::tile_bf16(m->L[1].doutp, m->L[1].dinp, m->Wb[1], m->W2p, s, true)) !=
+        CHEM_OK)
+      return st;
     m->wt_stale = false;
   }
   if (m->use_fp8) {
@@ -608,7 +617,32 @@ chem_status forward_chunk(ann_model *m, int64_t n, int64_t ld, const double *T, 
   }
   const u16 *in = m->X;
   bool in_tiled = false;  // X (K = 32) is one K-block either way
-  for (int l = 0; l < 4; ++l) {
+  int l0 = 0;
+  {
+    // the first two layers in one kernel (the 1600-wide activations stay on
+    // chip) when their shapes allow it
+    const ann::Layer &L0 = m->L[0], &L1 = m->L[1];
+    ann::Mlp12Args f{};
+    f.M = (int)n;
+    f.N = L1.doutp;
+    f.K = L1.dinp;
+    f.X = m->X;
+    f.W1 = m->Wb[0];
+    f.b1 = m->bm[0];
+    f.W2p = m->W2p;
+    f.ldw2 = (long)L1.doutp * 32;
+    f.b2 = m->bm[1];
+    f.H = m->H[1];
+    f.ldh = tl ? cap * 32 : L1.doutp;
+    f.tiled = tl;
+    if (!keep_h1 && L0.dinp == 32 && L0.doutp == L1.dinp && ann::mlp12_ok(f)) {
+      if ((st = ann::mlp12(f, s, "mlp_l12")) != CHEM_OK) return st;
+      in = m->H[1];
+      in_tiled = tl;
+      l0 = 2;
+    }
+  }
+  for (int l = l0; l < 4; ++l) {
     const ann::Layer &L = m->L[l];
     ann::GemmArgs g{};
     g.M = (int)n;
@@ -1065,7 +1099,7 @@ extern "C" chem_status ann_quantize_fp8(ann_model *m, chem_batch calib, const do
   if ((st = grow_infer(m, n)) != CHEM_OK) return st;
   const bool prev = m->use_fp8;
   m->use_fp8 = false;  // calibrate on the BF16 activations
-  st = forward_chunk(m, n, calib.ld, T, p, Y, m->U, m->L[3].doutp, nullptr, 0.0f, s);
+  st = forward_chunk(m, n, calib.ld, T, p, Y, m->U, m->L[3].doutp, nullptr, 0.0f, s, true);
   m->use_fp8 = prev;
   if (st != CHEM_OK) return st;
   m->n2p = fp8_n2p(m);

@@ -74,6 +74,32 @@ chem_status gemm(const GemmArgs &g, bool AK, bool BK, int epi, hipStream_t s,
 // Whether gemm() can run this forward layer with EPI_GELU_NEXT (the output
 // layer fused into its epilogue).
 bool gemm_fuses_next(const GemmArgs &g);
+// The first two hidden layers in one kernel: H = GELU(W2 GELU(W1 x + b1) + b2)
+// for every cell, the first layer recomputed per K-step of the second from the
+// cell's 32 inputs, so its activations never reach HBM.
+struct Mlp12Args {
+  int M, N, K;      // cells, second-layer outputs, first-layer outputs
+  const u16 *X;     // [M][32] BF16 network inputs
+  const u16 *W1;    // [K][32] BF16 first-layer weights
+  const float *b1;  // [K]
+  const u16 *W2p;   // second-layer weights [N][K] K-blocked by 32, each block
+                    // permuted by mlp12_slot (tile_bf16 with permute = true)
+  long ldw2;        // elements between K-blocks of W2p (>= 32 N)
+  const float *b2;  // [N]
+  u16 *H;           // BF16 output: [M][ldh] row-major, or K-blocked by 32
+  long ldh;         // (tiled: elements between K-blocks) when tiled is set
+  bool tiled;
+};
+// Position of first-layer feature f (0..31 within one K-step) in mlp12's
+// second-layer K-step: the MFMA leaves features 4g..4g+3 and 16+4g..16+4g+3
+// with the lanes of 16-lane group g, which supply K positions 8g..8g+7.
+__host__ __device__ inline int mlp12_slot(int f) {
+  return 8 * ((f & 15) >> 2) + 4 * (f >> 4) + (f & 3);
+}
+// Whether mlp12() takes this shape (32 inputs, K a multiple of 32 up to
+// 2048, N a multiple of 400, aligned operands).
+bool mlp12_ok(const Mlp12Args &g);
+chem_status mlp12(const Mlp12Args &g, hipStream_t s, const char *label);
 // E4M3 x E4M3 GEMM (both K-contiguous, K a multiple of 64), epi GELU or GELU_Q8.
 chem_status gemm8(const GemmArgs &g, int epi, hipStream_t s, const char *label);
 // max |x| over n BF16 (bf16 = true) or FP32 values, into part[0..nparts)
@@ -123,8 +149,11 @@ chem_status sum_splits(int64_t n, int S, const float *part, long stride, float *
 chem_status adam(int64_t n, float *W, const float *g, float *m, float *v, u16 *Wb, float lr,
                  float b1, float b2, float eps, float bc1, float bc2, hipStream_t s);
 chem_status to_bf16(int64_t n, const float *src, u16 *dst, hipStream_t s);
-// dst [K/32][N][32] from src [N][K] (BF16, K a multiple of 32)
-chem_status tile_bf16(int N, int K, const u16 *src, u16 *dst, hipStream_t s);
+// dst [K/32][N][32] from src [N][K] (BF16, K a multiple of 32); with permute,
+// element k % 32 of each block goes to position mlp12_slot(k % 32) (the K
+// order in which mlp12 produces the first layer's features)
+chem_status tile_bf16(int N, int K, const u16 *src, u16 *dst, hipStream_t s,
+                      bool permute = false);
 
 struct PostArgs {
   int64_t n, ld;

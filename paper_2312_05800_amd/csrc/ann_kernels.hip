@@ -544,6 +544,230 @@ chem_status gemm_dma16_cfg(const GemmArgs &g, int epi, hipStream_t s) {
   return CHEM_OK;
 }
 
+// ------------------------------------------- fused first two layers
+// H[cell][n] = GELU(b2 + sum_k W2[n][k] GELU(b1[k] + W1[k] . x[cell])) in one
+// kernel: each 32-feature K-step of the second layer is produced in
+// registers by the first layer (K = 32: one v_mfma_f32_16x16x32_bf16 per
+// 16 features x 16 cells, the bias as its C input) from the block's inputs,
+// so the 1600-wide first activation is neither written nor read back.  The
+// first layer's result leaves lane l with cell l % 16 and features 4g..4g+3
+// and 16+4g..16+4g+3 (g = l / 16) of the K-step; the second layer's MFMA
+// takes K positions 8g..8g+7 from lane group g, so the step's features enter
+// in that permuted order and the second layer's weights are stored with the
+// same permutation within each 32-wide K-block (mlp12_slot).  The tile is
+// the second layer's 256 cells x 400 features: the block's two feature
+// tiles each recompute the first layer for their cells (8 % more MFMA work,
+// twice the GELUs of the first layer).  The ring stage of K-step kt carries
+// the second layer's weights of step kt and the first layer's of step kt + 1,
+// whose GELUs then overlap the multiplications of step kt.
+constexpr int MLP12_KMAX = 2048;
+constexpr int PHASE = 4;
+
+template <int TN16>
+struct Mlp12Tile {
+  static constexpr int WM = 8, TM16 = 2, BK = 32, STAGES = 3;
+  static constexpr int BM = WM * TM16 * 16, BN = TN16 * 16;
+  static constexpr int R1 = 32;  // first-layer weight rows of one K-step
+  static constexpr int ROWS = R1 + BN;
+};
+
+// One block's tile; MULFIRST: this wave multiplies before it produces (the
+// whole body is instantiated per order, so that no accumulator crosses a
+// branch).
+template <int TN16, bool MULFIRST>
+__device__ __forceinline__ void mlp12_tile(const Mlp12Args &g, u16 *S, float *b1_s,
+                                           float *bias_s, int wave) {
+  using TL = Mlp12Tile<TN16>;
+  constexpr int WM = TL::WM, TM16 = TL::TM16, BK = TL::BK, STAGES = TL::STAGES;
+  constexpr int BM = TL::BM, BN = TL::BN, R1 = TL::R1, ROWS = TL::ROWS;
+  constexpr int NI = ROWS / 16;
+  constexpr int NPW = (NI + WM - 1) / WM;
+  constexpr int NMIN = NI / WM;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int ntn = (g.N + BN - 1) / BN;
+  const int ntm = (g.M + BM - 1) / BM;
+  const int total = ntn * ntm;
+  const int per_xcd = (total + 7) / 8;
+  const int logical = (int)(blockIdx.x % 8) * per_xcd + (int)(blockIdx.x / 8);
+  if (logical >= total) return;
+  const long m0 = (long)(logical / ntn) * BM, n0 = (long)(logical % ntn) * BN;
+  for (int c = tid; c < BN / 4; c += WM * 64) {
+    float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (n0 + 4 * c < g.N) v = *(const float4 *)(g.b2 + n0 + 4 * c);
+    *(float4 *)&bias_s[4 * c] = v;
+  }
+  for (int c = tid; c < g.K / 4; c += WM * 64) *(float4 *)&b1_s[4 * c] = *(const float4 *)(g.b1 + 4 * c);
+
+  // the wave's 32 cells as the first layer's B operand (lane: cell l % 16 of
+  // tile i, inputs 8g..8g+7); rows past M clamped (never stored)
+  const int cc = lane >> 4, hf = 4 * cc;
+  bf16x8 xin[TM16];
+#pragma unroll
+  for (int i = 0; i < TM16; ++i) {
+    long row = m0 + wave * TM16 * 16 + i * 16 + (lane & 15);
+    if (row >= g.M) row = g.M - 1;
+    xin[i] = *(const bf16x8 *)(g.X + row * 32 + cc * 8);
+  }
+  __syncthreads();  // b1_s, bias_s
+
+  // first layer for the 32 features of K-step kt: w1[t] = weight rows
+  // 16t + l % 16 of the step (the MFMA's A operand)
+  auto layer1 = [&](const bf16x8(&w1)[2], int kt, bf16x8(&h)[TM16]) __attribute__((always_inline)) {
+    const float4 c0 = *(const float4 *)&b1_s[kt * 32 + hf];
+    const float4 c1 = *(const float4 *)&b1_s[kt * 32 + 16 + hf];
+#pragma unroll
+    for (int i = 0; i < TM16; ++i) {
+      f32x4 z0 = (f32x4){c0.x, c0.y, c0.z, c0.w}, z1 = (f32x4){c1.x, c1.y, c1.z, c1.w};
+      z0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1[0], xin[i], z0, 0, 0, 0);
+      z1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1[1], xin[i], z1, 0, 0, 0);
+      const bf16x2 a = __builtin_convertvector((f32x2){gelu(z0[0]), gelu(z0[1])}, bf16x2);
+      const bf16x2 b = __builtin_convertvector((f32x2){gelu(z0[2]), gelu(z0[3])}, bf16x2);
+      const bf16x2 c = __builtin_convertvector((f32x2){gelu(z1[0]), gelu(z1[1])}, bf16x2);
+      const bf16x2 d = __builtin_convertvector((f32x2){gelu(z1[2]), gelu(z1[3])}, bf16x2);
+      h[i] = (bf16x8){a[0], a[1], b[0], b[1], c[0], c[1], d[0], d[1]};
+    }
+  };
+
+  // K-step 0 of the first layer straight from global memory
+  const int nk = g.K / BK;
+  bf16x8 h[TM16];
+  {
+    bf16x8 w1[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+      w1[t] = *(const bf16x8 *)(g.W1 + (t * 16 + (lane & 15)) * 32 + cc * 8);
+    layer1(w1, 0, h);
+  }
+
+  // DMA rows: the first R1 rows of a stage are the first layer's weights of
+  // the next K-step, then BN rows of the second layer's (clamped past N)
+  const u16 *const sB = g.W2p + n0 * BK;
+  unsigned voff[NPW];
+#pragma unroll
+  for (int i = 0; i < NPW; ++i) {
+    const int gi = i * WM + wave;
+    const int row = gi * 16 + (lane >> 2);
+    const int chunk = (lane & 3) ^ swz(row);
+    unsigned o = 0;
+    if (gi < NI) {
+      if (row < R1) {
+        o = (unsigned)((row * BK + chunk * 8) * 2);
+      } else {
+        const long n = n0 + (row - R1) < g.N ? n0 + (row - R1) : g.N - 1;
+        o = (unsigned)(((n - n0) * BK + chunk * 8) * 2);
+      }
+    }
+    voff[i] = o;
+  }
+  const unsigned lds0 =
+      (unsigned)(uintptr_t)(__attribute__((address_space(3))) u16 *)(S);
+  auto issue = [&](int stage, int kt) {
+    const int k1 = kt + 1 < nk ? kt + 1 : nk - 1;
+#pragma unroll
+    for (int i = 0; i < NPW; ++i) {
+      const int gi = i * WM + wave;
+      if (gi < NI)
+        lds_dma16s(gi * 16 < R1 ? g.W1 + (long)k1 * R1 * BK : sB + kt * g.ldw2, voff[i],
+                   lds0 + (unsigned)((stage * ROWS + gi * 16) * BK * 2));
+    }
+  };
+
+  f32x4 acc[TM16][TN16];
+#pragma unroll
+  for (int i = 0; i < TM16; ++i)
+#pragma unroll
+    for (int j = 0; j < TN16; ++j) acc[i][j] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
+
+  issue(0, 0);
+  if (nk > 1) issue(1, 1);
+  for (int kt = 0; kt < nk; ++kt) {
+    // as in k_gemm_dma16: own loads of stage kt done, barrier publishes all
+    if (kt + 1 < nk)
+      asm volatile("s_waitcnt vmcnt(%0)\n\ts_barrier" : : "n"(NMIN) : "memory");
+    else
+      asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" : : : "memory");
+    if (kt + 2 < nk) issue((kt + 2) % STAGES, kt + 2);
+    const u16 *T = S + (kt % STAGES) * ROWS * BK;
+    // the next K-step's first-layer features (the last step recomputes its
+    // own, unused): VALU-heavy
+    bf16x8 hn[TM16];
+    auto produce = [&]() __attribute__((always_inline)) {
+      bf16x8 w1[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const int row = t * 16 + (lane & 15);
+        w1[t] = *(const bf16x8 *)&T[row * BK + ((cc ^ swz(row)) * 8)];
+      }
+      layer1(w1, kt + 1 < nk ? kt + 1 : kt, hn);
+    };
+    // this K-step of the second layer: MFMA-heavy
+    auto multiply = [&]() __attribute__((always_inline)) {
+#pragma unroll
+      for (int j = 0; j < TN16; ++j) {
+        const int row = R1 + j * 16 + (lane & 15);
+        const bf16x8 w = *(const bf16x8 *)&T[row * BK + ((cc ^ swz(row)) * 8)];
+#pragma unroll
+        for (int i = 0; i < TM16; ++i)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, h[i], acc[i][j], 0, 0, 0);
+      }
+    };
+    if (MULFIRST) {
+      multiply();
+      produce();
+    } else {
+      produce();
+      multiply();
+    }
+#pragma unroll
+    for (int i = 0; i < TM16; ++i) h[i] = hn[i];
+  }
+
+  // epilogue: bias + GELU, BF16 (lane: 4 consecutive features of one cell)
+  long rb[TM16];
+  bool live[TM16];
+#pragma unroll
+  for (int i = 0; i < TM16; ++i) {
+    rb[i] = m0 + wave * TM16 * 16 + i * 16 + (lane & 15);
+    live[i] = rb[i] < g.M;
+  }
+#pragma unroll
+  for (int j = 0; j < TN16; ++j) {
+    const long cj = n0 + j * 16;  // uniform
+    if (cj >= g.N) break;
+    const float4 b = *(const float4 *)&bias_s[j * 16 + hf];
+#pragma unroll
+    for (int i = 0; i < TM16; ++i) {
+      if (!live[i]) continue;
+      const long row = rb[i];
+      const bf16x2 lo = __builtin_convertvector(
+          (f32x2){gelu(acc[i][j][0] + b.x), gelu(acc[i][j][1] + b.y)}, bf16x2);
+      const bf16x2 hi = __builtin_convertvector(
+          (f32x2){gelu(acc[i][j][2] + b.z), gelu(acc[i][j][3] + b.w)}, bf16x2);
+      uint2 o;
+      o.x = __builtin_bit_cast(unsigned, lo);
+      o.y = __builtin_bit_cast(unsigned, hi);
+      u16 *const at = g.tiled ? g.H + (row * 32 + hf) + ((cj / 32) * g.ldh + cj % 32)
+                              : g.H + (row * g.ldh + hf) + cj;
+      *(uint2 *)at = o;
+    }
+  }
+}
+
+// waves (wave & PHASE) != 0 multiply before they produce: one wave's GELUs
+// can then overlap the other's MFMAs on the same SIMD
+template <int TN16>
+__global__ __launch_bounds__(512) void k_mlp12(Mlp12Args g) {
+  using TL = Mlp12Tile<TN16>;
+  __shared__ __attribute__((aligned(1024))) u16 S[TL::STAGES * TL::ROWS * TL::BK];
+  __shared__ __attribute__((aligned(16))) float b1_s[MLP12_KMAX];
+  __shared__ __attribute__((aligned(16))) float bias_s[TL::BN];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (wave & PHASE)
+    mlp12_tile<TN16, true>(g, S, b1_s, bias_s, wave);
+  else
+    mlp12_tile<TN16, false>(g, S, b1_s, bias_s, wave);
+}
+
 template <int WM, int WN, int TM, int TN>
 chem_status gemm_cfg(const GemmArgs &g, bool AK, bool BK, int epi, hipStream_t s) {
   constexpr int BM = WM * TM * 32, BN = WN * TN * 32;
@@ -888,7 +1112,8 @@ __global__ void k_features(FeatArgs a) {
   const int64_t c = a.index ? a.index[i] : i;
   u16 *out = a.X + i * dinp;
   bool outside = false;
-#pragma unroll
+  constexpr int UNROLL = DINP > 0 ? DINP / 8 : 1;
+#pragma unroll UNROLL
   for (int j0 = 0; j0 < (DINP > 0 ? DINP : 1 << 30); j0 += 8) {
     if (DINP == 0 && j0 >= dinp) break;
     float z[8];
@@ -1023,12 +1248,13 @@ __global__ void k_to_bf16(int64_t n, const float *src, u16 *dst) {
 
 // K-blocked copy: element (r, k) of src [R][K] (KB-element blocks) to
 // dst[(k / KB) R KB + r KB + k % KB]; one thread per element.
-template <typename T, int KB>
+template <typename T, int KB, bool PERM = false>
 __global__ void k_tile(int R, int K, const T *src, T *dst) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (int64_t)R * K) return;
   const int r = (int)(i / K), k = (int)(i % K);
-  dst[(int64_t)(k / KB) * R * KB + (int64_t)r * KB + k % KB] = src[i];
+  const int kk = PERM ? mlp12_slot(k % KB) : k % KB;
+  dst[(int64_t)(k / KB) * R * KB + (int64_t)r * KB + kk] = src[i];
 }
 
 // ----------------------------------------------------------------- post
@@ -1364,6 +1590,27 @@ chem_status gemm(const GemmArgs &g, bool AK, bool BK, int epi, hipStream_t s,
   return gemm_cfg<2, 2, 2, 2>(g, AK, BK, epi, s);
 }
 
+bool mlp12_ok(const Mlp12Args &g) {
+  auto al = [](const void *p, uintptr_t a) { return p && ((uintptr_t)p & (a - 1)) == 0; };
+  return g.K > 0 && g.K % 32 == 0 && g.K <= MLP12_KMAX && g.N > 0 && g.N % 400 == 0 &&
+         g.ldw2 >= 32L * g.N && g.ldw2 % 8 == 0 &&
+         (g.tiled ? g.ldh % 8 == 0 : (g.ldh >= g.N && g.ldh % 4 == 0)) && al(g.X, 16) &&
+         al(g.W1, 16) && al(g.W2p, 16) && al(g.b1, 16) && al(g.b2, 16) && al(g.H, 8);
+}
+
+chem_status mlp12(const Mlp12Args &g, hipStream_t s, const char *label) {
+  if (g.M <= 0) return CHEM_OK;
+  chem::ProfScope prof(label, s);
+  if (!mlp12_ok(g)) {
+    chem::set_error("mlp12: unsupported shape or misaligned operand");
+    return CHEM_EUNSUPPORTED;
+  }
+  const long total = (long)((g.M + 255) / 256) * (g.N / 400);
+  hipLaunchKernelGGL((k_mlp12<25>), dim3((unsigned)(((total + 7) / 8) * 8)), dim3(512), 0, s, g);
+  CHEM_HIP(hipGetLastError());
+  return CHEM_OK;
+}
+
 chem_status gemm8(const GemmArgs &g, int epi, hipStream_t s, const char *label) {
   if (g.M <= 0 || g.N <= 0) return CHEM_OK;
   if (g.K % 64 != 0 || g.lda % 16 != 0 || g.ldb % 16 != 0) {
@@ -1439,13 +1686,17 @@ chem_status l1_grad(int64_t n, int K, int doutp, const float *U, const float *Ut
   return CHEM_OK;
 }
 
-chem_status tile_bf16(int N, int K, const u16 *src, u16 *dst, hipStream_t s) {
+chem_status tile_bf16(int N, int K, const u16 *src, u16 *dst, hipStream_t s, bool permute) {
   if (K % 32 != 0) {
     chem::set_error("tile_bf16: K must be a multiple of 32");
     return CHEM_EINVAL;
   }
-  hipLaunchKernelGGL((k_tile<u16, 32>), dim3(nblk((int64_t)N * K, 256)), dim3(256), 0, s, N, K,
-                     src, dst);
+  if (permute)
+    hipLaunchKernelGGL((k_tile<u16, 32, true>), dim3(nblk((int64_t)N * K, 256)), dim3(256), 0, s,
+                       N, K, src, dst);
+  else
+    hipLaunchKernelGGL((k_tile<u16, 32>), dim3(nblk((int64_t)N * K, 256)), dim3(256), 0, s, N,
+                       K, src, dst);
   CHEM_HIP(hipGetLastError());
   return CHEM_OK;
 }

@@ -50,6 +50,9 @@ __device__ __forceinline__ double TC_S(int s, int j) {
                  : (s == 3 ? (j == 0 ? TC[3][0] : (j == 1 ? TC[3][1] : TC[3][2])) : 0.0));
 }
 __device__ __forceinline__ bool TNEWF_S(int s) { return s == 2 || s == 3; }
+// stage 0's f(y_n) is evaluated once per attempt, before the stage loop
+static_assert(TNEWF[0] && !TNEWF[1] && TNEWF[2] && TNEWF[3],
+              "TNEWF_S: stage 1 reuses f(y_n), stages 2 and 3 evaluate f at a new point");
 
 enum { CELL_OK = 0, CELL_MAX_STEPS = 1, CELL_H_UNDERFLOW = 2, CELL_NONFINITE = 3,
        CELL_SINGULAR = 4 };
