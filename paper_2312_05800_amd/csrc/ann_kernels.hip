@@ -563,6 +563,12 @@ chem_status gemm_dma16_cfg(const GemmArgs &g, int epi, hipStream_t s) {
 // the second layer's weights of step kt and the first layer's of step kt + 1,
 // whose GELUs then overlap the multiplications of step kt.
 constexpr int MLP12_KMAX = 2048;
+// second-layer weight fragments in flight ahead of their MFMAs; whether the
+// order of LDS reads, MFMAs (and MLP12_VALU VALU instructions between MFMA
+// pairs) is pinned for the scheduler
+constexpr int MLP12_PF = 2;
+constexpr bool MLP12_PIN = false;
+constexpr int MLP12_VALU = 0;
 constexpr int PHASE = 4;
 
 template <int TN16>
@@ -642,35 +648,24 @@ __device__ __forceinline__ void mlp12_tile(const Mlp12Args &g, u16 *S, float *b1
   }
 
   // DMA rows: the first R1 rows of a stage are the first layer's weights of
-  // the next K-step, then BN rows of the second layer's (clamped past N)
+  // the next K-step, then BN rows of the second layer's (all valid: N is a
+  // multiple of BN).  A 16-row group starts at a multiple of 16, so the
+  // swizzle of row 16 gi + l / 4 is (l / 16) & 3 for every group: one
+  // per-lane byte offset serves all of them, the rest is wave-uniform.
   const u16 *const sB = g.W2p + n0 * BK;
-  unsigned voff[NPW];
-#pragma unroll
-  for (int i = 0; i < NPW; ++i) {
-    const int gi = i * WM + wave;
-    const int row = gi * 16 + (lane >> 2);
-    const int chunk = (lane & 3) ^ swz(row);
-    unsigned o = 0;
-    if (gi < NI) {
-      if (row < R1) {
-        o = (unsigned)((row * BK + chunk * 8) * 2);
-      } else {
-        const long n = n0 + (row - R1) < g.N ? n0 + (row - R1) : g.N - 1;
-        o = (unsigned)(((n - n0) * BK + chunk * 8) * 2);
-      }
-    }
-    voff[i] = o;
-  }
+  const unsigned loff =
+      (unsigned)((lane >> 2) * BK * 2 + (((lane & 3) ^ ((lane >> 4) & 3)) * 16));
   const unsigned lds0 =
       (unsigned)(uintptr_t)(__attribute__((address_space(3))) u16 *)(S);
-  auto issue = [&](int stage, int kt) {
+  auto issue = [&](int stage, int kt) __attribute__((always_inline)) {
     const int k1 = kt + 1 < nk ? kt + 1 : nk - 1;
 #pragma unroll
     for (int i = 0; i < NPW; ++i) {
       const int gi = i * WM + wave;
       if (gi < NI)
-        lds_dma16s(gi * 16 < R1 ? g.W1 + (long)k1 * R1 * BK : sB + kt * g.ldw2, voff[i],
-                   lds0 + (unsigned)((stage * ROWS + gi * 16) * BK * 2));
+        lds_dma16s(gi * 16 < R1 ? g.W1 + ((long)k1 * R1 + gi * 16) * BK
+                                : sB + kt * g.ldw2 + (long)(gi * 16 - R1) * BK,
+                   loff, lds0 + (unsigned)((stage * ROWS + gi * 16) * BK * 2));
     }
   };
 
@@ -702,15 +697,29 @@ __device__ __forceinline__ void mlp12_tile(const Mlp12Args &g, u16 *S, float *b1
       }
       layer1(w1, kt + 1 < nk ? kt + 1 : kt, hn);
     };
-    // this K-step of the second layer: MFMA-heavy
+    // this K-step of the second layer: MFMA-heavy; the weight fragments are
+    // read MLP12_PF feature tiles ahead of their MFMAs
+    auto bfrag = [&](int j) __attribute__((always_inline)) {
+      const int row = R1 + j * 16 + (lane & 15);
+      return *(const bf16x8 *)&T[row * BK + ((cc ^ swz(row)) * 8)];
+    };
     auto multiply = [&]() __attribute__((always_inline)) {
+      bf16x8 wq[MLP12_PF];
+#pragma unroll
+      for (int q = 0; q < MLP12_PF; ++q) wq[q] = bfrag(q);
+      if (MLP12_PIN) __builtin_amdgcn_sched_group_barrier(0x100, MLP12_PF, 0);
 #pragma unroll
       for (int j = 0; j < TN16; ++j) {
-        const int row = R1 + j * 16 + (lane & 15);
-        const bf16x8 w = *(const bf16x8 *)&T[row * BK + ((cc ^ swz(row)) * 8)];
+        const bf16x8 w = wq[j % MLP12_PF];
+        if (j + MLP12_PF < TN16) wq[j % MLP12_PF] = bfrag(j + MLP12_PF);
 #pragma unroll
         for (int i = 0; i < TM16; ++i)
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, h[i], acc[i][j], 0, 0, 0);
+        if (MLP12_PIN) {
+          if (j + MLP12_PF < TN16) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+          __builtin_amdgcn_sched_group_barrier(0x008, TM16, 0);
+          if (MLP12_VALU) __builtin_amdgcn_sched_group_barrier(0x002, MLP12_VALU, 0);
+        }
       }
     };
     if (MULFIRST) {
