@@ -563,6 +563,9 @@ chem_status gemm_dma16_cfg(const GemmArgs &g, int epi, hipStream_t s) {
 // the second layer's weights of step kt and the first layer's of step kt + 1,
 // whose GELUs then overlap the multiplications of step kt.
 constexpr int MLP12_KMAX = 2048;
+// waves per block and 16-cell tiles per wave (block: MLP12_WM MLP12_TM16 16
+// cells x 400 features)
+constexpr int MLP12_WM = 8, MLP12_TM16 = 2;
 // second-layer weight fragments in flight ahead of their MFMAs; whether the
 // order of LDS reads, MFMAs (and MLP12_VALU VALU instructions between MFMA
 // pairs) is pinned for the scheduler
@@ -573,7 +576,7 @@ constexpr int PHASE = 4;
 
 template <int TN16>
 struct Mlp12Tile {
-  static constexpr int WM = 8, TM16 = 2, BK = 32, STAGES = 3;
+  static constexpr int WM = MLP12_WM, TM16 = MLP12_TM16, BK = 32, STAGES = 3;
   static constexpr int BM = WM * TM16 * 16, BN = TN16 * 16;
   static constexpr int R1 = 32;  // first-layer weight rows of one K-step
   static constexpr int ROWS = R1 + BN;
@@ -767,7 +770,7 @@ __device__ __forceinline__ void mlp12_tile(const Mlp12Args &g, u16 *S, float *b1
 // waves (wave & PHASE) != 0 multiply before they produce: one wave's GELUs
 // can then overlap the other's MFMAs on the same SIMD
 template <int TN16>
-__global__ __launch_bounds__(512) void k_mlp12(Mlp12Args g) {
+__global__ __launch_bounds__(MLP12_WM * 64) void k_mlp12(Mlp12Args g) {
   using TL = Mlp12Tile<TN16>;
   __shared__ __attribute__((aligned(1024))) u16 S[TL::STAGES * TL::ROWS * TL::BK];
   __shared__ __attribute__((aligned(16))) float b1_s[MLP12_KMAX];
@@ -1305,8 +1308,8 @@ constexpr int EMAX = 8;
 // Y0 + dY (kept in registers, KP >= K slots), the element sums of Y0 and of
 // Y0 - Y', the weighted normal matrix and h(T0, Y0); Y0 itself is not kept (it
 // is read again for RR).  Four waves per SIMD (a few spilled registers) beat
-// two spill-free ones by 1.25x: the kernel is latency-bound (FP64 Newton and
-// Cholesky chains per cell).
+// two spill-free ones: the kernel is latency-bound (FP64 Cholesky and Newton
+// chains per cell).
 template <int KP, int EP>
 __global__ __launch_bounds__(128, 4) void k_post(chem::DevMech M, PostArgs a) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1437,23 +1440,52 @@ __global__ __launch_bounds__(128, 4) void k_post(chem::DevMech M, PostArgs a) {
   if (!ok || !(res <= (double)a.residual_tol)) flag |= 2;
 
   if (flag == 0) {
-    // temperature from h(T, Y) = h(T0, Y0) by Newton in FP64
-    double T = T0;
-    for (int it = 0; it < 20; ++it) {
-      double h = 0.0, cp = 0.0;
-      tpowers(T, Tp);
+    // temperature from h(T, Y) = h(T0, Y0) by Newton in FP64.  h and c_p of
+    // the mixture are linear in Y: with every species in the NASA range it
+    // takes at a reference temperature, they are polynomials in T whose
+    // coefficients are the Y / W-weighted sums of the species' (hm: h/RT
+    // terms with the divisors folded in, cm: c_p/R terms), exact for
+    // tlo < T <= thi; a Newton step then costs O(1), and the sums are built
+    // again only if an iterate leaves that interval.
+    double hm[6], cm[5], tlo = 0.0, thi = -1.0;
+    auto mixture = [&](double Tr) __attribute__((always_inline)) {
+#pragma unroll
+      for (int q = 0; q < 6; ++q) hm[q] = 0.0;
+#pragma unroll
+      for (int q = 0; q < 5; ++q) cm[q] = 0.0;
+      tlo = -INFINITY;
+      thi = INFINITY;
 #pragma unroll
       for (int k = 0; k < KP; ++k) {
         if (k < K) {
-          double hRT, cpR;
-          species_h_cp(M, k, Tp, hRT, cpR);
-          h += yn[k] * RG * T * hRT * M.invW[k];
-          cp += yn[k] * RG * cpR * M.invW[k];
+          const double w = yn[k] * M.invW[k];
+          const double tm = M.Tmid[k];
+          const bool low = Tr <= tm;
+          thi = low ? fmin(thi, tm) : thi;
+          tlo = low ? tlo : fmax(tlo, tm);
+#pragma unroll
+          for (int q = 0; q < 6; ++q) {
+            const double lo = M.nasa_h[7 * k + q], hi = M.nasa_hh[7 * k + q];
+            hm[q] += w * (low ? lo : hi);
+          }
+#pragma unroll
+          for (int q = 0; q < 5; ++q) {
+            const double lo = M.nasa_lo[7 * k + q], hi = M.nasa_hi[7 * k + q];
+            cm[q] += w * (low ? lo : hi);
+          }
         }
       }
-      const double dT = (h - h0) / cp;
+    };
+    double T = T0;
+    for (int it = 0; it < 20; ++it) {
+      if (!(T > tlo && T <= thi)) mixture(T);
+      tpowers(T, Tp);
+      const double hRT = hm[0] + hm[1] * Tp[0] + hm[2] * Tp[1] + hm[3] * Tp[2] +
+                         hm[4] * Tp[3] + hm[5] * Tp[4];
+      const double cpR = cm[0] + cm[1] * Tp[0] + cm[2] * Tp[1] + cm[3] * Tp[2] + cm[4] * Tp[3];
+      const double dT = (RG * T * hRT - h0) / (RG * cpR);
       T -= dT;
-      if (fabs(dT) < 1e-9 * T) break;
+      if (!isfinite(T) || fabs(dT) < 1e-9 * T) break;
     }
     if (!isfinite(T) || !(T > 0.0)) flag |= 2;
     if (flag == 0) {
@@ -1616,8 +1648,10 @@ chem_status mlp12(const Mlp12Args &g, hipStream_t s, const char *label) {
     chem::set_error("mlp12: unsupported shape or misaligned operand");
     return CHEM_EUNSUPPORTED;
   }
-  const long total = (long)((g.M + 255) / 256) * (g.N / 400);
-  hipLaunchKernelGGL((k_mlp12<25>), dim3((unsigned)(((total + 7) / 8) * 8)), dim3(512), 0, s, g);
+  constexpr int BM = Mlp12Tile<25>::BM;
+  const long total = (long)((g.M + BM - 1) / BM) * (g.N / 400);
+  hipLaunchKernelGGL((k_mlp12<25>), dim3((unsigned)(((total + 7) / 8) * 8)), dim3(MLP12_WM * 64),
+                     0, s, g);
   CHEM_HIP(hipGetLastError());
   return CHEM_OK;
 }
