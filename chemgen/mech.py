@@ -28,10 +28,13 @@ Construction (all seeded, numpy PCG64):
   saturating curve from a 300 K value to a 3000 K value fixed by the atom count
   (2.5/3.5/4+0.5(n-3) and 2.5/4.5/3n-2 for mono-, di- and polyatomic), scaled
   by U(0.9, 1.1) with a seeded knee temperature.  Its NASA-7 fit (a1..a5) is a
-  least-squares fit on [200, 1000] K and [1000, 3500] K; a1 of the high range
-  is shifted for c_p continuity at 1000 K, a6/a7 of the low range reproduce
+  least-squares fit on [200, T_mid] K and [T_mid, 3500] K; a1 of the high range
+  is shifted for c_p continuity at T_mid, a6/a7 of the low range reproduce
   h_f and s at 298.15 K, and a6/a7 of the high range make h and s continuous
-  at 1000 K.
+  at T_mid.  T_mid = 1000 K for every species, unless the configuration has
+  ``tmid_range = (lo, hi)``: then each species' T_mid is drawn uniformly from
+  it by a generator of its own (seed + 7919), leaving the other draws as they
+  are.
 
 NASA array layout per species (17 doubles): T_low, T_mid, T_high,
 a1..a7 of the low range, a1..a7 of the high range.
@@ -188,7 +191,7 @@ def _s_poly(a, T):  # S/R without the a7 constant
     return a[0] * np.log(T) + a[1] * T + a[2] * T**2 / 2 + a[3] * T**3 / 3 + a[4] * T**4 / 4
 
 
-def _make_thermo(species, comp_counts, rng):
+def _make_thermo(species, comp_counts, rng, tmid=None):
     K = len(species)
     nasa = np.zeros((K, 17))
     hf = np.zeros(K)
@@ -210,19 +213,20 @@ def _make_thermo(species, comp_counts, rng):
             lo, hi = 4.0 + 0.5 * (n_at - 3), 3.0 * n_at - 2.0
         scale = 1.0 if n_at == 1 else rng.uniform(0.9, 1.1)
         theta = rng.uniform(500.0, 1500.0)
-        Tl = np.linspace(200.0, 1000.0, 81)
-        Th = np.linspace(1000.0, 3500.0, 126)
+        tm = 1000.0 if tmid is None else float(tmid[k])
+        Tl = np.linspace(200.0, tm, 81)
+        Th = np.linspace(tm, 3500.0, 126)
         al = _fit_range(Tl, _cp_curve(Tl, lo, hi, theta, scale))
         ah = _fit_range(Th, _cp_curve(Th, lo, hi, theta, scale))
-        cpl = sum(al[i] * 1000.0**i for i in range(5))
-        cph = sum(ah[i] * 1000.0**i for i in range(5))
+        cpl = sum(al[i] * tm**i for i in range(5))
+        cph = sum(ah[i] * tm**i for i in range(5))
         ah[0] += cpl - cph
         T0 = 298.15
         a6l = hf[k] / R_GAS - _h_poly(al, T0)
         a7l = s298[k] / R_GAS - _s_poly(al, T0)
-        a6h = (_h_poly(al, 1000.0) + a6l) - _h_poly(ah, 1000.0)
-        a7h = (_s_poly(al, 1000.0) + a7l) - _s_poly(ah, 1000.0)
-        nasa[k, 0:3] = (200.0, 1000.0, 3500.0)
+        a6h = (_h_poly(al, tm) + a6l) - _h_poly(ah, tm)
+        a7h = (_s_poly(al, tm) + a7l) - _s_poly(ah, tm)
+        nasa[k, 0:3] = (200.0, tm, 3500.0)
         nasa[k, 3:8] = al
         nasa[k, 8] = a6l
         nasa[k, 9] = a7l
@@ -279,7 +283,11 @@ def make_mechanism(cfg: str | dict, seed: int | None = None) -> Mech:
         for e in range(E):
             w += comp[k, e] * awt[e]
         W[k] = w
-    nasa, hf, s298 = _make_thermo(species, comp.sum(axis=1), rng)
+    tmid = None
+    if c.get("tmid_range") is not None:
+        trng = np.random.Generator(np.random.PCG64(seed + 7919))
+        tmid = trng.uniform(*c["tmid_range"], size=K)
+    nasa, hf, s298 = _make_thermo(species, comp.sum(axis=1), rng, tmid)
 
     cands = _enumerate_candidates(comp, radical)
     order = rng.permutation(len(cands))

@@ -226,6 +226,54 @@ def test_post_and_fallback(dev, mech, data):
                                atol=1e-8 * np.abs(oc["RR"]).max())
 
 
+def test_post_tmid_crossing(dev, mech, data):
+    """Post-processing on a mechanism whose species switch NASA ranges at
+    different temperatures (T_mid drawn in [700, 1400] K), with cells started
+    within +-0.05 K of some species' T_mid (about the size of the step's
+    temperature change), so that the enthalpy Newton for T crosses range
+    switches: flags, T, Y and RR match the oracle's
+    post-processing of the same network output."""
+    import torch
+    import paper_2312_05800_amd as P
+    _say("[ann post, per-species T_mid]")
+    K = mech.K
+    mt = chemgen.make_mechanism(dict(chemgen.MECH_CONFIGS["ch4"], tmid_range=(700.0, 1400.0),
+                                     name="ch4_tmid"))
+    om = oracle.OracleMech(mt)
+    params = oann.init_params([K + 2, *HID, K], seed=17)
+    params[3] = (params[3][0] * 0.05, params[3][1] * 0.05)
+    nm = _norm_from(data)
+    m = _model(mt, params, nm)
+    gm = P.Mechanism(mt)
+    N = 1200
+    T, p, Y = chemgen.make_states(mt, "ch4", N=N, seed=1717)
+    rng = np.random.default_rng(1718)
+    tm = mt.nasa[:, 1]
+    T[:600] = tm[rng.integers(0, K, 600)] + rng.uniform(-0.05, 0.05, 600)
+    Td, pd, Yd = to_dev(T, dev), to_dev(p, dev), to_dev(Y, dev)
+    U = m.forward(Td, pd, Yd, K).cpu().numpy().astype(np.float64)
+    RR = torch.zeros((K, N), dtype=torch.float64, device=dev)
+    flags = torch.zeros(N, dtype=torch.uint8, device=dev)
+    m.step(gm, 1e-5, Td, pd, Yd, RR=RR, flags=flags, fallback=False)
+    torch.cuda.synchronize()
+    o = oann.post(om, T, p, Y, U.T, _f32(nm["mu_out"]), _f32(nm["sd_out"]), 1e-5,
+                  lo=_f32(nm["lo"]), hi=_f32(nm["hi"]))
+    fg = flags.cpu().numpy()
+    near = (o["residual"] > 0.5e-6) & (o["residual"] < 2e-6)
+    assert ((fg == o["flags"]) | near).all()
+    ok = (fg == 0) & (o["flags"] == 0)
+    lo_t, hi_t = np.minimum(T, o["T"]), np.maximum(T, o["T"])
+    crossed = ok & ((tm[:, None] > lo_t[None, :]) & (tm[:, None] <= hi_t[None, :])).any(axis=0)
+    _say(f"  unflagged {ok.sum()} of {N}, Newton across a T_mid in {crossed.sum()} cells")
+    assert crossed.sum() >= 20
+    Yg, Tg, RRg = Yd.cpu().numpy(), Td.cpu().numpy(), RR.cpu().numpy()
+    assert np.all(np.abs(Yg - o["Y"])[:, ok] <= 1e-5 * np.abs(o["Y"][:, ok]) + 1e-9)
+    np.testing.assert_allclose(Tg[ok], o["T"][ok], rtol=1e-7)
+    np.testing.assert_allclose(Tg[crossed], o["T"][crossed], rtol=1e-7)
+    np.testing.assert_allclose(RRg[:, ok], o["RR"][:, ok], rtol=1e-4,
+                               atol=1e-6 * np.abs(o["RR"][:, ok]).max())
+
+
 def test_save_load_roundtrip(dev, mech, data):
     import torch
     import paper_2312_05800_amd as P

@@ -59,6 +59,29 @@ def test_nasa_reference_values_and_continuity(which, om_h2, om_ch4):
     assert np.all(cp3000 >= cp - 0.3)
 
 
+def test_nasa_per_species_tmid(which, om_h2, om_ch4):
+    """With per-species T_mid (the generator's tmid_range option) every
+    species' c_p, h and s are continuous at its own T_mid, the reference
+    values at 298.15 K still hold, and the kinetics are those of the default
+    mechanism."""
+    base = _om(which, om_h2, om_ch4).mech
+    cfg = dict(chemgen.MECH_CONFIGS[which], tmid_range=(700.0, 1400.0), name=which + "_tmid")
+    m = chemgen.make_mechanism(cfg)
+    om = oracle.OracleMech(m)
+    tm = m.nasa[:, 1]
+    assert np.all((tm >= 700.0) & (tm <= 1400.0)) and np.unique(tm).size == m.K
+    np.testing.assert_array_equal(m.A, base.A)
+    np.testing.assert_array_equal(m.rsp, base.rsp)
+    cp, hRT, sR = oracle.thermo(om, 298.15)
+    np.testing.assert_allclose(hRT * RGAS * 298.15, m.hf298, atol=1e-6)
+    np.testing.assert_allclose(sR * RGAS, m.s298, rtol=1e-12)
+    for k in range(m.K):
+        lo = oracle.thermo(om, tm[k])
+        hi = oracle.thermo(om, np.nextafter(tm[k], 4000.0))
+        for a, b in zip(lo, hi):
+            np.testing.assert_allclose(a[k], b[k], rtol=1e-11)
+
+
 def test_element_conservation_of_wdot(which, om_h2, om_ch4):
     """Every reaction conserves atoms, so sum_k a_ek wdot_k = 0 (P1) and, with
     W_k = sum_e a_ek A_e, sum_k W_k wdot_k = 0 i.e. sum_k dY_k/dt = 0 (P2)."""
