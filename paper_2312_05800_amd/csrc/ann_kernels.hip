@@ -566,12 +566,8 @@ constexpr int MLP12_KMAX = 2048;
 // waves per block and 16-cell tiles per wave (block: MLP12_WM MLP12_TM16 16
 // cells x 400 features)
 constexpr int MLP12_WM = 8, MLP12_TM16 = 2;
-// second-layer weight fragments in flight ahead of their MFMAs; whether the
-// order of LDS reads, MFMAs (and MLP12_VALU VALU instructions between MFMA
-// pairs) is pinned for the scheduler
+// second-layer weight fragments in flight ahead of their MFMAs
 constexpr int MLP12_PF = 2;
-constexpr bool MLP12_PIN = false;
-constexpr int MLP12_VALU = 0;
 constexpr int PHASE = 4;
 
 template <int TN16>
@@ -710,7 +706,6 @@ __device__ __forceinline__ void mlp12_tile(const Mlp12Args &g, u16 *S, float *b1
       bf16x8 wq[MLP12_PF];
 #pragma unroll
       for (int q = 0; q < MLP12_PF; ++q) wq[q] = bfrag(q);
-      if (MLP12_PIN) __builtin_amdgcn_sched_group_barrier(0x100, MLP12_PF, 0);
 #pragma unroll
       for (int j = 0; j < TN16; ++j) {
         const bf16x8 w = wq[j % MLP12_PF];
@@ -718,11 +713,6 @@ __device__ __forceinline__ void mlp12_tile(const Mlp12Args &g, u16 *S, float *b1
 #pragma unroll
         for (int i = 0; i < TM16; ++i)
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, h[i], acc[i][j], 0, 0, 0);
-        if (MLP12_PIN) {
-          if (j + MLP12_PF < TN16) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
-          __builtin_amdgcn_sched_group_barrier(0x008, TM16, 0);
-          if (MLP12_VALU) __builtin_amdgcn_sched_group_barrier(0x002, MLP12_VALU, 0);
-        }
       }
     };
     if (MULFIRST) {
