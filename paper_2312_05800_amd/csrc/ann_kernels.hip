@@ -1107,45 +1107,67 @@ __device__ __forceinline__ float boxcox_fast(float y, float lam) {
 // One thread per cell: raw features (T, p, Box-Cox of Y), the optional
 // out-of-distribution bit, z-scored BF16 row of X.  DINP > 0 fixes the padded
 // width at compile time, so all of a cell's loads are issued before the first
-// one is used.
+// one is used, and the block's rows are staged in LDS (rows padded by one
+// 16-byte chunk: conflict-free) and stored as consecutive 16-byte chunks per
+// lane, whole 128-byte lines per store (a lane writing its own row left every
+// line a quarter full per store and doubled the bytes written).
+constexpr int FEAT_BLOCK = 256;
+
 template <int DINP>
-__global__ void k_features(FeatArgs a) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= a.n) return;
+__global__ __launch_bounds__(FEAT_BLOCK) void k_features(FeatArgs a) {
+  constexpr int CH = DINP > 0 ? DINP / 8 : 1;  // 16-byte chunks per row
+  __shared__ uint4 stage[DINP > 0 ? FEAT_BLOCK * (CH + 1) : 1];
+  const int64_t i = (int64_t)blockIdx.x * FEAT_BLOCK + threadIdx.x;
+  const bool live = i < a.n;
+  if (DINP == 0 && !live) return;
   const int dinp = DINP > 0 ? DINP : a.dinp;
-  const int64_t c = a.index ? a.index[i] : i;
-  u16 *out = a.X + i * dinp;
-  bool outside = false;
-  constexpr int UNROLL = DINP > 0 ? DINP / 8 : 1;
+  if (live) {
+    const int64_t c = a.index ? a.index[i] : i;
+    u16 *out = a.X + i * dinp;
+    bool outside = false;
+    constexpr int UNROLL = DINP > 0 ? DINP / 8 : 1;
 #pragma unroll UNROLL
-  for (int j0 = 0; j0 < (DINP > 0 ? DINP : 1 << 30); j0 += 8) {
-    if (DINP == 0 && j0 >= dinp) break;
-    float z[8];
+    for (int j0 = 0; j0 < (DINP > 0 ? DINP : 1 << 30); j0 += 8) {
+      if (DINP == 0 && j0 >= dinp) break;
+      float z[8];
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const int j = j0 + t;
-      z[t] = 0.0f;
-      if (j < a.K + 2) {
-        float x;
-        if (j == 0) x = (float)a.T[c];
-        else if (j == 1) x = (float)a.p[c];
-        else x = boxcox_fast((float)a.Y[(int64_t)(j - 2) * a.ld + c], a.lambda);
-        if (a.ood) {
-          const float lo = a.lo[j], hi = a.hi[j], span = hi - lo;
-          const float tol = span > 0.0f ? a.ood_margin * span : 1e-6f * fmaxf(fabsf(hi), 1e-30f);
-          if (!(x >= lo - tol && x <= hi + tol)) outside = true;
+      for (int t = 0; t < 8; ++t) {
+        const int j = j0 + t;
+        z[t] = 0.0f;
+        if (j < a.K + 2) {
+          float x;
+          if (j == 0) x = (float)a.T[c];
+          else if (j == 1) x = (float)a.p[c];
+          else x = boxcox_fast((float)a.Y[(int64_t)(j - 2) * a.ld + c], a.lambda);
+          if (a.ood) {
+            const float lo = a.lo[j], hi = a.hi[j], span = hi - lo;
+            const float tol =
+                span > 0.0f ? a.ood_margin * span : 1e-6f * fmaxf(fabsf(hi), 1e-30f);
+            if (!(x >= lo - tol && x <= hi + tol)) outside = true;
+          }
+          z[t] = (x - a.mu[j]) / a.sd[j];
         }
-        z[t] = (x - a.mu[j]) / a.sd[j];
       }
+      uint4 o;
+      o.x = __builtin_bit_cast(unsigned, __builtin_convertvector((f32x2){z[0], z[1]}, bf16x2));
+      o.y = __builtin_bit_cast(unsigned, __builtin_convertvector((f32x2){z[2], z[3]}, bf16x2));
+      o.z = __builtin_bit_cast(unsigned, __builtin_convertvector((f32x2){z[4], z[5]}, bf16x2));
+      o.w = __builtin_bit_cast(unsigned, __builtin_convertvector((f32x2){z[6], z[7]}, bf16x2));
+      if (DINP > 0)
+        stage[threadIdx.x * (CH + 1) + j0 / 8] = o;
+      else
+        *(uint4 *)(out + j0) = o;
     }
-    uint4 o;
-    o.x = __builtin_bit_cast(unsigned, __builtin_convertvector((f32x2){z[0], z[1]}, bf16x2));
-    o.y = __builtin_bit_cast(unsigned, __builtin_convertvector((f32x2){z[2], z[3]}, bf16x2));
-    o.z = __builtin_bit_cast(unsigned, __builtin_convertvector((f32x2){z[4], z[5]}, bf16x2));
-    o.w = __builtin_bit_cast(unsigned, __builtin_convertvector((f32x2){z[6], z[7]}, bf16x2));
-    *(uint4 *)(out + j0) = o;
+    if (a.ood) a.ood[i] = outside ? 1 : 0;
   }
-  if (a.ood) a.ood[i] = outside ? 1 : 0;
+  if (DINP > 0) {
+    __syncthreads();
+    const int64_t r0 = (int64_t)blockIdx.x * FEAT_BLOCK;
+    const int rows = a.n - r0 < FEAT_BLOCK ? (int)(a.n - r0) : FEAT_BLOCK;
+    uint4 *const dst = (uint4 *)(a.X + r0 * DINP);
+    for (int f = threadIdx.x; f < rows * CH; f += FEAT_BLOCK)
+      dst[f] = stage[(f / CH) * (CH + 1) + f % CH];
+  }
 }
 
 __global__ void k_targets(TargetArgs a) {
@@ -1698,9 +1720,9 @@ chem_status features(const FeatArgs &a, hipStream_t s) {
   if (a.n <= 0) return CHEM_OK;
   chem::ProfScope prof("ann_features", s);
   if (a.dinp == 32)
-    hipLaunchKernelGGL(k_features<32>, dim3(nblk(a.n, 256)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_features<32>, dim3(nblk(a.n, FEAT_BLOCK)), dim3(FEAT_BLOCK), 0, s, a);
   else
-    hipLaunchKernelGGL(k_features<0>, dim3(nblk(a.n, 256)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_features<0>, dim3(nblk(a.n, FEAT_BLOCK)), dim3(FEAT_BLOCK), 0, s, a);
   CHEM_HIP(hipGetLastError());
   return CHEM_OK;
 }
