@@ -242,6 +242,17 @@ def main():
     n_fallback = int(nfb.item())
     log(f"[ann] {args.steps} steps in {t_ann:.3f} s; fallback cells {n_fallback}")
 
+    # ---- the same step captured as a HIP graph: one launch per step ----
+    P.profile_enable(False)
+    graph = model.step_graph(gm, 1e-5, Td, pd, Yd, RR=RR, flags=flags, n_fallback=nfb)
+    t_graph = timed_loop(graph.launch, restore, args.steps, args.warmup)
+    graph_equal = bool(np.array_equal(Td.cpu().numpy(), ann_T) and
+                       np.array_equal(Yd.cpu().numpy(), ann_Y))
+    del graph
+    P.profile_enable(True)
+    P.profile_read()
+    log(f"[ann graph] {args.steps} steps in {t_graph:.3f} s; equal to eager: {graph_equal}")
+
     # ---- FP8 E4M3 hidden layers (static per-tensor scales from 2^16 states) ----
     fp8 = None
     if args.fp8:
@@ -257,7 +268,13 @@ def main():
         model.set_precision(0)
         log(f"[fp8] {args.steps} steps in {t_fp8:.3f} s; fallback cells {fp8['fallback']}")
 
-    # ---- FP64 integrator step ----
+    # ---- FP64 integrator step, launch shape from the autotuner ----
+    tune_default = P.chem_get_tuning(gm)
+    si = torch.from_numpy(np.linspace(0, N - 1, 1 << 15).astype(np.int64)).to(dev)
+    tuning = P.chem_autotune(gm, 1e-5, T0d[si].contiguous(), pd[si].contiguous(),
+                             Y0d[:, si].contiguous())
+    P.profile_read()  # drop the tuner's launches
+    log(f"[fp64] autotuned launch shape {tuning} (default {tune_default})")
     st = torch.zeros((3, N), dtype=torch.int32, device=dev)
     t_fp64 = timed_loop(lambda: P.chem_step(gm, 1e-5, Td, pd, Yd, stats=st), restore,
                         args.fp64_steps, 1)
@@ -377,6 +394,11 @@ def main():
             "cells": N, "species": K, "reactions": mech.R, "dt": 1e-5,
             "hidden": list(HIDDEN)},
         "fp64": {"cells_per_s": round(fp64_cps, 1), "steps": args.fp64_steps,
+                 "launch_shape": {"lanes_per_cell": tuning["lanes_per_cell"],
+                                  "waves_per_cu": tuning["waves_per_cu"],
+                                  "tuned_on": "2^15 evenly spaced cells",
+                                  "default": {k: tune_default[k] for k in
+                                              ("lanes_per_cell", "waves_per_cu")}},
                  "ms_per_step": round(1e3 * t_fp64 / args.fp64_steps, 3),
                  "attempts_per_cell": round(attempts / N, 3),
                  "max_rel_err_vs_oracle": fp_err, "dtype": "f64"},
@@ -408,6 +430,8 @@ def main():
                           # T, p, Y in; T, Y, stats out (FP64 SoA, int32 stats)
                           "algorithmic_bytes_per_launch": N * (8 + 8 + 8 * K + 8 + 8 * K + 12)},
         "kernels_ann": kernels_ann,
+        "ann_step_graph": {"ms_per_step": round(1e3 * t_graph / args.steps, 4),
+                           "equal_to_eager": graph_equal},
         "fp8": fp8_out,
         "cpu_baseline": {"value": round(cpu_cps, 2), "unit": "cells/s", "cores": nthr,
                          "kind": "oracle",

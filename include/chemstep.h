@@ -266,6 +266,62 @@ chem_status ann_get_fp8_scales(const ann_model *m, float *act, float *wgt);
 chem_status ann_save(const ann_model *m, const char *path);
 chem_status ann_load(const char *path, ann_model **out);
 
+/* ------------------------------------------------------ launch autotuning
+ * The persistent integrator's launch shape: lanes per cell (a power of two
+ * >= K + 1, at most 64; a wavefront carries 64 / lanes cells) and resident
+ * wavefronts per CU (each holds its cells' LDS slices; 0 = as many as the LDS
+ * allows).  Per-cell results do not depend on the shape beyond the rounding
+ * of wave-level reductions (well inside the step's error control). */
+typedef struct {
+  int32_t lanes_per_cell; /* 0 = the smallest power of two >= K + 1 */
+  int32_t waves_per_cu;   /* 0 = LDS-limited maximum */
+  double cells_per_s;     /* measured by chem_autotune (output only) */
+} chem_tuning;
+
+/* For the GPU chemistry step of Sec. 2 under uneven stiffness across cells:
+ * times chem_step with every candidate launch shape on a device copy of the
+ * sample cells (T, p, Y as in chem_step; the caller's arrays are not
+ * modified), keeps the fastest in the mechanism handle for later chem_step,
+ * chem_step_sets and fallback launches, and returns it (host, nullable).
+ * Allocates and frees its scratch copies and synchronises `stream`; must not
+ * run concurrently with other calls on the same handle. */
+chem_status chem_autotune(chem_mech *m, chem_batch sample, double dt, const double *T,
+                          const double *p, const double *Y, const chem_step_opts *opts,
+                          void *stream, chem_tuning *best);
+/* Set the launch shape by hand (NULL = the default heuristic); CHEM_EINVAL for
+ * a shape the mechanism cannot use. */
+chem_status chem_set_tuning(chem_mech *m, const chem_tuning *t);
+/* The launch shape chem_step will use (lanes_per_cell and waves_per_cu
+ * resolved; cells_per_s as last measured, else 0). */
+chem_status chem_get_tuning(const chem_mech *m, chem_tuning *out);
+
+/* ------------------------------------------------------- captured steps
+ * Sec. 2 keeps the whole time step on the GPU without host round trips; a
+ * step recorded once as a HIP graph is replayed by one launch: the same
+ * kernels, arguments and device pointers as the call that was captured (the
+ * arrays are read and written again at every replay, so refill them between
+ * replays).  Workspace growth happens before capture; afterwards the model's
+ * inference workspace cannot grow (a larger ann_step returns CHEM_EINVAL)
+ * until its graphs are destroyed.  Destroy every graph before the model or
+ * mechanism it refers to. */
+typedef struct chem_graph chem_graph;
+/* ann_step captured; the BF16 weight layouts are rebuilt inside the graph, so
+ * replays use the model's current weights (training between replays is
+ * seen); precision and options are those at capture. */
+chem_status ann_step_graph_create(ann_model *m, const chem_mech *mech, chem_batch batch,
+                                  double dt, double *T, const double *p, double *Y, double *RR,
+                                  uint8_t *flags, int64_t *n_fallback,
+                                  const ann_step_opts *opts, const chem_step_opts *fb_opts,
+                                  void *stream, chem_graph **out);
+/* chem_step captured (launch shape as tuned at capture). */
+chem_status chem_step_graph_create(const chem_mech *m, chem_batch batch, double dt,
+                                   const double *dt_cell, double *T, const double *p, double *Y,
+                                   double *RR, double *h_hint, int32_t *stats,
+                                   const chem_step_opts *opts, void *stream, chem_graph **out);
+/* Replay on `stream` (asynchronous). */
+chem_status chem_graph_launch(chem_graph *g, void *stream);
+void chem_graph_destroy(chem_graph *g);
+
 /* ---------------------------------------------------------- launch timing
  * Instrumentation for measurement: when enabled, every kernel launch the
  * library issues is bracketed by HIP events on its own stream.

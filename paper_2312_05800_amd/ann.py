@@ -48,6 +48,8 @@ def _prototypes(L):
     L.ann_quantize_fp8.argtypes = [_P, Batch, _P, _P, _P, _P]
     L.ann_set_precision.argtypes = [_P, C.c_int32]
     L.ann_get_fp8_scales.argtypes = [_P, _P, _P]
+    L.ann_step_graph_create.argtypes = [_P, _P, Batch, C.c_double, _P, _P, _P, _P, _P, _P, _P,
+                                        _P, _P, C.POINTER(_P)]
     L.ann_save.argtypes = [_P, C.c_char_p]
     L.ann_load.argtypes = [C.c_char_p, C.POINTER(_P)]
 
@@ -189,6 +191,24 @@ class AnnModel:
             _dptr(p, f64, "p"), _dptr(Y, f64, "Y"), _dptr(RR, f64, "RR"),
             _dptr(flags, torch.uint8, "flags"), _dptr(n_fallback, torch.int64, "n_fallback"),
             C.byref(o), None if fo is None else C.byref(fo), _stream(stream)))
+
+    def step_graph(self, mech, dt, T, p, Y, RR=None, flags=None, n_fallback=None,
+                   residual_tol=1e-6, ood_margin=0.05, fallback=True, fb_opts=None):
+        """ann_step captured as a graph on these arrays (see step)."""
+        import torch
+        from .binding import Graph
+        n = T.shape[0]
+        ld = _soa(Y, mech.K, n, "Y")
+        o = StepOptsANN(float(residual_tol), float(ood_margin), 1 if fallback else 0, 0.0)
+        fo = _opts(fb_opts)
+        f64 = torch.float64
+        h = _P()
+        check("ann_step_graph_create", lib().ann_step_graph_create(
+            self.handle, mech.handle, Batch(n, ld), float(dt), _dptr(T, f64, "T"),
+            _dptr(p, f64, "p"), _dptr(Y, f64, "Y"), _dptr(RR, f64, "RR"),
+            _dptr(flags, torch.uint8, "flags"), _dptr(n_fallback, torch.int64, "n_fallback"),
+            C.byref(o), None if fo is None else C.byref(fo), None, C.byref(h)))
+        return Graph(h, (self, mech, T, p, Y, RR, flags, n_fallback))
 
     def train_step(self, T, p, Y0, Y1, loss, index=None, B=None, lr=1e-3, beta1=0.9,
                    beta2=0.999, eps=1e-8, stream=None):

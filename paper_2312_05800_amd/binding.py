@@ -43,6 +43,11 @@ class ChemSet(C.Structure):
                 ("Y", _P), ("RR", _P), ("h_hint", _P), ("stats", _P)]
 
 
+class Tuning(C.Structure):
+    _fields_ = [("lanes_per_cell", C.c_int32), ("waves_per_cu", C.c_int32),
+                ("cells_per_s", C.c_double)]
+
+
 class StepOpts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("atol_Y", C.c_double), ("atol_T", C.c_double),
                 ("h0", C.c_double), ("h_min", C.c_double), ("max_steps", C.c_int32)]
@@ -67,6 +72,13 @@ def lib():
             L.chem_rates.argtypes = [_P, Batch, _P, _P, _P, _P, _P, _P, _P]
             L.chem_step.argtypes = [_P, Batch, C.c_double, _P, _P, _P, _P, _P, _P, _P, _P, _P]
             L.chem_step_sets.argtypes = [_P, C.c_int32, _P, _P, _P]
+            L.chem_autotune.argtypes = [_P, Batch, C.c_double, _P, _P, _P, _P, _P, _P]
+            L.chem_set_tuning.argtypes = [_P, _P]
+            L.chem_get_tuning.argtypes = [_P, _P]
+            L.chem_step_graph_create.argtypes = [_P, Batch, C.c_double, _P, _P, _P, _P, _P, _P,
+                                                 _P, _P, _P, C.POINTER(_P)]
+            L.chem_graph_launch.argtypes = [_P, _P]
+            L.chem_graph_destroy.argtypes = [_P]
             L.chem_profile_enable.argtypes = [C.c_int32]
             L.chem_profile_read.argtypes = [_P, _P, _P, C.c_int32]
             L.chem_profile_read.restype = C.c_int32
@@ -225,6 +237,70 @@ def chem_step_sets(mech: Mechanism, sets, opts=None, stream=None):
     check("chem_step_sets", lib().chem_step_sets(mech.handle, len(sets), C.addressof(arr),
                                                  None if o is None else C.byref(o),
                                                  _stream(stream)))
+
+
+def chem_autotune(mech: Mechanism, dt, T, p, Y, opts=None, stream=None):
+    """Time the integrator's launch shapes on these cells (not modified) and
+    keep the fastest in the mechanism; returns it as a dict."""
+    import torch
+    n = T.shape[0]
+    ld = _soa(Y, mech.K, n, "Y")
+    o = _opts(opts)
+    t = Tuning()
+    f64 = torch.float64
+    check("chem_autotune", lib().chem_autotune(
+        mech.handle, Batch(n, ld), float(dt), _dptr(T, f64, "T"), _dptr(p, f64, "p"),
+        _dptr(Y, f64, "Y"), None if o is None else C.byref(o), _stream(stream), C.byref(t)))
+    return dict(lanes_per_cell=t.lanes_per_cell, waves_per_cu=t.waves_per_cu,
+                cells_per_s=t.cells_per_s)
+
+
+def chem_set_tuning(mech: Mechanism, lanes_per_cell=0, waves_per_cu=0, default=False):
+    """Set the integrator launch shape (default=True: the built-in heuristic)."""
+    t = Tuning(int(lanes_per_cell), int(waves_per_cu), 0.0)
+    check("chem_set_tuning", lib().chem_set_tuning(mech.handle, None if default else C.byref(t)))
+
+
+def chem_get_tuning(mech: Mechanism):
+    t = Tuning()
+    check("chem_get_tuning", lib().chem_get_tuning(mech.handle, C.byref(t)))
+    return dict(lanes_per_cell=t.lanes_per_cell, waves_per_cu=t.waves_per_cu,
+                cells_per_s=t.cells_per_s)
+
+
+class Graph:
+    """A captured step (chem_graph).  Holds references to the objects and
+    arrays it was captured with, so none of them is freed before it."""
+
+    def __init__(self, handle, keep):
+        self.handle = handle
+        self._keep = keep
+
+    def launch(self, stream=None):
+        check("chem_graph_launch", lib().chem_graph_launch(self.handle, _stream(stream)))
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h and _lib is not None:
+            _lib.chem_graph_destroy(h)
+            self.handle = None
+
+
+def chem_step_graph(mech: Mechanism, dt, T, p, Y, dt_cell=None, RR=None, h_hint=None, stats=None,
+                    opts=None):
+    """chem_step captured as a graph on these arrays (see chem_step)."""
+    import torch
+    n = T.shape[0]
+    ld = _soa(Y, mech.K, n, "Y")
+    o = _opts(opts)
+    f64 = torch.float64
+    h = _P()
+    check("chem_step_graph_create", lib().chem_step_graph_create(
+        mech.handle, Batch(n, ld), float(dt), _dptr(dt_cell, f64, "dt_cell"), _dptr(T, f64, "T"),
+        _dptr(p, f64, "p"), _dptr(Y, f64, "Y"), _dptr(RR, f64, "RR"),
+        _dptr(h_hint, f64, "h_hint"), _dptr(stats, torch.int32, "stats"),
+        None if o is None else C.byref(o), None, C.byref(h)))
+    return Graph(h, (mech, T, p, Y, dt_cell, RR, h_hint, stats))
 
 
 def profile_enable(on: bool = True):

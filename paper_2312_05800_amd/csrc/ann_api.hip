@@ -79,6 +79,7 @@ struct ann_model {
   int n2p = 0, k3p = 0, kq1 = 0;           // FP8 widths: L2 out (x32), L3 in / L2 in (x128)
   uint8_t *H1q = nullptr, *H2q = nullptr;  // inference workspace (E4M3 activations)
   uint8_t *ood = nullptr;                  // per-cell out-of-distribution bits
+  int graph_refs = 0;  // live captured steps that use the inference workspace
 };
 
 using namespace chem;
@@ -101,6 +102,11 @@ int fp8_k3p(const ann_model *m) { return (fp8_n2p(m) + 127) / 128 * 128; }
 chem_status grow_infer(ann_model *m, int64_t n) {
   const int64_t need = n < CHUNK ? n : CHUNK;
   if (m->wi.cap >= need) return CHEM_OK;
+  if (m->graph_refs > 0) {
+    set_error("ann: the inference workspace is held by a captured step (destroy its graphs "
+              "before a call with more cells)");
+    return CHEM_EINVAL;
+  }
   const int64_t cap = need;
   size_t off = 0;
   auto sect = [&](size_t bytes) {
@@ -726,6 +732,31 @@ extern "C" chem_status ann_forward(ann_model *m, chem_batch batch, const double 
 }
 
 namespace {
+// Workspace and fallback list for an ann_step over n cells (the only
+// allocations of the step).
+chem_status step_prepare(ann_model *m, int64_t n, bool fallback) {
+  chem_status st = grow_infer(m, n);
+  if (st != CHEM_OK) return st;
+  if (fallback && m->fb_cap < n) {
+    if (m->graph_refs > 0) {
+      set_error("ann_step: the fallback list is held by a captured step (destroy its graphs "
+                "before a call with more cells)");
+      return CHEM_EINVAL;
+    }
+    if (m->fb_index) (void)hipFree(m->fb_index);
+    m->fb_index = nullptr;
+    m->fb_cap = 0;
+    if (hipMalloc((void **)&m->fb_index, (size_t)n * 4) != hipSuccess) {
+      set_error("ann_step: cannot allocate the fallback list");
+      return CHEM_ENOMEM;
+    }
+    m->fb_cap = n;
+  }
+  return CHEM_OK;
+}
+
+void release_graph(void *owner) { ((ann_model *)owner)->graph_refs--; }
+
 __global__ void k_zero_counter(unsigned long long *c) {
   if (threadIdx.x == 0) *c = 0ull;
 }
@@ -769,18 +800,8 @@ extern "C" chem_status ann_step(ann_model *m, const chem_mech *mech, chem_batch 
     return CHEM_EINVAL;
   }
   const StepOpts fo = resolve_opts(fb_opts);
-  st = grow_infer(m, batch.n);
+  st = step_prepare(m, batch.n, o.fallback != 0);
   if (st != CHEM_OK) return st;
-  if (o.fallback && m->fb_cap < batch.n) {
-    if (m->fb_index) (void)hipFree(m->fb_index);
-    m->fb_index = nullptr;
-    m->fb_cap = 0;
-    if (hipMalloc((void **)&m->fb_index, (size_t)batch.n * 4) != hipSuccess) {
-      set_error("ann_step: cannot allocate the fallback list");
-      return CHEM_ENOMEM;
-    }
-    m->fb_cap = batch.n;
-  }
   hipStream_t s = (hipStream_t)stream;
   hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, s, m->fb_count);
   // a step other than the one the network was trained for: every cell falls back
@@ -1187,5 +1208,36 @@ extern "C" chem_status ann_get_fp8_scales(const ann_model *m, float *act, float 
     wgt[0] = m->sw[1];
     wgt[1] = m->sw[2];
   }
+  return CHEM_OK;
+}
+
+extern "C" chem_status ann_step_graph_create(ann_model *m, const chem_mech *mech, chem_batch batch,
+                                             double dt, double *T, const double *p, double *Y,
+                                             double *RR, uint8_t *flags, int64_t *n_fallback,
+                                             const ann_step_opts *opts,
+                                             const chem_step_opts *fb_opts, void *stream,
+                                             chem_graph **out) {
+  (void)stream;  // the preparation allocates synchronously; nothing is enqueued
+  chem_status st = check_model("ann_step_graph_create", m);
+  if (st != CHEM_OK) return st;
+  if (batch.n < 1) {
+    set_error("ann_step_graph_create: empty batch");
+    return CHEM_EINVAL;
+  }
+  // allocations before the capture; inside it, the BF16 weight layouts are
+  // rebuilt from the BF16 copies (so replays follow weight updates)
+  st = step_prepare(m, batch.n, !opts || opts->fallback != 0);
+  if (st != CHEM_OK) return st;
+  m->wt_stale = true;
+  st = capture_graph(
+      [&](hipStream_t cs) {
+        return ann_step(m, mech, batch, dt, T, p, Y, RR, flags, n_fallback, opts, fb_opts, cs);
+      },
+      out);
+  m->wt_stale = true;  // nothing ran during the capture
+  if (st != CHEM_OK) return st;
+  m->graph_refs++;
+  (*out)->release = release_graph;
+  (*out)->owner = m;
   return CHEM_OK;
 }

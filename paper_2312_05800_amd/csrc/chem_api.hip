@@ -409,3 +409,205 @@ extern "C" chem_status chem_step_sets(const chem_mech *m, int32_t n_sets, const 
   return launch_step(m, total, 0, 0.0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
                      nullptr, o, nullptr, st, nullptr, nullptr, dsets, doff, n_sets);
 }
+
+// ------------------------------------------------------ launch autotuning
+
+namespace {
+bool valid_opts(const StepOpts &o) {
+  return o.rtol > 0.0 && o.atol_Y >= 0.0 && o.atol_T >= 0.0 && o.h0 > 0.0 && o.h_min >= 0.0 &&
+         o.max_steps >= 1;
+}
+
+// the waves-per-CU value a launch with G lanes per cell uses
+int resolved_waves(const chem_mech *m, int G) {
+  const int wmax = max_waves_per_cu(step_lds_bytes(m, G));
+  return (m->tune_waves > 0 && m->tune_waves < wmax) ? m->tune_waves : wmax;
+}
+}  // namespace
+
+extern "C" chem_status chem_set_tuning(chem_mech *m, const chem_tuning *t) {
+  if (!m) {
+    set_error("chem_set_tuning: null mechanism");
+    return CHEM_EINVAL;
+  }
+  if (!t) {
+    m->tune_G = 0;
+    m->tune_waves = 0;
+    m->tune_cps = 0.0;
+    return CHEM_OK;
+  }
+  const int g0 = group_size(m->d.n), G = t->lanes_per_cell;
+  if (G != 0 && !((G == 16 || G == 32 || G == 64) && G >= g0)) {
+    set_error("chem_set_tuning: lanes_per_cell must be 0 or 16/32/64 >= %d", g0);
+    return CHEM_EINVAL;
+  }
+  if (t->waves_per_cu < 0 || t->waves_per_cu > 32) {
+    set_error("chem_set_tuning: waves_per_cu must be in [0, 32]");
+    return CHEM_EINVAL;
+  }
+  m->tune_G = G;
+  m->tune_waves = t->waves_per_cu;
+  m->tune_cps = 0.0;
+  return CHEM_OK;
+}
+
+extern "C" chem_status chem_get_tuning(const chem_mech *m, chem_tuning *out) {
+  if (!m || !out) {
+    set_error("chem_get_tuning: null argument");
+    return CHEM_EINVAL;
+  }
+  const int G = m->tune_G ? m->tune_G : group_size(m->d.n);
+  out->lanes_per_cell = G;
+  out->waves_per_cu = resolved_waves(m, G);
+  out->cells_per_s = m->tune_cps;
+  return CHEM_OK;
+}
+
+extern "C" chem_status chem_autotune(chem_mech *m, chem_batch sample, double dt,
+                                     const double *T, const double *p, const double *Y,
+                                     const chem_step_opts *opts, void *stream,
+                                     chem_tuning *best) {
+  chem_status st = check_batch("chem_autotune", m, sample);
+  if (st != CHEM_OK) return st;
+  if (sample.n < 1 || !T || !p || !Y || !(dt > 0.0 && isfinite(dt))) {
+    set_error("chem_autotune: needs a non-empty sample, non-null arrays and a positive dt");
+    return CHEM_EINVAL;
+  }
+  const StepOpts o = resolve_opts(opts);
+  if (!valid_opts(o)) {
+    set_error("chem_autotune: invalid options");
+    return CHEM_EINVAL;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t n = sample.n;
+  const int K = m->K;
+  // candidates: every usable lane group, and 1/4 .. 4/4 of the waves per CU
+  // its LDS allows
+  struct Cand {
+    int G, w;
+  };
+  std::vector<Cand> cands;
+  for (int G = group_size(m->d.n); G <= 64; G *= 2) {
+    const int wmax = max_waves_per_cu(step_lds_bytes(m, G));
+    int last = 0;
+    for (int q = 4; q >= 1; --q) {
+      const int w = (wmax * q + 3) / 4;
+      if (w >= 1 && w != last) cands.push_back(Cand{G, w});
+      last = w;
+    }
+  }
+  double *buf = nullptr;
+  hipEvent_t ea = nullptr, eb = nullptr;
+  auto cleanup = [&]() {
+    if (ea) (void)hipEventDestroy(ea);
+    if (eb) (void)hipEventDestroy(eb);
+    if (buf) (void)hipFree(buf);
+  };
+  if (hipMalloc(&buf, (size_t)n * (K + 1) * sizeof(double)) != hipSuccess) {
+    set_error("chem_autotune: cannot allocate %lld scratch cells", (long long)n);
+    return CHEM_ENOMEM;
+  }
+  double *const Ts = buf, *const Ys = buf + n;
+  if (hipEventCreate(&ea) != hipSuccess || hipEventCreate(&eb) != hipSuccess) {
+    cleanup();
+    set_error("chem_autotune: hipEventCreate failed");
+    return CHEM_EHIP;
+  }
+  const int saveG = m->tune_G, saveW = m->tune_waves;
+  Cand bc{saveG, saveW};
+  float best_ms = INFINITY;
+  for (const Cand &c : cands) {
+    m->tune_G = c.G;
+    m->tune_waves = c.w;
+    float ms = INFINITY;
+    for (int rep = 0; rep < 2 && st == CHEM_OK; ++rep) {  // the first run warms up
+      hipError_t e = hipMemcpyAsync(Ts, T, (size_t)n * 8, hipMemcpyDeviceToDevice, s);
+      if (e == hipSuccess)
+        e = hipMemcpy2DAsync(Ys, (size_t)n * 8, Y, (size_t)sample.ld * 8, (size_t)n * 8, K,
+                             hipMemcpyDeviceToDevice, s);
+      if (e == hipSuccess) e = hipEventRecord(ea, s);
+      if (e != hipSuccess) {
+        st = hip_fail(e, "chem_autotune: staging the sample");
+        break;
+      }
+      st = launch_step(m, n, n, dt, nullptr, Ts, p, Ys, nullptr, nullptr, nullptr, o, nullptr, s);
+      if (st != CHEM_OK) break;
+      e = hipEventRecord(eb, s);
+      if (e == hipSuccess) e = hipEventSynchronize(eb);
+      float t = 0.0f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&t, ea, eb);
+      if (e != hipSuccess) {
+        st = hip_fail(e, "chem_autotune: timing");
+        break;
+      }
+      ms = fminf(ms, t);
+    }
+    if (st == CHEM_EUNSUPPORTED) {  // this lane group does not fit the LDS
+      st = CHEM_OK;
+      continue;
+    }
+    if (st != CHEM_OK) break;
+    if (ms < best_ms) {
+      best_ms = ms;
+      bc = c;
+    }
+  }
+  cleanup();
+  if (st != CHEM_OK || !(best_ms < INFINITY)) {
+    m->tune_G = saveG;
+    m->tune_waves = saveW;
+    if (st == CHEM_OK) {
+      set_error("chem_autotune: no launch shape could run");
+      st = CHEM_EUNSUPPORTED;
+    }
+    return st;
+  }
+  m->tune_G = bc.G;
+  m->tune_waves = bc.w;
+  m->tune_cps = (double)n / (best_ms * 1e-3);
+  if (best) {
+    best->lanes_per_cell = bc.G;
+    best->waves_per_cu = resolved_waves(m, bc.G);
+    best->cells_per_s = m->tune_cps;
+  }
+  return CHEM_OK;
+}
+
+// ------------------------------------------------------- captured steps
+
+extern "C" chem_status chem_step_graph_create(const chem_mech *m, chem_batch batch, double dt,
+                                              const double *dt_cell, double *T, const double *p,
+                                              double *Y, double *RR, double *h_hint,
+                                              int32_t *stats, const chem_step_opts *opts,
+                                              void *stream, chem_graph **out) {
+  (void)stream;  // nothing runs before the capture
+  chem_status st = check_batch("chem_step_graph_create", m, batch);
+  if (st != CHEM_OK) return st;
+  if (batch.n < 1) {
+    set_error("chem_step_graph_create: empty batch");
+    return CHEM_EINVAL;
+  }
+  return capture_graph(
+      [&](hipStream_t cs) {
+        return chem_step(m, batch, dt, dt_cell, T, p, Y, RR, h_hint, stats, opts, cs);
+      },
+      out);
+}
+
+extern "C" chem_status chem_graph_launch(chem_graph *g, void *stream) {
+  if (!g || !g->e) {
+    set_error("chem_graph_launch: null graph");
+    return CHEM_EINVAL;
+  }
+  CHEM_HIP(hipGraphLaunch(g->e, (hipStream_t)stream));
+  return CHEM_OK;
+}
+
+extern "C" void chem_graph_destroy(chem_graph *g) {
+  if (!g) return;
+  if (g->release) g->release(g->owner);
+  if (g->e) (void)hipGraphExecDestroy(g->e);
+  if (g->g) (void)hipGraphDestroy(g->g);
+  if (g->s) (void)hipStreamDestroy(g->s);
+  delete g;
+}

@@ -58,6 +58,21 @@ struct chem_mech {
   size_t set_cap = 0;
   int device;
   int K, R, E;
+  // integrator launch shape (0 = default heuristic), set by chem_autotune or
+  // chem_set_tuning
+  int tune_G = 0, tune_waves = 0;
+  double tune_cps = 0.0;
+};
+
+// A captured step: the graph, its executable and the stream it was captured
+// on; `release` (if set) runs at destruction (returns the model's workspace
+// to growable).
+struct chem_graph {
+  hipGraph_t g = nullptr;
+  hipGraphExec_t e = nullptr;
+  hipStream_t s = nullptr;
+  void (*release)(void *) = nullptr;
+  void *owner = nullptr;
 };
 
 namespace chem {
@@ -79,7 +94,53 @@ class ProfScope {
 };
 
 void set_error(const char *fmt, ...);
+
+// ProfScope is a no-op while suspended (graph capture).
+void profile_suspend(bool on);
+
 chem_status hip_fail(hipError_t e, const char *what);
+
+// Records body(stream) on a fresh stream (default priority) into a HIP graph
+// and instantiates it; launch timing is suspended meanwhile.  On failure
+// nothing is left behind.
+template <typename F>
+chem_status capture_graph(F &&body, chem_graph **out) {
+  if (!out) {
+    set_error("graph: null output handle");
+    return CHEM_EINVAL;
+  }
+  *out = nullptr;
+  chem_graph *cg = new chem_graph();
+  hipError_t e = hipStreamCreateWithFlags(&cg->s, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    delete cg;
+    return hip_fail(e, "graph: hipStreamCreateWithFlags");
+  }
+  chem_status st = CHEM_OK;
+  profile_suspend(true);
+  e = hipStreamBeginCapture(cg->s, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    st = body(cg->s);
+    const hipError_t e2 = hipStreamEndCapture(cg->s, &cg->g);
+    if (st == CHEM_OK && e2 != hipSuccess) st = hip_fail(e2, "graph: hipStreamEndCapture");
+    if (st == CHEM_OK) {
+      const hipError_t e3 = hipGraphInstantiate(&cg->e, cg->g, nullptr, nullptr, 0);
+      if (e3 != hipSuccess) st = hip_fail(e3, "graph: hipGraphInstantiate");
+    }
+  } else {
+    st = hip_fail(e, "graph: hipStreamBeginCapture");
+  }
+  profile_suspend(false);
+  if (st != CHEM_OK) {
+    if (cg->e) (void)hipGraphExecDestroy(cg->e);
+    if (cg->g) (void)hipGraphDestroy(cg->g);
+    (void)hipStreamDestroy(cg->s);
+    delete cg;
+    return st;
+  }
+  *out = cg;
+  return CHEM_OK;
+}
 
 #define CHEM_HIP(call)                                   \
   do {                                                   \
@@ -93,6 +154,12 @@ StepOpts resolve_opts(const chem_step_opts *o);
 chem_status launch_rates(const chem_mech *m, int64_t n, int64_t ld, const double *T,
                          const double *p, const double *Y, double *wdot, double *dTdt,
                          double *kfkr, hipStream_t s);
+// smallest lane group (16, 32 or 64) that holds n = K + 1 components
+int group_size(int n);
+// LDS bytes of one integrator wavefront with G lanes per cell
+size_t step_lds_bytes(const chem_mech *m, int G);
+// resident integrator wavefronts per CU that the LDS allows (1..32)
+int max_waves_per_cu(size_t sh);
 chem_status launch_step(const chem_mech *m, int64_t n, int64_t ld, double dt,
                         const double *dt_cell, double *T, const double *p, double *Y,
                         double *RR, double *h_hint, int32_t *stats, const StepOpts &o,

@@ -594,8 +594,6 @@ size_t lds_bytes(int R, int n, int cpw) {
   return (size_t)cpw * GLds<G>::doubles(R, n) * sizeof(double);
 }
 
-int group_size(int n) { return n <= 16 ? 16 : (n <= 32 ? 32 : 64); }
-
 chem_status check_lds(size_t sh, int *cus) {
   int dev = 0, maxsh = 0;
   CHEM_HIP(hipGetDevice(&dev));
@@ -612,6 +610,19 @@ chem_status check_lds(size_t sh, int *cus) {
 }
 
 }  // namespace
+
+int group_size(int n) { return n <= 16 ? 16 : (n <= 32 ? 32 : 64); }
+
+size_t step_lds_bytes(const chem_mech *m, int G) {
+  const int cpw = 64 / G;
+  return G == 16 ? lds_bytes<16>(m->R, m->d.n, cpw)
+                 : (G == 32 ? lds_bytes<32>(m->R, m->d.n, cpw) : lds_bytes<64>(m->R, m->d.n, cpw));
+}
+
+int max_waves_per_cu(size_t sh) {
+  const int w = (int)((160 * 1024) / (sh > 0 ? sh : 1));
+  return w < 1 ? 1 : (w > 32 ? 32 : w);
+}
 
 chem_status launch_rates(const chem_mech *m, int64_t N, int64_t ld, const double *T,
                          const double *p, const double *Y, double *wdot, double *dTdt,
@@ -650,22 +661,16 @@ chem_status launch_step(const chem_mech *m, int64_t N, int64_t ld, double dt,
                         const chem_set *sets, const int64_t *set_off, int n_sets) {
   StepArgs A{N,       ld,    dt,          dt_cell, T,     p,    Y,       RR,     h_hint,
              stats,   index, o,           m->counters, n_dev, flags, sets, set_off, n_sets};
-  const int G = group_size(m->d.n);
+  const int G = m->tune_G ? m->tune_G : group_size(m->d.n);
   const int cpw = 64 / G;
-  size_t sh = G == 16 ? lds_bytes<16>(m->R, m->d.n, cpw)
-                      : (G == 32 ? lds_bytes<32>(m->R, m->d.n, cpw) : lds_bytes<64>(m->R, m->d.n, cpw));
+  const size_t sh = step_lds_bytes(m, G);
   int cus = 0;
   chem_status st = check_lds(sh, &cus);
   if (st != CHEM_OK) return st;
-  // persistent grid: enough single-wave blocks to fill every CU's LDS, or the
-  // number of waves per CU given by CHEMSTEP_STEP_WAVES_PER_CU (tuning)
-  int per_cu = (int)((160 * 1024) / (sh > 0 ? sh : 1));
-  if (const char *env = getenv("CHEMSTEP_STEP_WAVES_PER_CU")) {
-    const int v = atoi(env);
-    if (v > 0 && v < per_cu) per_cu = v;
-  }
-  if (per_cu < 1) per_cu = 1;
-  if (per_cu > 32) per_cu = 32;
+  // persistent grid: enough single-wave blocks to fill every CU's LDS, or
+  // the tuned number of waves per CU
+  int per_cu = max_waves_per_cu(sh);
+  if (m->tune_waves > 0 && m->tune_waves < per_cu) per_cu = m->tune_waves;
   int64_t want = (N + cpw - 1) / cpw;  // with n_dev, N is an upper bound
   int64_t blocks = (int64_t)cus * per_cu;
   if (blocks > want) blocks = want;

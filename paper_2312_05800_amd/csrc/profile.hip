@@ -19,6 +19,7 @@ struct Rec {
 
 std::mutex g_mu;
 bool g_on = false;
+bool g_suspended = false;  // during graph capture
 std::vector<Rec> g_recs;
 std::vector<hipEvent_t> g_pool;
 
@@ -35,9 +36,14 @@ hipEvent_t get_event() {
 
 }  // namespace
 
+void profile_suspend(bool on) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_suspended = on;
+}
+
 ProfScope::ProfScope(const char *label, hipStream_t s) : label_(label), s_(s) {
   std::lock_guard<std::mutex> lk(g_mu);
-  if (!g_on) return;
+  if (!g_on || g_suspended) return;
   a_ = get_event();
   b_ = get_event();
   if (a_ && b_) {

@@ -51,3 +51,23 @@ def test_invalid_mechanism_rejected_on_host():
     with pytest.raises(P.ChemError) as e:
         P.Mechanism(big)
     assert e.value.status == 6
+
+
+def test_tuning_and_graph_arguments_rejected_on_host():
+    """Null handles are rejected before any device call (no GPU needed);
+    destroying a null graph is a no-op."""
+    import ctypes as C
+    import paper_2312_05800_amd as P
+    L = P.lib()
+    assert L.chem_set_tuning(None, None) == 1
+    assert L.chem_get_tuning(None, None) == 1
+    assert L.chem_graph_launch(None, None) == 1
+    L.chem_graph_destroy(None)
+    h = C.c_void_p()
+    assert L.chem_autotune(None, P.binding.Batch(1, 1), 1e-6, None, None, None, None, None,
+                           None) == 1
+    assert L.chem_step_graph_create(None, P.binding.Batch(1, 1), 1e-6, None, None, None, None,
+                                    None, None, None, None, None, C.byref(h)) == 1
+    assert L.ann_step_graph_create(None, None, P.binding.Batch(1, 1), 1e-6, None, None, None,
+                                   None, None, None, None, None, None, C.byref(h)) == 1
+    assert not h.value
