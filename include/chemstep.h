@@ -318,8 +318,15 @@ chem_status chem_step_graph_create(const chem_mech *m, chem_batch batch, double 
                                    const double *dt_cell, double *T, const double *p, double *Y,
                                    double *RR, double *h_hint, int32_t *stats,
                                    const chem_step_opts *opts, void *stream, chem_graph **out);
+/* chem_step_sets captured: the set table is validated and copied into
+ * device memory owned by the graph (synchronising `stream`), so replays
+ * integrate the same sets whatever later calls do. */
+chem_status chem_step_sets_graph_create(const chem_mech *m, int32_t n_sets, const chem_set *sets,
+                                        const chem_step_opts *opts, void *stream,
+                                        chem_graph **out);
 /* Replay on `stream` (asynchronous). */
 chem_status chem_graph_launch(chem_graph *g, void *stream);
+/* Destroy a graph whose replays have finished (synchronise their stream). */
 void chem_graph_destroy(chem_graph *g);
 
 /* ---------------------------------------------------------- launch timing

@@ -77,6 +77,7 @@ def lib():
             L.chem_get_tuning.argtypes = [_P, _P]
             L.chem_step_graph_create.argtypes = [_P, Batch, C.c_double, _P, _P, _P, _P, _P, _P,
                                                  _P, _P, _P, C.POINTER(_P)]
+            L.chem_step_sets_graph_create.argtypes = [_P, C.c_int32, _P, _P, _P, C.POINTER(_P)]
             L.chem_graph_launch.argtypes = [_P, _P]
             L.chem_graph_destroy.argtypes = [_P]
             L.chem_profile_enable.argtypes = [C.c_int32]
@@ -219,10 +220,7 @@ def chem_step(mech: Mechanism, dt, T, p, Y, dt_cell=None, RR=None, h_hint=None, 
         None if o is None else C.byref(o), _stream(stream)))
 
 
-def chem_step_sets(mech: Mechanism, sets, opts=None, stream=None):
-    """chem_step over several cell sets in one launch.  ``sets``: sequence of
-    dicts with keys dt, T, p, Y and optionally RR, h_hint, stats (tensors as
-    in chem_step); updated in place."""
+def _set_table(mech, sets):
     import torch
     f64 = torch.float64
     arr = (ChemSet * max(1, len(sets)))()
@@ -233,10 +231,29 @@ def chem_step_sets(mech: Mechanism, sets, opts=None, stream=None):
                          _dptr(st["p"], f64, "p"), _dptr(st["Y"], f64, "Y"),
                          _dptr(st.get("RR"), f64, "RR"), _dptr(st.get("h_hint"), f64, "h_hint"),
                          _dptr(st.get("stats"), torch.int32, "stats"))
+    return arr
+
+
+def chem_step_sets(mech: Mechanism, sets, opts=None, stream=None):
+    """chem_step over several cell sets in one launch.  ``sets``: sequence of
+    dicts with keys dt, T, p, Y and optionally RR, h_hint, stats (tensors as
+    in chem_step); updated in place."""
+    arr = _set_table(mech, sets)
     o = _opts(opts)
     check("chem_step_sets", lib().chem_step_sets(mech.handle, len(sets), C.addressof(arr),
                                                  None if o is None else C.byref(o),
                                                  _stream(stream)))
+
+
+def chem_step_sets_graph(mech: Mechanism, sets, opts=None, stream=None):
+    """chem_step_sets captured as a graph on these sets (see chem_step_sets)."""
+    arr = _set_table(mech, sets)
+    o = _opts(opts)
+    h = _P()
+    check("chem_step_sets_graph_create", lib().chem_step_sets_graph_create(
+        mech.handle, len(sets), C.addressof(arr), None if o is None else C.byref(o),
+        _stream(stream), C.byref(h)))
+    return Graph(h, (mech, [dict(st) for st in sets]))
 
 
 def chem_autotune(mech: Mechanism, dt, T, p, Y, opts=None, stream=None):

@@ -355,59 +355,85 @@ extern "C" chem_status chem_step(const chem_mech *m, chem_batch batch, double dt
                      (hipStream_t)stream);
 }
 
-extern "C" chem_status chem_step_sets(const chem_mech *m, int32_t n_sets, const chem_set *sets,
-                                      const chem_step_opts *opts, void *stream) {
-  if (!m || n_sets < 0 || (n_sets > 0 && !sets)) {
-    set_error("chem_step_sets: null mechanism or set table");
-    return CHEM_EINVAL;
-  }
-  if (n_sets > (1 << 20)) {
-    set_error("chem_step_sets: at most 2^20 sets");
-    return CHEM_EINVAL;
-  }
-  StepOpts o = resolve_opts(opts);
-  if (!(o.rtol > 0.0) || !(o.atol_Y >= 0.0) || !(o.atol_T >= 0.0) || !(o.h0 > 0.0) ||
-      !(o.h_min >= 0.0) || o.max_steps < 1) {
-    set_error("chem_step_sets: invalid options");
-    return CHEM_EINVAL;
-  }
+namespace {
+// Validates a set table and lays it out in device memory *buf (grown to
+// fit; capacity *cap): the descriptors, then the first queue index of every
+// set.  The copy has completed on `s` when this returns (its pageable source
+// is a local).
+chem_status stage_sets(const char *fn, int32_t n_sets, const chem_set *sets, hipStream_t s,
+                       void **buf, size_t *cap, const chem_set **dsets, const int64_t **doff,
+                       int64_t *total) {
   std::vector<int64_t> off(n_sets + 1, 0);
-  for (int s = 0; s < n_sets; ++s) {
-    const chem_set &c = sets[s];
+  for (int i = 0; i < n_sets; ++i) {
+    const chem_set &c = sets[i];
     if (c.n < 0 || c.ld < c.n || (c.n > 0 && (!c.T || !c.p || !c.Y)) ||
         (c.n > 0 && !(c.dt > 0.0 && isfinite(c.dt)))) {
-      set_error("chem_step_sets: set %d has bad sizes, null arrays or dt", s);
+      set_error("%s: set %d has bad sizes, null arrays or dt", fn, i);
       return CHEM_EINVAL;
     }
-    off[s + 1] = off[s] + c.n;
+    off[i + 1] = off[i] + c.n;
   }
-  const int64_t total = off[n_sets];
-  if (total == 0) return CHEM_OK;
+  *total = off[n_sets];
+  if (*total == 0) return CHEM_OK;
   const size_t tb = (size_t)n_sets * sizeof(chem_set);
-  const size_t need = ((tb + 255) & ~size_t(255)) + off.size() * 8;
-  chem_mech *mm = const_cast<chem_mech *>(m);
-  if (mm->set_cap < need) {
-    if (mm->set_buf) (void)hipFree(mm->set_buf);
-    mm->set_buf = nullptr;
-    mm->set_cap = 0;
-    if (hipMalloc(&mm->set_buf, need) != hipSuccess) {
-      set_error("chem_step_sets: cannot allocate the set table");
+  const size_t ob = (tb + 255) & ~size_t(255);
+  const size_t need = ob + off.size() * 8;
+  if (*cap < need) {
+    if (*buf) (void)hipFree(*buf);
+    *buf = nullptr;
+    *cap = 0;
+    if (hipMalloc(buf, need) != hipSuccess) {
+      *buf = nullptr;
+      set_error("%s: cannot allocate the set table", fn);
       return CHEM_ENOMEM;
     }
-    mm->set_cap = need;
+    *cap = need;
   }
   std::vector<unsigned char> host(need);
   memcpy(host.data(), sets, tb);
-  memcpy(host.data() + ((tb + 255) & ~size_t(255)), off.data(), off.size() * 8);
-  hipStream_t st = (hipStream_t)stream;
-  CHEM_HIP(hipMemcpyAsync(mm->set_buf, host.data(), need, hipMemcpyHostToDevice, st));
-  // the pageable source must stay valid until the copy has been staged
-  CHEM_HIP(hipStreamSynchronize(st));
-  const chem_set *dsets = (const chem_set *)mm->set_buf;
-  const int64_t *doff =
-      (const int64_t *)((unsigned char *)mm->set_buf + ((tb + 255) & ~size_t(255)));
+  memcpy(host.data() + ob, off.data(), off.size() * 8);
+  CHEM_HIP(hipMemcpyAsync(*buf, host.data(), need, hipMemcpyHostToDevice, s));
+  CHEM_HIP(hipStreamSynchronize(s));
+  *dsets = (const chem_set *)*buf;
+  *doff = (const int64_t *)((unsigned char *)*buf + ob);
+  return CHEM_OK;
+}
+
+chem_status check_sets_call(const char *fn, const chem_mech *m, int32_t n_sets,
+                            const chem_set *sets, const chem_step_opts *opts, StepOpts *o) {
+  if (!m || n_sets < 0 || (n_sets > 0 && !sets)) {
+    set_error("%s: null mechanism or set table", fn);
+    return CHEM_EINVAL;
+  }
+  if (n_sets > (1 << 20)) {
+    set_error("%s: at most 2^20 sets", fn);
+    return CHEM_EINVAL;
+  }
+  *o = resolve_opts(opts);
+  if (!(o->rtol > 0.0) || !(o->atol_Y >= 0.0) || !(o->atol_T >= 0.0) || !(o->h0 > 0.0) ||
+      !(o->h_min >= 0.0) || o->max_steps < 1) {
+    set_error("%s: invalid options", fn);
+    return CHEM_EINVAL;
+  }
+  return CHEM_OK;
+}
+}  // namespace
+
+extern "C" chem_status chem_step_sets(const chem_mech *m, int32_t n_sets, const chem_set *sets,
+                                      const chem_step_opts *opts, void *stream) {
+  StepOpts o;
+  chem_status st = check_sets_call("chem_step_sets", m, n_sets, sets, opts, &o);
+  if (st != CHEM_OK) return st;
+  chem_mech *mm = const_cast<chem_mech *>(m);
+  hipStream_t s = (hipStream_t)stream;
+  const chem_set *dsets = nullptr;
+  const int64_t *doff = nullptr;
+  int64_t total = 0;
+  st = stage_sets("chem_step_sets", n_sets, sets, s, &mm->set_buf, &mm->set_cap, &dsets, &doff,
+                  &total);
+  if (st != CHEM_OK || total == 0) return st;
   return launch_step(m, total, 0, 0.0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
-                     nullptr, o, nullptr, st, nullptr, nullptr, dsets, doff, n_sets);
+                     nullptr, o, nullptr, s, nullptr, nullptr, dsets, doff, n_sets);
 }
 
 // ------------------------------------------------------ launch autotuning
@@ -594,6 +620,46 @@ extern "C" chem_status chem_step_graph_create(const chem_mech *m, chem_batch bat
       out);
 }
 
+namespace {
+void free_device(void *p) { (void)hipFree(p); }
+}  // namespace
+
+extern "C" chem_status chem_step_sets_graph_create(const chem_mech *m, int32_t n_sets,
+                                                   const chem_set *sets,
+                                                   const chem_step_opts *opts, void *stream,
+                                                   chem_graph **out) {
+  StepOpts o;
+  chem_status st = check_sets_call("chem_step_sets_graph_create", m, n_sets, sets, opts, &o);
+  if (st != CHEM_OK) return st;
+  // the graph owns its own copy of the table
+  void *buf = nullptr;
+  size_t cap = 0;
+  const chem_set *dsets = nullptr;
+  const int64_t *doff = nullptr;
+  int64_t total = 0;
+  st = stage_sets("chem_step_sets_graph_create", n_sets, sets, (hipStream_t)stream, &buf, &cap,
+                  &dsets, &doff, &total);
+  if (st == CHEM_OK && total == 0) {
+    set_error("chem_step_sets_graph_create: no cells");
+    st = CHEM_EINVAL;
+  }
+  if (st == CHEM_OK)
+    st = capture_graph(
+        [&](hipStream_t cs) {
+          return launch_step(m, total, 0, 0.0, nullptr, nullptr, nullptr, nullptr, nullptr,
+                             nullptr, nullptr, o, nullptr, cs, nullptr, nullptr, dsets, doff,
+                             n_sets);
+        },
+        out);
+  if (st != CHEM_OK) {
+    if (buf) (void)hipFree(buf);
+    return st;
+  }
+  (*out)->release = free_device;
+  (*out)->owner = buf;
+  return CHEM_OK;
+}
+
 extern "C" chem_status chem_graph_launch(chem_graph *g, void *stream) {
   if (!g || !g->e) {
     set_error("chem_graph_launch: null graph");
@@ -605,9 +671,9 @@ extern "C" chem_status chem_graph_launch(chem_graph *g, void *stream) {
 
 extern "C" void chem_graph_destroy(chem_graph *g) {
   if (!g) return;
-  if (g->release) g->release(g->owner);
   if (g->e) (void)hipGraphExecDestroy(g->e);
   if (g->g) (void)hipGraphDestroy(g->g);
   if (g->s) (void)hipStreamDestroy(g->s);
+  if (g->release) g->release(g->owner);
   delete g;
 }

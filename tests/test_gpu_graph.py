@@ -185,3 +185,46 @@ def test_autotune_keeps_parity(dev, mech):
         P.chem_set_tuning(gm, 16, 0)  # 16 lanes cannot hold K + 1 = 31 components
     P.chem_set_tuning(gm, default=True)
     assert P.chem_get_tuning(gm) == d0
+
+
+def test_step_sets_graph_replays(dev, mech):
+    """Uneven sets captured once: the graph keeps its own copy of the set
+    table, so an eager chem_step_sets on other sets between replays does not
+    change what it integrates; every replay equals the eager call."""
+    import torch
+    import paper_2312_05800_amd as P
+    _say("[graph] chem_step_sets")
+    gm = P.Mechanism(mech)
+    sizes, dts = [0, 5, 120, 700], [1e-6, 1e-5, 3e-7, 2e-6]
+    host = []
+    for i, (nc, dt) in enumerate(zip(sizes, dts)):
+        T, p, Y = chemgen.make_states(mech, dict(fuel="CH4", phi=(0.5, 1.3),
+                                                 T=("uniform", 300.0, 2500.0), N=nc),
+                                      seed=900 + i)
+        host.append((T, p, Y, dt))
+
+    def fresh():
+        return [dict(dt=dt, T=to_dev(T, dev), p=to_dev(p, dev), Y=to_dev(Y, dev),
+                     RR=torch.zeros((mech.K, T.size), dtype=torch.float64, device=dev),
+                     stats=torch.zeros((3, T.size), dtype=torch.int32, device=dev))
+                for T, p, Y, dt in host]
+
+    ref = fresh()
+    P.chem_step_sets(gm, ref)
+    torch.cuda.synchronize()
+    sets = fresh()
+    g = P.chem_step_sets_graph(gm, sets)
+    other = fresh()[1:3]
+    for rep in range(3):
+        for d, (T, p, Y, dt) in zip(sets, host):
+            d["T"].copy_(to_dev(T, dev))
+            d["Y"].copy_(to_dev(Y, dev))
+        torch.cuda.synchronize()
+        g.launch()
+        torch.cuda.synchronize()
+        for d, r in zip(sets, ref):
+            for k in ("T", "Y", "RR", "stats"):
+                assert torch.equal(d[k], r[k]), (rep, k)
+        P.chem_step_sets(gm, other)  # eager work on another table
+        torch.cuda.synchronize()
+    del g
