@@ -162,6 +162,82 @@ def timed_loop(run, restore, steps, warmup):
     return time.perf_counter() - t
 
 
+def time_sets(P, mech, gm, dev, args):
+    """Uneven batched workload (independent cell sets of very different size
+    and dt): one chem_step launch per set, against all sets on one persistent
+    queue (chem_step_sets) and that call replayed as a captured graph.  Each
+    variant runs once from the same restored states; the three must agree bit
+    for bit, and a sample of cells from every set is checked against the
+    oracle."""
+    import numpy as np
+    import torch
+    import chemgen
+    import oracle
+    ws = chemgen.multiset_workload(mech, seed=44, n_sets=args.sets,
+                                   max_total=args.sets_max_cells or None)
+    total = int(sum(w["N"] for w in ws))
+    log(f"[sets] {len(ws)} sets, {total} cells")
+    pristine = [(torch.from_numpy(w["T"]).to(dev), torch.from_numpy(w["p"]).to(dev),
+                 torch.from_numpy(w["Y"]).to(dev)) for w in ws]
+    live = [dict(dt=w["dt"], T=T0.clone(), p=p0, Y=Y0.clone(),
+                 stats=torch.zeros((3, w["N"]), dtype=torch.int32, device=dev))
+            for w, (T0, p0, Y0) in zip(ws, pristine)]
+
+    def restore():
+        for d, (T0, _, Y0) in zip(live, pristine):
+            d["T"].copy_(T0)
+            d["Y"].copy_(Y0)
+
+    def snapshot():
+        return [(d["T"].clone(), d["Y"].clone()) for d in live]
+
+    def same(a, b):
+        return all(torch.equal(x[0], y[0]) and torch.equal(x[1], y[1]) for x, y in zip(a, b))
+
+    def per_set():
+        for d in live:
+            if d["T"].shape[0]:
+                P.chem_step(gm, d["dt"], d["T"], d["p"], d["Y"], stats=d["stats"])
+
+    t_naive = timed_loop(per_set, restore, 1, 0)
+    ref = snapshot()
+    t_queue = timed_loop(lambda: P.chem_step_sets(gm, live), restore, 1, 0)
+    eq_queue = same(snapshot(), ref)
+    attempts = int(sum(int(d["stats"][0].sum() + d["stats"][1].sum()) for d in live))
+    g = P.chem_step_sets_graph(gm, live)
+    t_graph = timed_loop(g.launch, restore, 1, 0)
+    eq_graph = same(snapshot(), ref)
+    del g
+    # oracle on up to 16 evenly spaced cells of every set
+    om = oracle.OracleMech(mech)
+    err = 0.0
+    nchk = 0
+    for w, d in zip(ws, live):
+        if w["N"] == 0:
+            continue
+        ii = np.unique(np.linspace(0, w["N"] - 1, min(16, w["N"])).astype(np.int64))
+        o = oracle.chem_step(om, w["dt"], w["T"][ii], w["p"][ii], w["Y"][:, ii])
+        Tg, Yg = d["T"].cpu().numpy()[ii], d["Y"].cpu().numpy()[:, ii]
+        big = np.abs(o["Y"]) > 1e-10
+        err = max(err, float(np.max(np.abs(Tg - o["T"]) / o["T"])),
+                  float(np.max(np.abs(Yg - o["Y"])[big] / np.abs(o["Y"])[big])))
+        nchk += ii.size
+    sizes = [w["N"] for w in ws]
+    out = {"workload": f"{len(ws)} CH4/air cell sets, sizes floor(10^U(3,6)) "
+                       f"({min(sizes)}..{max(sizes)}), dt 10^U(-7,-4) s per set, "
+                       "T ~ U(300, 2500) K (seed 44)",
+           "cells": total, "attempts_per_cell": round(attempts / max(total, 1), 3),
+           "one_launch_per_set": {"s": round(t_naive, 3), "cells_per_s": round(total / t_naive, 1)},
+           "persistent_queue": {"s": round(t_queue, 3), "cells_per_s": round(total / t_queue, 1),
+                                "equal_to_per_set": eq_queue},
+           "persistent_queue_graph": {"s": round(t_graph, 3),
+                                      "cells_per_s": round(total / t_graph, 1),
+                                      "equal_to_per_set": eq_graph},
+           "max_rel_err_vs_oracle": err, "oracle_cells": nchk}
+    log(f"[sets] per-set {t_naive:.2f} s, queue {t_queue:.2f} s, graph {t_graph:.2f} s")
+    return out
+
+
 def nrmse_table(dY_model, dY_ref, Yref_mean, names, rtol=1e-6):
     """Range-normalised RMSE of Delta-Y per species.  Majors: mean Y >= 1e-3
     and a reference Delta-Y range of at least 10 rtol mean(Y), i.e. a change
@@ -197,6 +273,10 @@ def main():
     ap.add_argument("--oracle-sample", type=int, default=2048)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--fp8", type=int, default=1, help="also time FP8 hidden layers (1/0)")
+    ap.add_argument("--sets", type=int, default=0,
+                    help="also time the uneven multi-set FP64 workload with this many sets")
+    ap.add_argument("--sets-max-cells", type=int, default=0,
+                    help="scale the set sizes down to at most this many cells in total")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the chemistry step has no inter-GPU exchange "
@@ -288,6 +368,7 @@ def main():
 
     ann_cps = N * args.steps / t_ann
     fp64_cps = N * args.fp64_steps / t_fp64
+    sets_out = time_sets(P, mech, gm, dev, args) if args.sets else None
 
     # ---- accuracy against the CPU oracle on an evenly spaced sample ----
     copy_probe(dev)
@@ -432,6 +513,7 @@ def main():
         "kernels_ann": kernels_ann,
         "ann_step_graph": {"ms_per_step": round(1e3 * t_graph / args.steps, 4),
                            "equal_to_eager": graph_equal},
+        "fp64_sets": sets_out,
         "fp8": fp8_out,
         "cpu_baseline": {"value": round(cpu_cps, 2), "unit": "cells/s", "cores": nthr,
                          "kind": "oracle",
