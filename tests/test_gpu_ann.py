@@ -350,6 +350,56 @@ def test_fp8_forward_parity(dev, mech, data):
     assert np.sqrt(((U2 - Ub) ** 2).mean()) <= 2e-3
 
 
+def test_inference_2p23_cells_in_chunks(dev, mech, data):
+    """2^23 cells (the low-precision inference size: four 2^21-cell chunks of
+    the inference workspace): BF16 and FP8 forward passes match the oracle's
+    emulation on rows sampled across all chunks, with the first and last rows
+    of every chunk."""
+    import torch
+    K = mech.K
+    N = 1 << 23
+    C = 1 << 21
+    _say(f"[ann {N} cells in chunks of {C}]")
+    params = oann.init_params([K + 2, *HID, K], seed=14)
+    nm = _norm_from(data)
+    m = _model(mech, params, nm)
+    p32 = _params32(params)
+    T, p, Y = chemgen.make_states(mech, "ch4_infer")
+    assert T.size == N
+    Td, pd, Yd = to_dev(T, dev), to_dev(p, dev), to_dev(Y, dev)
+    edges = [np.array([c * C - 1, c * C]) for c in range(1, N // C)]
+    idx = np.unique(np.concatenate([np.linspace(0, N - 1, 97).astype(np.int64),
+                                    np.array([0, 1, N - 2, N - 1]), *edges]))
+    it = torch.from_numpy(idx).to(dev)
+    X = _oracle_inputs(nm, T[idx], p[idx], Y[:, idx])
+    del T, p, Y
+    U = m.forward(Td, pd, Yd, K)
+    torch.cuda.synchronize()
+    assert torch.isfinite(U).all()
+    Ug = U[it].cpu().numpy().astype(np.float64)
+    del U
+    Uo = oann.forward(p32, X, prec="bf16")
+    err = np.abs(Ug - Uo)
+    _say(f"  bf16 max abs {err.max():.3e} rms {np.sqrt((err ** 2).mean()):.3e} ({idx.size} rows)")
+    assert err.max() <= 2e-2 and np.sqrt((err ** 2).mean()) <= 2e-3
+    Tc, pc, Yc = chemgen.make_states(mech, "ch4_val")
+    m.quantize_fp8(to_dev(Tc, dev), to_dev(pc, dev), to_dev(Yc, dev))
+    sa, sw = m.fp8_scales()
+    U8 = m.forward(Td, pd, Yd, K)
+    torch.cuda.synchronize()
+    assert torch.isfinite(U8).all()
+    U8g = U8[it].cpu().numpy().astype(np.float64)
+    del U8
+    sc = {1: (float(sa[0]), float(sw[0])), 2: (float(sa[1]), float(sw[1]))}
+    Uo8 = oann.forward(p32, X, prec="fp8", fp8_scales=sc)
+    err8 = np.abs(U8g - Uo8)
+    e_fmt = np.abs(Uo8 - Uo)
+    _say(f"  fp8 max abs {err8.max():.3e} rms {np.sqrt((err8 ** 2).mean()):.3e}; "
+         f"fp8-vs-bf16 rms {np.sqrt((e_fmt ** 2).mean()):.3e}")
+    assert np.sqrt((err8 ** 2).mean()) < 0.25 * np.sqrt((e_fmt ** 2).mean())
+    assert err8.max() <= 5e-2
+
+
 def test_large_tile_paths_ragged(dev, mech, data):
     """At a cell count that selects the 256-cell direct-to-LDS GEMM tiles and
     leaves a ragged last tile (3 * 2^16 + 37 cells), BF16 and FP8 forward
