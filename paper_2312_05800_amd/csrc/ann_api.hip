@@ -607,6 +607,19 @@ chem_status forward_chunk(ann_model *m, int64_t n, int64_t ld, const double *T, 
     q.Cb = m->H[2];
     q.ldcb = L2.doutp;
     q.tiled = tl ? (ann::TILED_A | ann::TILED_B) : 0;
+    // the output layer rides in the epilogue of the last hidden layer when
+    // the tiling allows it (its activations then never reach HBM)
+    q.B2 = m->Wb[3];
+    q.bias2 = m->bm[3];
+    q.N2 = m->L[3].doutp;
+    q.Cf = U;
+    q.ldcf = ldu;
+    if (ann::gemm8_fuses_next(q)) return ann::gemm8(q, ann::EPI_GELU_NEXT, s, "mlp_l3_l4_fp8");
+    q.B2 = nullptr;
+    q.bias2 = nullptr;
+    q.N2 = 0;
+    q.Cf = nullptr;
+    q.ldcf = 0;
     if ((st = ann::gemm8(q, ann::EPI_GELU, s, "mlp_l3_fp8")) != CHEM_OK) return st;
     ann::GemmArgs o{};
     o.M = (int)n;

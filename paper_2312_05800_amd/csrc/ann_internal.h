@@ -100,7 +100,11 @@ __host__ __device__ inline int mlp12_slot(int f) {
 // 2048, N a multiple of 400, aligned operands).
 bool mlp12_ok(const Mlp12Args &g);
 chem_status mlp12(const Mlp12Args &g, hipStream_t s, const char *label);
-// E4M3 x E4M3 GEMM (both K-contiguous, K a multiple of 64), epi GELU or GELU_Q8.
+// Whether gemm8() can run this layer with EPI_GELU_NEXT (the BF16 output
+// layer fused into its epilogue).
+bool gemm8_fuses_next(const GemmArgs &g);
+// E4M3 x E4M3 GEMM (both K-contiguous, K a multiple of 64), epi GELU, GELU_Q8
+// or GELU_NEXT.
 chem_status gemm8(const GemmArgs &g, int epi, hipStream_t s, const char *label);
 // max |x| over n BF16 (bf16 = true) or FP32 values, into part[0..nparts)
 chem_status amax(int64_t n, const void *x, bool bf16, float *part, int nparts, hipStream_t s);

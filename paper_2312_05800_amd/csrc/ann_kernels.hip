@@ -926,9 +926,10 @@ __global__ __launch_bounds__(WM *WN * 64) void k_gemm8(GemmArgs g) {
 // multiply the accumulator in the epilogue.
 __device__ __forceinline__ int swz8(int r) { return (r >> 1) & 7; }
 
-template <int WM, int TM16, int TN16, int EPI>
+template <int WM, int TM16, int TN16, int EPI, int STAGES = 3>
 __global__ __launch_bounds__(WM * 64) void k_gemm8_dma16(GemmArgs g) {
-  constexpr int BK = 128, STAGES = 3;
+  constexpr int BK = 128;
+  static_assert(STAGES == 2 || STAGES == 3, "ring of 3 stages, or 2 for the widest tiles");
   constexpr int BM = WM * TM16 * 16, BN = TN16 * 16, ROWS = BM + BN;
   constexpr int NI = ROWS / 8;
   constexpr int NPW = (NI + WM - 1) / WM;
@@ -1001,13 +1002,17 @@ __global__ __launch_bounds__(WM * 64) void k_gemm8_dma16(GemmArgs g) {
                    (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
   };
   issue(0, 0);
-  if (nk > 1) issue(1, 1);
+  if (STAGES == 3 && nk > 1) issue(1, 1);
   for (int kt = 0; kt < nk; ++kt) {
-    if (kt + 1 < nk)
+    // 3 stages: as in k_gemm_dma16.  2 stages: the only loads in flight are
+    // stage kt's; after the barrier the other stage (read in step kt - 1)
+    // takes step kt + 1.
+    if (STAGES == 3 && kt + 1 < nk)
       asm volatile("s_waitcnt vmcnt(%0)\n\ts_barrier" : : "n"(NMIN) : "memory");
     else
       asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" : : : "memory");
-    if (kt + 2 < nk) issue((kt + 2) % STAGES, kt + 2);
+    if (STAGES == 3 && kt + 2 < nk) issue((kt + 2) % STAGES, kt + 2);
+    if (STAGES == 2 && kt + 1 < nk) issue((kt + 1) % STAGES, kt + 1);
     const uint8_t *T = S + (kt % STAGES) * ROWS * BK;
     i32x8 x[TM16];
 #pragma unroll
@@ -1023,6 +1028,63 @@ __global__ __launch_bounds__(WM * 64) void k_gemm8_dma16(GemmArgs g) {
   }
 
   const int hf = 4 * (lane >> 4);
+  if constexpr (EPI == EPI_GELU_NEXT) {
+    // the output layer in the epilogue, as in k_gemm_dma16: the block holds
+    // all BN >= N features of its cells; W2 [N2 = 32][N] BF16 staged in the
+    // idle ring (rows padded by 4 elements)
+    constexpr int LW = BN + 4;
+    asm volatile("s_barrier" : : : "memory");  // every wave is done with the ring
+    u16 *const Wl = (u16 *)S;
+    for (int c = tid; c < g.N2 * (BN / 4); c += WM * 64) {
+      const int r = c / (BN / 4), q = (c % (BN / 4)) * 4;
+      uint2 v = make_uint2(0, 0);
+      if (q < g.N) v = *(const uint2 *)(g.B2 + (long)r * g.N + q);
+      *(uint2 *)&Wl[r * LW + q] = v;
+    }
+    __syncthreads();
+    constexpr int TO = 2;  // output tiles (N2 = 32)
+    f32x4 u[TO][TM16];
+#pragma unroll
+    for (int o = 0; o < TO; ++o)
+#pragma unroll
+      for (int i = 0; i < TM16; ++i) u[o][i] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int j = 0; j < TN16; ++j) {
+      const float4 b = *(const float4 *)&bias_s[j * 16 + hf];
+      s16x4 w[TO];
+#pragma unroll
+      for (int o = 0; o < TO; ++o)
+        w[o] = *(const s16x4 *)&Wl[(o * 16 + (lane & 15)) * LW + j * 16 + hf];
+#pragma unroll
+      for (int i = 0; i < TM16; ++i) {
+        const bf16x2 lo = __builtin_convertvector(
+            (f32x2){gelu(acc[i][j][0] * g.scale + b.x), gelu(acc[i][j][1] * g.scale + b.y)},
+            bf16x2);
+        const bf16x2 hi = __builtin_convertvector(
+            (f32x2){gelu(acc[i][j][2] * g.scale + b.z), gelu(acc[i][j][3] * g.scale + b.w)},
+            bf16x2);
+        const unsigned ul = __builtin_bit_cast(unsigned, lo), uh = __builtin_bit_cast(unsigned, hi);
+        const s16x4 h = (s16x4){(short)(ul & 0xffff), (short)(ul >> 16), (short)(uh & 0xffff),
+                                (short)(uh >> 16)};
+#pragma unroll
+        for (int o = 0; o < TO; ++o)
+          u[o][i] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w[o], h, u[o][i], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int o = 0; o < TO; ++o) {
+      const float4 b2 = *(const float4 *)(g.bias2 + o * 16 + hf);
+#pragma unroll
+      for (int i = 0; i < TM16; ++i) {
+        const long row = m0 + wave * TM16 * 16 + i * 16 + (lane & 15);
+        if (row < g.M)
+          *(float4 *)(g.Cf + row * g.ldcf + o * 16 + hf) =
+              make_float4(u[o][i][0] + b2.x, u[o][i][1] + b2.y, u[o][i][2] + b2.z,
+                          u[o][i][3] + b2.w);
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int j = 0; j < TN16; ++j) {
     if (n0 + j * 16 >= g.N) break;
@@ -1052,15 +1114,20 @@ __global__ __launch_bounds__(WM * 64) void k_gemm8_dma16(GemmArgs g) {
   }
 }
 
-template <int WM, int TM16, int TN16>
+template <int WM, int TM16, int TN16, int STAGES = 3>
 chem_status gemm8_dma16_cfg(const GemmArgs &g, int epi, hipStream_t s) {
   constexpr int BM = WM * TM16 * 16, BN = TN16 * 16;
   const long total = (long)((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
   dim3 grid((unsigned)(((total + 7) / 8) * 8)), block(WM * 64);
   if (epi == EPI_GELU_Q8)
-    hipLaunchKernelGGL((k_gemm8_dma16<WM, TM16, TN16, EPI_GELU_Q8>), grid, block, 0, s, g);
+    hipLaunchKernelGGL((k_gemm8_dma16<WM, TM16, TN16, EPI_GELU_Q8, STAGES>), grid, block, 0, s,
+                       g);
   else if (epi == EPI_GELU)
-    hipLaunchKernelGGL((k_gemm8_dma16<WM, TM16, TN16, EPI_GELU>), grid, block, 0, s, g);
+    hipLaunchKernelGGL((k_gemm8_dma16<WM, TM16, TN16, EPI_GELU, STAGES>), grid, block, 0, s, g);
+  else if (epi == EPI_GELU_NEXT && g.N <= BN && g.N2 == 32 &&
+           g.N2 * (BN + 4) * 2 <= STAGES * (BM + BN) * 128 && g.ldcf % 4 == 0)
+    hipLaunchKernelGGL((k_gemm8_dma16<WM, TM16, TN16, EPI_GELU_NEXT, STAGES>), grid, block, 0, s,
+                       g);
   else {
     chem::set_error("gemm8: unsupported epilogue");
     return CHEM_EUNSUPPORTED;
@@ -1668,6 +1735,13 @@ chem_status mlp12(const Mlp12Args &g, hipStream_t s, const char *label) {
   return CHEM_OK;
 }
 
+bool gemm8_fuses_next(const GemmArgs &g) {
+  return g.K % 128 == 0 && g.lda % 16 == 0 && g.ldb % 16 == 0 && g.N == 416 &&
+         (long)((g.M + 127) / 128) >= 512 && g.N2 == 32 && g.N2 <= g.ldcf && g.ldcf % 4 == 0 &&
+         g.B2 && g.bias && g.bias2 && ((uintptr_t)g.B2 & 7) == 0 &&
+         ((uintptr_t)g.A8 & 15) == 0 && ((uintptr_t)g.B8 & 15) == 0;
+}
+
 chem_status gemm8(const GemmArgs &g, int epi, hipStream_t s, const char *label) {
   if (g.M <= 0 || g.N <= 0) return CHEM_OK;
   if (g.K % 64 != 0 || g.lda % 16 != 0 || g.ldb % 16 != 0) {
@@ -1675,6 +1749,14 @@ chem_status gemm8(const GemmArgs &g, int epi, hipStream_t s, const char *label) 
     return CHEM_EINVAL;
   }
   chem::ProfScope prof(label, s);
+  if (epi == EPI_GELU_NEXT) {
+    // 128 cells x all 416 features per block (two ring stages fit the LDS)
+    if (!gemm8_fuses_next(g)) {
+      chem::set_error("gemm8: the fused output layer needs the 128 x 416 tiling");
+      return CHEM_EUNSUPPORTED;
+    }
+    return gemm8_dma16_cfg<8, 1, 26, 2>(g, epi, s);
+  }
   if (g.K % 128 == 0 && g.N % 16 == 0 && ((uintptr_t)g.A8 & 15) == 0 &&
       ((uintptr_t)g.B8 & 15) == 0 && g.ldcb % 4 == 0 && g.ldcq % 4 == 0) {
     // 256 x 160 tiles (N a multiple of 160), else 128 x 208 (N of 208)

@@ -466,3 +466,21 @@ def test_large_tile_paths_ragged(dev, mech, data):
          f"fp8-vs-bf16 rms {np.sqrt((e_fmt ** 2).mean()):.3e}")
     assert np.sqrt((err8 ** 2).mean()) < 0.25 * np.sqrt((e_fmt ** 2).mean())
     assert err8.max() <= 5e-2
+    # ann_step on the FP8 path (the output layer fused into the last hidden
+    # layer's epilogue): the oracle's post-processing of the FP8 forward output
+    RR8 = torch.zeros((K, N), dtype=torch.float64, device=dev)
+    flags8 = torch.zeros(N, dtype=torch.uint8, device=dev)
+    U8full = U8.cpu().numpy().astype(np.float64)
+    gm = P.Mechanism(mech)
+    m.step(gm, 1e-5, Td, pd, Yd, RR=RR8, flags=flags8, fallback=False)
+    torch.cuda.synchronize()
+    o8 = oann.post(om, T[idx], p[idx], Y[:, idx], U8full[idx].T, _f32(nm["mu_out"]),
+                   _f32(nm["sd_out"]), 1e-5, lo=_f32(nm["lo"]), hi=_f32(nm["hi"]))
+    fg8 = flags8[it].cpu().numpy()
+    near8 = (o8["residual"] > 0.5e-6) & (o8["residual"] < 2e-6)
+    assert ((fg8 == o8["flags"]) | near8).all()
+    ok8 = (fg8 == 0) & (o8["flags"] == 0)
+    assert ok8.sum() > len(idx) // 4
+    Yg8 = Yd[:, it].cpu().numpy()
+    assert np.all(np.abs(Yg8 - o8["Y"])[:, ok8] <= 1e-5 * np.abs(o8["Y"][:, ok8]) + 1e-9)
+    np.testing.assert_allclose(Td[it].cpu().numpy()[ok8], o8["T"][ok8], rtol=1e-6)
