@@ -350,6 +350,46 @@ def test_fp8_forward_parity(dev, mech, data):
     assert np.sqrt(((U2 - Ub) ** 2).mean()) <= 2e-3
 
 
+def test_fp8_step_row_major_fused_output(dev, mech, data):
+    """FP8 ann_step on 70 001 cells: enough for the output layer to ride in
+    the last FP8 layer's epilogue, too few for the K-blocked layouts (the
+    row-major operands of that kernel); matches the oracle's post-processing
+    of the FP8 forward output on sampled cells, the last ones included."""
+    import torch
+    import paper_2312_05800_amd as P
+    K = mech.K
+    N = 70001
+    _say(f"[ann fp8 step] N={N}")
+    params = oann.init_params([K + 2, *HID, K], seed=15)
+    params[3] = (params[3][0] * 0.02, params[3][1] * 0.02)
+    nm = _norm_from(data)
+    m = _model(mech, params, nm)
+    Tc, pc, Yc = chemgen.make_states(mech, "ch4", N=2048, seed=916)
+    m.quantize_fp8(to_dev(Tc, dev), to_dev(pc, dev), to_dev(Yc, dev))
+    T, p, Y = chemgen.make_states(mech, "ch4", N=N, seed=917)
+    Td, pd, Yd = to_dev(T, dev), to_dev(p, dev), to_dev(Y, dev)
+    U8 = m.forward(Td, pd, Yd, K).cpu().numpy().astype(np.float64)
+    RR = torch.zeros((K, N), dtype=torch.float64, device=dev)
+    flags = torch.zeros(N, dtype=torch.uint8, device=dev)
+    gm = P.Mechanism(mech)
+    m.step(gm, 1e-5, Td, pd, Yd, RR=RR, flags=flags, fallback=False)
+    torch.cuda.synchronize()
+    idx = np.unique(np.concatenate([np.linspace(0, N - 1, 300).astype(np.int64),
+                                    np.arange(N - 20, N)]))
+    om = oracle.OracleMech(mech)
+    o = oann.post(om, T[idx], p[idx], Y[:, idx], U8[idx].T, _f32(nm["mu_out"]),
+                  _f32(nm["sd_out"]), 1e-5, lo=_f32(nm["lo"]), hi=_f32(nm["hi"]))
+    fg = flags.cpu().numpy()[idx]
+    near = (o["residual"] > 0.5e-6) & (o["residual"] < 2e-6)
+    assert ((fg == o["flags"]) | near).all()
+    ok = (fg == 0) & (o["flags"] == 0)
+    _say(f"  unflagged {ok.sum()} of {idx.size} sampled cells")
+    assert ok.sum() > idx.size // 4
+    Yg = Yd.cpu().numpy()[:, idx]
+    assert np.all(np.abs(Yg - o["Y"])[:, ok] <= 1e-5 * np.abs(o["Y"][:, ok]) + 1e-9)
+    np.testing.assert_allclose(Td.cpu().numpy()[idx][ok], o["T"][ok], rtol=1e-6)
+
+
 def test_inference_2p23_cells_in_chunks(dev, mech, data):
     """2^23 cells (the low-precision inference size: four 2^21-cell chunks of
     the inference workspace): BF16 and FP8 forward passes match the oracle's
