@@ -1178,13 +1178,13 @@ __device__ __forceinline__ float boxcox_fast(float y, float lam) {
 // 16-byte chunk: conflict-free) and stored as consecutive 16-byte chunks per
 // lane, whole 128-byte lines per store (a lane writing its own row left every
 // line a quarter full per store and doubled the bytes written).
-constexpr int FEAT_BLOCK = 256;
-
-template <int DINP>
-__global__ __launch_bounds__(FEAT_BLOCK) void k_features(FeatArgs a) {
+// BLK cells per block: 256 for large batches, 64 for small ones (a training
+// batch of 8192 cells fills 128 blocks instead of 32).
+template <int DINP, int BLK>
+__global__ __launch_bounds__(BLK) void k_features(FeatArgs a) {
   constexpr int CH = DINP > 0 ? DINP / 8 : 1;  // 16-byte chunks per row
-  __shared__ uint4 stage[DINP > 0 ? FEAT_BLOCK * (CH + 1) : 1];
-  const int64_t i = (int64_t)blockIdx.x * FEAT_BLOCK + threadIdx.x;
+  __shared__ uint4 stage[DINP > 0 ? BLK * (CH + 1) : 1];
+  const int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x;
   const bool live = i < a.n;
   if (DINP == 0 && !live) return;
   const int dinp = DINP > 0 ? DINP : a.dinp;
@@ -1229,27 +1229,48 @@ __global__ __launch_bounds__(FEAT_BLOCK) void k_features(FeatArgs a) {
   }
   if (DINP > 0) {
     __syncthreads();
-    const int64_t r0 = (int64_t)blockIdx.x * FEAT_BLOCK;
-    const int rows = a.n - r0 < FEAT_BLOCK ? (int)(a.n - r0) : FEAT_BLOCK;
+    const int64_t r0 = (int64_t)blockIdx.x * BLK;
+    const int rows = a.n - r0 < BLK ? (int)(a.n - r0) : BLK;
     uint4 *const dst = (uint4 *)(a.X + r0 * DINP);
-    for (int f = threadIdx.x; f < rows * CH; f += FEAT_BLOCK)
+    for (int f = threadIdx.x; f < rows * CH; f += BLK)
       dst[f] = stage[(f / CH) * (CH + 1) + f % CH];
   }
 }
+
+// One cell per thread.  The loads of a batch of TGT_BATCH outputs are all
+// issued before the first store (the output rows may not alias the inputs, but
+// the compiler cannot know that), and a padded width that is a multiple of 4
+// is written with 16-byte stores.
+constexpr int TGT_BATCH = 8;
 
 __global__ void k_targets(TargetArgs a) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
   const int64_t c = a.index ? a.index[i] : i;
   float *out = a.U + i * a.doutp;
-  for (int k = 0; k < a.doutp; ++k) {
-    float v = 0.0f;
-    if (k < a.K) {
-      // the change of the mass fraction over the step (FP64 difference)
-      const double d = a.Y1[(int64_t)k * a.ld + c] - a.Y0[(int64_t)k * a.ld + c];
-      v = (float)((d - a.mu[k]) / a.sd[k]);
+  const bool vec = (a.doutp & 3) == 0 && ((uintptr_t)a.U & 15) == 0;
+  for (int k0 = 0; k0 < a.doutp; k0 += TGT_BATCH) {
+    double y1[TGT_BATCH], y0[TGT_BATCH];
+#pragma unroll
+    for (int j = 0; j < TGT_BATCH; ++j) {
+      const int k = k0 + j;
+      y1[j] = k < a.K ? a.Y1[(int64_t)k * a.ld + c] : 0.0;
+      y0[j] = k < a.K ? a.Y0[(int64_t)k * a.ld + c] : 0.0;
     }
-    out[k] = v;
+    float v[TGT_BATCH];
+#pragma unroll
+    for (int j = 0; j < TGT_BATCH; ++j) {
+      const int k = k0 + j;
+      // the change of the mass fraction over the step (FP64 difference)
+      v[j] = k < a.K ? (float)((y1[j] - y0[j] - a.mu[k]) / a.sd[k]) : 0.0f;
+    }
+    if (vec && k0 + TGT_BATCH <= a.doutp) {
+#pragma unroll
+      for (int j = 0; j < TGT_BATCH; j += 4)
+        *(float4 *)(out + k0 + j) = make_float4(v[j], v[j + 1], v[j + 2], v[j + 3]);
+    } else {
+      for (int j = 0; j < TGT_BATCH && k0 + j < a.doutp; ++j) out[k0 + j] = v[j];
+    }
   }
 }
 
@@ -1294,13 +1315,25 @@ __global__ void k_loss_final(const double *part, int nparts, double scale, float
 // Column sums in two fixed-order passes (FP64 accumulation): block row q
 // sums rows [q M / P, (q + 1) M / P) of its columns into part[q][j]; the final
 // pass adds the P partials in order of q.
+// Both passes issue COLSUM_BATCH loads before adding them, in order, to the
+// running sum (the same order as one load at a time).
+constexpr int COLSUM_BATCH = 8;
+
 __global__ void k_colsum_part(int64_t M, int N, const float *X, long ldx, double *part) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= N) return;
   const int P = gridDim.y, q = blockIdx.y;
   const int64_t m0 = M * q / P, m1 = M * (q + 1) / P;
   double s = 0.0;
-  for (int64_t m = m0; m < m1; ++m) s += X[m * ldx + j];
+  int64_t m = m0;
+  for (; m + COLSUM_BATCH <= m1; m += COLSUM_BATCH) {
+    float x[COLSUM_BATCH];
+#pragma unroll
+    for (int r = 0; r < COLSUM_BATCH; ++r) x[r] = X[(m + r) * ldx + j];
+#pragma unroll
+    for (int r = 0; r < COLSUM_BATCH; ++r) s += x[r];
+  }
+  for (; m < m1; ++m) s += X[m * ldx + j];
   part[(int64_t)q * N + j] = s;
 }
 
@@ -1308,7 +1341,15 @@ __global__ void k_colsum_fin(int N, int P, const double *part, float *out) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= N) return;
   double s = 0.0;
-  for (int q = 0; q < P; ++q) s += part[(int64_t)q * N + j];
+  int q = 0;
+  for (; q + COLSUM_BATCH <= P; q += COLSUM_BATCH) {
+    double x[COLSUM_BATCH];
+#pragma unroll
+    for (int r = 0; r < COLSUM_BATCH; ++r) x[r] = part[(int64_t)(q + r) * N + j];
+#pragma unroll
+    for (int r = 0; r < COLSUM_BATCH; ++r) s += x[r];
+  }
+  for (; q < P; ++q) s += part[(int64_t)q * N + j];
   out[j] = (float)s;
 }
 
@@ -1801,17 +1842,20 @@ chem_status quant_e4m3(const float *src, long ld_src, int rows, int cols, uint8_
 chem_status features(const FeatArgs &a, hipStream_t s) {
   if (a.n <= 0) return CHEM_OK;
   chem::ProfScope prof("ann_features", s);
-  if (a.dinp == 32)
-    hipLaunchKernelGGL(k_features<32>, dim3(nblk(a.n, FEAT_BLOCK)), dim3(FEAT_BLOCK), 0, s, a);
+  const bool small = a.n < (int64_t)256 * 1024;
+  if (a.dinp == 32 && small)
+    hipLaunchKernelGGL((k_features<32, 64>), dim3(nblk(a.n, 64)), dim3(64), 0, s, a);
+  else if (a.dinp == 32)
+    hipLaunchKernelGGL((k_features<32, 256>), dim3(nblk(a.n, 256)), dim3(256), 0, s, a);
   else
-    hipLaunchKernelGGL(k_features<0>, dim3(nblk(a.n, FEAT_BLOCK)), dim3(FEAT_BLOCK), 0, s, a);
+    hipLaunchKernelGGL((k_features<0, 256>), dim3(nblk(a.n, 256)), dim3(256), 0, s, a);
   CHEM_HIP(hipGetLastError());
   return CHEM_OK;
 }
 
 chem_status targets(const TargetArgs &a, hipStream_t s) {
   if (a.n <= 0) return CHEM_OK;
-  hipLaunchKernelGGL(k_targets, dim3(nblk(a.n, 256)), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_targets, dim3(nblk(a.n, 64)), dim3(64), 0, s, a);
   CHEM_HIP(hipGetLastError());
   return CHEM_OK;
 }
