@@ -127,8 +127,15 @@ __global__ __launch_bounds__(WM *WN * 64) void k_gemm(GemmArgs g) {
   // split-K range of this block (blockIdx.y); the whole K when not split
   const int kper = g.ksplit > 1 ? g.K / g.ksplit : g.K;
   const int kbase = (int)blockIdx.y * kper;
+  // K-contiguous operands move as 16-byte chunks (8 K values of one row).  An
+  // MN-contiguous operand moves as blocks of 4 K rows x 8 columns: four
+  // coalesced 16-byte loads, a transpose in registers, and eight 8-byte LDS
+  // stores (4 K values of one column each), in place of 2-byte stores that
+  // fell on four LDS banks.
   constexpr int ACH = BM * BK / 8, BCH = BN * BK / 8;
-  constexpr int APT = (ACH + NT - 1) / NT, BPT = (BCH + NT - 1) / NT;
+  constexpr int ATB = BM * BK / 32, BTB = BN * BK / 32;
+  constexpr int APT = AK ? (ACH + NT - 1) / NT : 4 * ((ATB + NT - 1) / NT);
+  constexpr int BPT = BKC ? (BCH + NT - 1) / NT : 4 * ((BTB + NT - 1) / NT);
   uint4 ra[APT], rb[BPT];
   f32x16 acc[TM][TN];
 #pragma unroll
@@ -138,69 +145,77 @@ __global__ __launch_bounds__(WM *WN * 64) void k_gemm(GemmArgs g) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
 
-  auto load = [&](int k0) {
+  // chunk c of a K-contiguous tile: row c / (BK / 8), K offset 8 (c % (BK / 8));
+  // block c of an MN-contiguous tile: K rows 4 (c % (BK / 4)) + 0..3, columns
+  // 8 (c / (BK / 4)) + 0..7
+  auto load_kc = [&](const u16 *src, long ld, long r0, long rows, int k0, int nch, uint4 *v,
+                     int cnt) {
 #pragma unroll
-    for (int i = 0; i < APT; ++i) {
+    for (int i = 0; i < cnt; ++i) {
       const int c = tid + i * NT;
-      uint4 v = make_uint4(0, 0, 0, 0);
-      if (c < ACH) {
-        if (AK) {
-          const int r = c / (BK / 8), kc = (c % (BK / 8)) * 8;
-          if (m0 + r < g.M) v = *(const uint4 *)(g.A + (m0 + r) * g.lda + k0 + kc);
-        } else {
-          const int kr = c / (BM / 8), mc = (c % (BM / 8)) * 8;
-          if (m0 + mc < g.M) v = *(const uint4 *)(g.A + (long)(k0 + kr) * g.lda + m0 + mc);
-        }
+      uint4 x = make_uint4(0, 0, 0, 0);
+      if (c < nch) {
+        const int r = c / (BK / 8), kc = (c % (BK / 8)) * 8;
+        if (r0 + r < rows) x = *(const uint4 *)(src + (r0 + r) * ld + k0 + kc);
       }
-      ra[i] = v;
-    }
-#pragma unroll
-    for (int i = 0; i < BPT; ++i) {
-      const int c = tid + i * NT;
-      uint4 v = make_uint4(0, 0, 0, 0);
-      if (c < BCH) {
-        if (BKC) {
-          const int r = c / (BK / 8), kc = (c % (BK / 8)) * 8;
-          if (n0 + r < g.N) v = *(const uint4 *)(g.B + (n0 + r) * g.ldb + k0 + kc);
-        } else {
-          const int kr = c / (BN / 8), nc = (c % (BN / 8)) * 8;
-          if (n0 + nc < g.N) v = *(const uint4 *)(g.B + (long)(k0 + kr) * g.ldb + n0 + nc);
-        }
-      }
-      rb[i] = v;
+      v[i] = x;
     }
   };
+  auto load_mn = [&](const u16 *src, long ld, long c0, long cols, int k0, int nblk_, uint4 *v,
+                     int cnt) {
+#pragma unroll
+    for (int i = 0; i < cnt / 4; ++i) {
+      const int c = tid + i * NT;
+      const int kq = (c % (BK / 4)) * 4, mc = (c / (BK / 4)) * 8;
+      const bool in = c < nblk_ && c0 + mc < cols;
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        v[4 * i + q] = in ? *(const uint4 *)(src + (long)(k0 + kq + q) * ld + c0 + mc)
+                          : make_uint4(0, 0, 0, 0);
+    }
+  };
+  auto store_kc = [&](u16 *dst, int nch, const uint4 *v, int cnt) {
+#pragma unroll
+    for (int i = 0; i < cnt; ++i) {
+      const int c = tid + i * NT;
+      if (c < nch) {
+        const int r = c / (BK / 8), kc = (c % (BK / 8)) * 8;
+        *(uint4 *)&dst[r * LK + kc] = v[i];
+      }
+    }
+  };
+  auto store_mn = [&](u16 *dst, int nblk_, const uint4 *v, int cnt) {
+    auto dw = [](const uint4 &x, int d) { return d == 0 ? x.x : (d == 1 ? x.y : (d == 2 ? x.z : x.w)); };
+    // the two BF16 of column j in K rows (a, b), row a in the low half
+    auto pair = [](unsigned a, unsigned b, int h) {
+      return h == 0 ? (a & 0xffffu) | (b << 16) : (a >> 16) | (b & 0xffff0000u);
+    };
+#pragma unroll
+    for (int i = 0; i < cnt / 4; ++i) {
+      const int c = tid + i * NT;
+      if (c < nblk_) {
+        const int kq = (c % (BK / 4)) * 4, mc = (c / (BK / 4)) * 8;
+        const uint4 *x = v + 4 * i;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int d = j >> 1, h = j & 1;
+          *(uint2 *)&dst[(mc + j) * LK + kq] = make_uint2(pair(dw(x[0], d), dw(x[1], d), h),
+                                                          pair(dw(x[2], d), dw(x[3], d), h));
+        }
+      }
+    }
+  };
+  auto load = [&](int k0) {
+    if constexpr (AK) load_kc(g.A, g.lda, m0, g.M, k0, ACH, ra, APT);
+    else load_mn(g.A, g.lda, m0, g.M, k0, ATB, ra, APT);
+    if constexpr (BKC) load_kc(g.B, g.ldb, n0, g.N, k0, BCH, rb, BPT);
+    else load_mn(g.B, g.ldb, n0, g.N, k0, BTB, rb, BPT);
+  };
   auto store = [&](int buf) {
-#pragma unroll
-    for (int i = 0; i < APT; ++i) {
-      const int c = tid + i * NT;
-      if (c < ACH) {
-        if (AK) {
-          const int r = c / (BK / 8), kc = (c % (BK / 8)) * 8;
-          *(uint4 *)&As[buf][r * LK + kc] = ra[i];
-        } else {
-          const int kr = c / (BM / 8), mc = (c % (BM / 8)) * 8;
-          const u16 *e = (const u16 *)&ra[i];
-#pragma unroll
-          for (int j = 0; j < 8; ++j) As[buf][(mc + j) * LK + kr] = e[j];
-        }
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < BPT; ++i) {
-      const int c = tid + i * NT;
-      if (c < BCH) {
-        if (BKC) {
-          const int r = c / (BK / 8), kc = (c % (BK / 8)) * 8;
-          *(uint4 *)&Bs[buf][r * LK + kc] = rb[i];
-        } else {
-          const int kr = c / (BN / 8), nc = (c % (BN / 8)) * 8;
-          const u16 *e = (const u16 *)&rb[i];
-#pragma unroll
-          for (int j = 0; j < 8; ++j) Bs[buf][(nc + j) * LK + kr] = e[j];
-        }
-      }
-    }
+    if constexpr (AK) store_kc(As[buf], ACH, ra, APT);
+    else store_mn(As[buf], ATB, ra, APT);
+    if constexpr (BKC) store_kc(Bs[buf], BCH, rb, BPT);
+    else store_mn(Bs[buf], BTB, rb, BPT);
   };
   auto compute = [&](int buf) {
 #pragma unroll
