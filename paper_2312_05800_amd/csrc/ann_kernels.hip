@@ -106,9 +106,14 @@ __device__ __forceinline__ unsigned e4m3x4(float a, float b, float c, float d) {
 // v_mfma_f32_32x32x16_bf16.  Operand tiles are staged through LDS in a
 // K-contiguous layout (double buffered); operands stored MN-contiguous in
 // global memory are transposed while being written to LDS.
-template <int WM, int WN, int TM, int TN, bool AK, bool BKC, int EPI>
+//
+// BK (32 or 64) is the K-step: with one step prefetched into registers while
+// the current one is multiplied, each step waits for one round trip of its
+// loads, so the training-size products (few blocks per CU) take 64-wide steps
+// when the K range of a block allows it.
+template <int WM, int WN, int TM, int TN, bool AK, bool BKC, int EPI, int BK = 32>
 __global__ __launch_bounds__(WM *WN * 64) void k_gemm(GemmArgs g) {
-  constexpr int BM = WM * TM * 32, BN = WN * TN * 32, BK = 32, LK = BK + 8;
+  constexpr int BM = WM * TM * 32, BN = WN * TN * 32, LK = BK + 8;
   constexpr int NT = WM * WN * 64;
   __shared__ __attribute__((aligned(16))) u16 As[2][BM * LK];
   __shared__ __attribute__((aligned(16))) u16 Bs[2][BN * LK];
@@ -126,7 +131,7 @@ __global__ __launch_bounds__(WM *WN * 64) void k_gemm(GemmArgs g) {
   const long m0 = (long)(logical / ntn) * BM, n0 = (long)(logical % ntn) * BN;
   // split-K range of this block (blockIdx.y); the whole K when not split
   const int kper = g.ksplit > 1 ? g.K / g.ksplit : g.K;
-  const int kbase = (int)blockIdx.y * kper;
+  const int kbase = (int)blockIdx.y * kper, kend = kbase + kper;
   // K-contiguous operands move as 16-byte chunks (8 K values of one row).  An
   // MN-contiguous operand moves as blocks of 4 K rows x 8 columns: four
   // coalesced 16-byte loads, a transpose in registers, and eight 8-byte LDS
@@ -156,7 +161,7 @@ __global__ __launch_bounds__(WM *WN * 64) void k_gemm(GemmArgs g) {
       uint4 x = make_uint4(0, 0, 0, 0);
       if (c < nch) {
         const int r = c / (BK / 8), kc = (c % (BK / 8)) * 8;
-        if (r0 + r < rows) x = *(const uint4 *)(src + (r0 + r) * ld + k0 + kc);
+        if (r0 + r < rows && k0 + kc < kend) x = *(const uint4 *)(src + (r0 + r) * ld + k0 + kc);
       }
       v[i] = x;
     }
@@ -170,8 +175,9 @@ __global__ __launch_bounds__(WM *WN * 64) void k_gemm(GemmArgs g) {
       const bool in = c < nblk_ && c0 + mc < cols;
 #pragma unroll
       for (int q = 0; q < 4; ++q)
-        v[4 * i + q] = in ? *(const uint4 *)(src + (long)(k0 + kq + q) * ld + c0 + mc)
-                          : make_uint4(0, 0, 0, 0);
+        v[4 * i + q] = in && k0 + kq + q < kend
+                           ? *(const uint4 *)(src + (long)(k0 + kq + q) * ld + c0 + mc)
+                           : make_uint4(0, 0, 0, 0);
     }
   };
   auto store_kc = [&](u16 *dst, int nch, const uint4 *v, int cnt) {
@@ -237,7 +243,9 @@ __global__ __launch_bounds__(WM *WN * 64) void k_gemm(GemmArgs g) {
     }
   };
 
-  const int nk = kper / BK;
+  // a K range that is not a multiple of BK ends with a zero-filled step (K is
+  // a multiple of 32, so 8-wide chunks and 4-row blocks are wholly in or out)
+  const int nk = (kper + BK - 1) / BK;
   load(kbase);
   store(0);
   __syncthreads();
@@ -257,6 +265,17 @@ __global__ __launch_bounds__(WM *WN * 64) void k_gemm(GemmArgs g) {
       const long col = n0 + wn * TN * 32 + j * 32 + (lane & 31);
       if (col >= g.N) continue;
       const float bias = g.bias ? g.bias[col] : 0.0f;
+      // the tile's 16 pre-activations are loaded before its first store (the
+      // stores may alias them as far as the compiler knows, which would make
+      // every load wait for the store before it)
+      float zt[16];
+      if constexpr (EPI == EPI_GELUGRAD) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const long row = m0 + wm * TM * 32 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+          zt[r] = row < g.M ? g.Z[row * g.ldz + col] : 0.0f;
+        }
+      }
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const long row = m0 + wm * TM * 32 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
@@ -272,7 +291,7 @@ __global__ __launch_bounds__(WM *WN * 64) void k_gemm(GemmArgs g) {
         } else if (EPI == EPI_GELU_Q8) {
           g.Cq[row * g.ldcq + col] = f2e4m3(gelu(v + bias) * g.qinv);
         } else {
-          const float d = v * gelu_grad(g.Z[row * g.ldz + col]);
+          const float d = v * gelu_grad(zt[r]);
           if (g.Cb) g.Cb[row * g.ldcb + col] = f2bf(d);
           if (g.Cf) g.Cf[row * g.ldcf + col] = d;
         }
@@ -787,29 +806,42 @@ __global__ __launch_bounds__(MLP12_WM * 64) void k_mlp12(Mlp12Args g) {
     mlp12_tile<TN16, false>(g, S, b1_s, bias_s, wave);
 }
 
-template <int WM, int WN, int TM, int TN>
-chem_status gemm_cfg(const GemmArgs &g, bool AK, bool BK, int epi, hipStream_t s) {
-  constexpr int BM = WM * TM * 32, BN = WN * TN * 32;
-  const long total = (long)((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
-  dim3 grid((unsigned)(((total + 7) / 8) * 8), g.ksplit > 1 ? g.ksplit : 1);
-  dim3 block(WM * WN * 64);
-  if (AK && BK && epi == EPI_GELU)
-    hipLaunchKernelGGL((k_gemm<WM, WN, TM, TN, true, true, EPI_GELU>), grid, block, 0, s, g);
-  else if (AK && BK && epi == EPI_F32)
-    hipLaunchKernelGGL((k_gemm<WM, WN, TM, TN, true, true, EPI_F32>), grid, block, 0, s, g);
-  else if (AK && BK && epi == EPI_GELU_Q8)
-    hipLaunchKernelGGL((k_gemm<WM, WN, TM, TN, true, true, EPI_GELU_Q8>), grid, block, 0, s, g);
-  else if (AK && !BK && epi == EPI_GELUGRAD)
-    hipLaunchKernelGGL((k_gemm<WM, WN, TM, TN, true, false, EPI_GELUGRAD>), grid, block, 0, s,
+template <int WM, int WN, int TM, int TN, int BK>
+chem_status gemm_launch(const GemmArgs &g, bool AK, bool BKC, int epi, dim3 grid, dim3 block,
+                        hipStream_t s) {
+  if (AK && BKC && epi == EPI_GELU)
+    hipLaunchKernelGGL((k_gemm<WM, WN, TM, TN, true, true, EPI_GELU, BK>), grid, block, 0, s, g);
+  else if (AK && BKC && epi == EPI_F32)
+    hipLaunchKernelGGL((k_gemm<WM, WN, TM, TN, true, true, EPI_F32, BK>), grid, block, 0, s, g);
+  else if (AK && BKC && epi == EPI_GELU_Q8)
+    hipLaunchKernelGGL((k_gemm<WM, WN, TM, TN, true, true, EPI_GELU_Q8, BK>), grid, block, 0, s,
                        g);
-  else if (!AK && !BK && epi == EPI_F32)
-    hipLaunchKernelGGL((k_gemm<WM, WN, TM, TN, false, false, EPI_F32>), grid, block, 0, s, g);
+  else if (AK && !BKC && epi == EPI_GELUGRAD)
+    hipLaunchKernelGGL((k_gemm<WM, WN, TM, TN, true, false, EPI_GELUGRAD, BK>), grid, block, 0,
+                       s, g);
+  else if (!AK && !BKC && epi == EPI_F32)
+    hipLaunchKernelGGL((k_gemm<WM, WN, TM, TN, false, false, EPI_F32, BK>), grid, block, 0, s,
+                       g);
   else {
     chem::set_error("gemm: unsupported layout/epilogue combination");
     return CHEM_EUNSUPPORTED;
   }
   CHEM_HIP(hipGetLastError());
   return CHEM_OK;
+}
+
+template <int WM, int WN, int TM, int TN>
+chem_status gemm_cfg(const GemmArgs &g, bool AK, bool BKC, int epi, hipStream_t s) {
+  constexpr int BM = WM * TM * 32, BN = WN * TN * 32;
+  const long total = (long)((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
+  dim3 grid((unsigned)(((total + 7) / 8) * 8), g.ksplit > 1 ? g.ksplit : 1);
+  dim3 block(WM * WN * 64);
+  // 64-wide K-steps for launches of up to 1024 blocks (the training batch);
+  // larger grids keep the smaller LDS footprint and more blocks per CU
+  const int kper = g.ksplit > 1 ? g.K / g.ksplit : g.K;
+  if (kper >= 64 && (long)grid.x * grid.y <= 1024)
+    return gemm_launch<WM, WN, TM, TN, 64>(g, AK, BKC, epi, grid, block, s);
+  return gemm_launch<WM, WN, TM, TN, 32>(g, AK, BKC, epi, grid, block, s);
 }
 
 // ------------------------------------------------------------ FP8 GEMM
