@@ -1354,8 +1354,17 @@ __global__ void k_l1(int64_t n, int K, int doutp, const float *U, const float *U
 
 __global__ void k_loss_final(const double *part, int nparts, double scale, float *loss) {
   if (threadIdx.x != 0) return;
+  // partials added in order, loaded eight at a time
   double s = 0.0;
-  for (int i = 0; i < nparts; ++i) s += part[i];
+  int i = 0;
+  for (; i + 8 <= nparts; i += 8) {
+    double x[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) x[r] = part[i + r];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) s += x[r];
+  }
+  for (; i < nparts; ++i) s += part[i];
   *loss = (float)(s * scale);
 }
 
@@ -1658,12 +1667,22 @@ __global__ __launch_bounds__(128, 4) void k_post(chem::DevMech M, PostArgs a) {
     if (flag == 0) {
       const double rho0 = p / (RG * T0 * S0);
       const double sc = rho0 / a.dt;
+      // Y0 is read again for the rates, eight species at a time before their
+      // stores (a load placed after a store that may alias it waits for it)
+      constexpr int WB = 8;
 #pragma unroll
-      for (int k = 0; k < KP; ++k) {
-        if (k < K) {
-          double *yp = a.Y + (int64_t)k * a.ld + i;
-          if (a.RR) a.RR[(int64_t)k * a.ld + i] = sc * (yn[k] - *yp);
-          *yp = yn[k];
+      for (int k0 = 0; k0 < KP; k0 += WB) {
+        double y0[WB];
+#pragma unroll
+        for (int t = 0; t < WB; ++t)
+          y0[t] = (a.RR && k0 + t < K) ? a.Y[(int64_t)(k0 + t) * a.ld + i] : 0.0;
+#pragma unroll
+        for (int t = 0; t < WB; ++t) {
+          const int k = k0 + t;
+          if (k < K) {
+            if (a.RR) a.RR[(int64_t)k * a.ld + i] = sc * (yn[k] - y0[t]);
+            a.Y[(int64_t)k * a.ld + i] = yn[k];
+          }
         }
       }
       a.T[i] = T;
