@@ -133,14 +133,16 @@ def test_fit_norm(dev, mech, data):
     assert g["lambda"] == pytest.approx(0.1) and g["dt_model"] == 1e-5
 
 
-def test_gradients_and_adam(dev, mech, data):
+@pytest.mark.parametrize("B", [256, 160])
+def test_gradients_and_adam(dev, mech, data, B):
+    """B = 256: split-K weight gradients; B = 160: row tiles that end inside
+    a 128-row tile and 64-wide K-steps that end with a zero-filled half."""
     import torch
-    _say("[ann grads]")
+    _say(f"[ann grads] B={B}")
     K = mech.K
     params = oann.init_params([K + 2, *HID, K], seed=9)
     nm = _norm_from(data)
     m = _model(mech, params, nm)
-    B = 256
     T, p, Y0, Y1 = data["T"][:B], data["p"][:B], data["Y0"][:, :B], data["Y1"][:, :B]
     loss = torch.zeros(1, dtype=torch.float32, device=dev)
     args = [to_dev(a, dev) for a in (T, p, Y0, Y1)]
