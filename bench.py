@@ -520,6 +520,18 @@ def main():
                          "sample": f"{ns} evenly spaced cells of the 2^20-cell workload, "
                                    f"FP64 RODAS3 oracle (plain C, OpenMP)"},
         "training": train_info,
+        # the paper's own speed figures, for context only (another machine,
+        # mechanism and workload; not a target of this measurement)
+        "paper_context": {
+            "reported": "chemistry time per LES step cut by 91.3 % (about 11.5x) with the "
+                        "ANN on one GPU against direct integration (CVODE) on 32 CPU cores, "
+                        "a 1-GPU-to-1-core ratio of 369; neither GPU nor CPU model is named; "
+                        "DRM19 (20 species), 2.5 M-cell LES, network trained at dt = 1 us "
+                        "(Sec. 4.2, Sec. 5)",
+            "this_run_ann_vs_cpu_oracle": round(ann_cps / cpu_cps, 1),
+            "this_run_ann_vs_cpu_oracle_per_core": round(ann_cps / cpu_cps * nthr, 1),
+            "cpu_oracle_cores": nthr,
+        },
     }
     print(json.dumps(out), flush=True)
 
