@@ -1288,7 +1288,7 @@ __global__ __launch_bounds__(BLK) void k_features(FeatArgs a) {
 // issued before the first store (the output rows may not alias the inputs, but
 // the compiler cannot know that), and a padded width that is a multiple of 4
 // is written with 16-byte stores.
-constexpr int TGT_BATCH = 8;
+constexpr int TGT_BATCH = 16;
 
 __global__ void k_targets(TargetArgs a) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1373,7 +1373,7 @@ __global__ void k_loss_final(const double *part, int nparts, double scale, float
 // pass adds the P partials in order of q.
 // Both passes issue COLSUM_BATCH loads before adding them, in order, to the
 // running sum (the same order as one load at a time).
-constexpr int COLSUM_BATCH = 8;
+constexpr int COLSUM_BATCH = 16;
 
 __global__ void k_colsum_part(int64_t M, int N, const float *X, long ldx, double *part) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
