@@ -256,6 +256,38 @@ def nrmse_table(dY_model, dY_ref, Yref_mean, names, rtol=1e-6):
     return out, (max(majors) if majors else float("nan"))
 
 
+def small_config(P, dev, oracle, nthr):
+    """The 9-species H2/air configuration (4096 cells, dt = 1e-6 s): GPU chem_step
+    cells/s, parity with the oracle on every cell, and the oracle's cells/s."""
+    import numpy as np
+    import torch
+    import chemgen
+    mech = chemgen.make_mechanism("h2")
+    T, p, Y = chemgen.make_states(mech, "h2")
+    N, dt = T.size, 1e-6
+    gm = P.Mechanism(mech)
+    T0d, pd, Y0d = (torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (T, p, Y))
+    Td, Yd = T0d.clone(), Y0d.clone()
+
+    def restore():
+        Td.copy_(T0d)
+        Yd.copy_(Y0d)
+    steps = 20
+    t = timed_loop(lambda: P.chem_step(gm, dt, Td, pd, Yd), restore, steps, 2)
+    om = oracle.OracleMech(mech)
+    tc = time.time()
+    o = oracle.chem_step(om, dt, T, p, Y)
+    tc = time.time() - tc
+    gT, gY = Td.cpu().numpy(), Yd.cpu().numpy()
+    big = np.abs(o["Y"]) > 1e-10
+    err = max(float(np.max(np.abs(gT - o["T"]) / o["T"])),
+              float(np.max(np.abs(gY - o["Y"])[big] / np.abs(o["Y"])[big])))
+    return {"workload": f"H2/air, {mech.K} species / {mech.R} reactions, {N} cells, dt=1e-6 s",
+            "gpu_cells_per_s": round(N * steps / t, 1), "gpu_ms_per_step": round(1e3 * t / steps, 4),
+            "max_rel_err_vs_oracle": err, "oracle_cells_per_s": round(N / tc, 1),
+            "oracle_cores": nthr}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -391,6 +423,13 @@ def main():
     if fp8 is not None:
         _, fp8["nrmse"] = nrmse_table(fp8["Y"][:, idx] - Y[:, idx], dY_ref, o["Y"].mean(axis=1),
                                       mech.species)
+    # the same error against the GPU FP64 integrator, on every cell
+    dY_fp = fp_Y - Y
+    _, ann_vs_fp64_all = nrmse_table(ann_Y - Y, dY_fp, fp_Y.mean(axis=1), mech.species)
+    fp8_vs_fp64_all = None
+    if fp8 is not None:
+        _, fp8_vs_fp64_all = nrmse_table(fp8["Y"] - Y, dY_fp, fp_Y.mean(axis=1), mech.species)
+    del dY_fp
     big = np.abs(o["Y"]) > 1e-10
     fp_err = max(float(np.max(np.abs(fp_T[idx] - o["T"]) / o["T"])),
                  float(np.max(np.abs(fp_Y[:, idx] - o["Y"])[big] / np.abs(o["Y"])[big])))
@@ -455,6 +494,31 @@ def main():
     oracle.chem_step(om, 1e-5, T[si], p[si], Y[:, si])
     tc = time.time() - tc
     cpu_cps = ns / tc
+    # the oracle on one core (the paper's per-core convention), ~3 s of work
+    s1 = pi[:32]
+    t1 = time.time()
+    oracle.chem_step(om, 1e-5, T[s1], p[s1], Y[:, s1], nthreads=1)
+    t1 = time.time() - t1
+    n1 = int(min(N, max(32, 3.0 / max(t1, 1e-6) * 32)))
+    s1 = np.linspace(0, N - 1, n1).astype(np.int64)
+    t1 = time.time()
+    oracle.chem_step(om, 1e-5, T[s1], p[s1], Y[:, s1], nthreads=1)
+    t1 = time.time() - t1
+    # the network on the host: the oracle's FP64 NumPy MLP (BLAS) on 2^16 cells
+    from oracle import ann as oann
+    shapes = [(HIDDEN[0], K + 2), (HIDDEN[1], HIDDEN[0]), (HIDDEN[2], HIDDEN[1]), (K, HIDDEN[2])]
+    params64 = [tuple(a.astype(np.float64) for a in model.get_layer(l, shapes[l]))
+                for l in range(4)]
+    nmz = model.get_norm(K + 2, K)
+    na = int(min(N, 1 << 16))
+    ai = np.linspace(0, N - 1, na).astype(np.int64)
+    ta = time.time()
+    feat = oann.features(T[ai], p[ai], Y[:, ai])
+    Xa = ((feat - nmz["mu_in"][:, None].astype(np.float64)) /
+          nmz["sd_in"][:, None].astype(np.float64)).T
+    oann.forward(params64, Xa, prec="fp64")
+    ta = time.time() - ta
+    small = small_config(P, dev, oracle, nthr)
 
     out = {
         "metric": METRIC,
@@ -520,6 +584,16 @@ def main():
                          "sample": f"{ns} evenly spaced cells of the 2^20-cell workload, "
                                    f"FP64 RODAS3 oracle (plain C, OpenMP)"},
         "training": train_info,
+        "cpu_baselines_more": {
+            "oracle_one_core": {"value": round(n1 / t1, 2), "unit": "cells/s", "cores": 1,
+                                "sample": f"{n1} evenly spaced cells of the 2^20-cell workload"},
+            "ann_numpy_fp64": {"value": round(na / ta, 1), "unit": "cells/s",
+                               "threads": os.environ.get("OMP_NUM_THREADS", "library default"),
+                               "sample": f"{na} evenly spaced cells: features and the FP64 "
+                                         f"MLP forward (NumPy/BLAS), no post-processing"}},
+        "accuracy_vs_gpu_fp64_all_cells": {"cells": N, "ann_nrmse_major_max": ann_vs_fp64_all,
+                                           "fp8_nrmse_major_max": fp8_vs_fp64_all},
+        "small_config": small,
         # the paper's own speed figures, for context only (another machine,
         # mechanism and workload; not a target of this measurement)
         "paper_context": {
