@@ -302,7 +302,7 @@ def main():
     ap.add_argument("--batch", type=int, default=8192)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--seed", type=int, default=55)
-    ap.add_argument("--oracle-sample", type=int, default=2048)
+    ap.add_argument("--oracle-sample", type=int, default=1 << 16)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--fp8", type=int, default=1, help="also time FP8 hidden layers (1/0)")
     ap.add_argument("--sets", type=int, default=0,
