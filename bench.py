@@ -423,6 +423,18 @@ def main():
     if fp8 is not None:
         _, fp8["nrmse"] = nrmse_table(fp8["Y"][:, idx] - Y[:, idx], dY_ref, o["Y"].mean(axis=1),
                                       mech.species)
+    # fallback without the element projection: the network's own state
+    # Y0 + dY (clipped at 0) tested against the same 1e-6 element residual
+    nmo = model.get_norm(K + 2, K)
+    idx_d = torch.from_numpy(idx).to(dev)
+    U = model.forward(T0d[idx_d].contiguous(), pd[idx_d].contiguous(),
+                      Y0d[:, idx_d].contiguous(), K).cpu().numpy().astype(np.float64).T
+    Yraw = np.maximum(Y[:, idx] + U * nmo["sd_out"][:, None] + nmo["mu_out"][:, None], 0.0)
+    Mel = (mech.awt[None, :] * mech.comp / mech.W[:, None]).T  # [E][K]
+    res_raw = np.abs(Mel @ (Yraw - Y[:, idx])).max(axis=0)
+    unprojected_flagged = int((res_raw > 1e-6).sum())
+    del U, Yraw
+
     # the same error against the GPU FP64 integrator, on every cell
     dY_fp = fp_Y - Y
     _, ann_vs_fp64_all = nrmse_table(ann_Y - Y, dY_fp, fp_Y.mean(axis=1), mech.species)
@@ -554,6 +566,10 @@ def main():
                      "euler_nrmse_major_max": euler_major,
                      "ann_T_rmse_K": ann_Terr,
                      "fallback_cells": n_fallback,
+                     "element_residual_flags_without_projection": {
+                         "cells": unprojected_flagged, "of": int(idx.size),
+                         "max_residual": float(res_raw.max()),
+                         "median_residual": float(np.median(res_raw)), "tol": 1e-6},
                      "per_species": {k: round(v["nrmse"], 5) for k, v in table.items()
                                      if v["major"]},
                      "unresolved_abundant": {k: dict(nrmse=round(v["nrmse"], 4),
