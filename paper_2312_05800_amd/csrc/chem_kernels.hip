@@ -429,6 +429,9 @@ __global__ __launch_bounds__(64) void k_step(DevMech M, StepArgs A) {
   int nacc = 0, nrej = 0, status = CELL_OK;
 
   const int64_t ncell = A.n_dev ? (int64_t)*A.n_dev : A.n;
+  // an empty device-side list (no cell fell back) ends every wave here,
+  // without a round of atomics on the queue counter
+  if (ncell <= 0) return;
   CellRef cr{};
   auto fetch = [&]() {
     unsigned long long c = 0;
