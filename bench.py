@@ -36,18 +36,25 @@ def log(*a):
 
 
 def rodas3_flops_per_attempt(mech):
-    """Algorithmic FP64 operations of one attempted RODAS3 step of one cell
-    (adds, multiplies, divides, FMA = 2, each exp/log/pow/sqrt = 1), counted
-    from the algorithm: 3 right-hand sides, 1 Jacobian, 1 LU, 4 solves, stage
-    combinations and the error norm."""
+    """Algorithmic FP64 flops of one attempted RODAS3 step of one cell (FMA =
+    2), counted from the method, not from the kernel: one analytic Jacobian
+    (40 R + 3 n^2), three right-hand sides (16 K + 33 R + 6 K each), forming
+    the Newton matrix (n^2), its LU ((2/3) n^3), four pairs of triangular
+    solves (2 n^2 each), the stage combinations (s^2 n) and the error norm
+    (4 n); the exponentials of the rate constants (2 R per right-hand side)
+    are counted separately."""
     K, R = mech.K, mech.R
     n = K + 1
-    nnz = int((mech.rsp >= 0).sum())
-    rhs = 44 * K + 30 * R + 2 * nnz + 6 * K + 24
-    jac = 34 * K + 16 * R + 25 * nnz + 11 * K * K + n * n
-    lu = sum(2 * j * j + j for j in range(1, n)) + n
-    solve = 2 * n * n - n
-    return 3 * rhs + jac + lu + 4 * solve + 60 * n
+    s, s_f = 4, 3
+    f_rhs = 16 * K + 25 * R + 8 * R + 6 * K
+    f_jac = 40 * R + 3 * n * n
+    return f_jac + s_f * f_rhs + n * n + (2.0 / 3.0) * n ** 3 + s * 2 * n * n + s * s * n + 4 * n
+
+
+def rodas3_exp_per_attempt(mech):
+    """Exponentials per attempted step: k_f and k_r of every reaction at each
+    of the three right-hand sides."""
+    return 2 * mech.R * 3
 
 
 def mlp_flops_per_cell(K):

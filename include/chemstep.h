@@ -195,6 +195,11 @@ chem_status ann_set_layer(ann_model *m, int32_t layer, const float *W, const flo
 chem_status ann_get_layer(const ann_model *m, int32_t layer, float *W, float *b);
 /* Gradients of the loss from the last ann_train_step (host arrays as above). */
 chem_status ann_get_grad(const ann_model *m, int32_t layer, float *dW, float *db);
+/* Adam's first and second moments of layer l (host arrays as for the layer:
+ * mW, vW [out][in], mb, vb [out]; any may be NULL): the optimiser state the
+ * next ann_train_step continues from (Sec. 3.2, Adam). */
+chem_status ann_get_moments(const ann_model *m, int32_t layer, float *mW, float *vW, float *mb,
+                            float *vb);
 chem_status ann_set_norm(ann_model *m, const ann_norm *norm);
 /* Host copies of the statistics; any pointer may be NULL. */
 chem_status ann_get_norm(const ann_model *m, float *mu_in, float *sd_in, float *lo, float *hi,
@@ -213,7 +218,7 @@ typedef struct {
   float residual_tol;   /* [1e-6] max |element mass fraction change| allowed */
   float ood_margin;     /* [0.05] widening of the training range, fraction of its span */
   int32_t fallback;     /* [1] integrate flagged cells with chem_step */
-  float audit_fraction; /* reserved, must be 0 */
+  float audit_fraction; /* reserved: must be 0 (any other value is CHEM_EINVAL) */
 } ann_step_opts;
 
 /* The surrogate chemistry step of every cell (the ANN replacing the
@@ -222,7 +227,9 @@ typedef struct {
  * squares (weights Y' + 1e-10), clipped at 0; T from h(T, Y) = h(T0, Y0) by
  * FP64 Newton; RR = rho0 (Y - Y0)/dt.  A cell is flagged (flags [n], nullable)
  * with bit 0 if an input lies outside the widened training range or dt
- * differs from dt_model, bit 1 if the element residual exceeds residual_tol;
+ * differs from dt_model, bit 1 if the element residual of the network's own
+ * state Y' (max_e |(M Y')_e - (M Y0)_e|, M the element mass fractions per
+ * unit mass fraction) or of the projected state exceeds residual_tol;
  * flagged cells keep their input state and, with fallback on, are integrated
  * by chem_step (fb_opts) on the same stream without a host round trip; bit 2
  * marks a failed fallback.  n_fallback (device int64, nullable) receives the

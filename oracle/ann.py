@@ -250,28 +250,41 @@ def density(mech, T, p, Y):
 
 
 def ood_flags(feat, lo, hi, margin=0.05):
-    """feat: raw features [F, N]; lo/hi: training-set range per feature."""
+    """feat: raw features [F, N]; lo/hi: training-set range per feature.  A
+    cell is out of distribution when any feature lies outside [lo - tol,
+    hi + tol] with tol = margin * (hi - lo), or, for a feature of zero
+    spread, tol = 1e-6 |hi|.  A non-finite feature is outside."""
     span = hi - lo
     tol = np.where(span > 0, margin * span, 1e-6 * np.maximum(np.abs(hi), 1e-30))
-    bad = (feat < (lo - tol)[:, None]) | (feat > (hi + tol)[:, None])
-    return bad.any(axis=0)
+    inside = (feat >= (lo - tol)[:, None]) & (feat <= (hi + tol)[:, None])
+    return (~inside).any(axis=0)
 
 
 def post(om: OracleMech, T0, p, Y0, u_z, mu_out, sd_out, dt, lo=None, hi=None,
          residual_tol=1e-6, margin=0.05, lam=LAMBDA):
-    """From the z-space network output u_z ([K, N]) to (T, Y, RR, flags)."""
+    """From the z-space network output u_z ([K, N]) to (T, Y, RR, flags).
+
+    Flag bit 1 (value 2) judges the network itself: it is set when the
+    element residual of the network's own state Y' = Y0 + dY, max_e
+    |(M Y')_e - (M Y0)_e|, exceeds residual_tol, and also when the projected
+    and clipped state still misses element conservation by more than that
+    (the projection removes the first residual exactly unless clipping at 0
+    breaks it).  A non-finite residual counts as exceeding."""
     mech = om.mech
     du = u_z * sd_out[:, None] + mu_out[:, None]
     Yp = Y0 + du
     Y = project(mech, Y0, Yp)
     Y = np.maximum(Y, 0.0)
     M = element_mass_matrix(mech)
+    res_raw = np.abs(M @ Yp - M @ Y0).max(axis=0)
     res = np.abs(M @ Y - M @ Y0).max(axis=0)
     flags = np.zeros(T0.size, dtype=np.uint8)
     if lo is not None:
         flags |= np.where(ood_flags(features(T0, p, Y0, lam), lo, hi, margin), 1, 0).astype(np.uint8)
-    flags |= np.where(res > residual_tol, 2, 0).astype(np.uint8)
+    bad = ~((res_raw <= residual_tol) & (res <= residual_tol))
+    flags |= np.where(bad, 2, 0).astype(np.uint8)
     T = temperature_newton(om, T0, Y0, Y)
     rho0 = density(mech, T0, p, Y0)
     RR = rho0[None, :] * (Y - Y0) / dt
-    return dict(T=T, Y=Y, RR=RR, flags=flags, residual=res, Yp=Yp)
+    return dict(T=T, Y=Y, RR=RR, flags=flags, residual=res, residual_raw=res_raw, Yp=Yp,
+                rho0=rho0)

@@ -6,7 +6,7 @@ import ctypes as C
 
 import numpy as np
 
-from .binding import Batch, StepOpts, _dptr, _opts, _soa, _stream, check, lib
+from .binding import Batch, StepOpts, _dptr, _opts, _soa, _stream, _vec, check, lib
 
 _P = C.c_void_p
 
@@ -37,6 +37,7 @@ def _prototypes(L):
     L.ann_set_layer.argtypes = [_P, C.c_int32, _P, _P]
     L.ann_get_layer.argtypes = [_P, C.c_int32, _P, _P]
     L.ann_get_grad.argtypes = [_P, C.c_int32, _P, _P]
+    L.ann_get_moments.argtypes = [_P, C.c_int32, _P, _P, _P, _P]
     L.ann_set_norm.argtypes = [_P, C.POINTER(Norm)]
     L.ann_get_norm.argtypes = [_P, _P, _P, _P, _P, _P, _P, _P, _P]
     L.ann_fit_norm.argtypes = [_P, Batch, _P, _P, _P, _P, C.c_float, C.c_double, _P]
@@ -114,6 +115,17 @@ class AnnModel:
                                                  b.ctypes.data))
         return W, b
 
+    def get_moments(self, layer, shape):
+        """Adam's (mW, vW, mb, vb) of a layer as host FP32 arrays."""
+        mW = np.zeros(shape, dtype=np.float32)
+        vW = np.zeros(shape, dtype=np.float32)
+        mb = np.zeros(shape[0], dtype=np.float32)
+        vb = np.zeros(shape[0], dtype=np.float32)
+        check("ann_get_moments", lib().ann_get_moments(
+            self.handle, int(layer), mW.ctypes.data, vW.ctypes.data, mb.ctypes.data,
+            vb.ctypes.data))
+        return mW, vW, mb, vb
+
     def set_norm(self, lam, dt_model, mu_in, sd_in, lo, hi, mu_out, sd_out):
         arrs = [np.ascontiguousarray(a, dtype=np.float32)
                 for a in (mu_in, sd_in, lo, hi, mu_out, sd_out)]
@@ -142,7 +154,7 @@ class AnnModel:
         ld = _soa(Y, Y.shape[0], n, "Y")
         f64 = torch.float64
         check("ann_quantize_fp8", lib().ann_quantize_fp8(
-            self.handle, Batch(n, ld), _dptr(T, f64, "T"), _dptr(p, f64, "p"),
+            self.handle, Batch(n, ld), _vec(T, n, "T", f64), _vec(p, n, "p", f64),
             _dptr(Y, f64, "Y"), _stream(stream)))
 
     def set_precision(self, prec):
@@ -159,9 +171,11 @@ class AnnModel:
         import torch
         n = T.shape[0]
         ld = _soa(Y0, Y0.shape[0], n, "Y0")
+        if Y1.shape[0] != Y0.shape[0] or _soa(Y1, Y0.shape[0], n, "Y1") != ld:
+            raise ValueError("Y1 must have the shape and leading dimension of Y0")
         f64 = torch.float64
         check("ann_fit_norm", lib().ann_fit_norm(
-            self.handle, Batch(n, ld), _dptr(T, f64, "T"), _dptr(p, f64, "p"),
+            self.handle, Batch(n, ld), _vec(T, n, "T", f64), _vec(p, n, "p", f64),
             _dptr(Y0, f64, "Y0"), _dptr(Y1, f64, "Y1"), float(lam), float(dt_model),
             _stream(stream)))
 
@@ -172,7 +186,7 @@ class AnnModel:
         U = torch.empty((n, n_out), dtype=torch.float32, device=T.device)
         f64 = torch.float64
         check("ann_forward", lib().ann_forward(
-            self.handle, Batch(n, ld), _dptr(T, f64, "T"), _dptr(p, f64, "p"),
+            self.handle, Batch(n, ld), _vec(T, n, "T", f64), _vec(p, n, "p", f64),
             _dptr(Y, f64, "Y"), _dptr(U), _stream(stream)))
         return U
 
@@ -183,13 +197,16 @@ class AnnModel:
         import torch
         n = T.shape[0]
         ld = _soa(Y, mech.K, n, "Y")
+        if RR is not None and _soa(RR, mech.K, n, "RR") != ld:
+            raise ValueError("RR must have the leading dimension of Y")
         o = StepOptsANN(float(residual_tol), float(ood_margin), 1 if fallback else 0, 0.0)
         fo = _opts(fb_opts)
         f64 = torch.float64
         check("ann_step", lib().ann_step(
-            self.handle, mech.handle, Batch(n, ld), float(dt), _dptr(T, f64, "T"),
-            _dptr(p, f64, "p"), _dptr(Y, f64, "Y"), _dptr(RR, f64, "RR"),
-            _dptr(flags, torch.uint8, "flags"), _dptr(n_fallback, torch.int64, "n_fallback"),
+            self.handle, mech.handle, Batch(n, ld), float(dt), _vec(T, n, "T", f64),
+            _vec(p, n, "p", f64), _dptr(Y, f64, "Y"), _dptr(RR, f64, "RR"),
+            _vec(flags, n, "flags", torch.uint8),
+            _vec(n_fallback, 1, "n_fallback", torch.int64),
             C.byref(o), None if fo is None else C.byref(fo), _stream(stream)))
 
     def step_graph(self, mech, dt, T, p, Y, RR=None, flags=None, n_fallback=None,
@@ -199,14 +216,17 @@ class AnnModel:
         from .binding import Graph
         n = T.shape[0]
         ld = _soa(Y, mech.K, n, "Y")
+        if RR is not None and _soa(RR, mech.K, n, "RR") != ld:
+            raise ValueError("RR must have the leading dimension of Y")
         o = StepOptsANN(float(residual_tol), float(ood_margin), 1 if fallback else 0, 0.0)
         fo = _opts(fb_opts)
         f64 = torch.float64
         h = _P()
         check("ann_step_graph_create", lib().ann_step_graph_create(
-            self.handle, mech.handle, Batch(n, ld), float(dt), _dptr(T, f64, "T"),
-            _dptr(p, f64, "p"), _dptr(Y, f64, "Y"), _dptr(RR, f64, "RR"),
-            _dptr(flags, torch.uint8, "flags"), _dptr(n_fallback, torch.int64, "n_fallback"),
+            self.handle, mech.handle, Batch(n, ld), float(dt), _vec(T, n, "T", f64),
+            _vec(p, n, "p", f64), _dptr(Y, f64, "Y"), _dptr(RR, f64, "RR"),
+            _vec(flags, n, "flags", torch.uint8),
+            _vec(n_fallback, 1, "n_fallback", torch.int64),
             C.byref(o), None if fo is None else C.byref(fo), None, C.byref(h)))
         return Graph(h, (self, mech, T, p, Y, RR, flags, n_fallback))
 
@@ -216,14 +236,20 @@ class AnnModel:
         the first B cells).  loss: device float32 [1] receiving the L1 loss."""
         import torch
         if index is not None:
+            # cells are gathered through the index: every array must hold the
+            # cells it can name (the library does not see their extent)
             B = index.shape[0]
-            ld = Y0.stride(0)
+            ncell = T.shape[0]
+            ld = _soa(Y0, Y0.shape[0], ncell, "Y0")
         else:
             B = T.shape[0] if B is None else B
+            ncell = B
             ld = _soa(Y0, Y0.shape[0], B, "Y0")
+        if Y1.shape[0] != Y0.shape[0] or _soa(Y1, Y0.shape[0], ncell, "Y1") != ld:
+            raise ValueError("Y1 must have the shape and leading dimension of Y0")
         o = TrainOpts(float(lr), float(beta1), float(beta2), float(eps))
         f64 = torch.float64
         check("ann_train_step", lib().ann_train_step(
-            self.handle, Batch(B, ld), _dptr(T, f64, "T"), _dptr(p, f64, "p"),
-            _dptr(Y0, f64, "Y0"), _dptr(Y1, f64, "Y1"), _dptr(index, torch.int64, "index"),
-            C.byref(o), _dptr(loss, torch.float32, "loss"), _stream(stream)))
+            self.handle, Batch(B, ld), _vec(T, ncell, "T", f64), _vec(p, ncell, "p", f64),
+            _dptr(Y0, f64, "Y0"), _dptr(Y1, f64, "Y1"), _vec(index, B, "index", torch.int64),
+            C.byref(o), _vec(loss, 1, "loss", torch.float32), _stream(stream)))

@@ -125,6 +125,21 @@ def _stream(stream):
     return C.c_void_p(s.cuda_stream)
 
 
+def _vec(t, n, name, dtype=None):
+    """Device pointer of a 1-D contiguous tensor holding at least n elements
+    (None -> NULL).  Raises ValueError before anything is launched."""
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dim() != 1 or (t.numel() > 1 and t.stride(0) != 1):
+        raise ValueError(f"{name} must be a contiguous 1-D tensor")
+    if t.numel() < n:
+        raise ValueError(f"{name} holds {t.numel()} elements, {n} needed")
+    return _dptr(t, dtype, name)
+
+
 def _soa(t, K, n, name):
     """Checks a [K][ld] species array and returns its leading dimension."""
     if n == 0 and t.dim() == 2 and t.shape[0] == K:
@@ -187,7 +202,7 @@ def chem_rates(mech: Mechanism, T, p, Y, dTdt: bool = True, kfkr: bool = False, 
     kk = torch.empty((2 * mech.R, ld), dtype=torch.float64, device=dev) if kfkr else None
     f64 = torch.float64
     check("chem_rates", lib().chem_rates(
-        mech.handle, Batch(n, ld), _dptr(T, f64, "T"), _dptr(p, f64, "p"), _dptr(Y, f64, "Y"),
+        mech.handle, Batch(n, ld), _vec(T, n, "T", f64), _vec(p, n, "p", f64), _dptr(Y, f64, "Y"),
         _dptr(wdot), _dptr(dT), _dptr(kk), _stream(stream)))
     out = dict(wdot=wdot[:, :n])
     if dTdt:
@@ -214,9 +229,9 @@ def chem_step(mech: Mechanism, dt, T, p, Y, dt_cell=None, RR=None, h_hint=None, 
     o = _opts(opts)
     f64 = torch.float64
     check("chem_step", lib().chem_step(
-        mech.handle, Batch(n, ld), float(dt), _dptr(dt_cell, f64, "dt_cell"), _dptr(T, f64, "T"),
-        _dptr(p, f64, "p"), _dptr(Y, f64, "Y"), _dptr(RR, f64, "RR"),
-        _dptr(h_hint, f64, "h_hint"), _dptr(stats, torch.int32, "stats"),
+        mech.handle, Batch(n, ld), float(dt), _vec(dt_cell, n, "dt_cell", f64),
+        _vec(T, n, "T", f64), _vec(p, n, "p", f64), _dptr(Y, f64, "Y"), _dptr(RR, f64, "RR"),
+        _vec(h_hint, n, "h_hint", f64), _dptr(stats, torch.int32, "stats"),
         None if o is None else C.byref(o), _stream(stream)))
 
 
@@ -227,10 +242,17 @@ def _set_table(mech, sets):
     for i, st in enumerate(sets):
         n = st["T"].shape[0]
         ld = _soa(st["Y"], mech.K, n, "Y")
-        arr[i] = ChemSet(n, ld, float(st["dt"]), _dptr(st["T"], f64, "T"),
-                         _dptr(st["p"], f64, "p"), _dptr(st["Y"], f64, "Y"),
-                         _dptr(st.get("RR"), f64, "RR"), _dptr(st.get("h_hint"), f64, "h_hint"),
-                         _dptr(st.get("stats"), torch.int32, "stats"))
+        RR, stats = st.get("RR"), st.get("stats")
+        if RR is not None and _soa(RR, mech.K, n, "RR") != ld:
+            raise ValueError("RR must have the leading dimension of Y")
+        if stats is not None and (stats.dim() != 2 or stats.shape[0] != 3
+                                  or (n > 0 and stats.stride(0) != ld)):
+            raise ValueError("stats must be an int32 [3, ld] tensor with the leading dimension "
+                             "of Y")
+        arr[i] = ChemSet(n, ld, float(st["dt"]), _vec(st["T"], n, "T", f64),
+                         _vec(st["p"], n, "p", f64), _dptr(st["Y"], f64, "Y"),
+                         _dptr(RR, f64, "RR"), _vec(st.get("h_hint"), n, "h_hint", f64),
+                         _dptr(stats, torch.int32, "stats"))
     return arr
 
 
@@ -266,7 +288,7 @@ def chem_autotune(mech: Mechanism, dt, T, p, Y, opts=None, stream=None):
     t = Tuning()
     f64 = torch.float64
     check("chem_autotune", lib().chem_autotune(
-        mech.handle, Batch(n, ld), float(dt), _dptr(T, f64, "T"), _dptr(p, f64, "p"),
+        mech.handle, Batch(n, ld), float(dt), _vec(T, n, "T", f64), _vec(p, n, "p", f64),
         _dptr(Y, f64, "Y"), None if o is None else C.byref(o), _stream(stream), C.byref(t)))
     return dict(lanes_per_cell=t.lanes_per_cell, waves_per_cu=t.waves_per_cu,
                 cells_per_s=t.cells_per_s)
@@ -312,10 +334,15 @@ def chem_step_graph(mech: Mechanism, dt, T, p, Y, dt_cell=None, RR=None, h_hint=
     o = _opts(opts)
     f64 = torch.float64
     h = _P()
+    if RR is not None and _soa(RR, mech.K, n, "RR") != ld:
+        raise ValueError("RR must have the leading dimension of Y")
+    if stats is not None and (stats.dim() != 2 or stats.shape[0] != 3 or stats.stride(0) != ld
+                              or stats.dtype != torch.int32):
+        raise ValueError("stats must be an int32 [3, ld] tensor with the leading dimension of Y")
     check("chem_step_graph_create", lib().chem_step_graph_create(
-        mech.handle, Batch(n, ld), float(dt), _dptr(dt_cell, f64, "dt_cell"), _dptr(T, f64, "T"),
-        _dptr(p, f64, "p"), _dptr(Y, f64, "Y"), _dptr(RR, f64, "RR"),
-        _dptr(h_hint, f64, "h_hint"), _dptr(stats, torch.int32, "stats"),
+        mech.handle, Batch(n, ld), float(dt), _vec(dt_cell, n, "dt_cell", f64),
+        _vec(T, n, "T", f64), _vec(p, n, "p", f64), _dptr(Y, f64, "Y"), _dptr(RR, f64, "RR"),
+        _vec(h_hint, n, "h_hint", f64), _dptr(stats, torch.int32, "stats"),
         None if o is None else C.byref(o), None, C.byref(h)))
     return Graph(h, (mech, T, p, Y, dt_cell, RR, h_hint, stats))
 

@@ -417,6 +417,19 @@ extern "C" chem_status ann_get_grad(const ann_model *m, int32_t layer, float *dW
   return download_pair(m, layer, m->gW[layer], m->gb[layer], dW, db);
 }
 
+extern "C" chem_status ann_get_moments(const ann_model *m, int32_t layer, float *mW, float *vW,
+                                       float *mb, float *vb) {
+  chem_status st = check_model("ann_get_moments", m);
+  if (st != CHEM_OK) return st;
+  if (layer < 0 || layer >= ann::NLAYER) {
+    set_error("ann_get_moments: bad layer index");
+    return CHEM_EINVAL;
+  }
+  st = download_pair(m, layer, m->mW[layer], m->mb[layer], mW, mb);
+  if (st != CHEM_OK) return st;
+  return download_pair(m, layer, m->vW[layer], m->vb[layer], vW, vb);
+}
+
 extern "C" chem_status ann_set_norm(ann_model *m, const ann_norm *nm) {
   chem_status st = check_model("ann_set_norm", m);
   if (st != CHEM_OK) return st;
@@ -483,11 +496,12 @@ extern "C" chem_status ann_fit_norm(ann_model *m, chem_batch batch, const double
   const int F = 2 * K + 2;
   const int nblocks = 256;
   double *part = nullptr;
-  CHEM_HIP(hipMalloc(&part, (size_t)nblocks * F * 4 * sizeof(double)));
+  CHEM_HIP(hipMalloc(&part, ((size_t)nblocks * F * 4 + F) * sizeof(double)));
   ann::StatArgs a{batch.n, batch.ld, T, p, Y0, Y1, K, lambda, part, nblocks};
   hipStream_t s = (hipStream_t)stream;
   st = ann::stats_partial(a, s);
-  std::vector<double> h((size_t)nblocks * F * 4);
+  // partial sums [nblocks][F][4], then the F shifts they were taken about
+  std::vector<double> h((size_t)nblocks * F * 4 + F);
   if (st == CHEM_OK) {
     hipError_t e = hipMemcpyAsync(h.data(), part, h.size() * 8, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -495,6 +509,7 @@ extern "C" chem_status ann_fit_norm(ann_model *m, chem_batch batch, const double
   }
   (void)hipFree(part);
   if (st != CHEM_OK) return st;
+  const double *shift = h.data() + (size_t)nblocks * F * 4;
   std::vector<float> mu(F), sd(F), lo(F), hi(F);
   for (int f = 0; f < F; ++f) {
     double s1 = 0, s2 = 0, mn = INFINITY, mx = -INFINITY;
@@ -505,8 +520,9 @@ extern "C" chem_status ann_fit_norm(ann_model *m, chem_batch batch, const double
       mn = fmin(mn, o[2]);
       mx = fmax(mx, o[3]);
     }
-    const double mean = s1 / batch.n;
-    const double var = fmax(s2 / batch.n - mean * mean, 0.0);
+    const double dmean = s1 / batch.n;
+    const double var = fmax(s2 / batch.n - dmean * dmean, 0.0);
+    const double mean = shift[f] + dmean;
     double sdv = sqrt(var);
     if (sdv < 1e-12 * fabs(mean) + 1e-30) sdv = 1.0;
     mu[f] = (float)mean;
@@ -782,6 +798,10 @@ extern "C" chem_status ann_step(ann_model *m, const chem_mech *mech, chem_batch 
                                 double *T, const double *p, double *Y, double *RR,
                                 uint8_t *flags, int64_t *n_fallback, const ann_step_opts *opts,
                                 const chem_step_opts *fb_opts, void *stream) {
+  if (opts && opts->audit_fraction != 0.0f) {
+    set_error("ann_step: audit_fraction is reserved and must be 0");
+    return CHEM_EINVAL;
+  }
   chem_status st = check_model("ann_step", m);
   if (st != CHEM_OK) return st;
   if (!mech) {

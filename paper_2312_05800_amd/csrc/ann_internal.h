@@ -185,7 +185,7 @@ struct StatArgs {
   const double *T, *p, *Y0, *Y1;
   int K;
   float lambda;
-  double *part;  // [nblocks][F][4] sums, sums of squares, min, max
+  double *part;  // [nblocks][F][4] sums and sums of squares of x - shift_f, min, max; then shift[F]
   int nblocks;
 };
 chem_status stats_partial(const StatArgs &a, hipStream_t s);

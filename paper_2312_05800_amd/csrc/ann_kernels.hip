@@ -1609,11 +1609,15 @@ __global__ __launch_bounds__(128, 4) void k_post(chem::DevMech M, PostArgs a) {
         if (e < E) z1[e] += M.Mel[e * K + k] * y;
     }
   }
-  double res = 0.0;
+  // residuals: of the network's own state Y' (r = M Y0 - M Y', which the
+  // projection removes), and of the projected, clipped state; either above
+  // the tolerance (or non-finite) flags the cell
+  const double rtol_e = (double)a.residual_tol;
+  bool bad = !ok;
 #pragma unroll
   for (int e = 0; e < EP; ++e)
-    if (e < E) res = fmax(res, fabs(z1[e] - z0[e]));
-  if (!ok || !(res <= (double)a.residual_tol)) flag |= 2;
+    if (e < E) bad = bad || !(fabs(z1[e] - z0[e]) <= rtol_e) || !(fabs(r[e]) <= rtol_e);
+  if (bad) flag |= 2;
 
   if (flag == 0) {
     // temperature from h(T, Y) = h(T0, Y0) by Newton in FP64.  h and c_p of
@@ -1705,25 +1709,30 @@ __global__ __launch_bounds__(128, 4) void k_post(chem::DevMech M, PostArgs a) {
 
 // Partial statistics of the training features: block (b, f) covers feature f
 // over cells b, b + nblocks, ...  Features 0..K+1 are the network inputs
-// (T, p, F(Y0)), features K+2..2K+1 the targets Y1 - Y0.  FP64.
+// (T, p, F(Y0)), features K+2..2K+1 the targets Y1 - Y0.  FP64.  The sums are
+// of x - x(cell 0) (the host adds the shift back), so the variance
+// E[d^2] - E[d]^2 does not cancel for a feature whose mean is large against
+// its spread; block 0 stores the shifts after the [nblocks][F][4] partials.
+__device__ __forceinline__ double stat_feature(const StatArgs &a, int f, int64_t i) {
+  const int K = a.K;
+  if (f == 0) return a.T[i];
+  if (f == 1) return a.p[i];
+  if (f < K + 2) return (double)boxcox_fast((float)a.Y0[(int64_t)(f - 2) * a.ld + i], a.lambda);
+  const int k = f - K - 2;
+  return a.Y1[(int64_t)k * a.ld + i] - a.Y0[(int64_t)k * a.ld + i];
+}
+
 __global__ void k_stats(StatArgs a) {
   __shared__ double s1[256], s2[256], mn[256], mx[256];
   const int f = blockIdx.y;
-  const int K = a.K;
+  const double shift = stat_feature(a, f, 0);
   double x1 = 0.0, x2 = 0.0, lo = INFINITY, hi = -INFINITY;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n;
        i += (int64_t)a.nblocks * blockDim.x) {
-    double x;
-    if (f == 0) x = a.T[i];
-    else if (f == 1) x = a.p[i];
-    else if (f < K + 2) {
-      x = (double)boxcox_fast((float)a.Y0[(int64_t)(f - 2) * a.ld + i], a.lambda);
-    } else {
-      const int k = f - K - 2;
-      x = a.Y1[(int64_t)k * a.ld + i] - a.Y0[(int64_t)k * a.ld + i];
-    }
-    x1 += x;
-    x2 += x * x;
+    const double x = stat_feature(a, f, i);
+    const double d = x - shift;
+    x1 += d;
+    x2 += d * d;
     lo = fmin(lo, x);
     hi = fmax(hi, x);
   }
@@ -1748,6 +1757,7 @@ __global__ void k_stats(StatArgs a) {
     o[1] = s2[0];
     o[2] = mn[0];
     o[3] = mx[0];
+    if (blockIdx.x == 0) a.part[(int64_t)a.nblocks * gridDim.y * 4 + f] = shift;
   }
 }
 

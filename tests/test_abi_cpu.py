@@ -71,3 +71,44 @@ def test_tuning_and_graph_arguments_rejected_on_host():
     assert L.ann_step_graph_create(None, None, P.binding.Batch(1, 1), 1e-6, None, None, None,
                                    None, None, None, None, None, None, C.byref(h)) == 1
     assert not h.value
+
+
+def test_reserved_audit_fraction_rejected_on_host():
+    """ann_step rejects a non-zero audit_fraction (reserved) before anything
+    else, so the check needs no model and no GPU."""
+    import ctypes as C
+    import paper_2312_05800_amd as P
+    from paper_2312_05800_amd.ann import StepOptsANN
+    L = P.lib()
+    o = StepOptsANN(1e-6, 0.05, 1, 0.25)
+    assert L.ann_step(None, None, P.binding.Batch(1, 1), 1e-5, None, None, None, None, None,
+                      None, C.byref(o), None, None) == 1
+    assert b"audit_fraction" in L.chem_last_error()
+    o = StepOptsANN(1e-6, 0.05, 1, 0.0)
+    assert L.ann_step(None, None, P.binding.Batch(1, 1), 1e-5, None, None, None, None, None,
+                      None, C.byref(o), None, None) == 1
+    assert b"null model" in L.chem_last_error()
+
+
+def test_binding_rejects_bad_1d_arrays():
+    """The binding checks every 1-D array for shape, contiguity and length
+    before calling the library (no GPU needed: the checks raise first)."""
+    import torch
+    from paper_2312_05800_amd.binding import _vec
+
+    class FakeCuda(torch.Tensor):
+        @property
+        def is_cuda(self):
+            return True
+    short = torch.zeros(4, dtype=torch.float64).as_subclass(FakeCuda)
+    with pytest.raises(ValueError):
+        _vec(short, 5, "T", torch.float64)
+    strided = torch.zeros(10, dtype=torch.float64)[::2].as_subclass(FakeCuda)
+    with pytest.raises(ValueError):
+        _vec(strided, 5, "T", torch.float64)
+    twod = torch.zeros((2, 3), dtype=torch.float64).as_subclass(FakeCuda)
+    with pytest.raises(ValueError):
+        _vec(twod, 2, "T", torch.float64)
+    assert _vec(None, 5, "T") is None
+    with pytest.raises(TypeError):
+        _vec(torch.zeros(5, dtype=torch.float64), 5, "T")

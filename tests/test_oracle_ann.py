@@ -161,3 +161,156 @@ def test_temperature_newton_conserves_enthalpy(om_ch4):
         h1 = oracle.mixture_enthalpy(om_ch4, Tn[i], out["Y"][:, i])
         assert abs(h1 - h0) <= 1e-9 * abs(h0) + 1e-6
     np.testing.assert_allclose(Tn, out["T"], rtol=1e-5)
+
+
+def test_forward_against_torch_reference():
+    """The oracle's network against an independent evaluation: torch on the
+    CPU in FP64, F.linear with exact-erf GELU on the hidden layers and a
+    linear output layer; and the BF16 emulation against torch's own bfloat16
+    casts of the same layer inputs and weights."""
+    import torch.nn.functional as F
+    rng = np.random.default_rng(11)
+    sizes = [9, 40, 24, 16, 5]
+    params = ann.init_params(sizes, seed=12)
+    X = rng.standard_normal((33, 9)) * 2.0
+    u = ann.forward(params, X)
+    h = torch.from_numpy(X)
+    for l, (W, b) in enumerate(params):
+        h = F.linear(h, torch.from_numpy(W), torch.from_numpy(b))
+        if l < len(params) - 1:
+            h = F.gelu(h, approximate="none")
+    np.testing.assert_allclose(u, h.numpy(), rtol=1e-12, atol=1e-14)
+
+    def bf(t):
+        return t.to(torch.float32).to(torch.bfloat16).to(torch.float64)
+    ub = ann.forward(params, X, prec="bf16")
+    h = torch.from_numpy(X)
+    for l, (W, b) in enumerate(params):
+        h = F.linear(bf(h), bf(torch.from_numpy(W)), torch.from_numpy(b))
+        if l < len(params) - 1:
+            h = F.gelu(h, approximate="none")
+    np.testing.assert_allclose(ub, h.numpy(), rtol=1e-12, atol=1e-14)
+    # a dropped bias or a GELU on the output layer would move the result
+    assert np.abs(ub - u).max() > 1e-4
+
+
+def test_adam_constant_gradient_closed_form():
+    """With a constant gradient g the bias-corrected moments are exactly
+    m_hat = g and v_hat = g^2 at every step, so after t steps
+    theta_t = theta_0 - t lr g / (|g| + eps), m_t = (1 - b1^t) g and
+    v_t = (1 - b2^t) g^2 (Kingma & Ba 2015, Algorithm 1 and Sec. 3)."""
+    rng = np.random.default_rng(3)
+    th0 = [(rng.standard_normal((4, 3)), rng.standard_normal(4))]
+    g = [(rng.standard_normal((4, 3)), rng.standard_normal(4))]
+    z = [(np.zeros((4, 3)), np.zeros(4))]
+    p, m, v = th0, z, z
+    lr, b1, b2 = 2e-3, 0.9, 0.999
+    for t in range(1, 6):
+        p, m, v = ann.adam_update(p, g, m, v, t, lr=lr, beta1=b1, beta2=b2)
+        for i in range(2):
+            gg = g[0][i]
+            np.testing.assert_allclose(p[0][i], th0[0][i] - t * lr * gg / (np.abs(gg) + 1e-8),
+                                       rtol=1e-12, atol=1e-15)
+            np.testing.assert_allclose(m[0][i], (1 - b1 ** t) * gg, rtol=1e-12)
+            np.testing.assert_allclose(v[0][i], (1 - b2 ** t) * gg * gg, rtol=1e-12)
+
+
+def test_adam_moments_are_exponential_averages():
+    """With changing gradients the moments are the exponentially weighted
+    sums m_t = (1 - b1) sum_i b1^(t-i) g_i and v_t = (1 - b2) sum_i
+    b2^(t-i) g_i^2 (Kingma & Ba 2015, Sec. 3), computed here directly from
+    the history; the step uses the bias-corrected moments, which for a
+    gradient that flips sign every step are checked against the sum formula."""
+    rng = np.random.default_rng(4)
+    th = [(rng.standard_normal((2, 2)), rng.standard_normal(2))]
+    hist = [[(rng.standard_normal((2, 2)), rng.standard_normal(2))] for _ in range(4)]
+    z = [(np.zeros((2, 2)), np.zeros(2))]
+    p, m, v = th, z, z
+    b1, b2, lr = 0.9, 0.999, 1e-3
+    for t in range(1, 5):
+        prev = p
+        p, m, v = ann.adam_update(p, hist[t - 1], m, v, t, lr=lr, beta1=b1, beta2=b2)
+        for i in range(2):
+            ms = sum((1 - b1) * b1 ** (t - j) * hist[j - 1][0][i] for j in range(1, t + 1))
+            vs = sum((1 - b2) * b2 ** (t - j) * hist[j - 1][0][i] ** 2 for j in range(1, t + 1))
+            np.testing.assert_allclose(m[0][i], ms, rtol=1e-12)
+            np.testing.assert_allclose(v[0][i], vs, rtol=1e-12)
+            # the bias-corrected step: m_t / sum of its weights, over sqrt of v_t / its weights
+            wm = sum((1 - b1) * b1 ** (t - j) for j in range(1, t + 1))
+            wv = sum((1 - b2) * b2 ** (t - j) for j in range(1, t + 1))
+            step = lr * (ms / wm) / (np.sqrt(vs / wv) + 1e-8)
+            np.testing.assert_allclose(prev[0][i] - p[0][i], step, rtol=1e-10, atol=1e-16)
+
+
+def test_ood_flags_hand_built_boxes():
+    """Out-of-distribution test on hand-made training boxes: the 5 % margin
+    of a feature's span, the relative 1e-6 rule of a zero-span feature (the
+    constant pressure), exact boundary values and non-finite features."""
+    lo = np.array([0.0, 101325.0, -10.0])
+    hi = np.array([10.0, 101325.0, 0.0])
+    base = np.array([5.0, 101325.0, -5.0])
+
+    def one(j, x):
+        f = base.copy()
+        f[j] = x
+        return bool(ann.ood_flags(f[:, None], lo, hi)[0])
+    assert not one(0, 5.0)
+    assert not one(0, -0.5) and not one(0, 10.5)        # exactly on the widened edge
+    assert one(0, -0.5000001) and one(0, 10.5000001)
+    assert not one(1, 101325.0 * (1 + 0.9e-6)) and not one(1, 101325.0 * (1 - 0.9e-6))
+    assert one(1, 101325.0 * (1 + 1.1e-6)) and one(1, 101325.0 * (1 - 1.1e-6))
+    assert not one(2, 0.49) and one(2, 0.51) and one(2, -10.51)
+    assert one(0, np.nan) and one(2, np.inf) and one(1, -np.inf)
+    # several cells at once: a cell is flagged if any feature is outside
+    F = np.stack([base, base, base], axis=1)
+    F[2, 1] = 0.6
+    F[0, 2] = -1.0
+    np.testing.assert_array_equal(ann.ood_flags(F, lo, hi), [False, True, True])
+
+
+def test_zstats_against_library_and_zero_spread():
+    """Per-row mean and population standard deviation against Python's
+    statistics module; rows without spread (constant, all zero, or spread
+    below 1e-12 of the mean) get a standard deviation of 1."""
+    import statistics
+    rng = np.random.default_rng(8)
+    A = np.stack([rng.standard_normal(50) * 3 + 7,
+                  np.full(50, 101325.0),
+                  np.zeros(50),
+                  1e6 + 1e-8 * rng.standard_normal(50),
+                  1e-20 * rng.standard_normal(50)])
+    mu, sd = ann.zstats(A)
+    for i in range(A.shape[0]):
+        assert abs(mu[i] - statistics.fmean(A[i])) <= 1e-12 * max(1.0, abs(mu[i]))
+    assert abs(sd[0] - statistics.pstdev(A[0])) <= 1e-12 * sd[0]
+    assert sd[1] == 1.0 and sd[2] == 1.0 and sd[3] == 1.0
+    assert abs(sd[4] - statistics.pstdev(A[4])) <= 1e-9 * sd[4]   # small but real spread
+
+
+def test_post_residual_flags_judge_the_network(om_ch4):
+    """Flag bit 1 is decided on the network's own state Y0 + dY: an output
+    that breaks element conservation by more than the tolerance is flagged
+    even though the projection repairs it; one that conserves elements (a
+    multiple of a reaction's stoichiometry) is not; a NaN output is flagged."""
+    m = om_ch4.mech
+    T, p, Y0 = chemgen.make_states(m, "ch4", N=4, seed=9)
+    K = m.K
+    M = ann.element_mass_matrix(m)
+    # a conserving change: move mass along reaction 0 (mass units)
+    r = np.zeros(K)
+    for s in range(4):
+        k = m.rsp[0, s]
+        if k >= 0:
+            r[k] += (1 if s >= 2 else -1) * m.rnu[0, s] * m.W[k]
+    assert np.abs(M @ r).max() < 1e-14 * np.abs(r).max()
+    du = np.zeros((K, 4))
+    # the reverse direction: products (all present at ~8e-7) give up 1e-7 at most
+    du[:, 0] = -1e-7 * r / np.abs(r).max()
+    assert np.all(Y0[:, 0] + du[:, 0] >= 0)
+    iH2O = m.index("H2O")
+    du[iH2O, 1] = 5e-6          # H and O mass appear from nowhere: residual ~ 5e-6 * 0.9
+    du[iH2O, 2] = 5e-7          # below the tolerance
+    du[:, 3] = np.nan
+    o = ann.post(om_ch4, T, p, Y0, du, np.zeros(K), np.ones(K), 1e-5)
+    assert o["residual_raw"][1] > 1e-6 and o["residual"][1] < 1e-9
+    np.testing.assert_array_equal(o["flags"] & 2, [0, 2, 0, 2])
