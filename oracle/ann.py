@@ -6,7 +6,9 @@ Follows the paper's ANN model (Sec. 3.2):
   u* = Y(t+dt) - Y(t), in physical mass-fraction units (only the inputs are
   Box-Cox transformed);
 * inputs and outputs z-score normalised with training-set statistics;
-* hidden layers 1600, 800, 400 with GELU; Adam; L1 loss (Eq. Loss).
+* hidden layers 1600, 800, 400 with GELU; Adam; L1 loss (Eq. Loss), with
+  the optional physics terms of Sec. 3.2 (mass-fraction sum, energy, heat
+  release rate; formulas are this project's reading, see physics_terms).
 
 Box-Cox (Box & Cox 1964): F(x) = (x^lambda - 1)/lambda with lambda = 0.1,
 which maps mass fractions in [0, 1] to [-1/lambda, 0]; negative mass
@@ -183,6 +185,88 @@ def backward(params, X, target, prec="fp64"):
             dh = gq @ Wq
             g = dh * gelu_grad(zs[l - 1])
     return grads, l1_loss(u, target)
+
+
+# ------------------------------------------------- physics terms of the loss
+#
+# Sec. 3.2 adds three physical principles to the loss -- conservation of the
+# mass-fraction sum, conservation of energy and the heat release rate --
+# without formulas.  Reading used here: each is an L1 penalty on a linear
+# functional of the predicted physical change dY_pred = sd u + mu, per
+# sample, made dimensionless by the size the functional would have if every
+# species were off by one standard deviation of its target:
+#   mass    s = sum_k dY_pred,k                    (the sum of Y stays 1)
+#   energy  s = sum_k h_k(T1) (dY_pred,k - dY*_k)  (h(T1, Y0 + dY_pred) =
+#           h(T1, Y1) = h(T0, Y0): the state keeps the enthalpy of the
+#           reference step at its final temperature T1)
+#   HRR     s = sum_k h_k(298.15 K) (dY_pred,k - dY*_k)  (the heat released
+#           over the step, -rho0/dt sum_k h_f,k dY_k, equals the reference's;
+#           the common factor rho0/dt cancels in the scaling)
+# with penalty |s| / sum_k |a_k| sd_k (a_k the functional's weights; 1 for
+# mass), averaged over the batch and weighted by w = (w_mass, w_energy,
+# w_hrr).  h_k in J/kg.
+
+T_REF_HRR = 298.15
+
+
+def species_enthalpy(om: OracleMech, T):
+    """h_k(T) in J/kg of every species at each temperature: [K, N]."""
+    T = np.atleast_1d(np.asarray(T, dtype=np.float64))
+    out = np.empty((om.K, T.size))
+    for i, t in enumerate(T):
+        _, hRT, _ = thermo(om, t)
+        out[:, i] = RGAS * t * hRT / om.mech.W
+    return out
+
+
+def physics_terms(u, target, mu_out, sd_out, h_T1, h_ref, w):
+    """Physics penalties and their gradient with respect to the network
+    output.  u, target: [N, K] z-space; mu_out, sd_out: [K]; h_T1, h_ref:
+    [K, N] species enthalpies (J/kg) at the reference step's final
+    temperature and at 298.15 K; w: (w_mass, w_energy, w_hrr).  Returns
+    (terms, grad): terms = the three batch means of the unweighted
+    penalties, grad = d(sum_t w_t terms_t)/du, [N, K]; sign(0) = 0."""
+    u = np.asarray(u, dtype=np.float64)
+    target = np.asarray(target, dtype=np.float64)
+    N, K = u.shape
+    sd = np.asarray(sd_out, dtype=np.float64)
+    mu = np.asarray(mu_out, dtype=np.float64)
+    dY = u * sd[None, :] + mu[None, :]             # predicted change
+    e = (u - target) * sd[None, :]                 # its error
+    terms = np.zeros(3)
+    grad = np.zeros_like(u)
+    funcs = [(np.ones((N, K)), dY.sum(axis=1)),
+             (h_T1.T, (h_T1.T * e).sum(axis=1)),
+             (h_ref.T, (h_ref.T * e).sum(axis=1))]
+    for t, (a, s) in enumerate(funcs):
+        D = (np.abs(a) * sd[None, :]).sum(axis=1)
+        terms[t] = np.mean(np.abs(s) / D)
+        grad += w[t] * np.sign(s)[:, None] * a * sd[None, :] / (D[:, None] * N)
+    return terms, grad
+
+
+def backward_phys(params, X, target, mu_out, sd_out, h_T1, h_ref, w, prec="fp64"):
+    """backward() for the loss L1 + sum_t w_t terms_t: the same layer
+    recursion, started from dL/du = sign(u - u*)/(N K) + the physics
+    gradient.  Returns (grads, total loss, L1 loss, terms)."""
+    L = len(params)
+    u, zs, hs = forward(params, X, prec=prec, keep=True)
+    N, nout = u.shape
+    terms, gphys = physics_terms(u, target, mu_out, sd_out, h_T1, h_ref, w)
+    g = np.sign(u - target) / (N * nout) + gphys
+    grads = [None] * L
+    for l in range(L - 1, -1, -1):
+        W, _ = params[l]
+        gq = round_bf16(g) if prec != "fp64" else g
+        dW = gq.T @ hs[l]
+        db = g.sum(axis=0)
+        grads[l] = (dW, db)
+        if l > 0:
+            Wq = round_bf16(W) if prec != "fp64" else W
+            dh = gq @ Wq
+            g = dh * gelu_grad(zs[l - 1])
+    l1 = l1_loss(u, target)
+    return grads, l1 + float(np.dot(w, terms)), l1, terms
 
 
 def adam_update(params, grads, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):

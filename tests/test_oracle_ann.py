@@ -314,3 +314,138 @@ def test_post_residual_flags_judge_the_network(om_ch4):
     o = ann.post(om_ch4, T, p, Y0, du, np.zeros(K), np.ones(K), 1e-5)
     assert o["residual_raw"][1] > 1e-6 and o["residual"][1] < 1e-9
     np.testing.assert_array_equal(o["flags"] & 2, [0, 2, 0, 2])
+
+
+# ---------------------------------------------- physics terms of the loss
+
+
+@pytest.fixture(scope="module")
+def phys_batch(mech_ch4, om_ch4):
+    """A few CH4/air states, their oracle step (the label), normalisation and
+    a perturbed network output."""
+    T, p, Y0 = chemgen.make_states(mech_ch4, "ch4", N=24, seed=61)
+    o = oracle.chem_step(om_ch4, 1e-5, T, p, Y0)
+    tgt_phys = ann.targets(Y0, o["Y"])
+    mu, sd = ann.zstats(tgt_phys)
+    tgt = ((tgt_phys - mu[:, None]) / sd[:, None]).T
+    rng = np.random.default_rng(62)
+    u = tgt + 0.3 * rng.standard_normal(tgt.shape)
+    return dict(T=T, p=p, Y0=Y0, Y1=o["Y"], T1=o["T"], mu=mu, sd=sd, tgt=tgt, u=u,
+                hT1=ann.species_enthalpy(om_ch4, o["T"]),
+                href=ann.species_enthalpy(om_ch4, np.full(T.size, ann.T_REF_HRR)))
+
+
+def test_phys_energy_term_is_an_enthalpy_difference(om_ch4, phys_batch):
+    """The energy functional equals h(T1, Y0 + dY_pred) - h(T1, Y1), the
+    mixture enthalpies taken from the C oracle (not from the linear form), and
+    that is h(T1, Y0 + dY_pred) - h(T0, Y0) up to the reference step's own
+    energy error (rtol-sized)."""
+    b = phys_batch
+    dYp = (b["u"] * b["sd"][None, :] + b["mu"][None, :]).T
+    s = ((b["u"] - b["tgt"]) * b["sd"][None, :] * b["hT1"].T).sum(axis=1)
+    for i in range(b["T"].size):
+        h_pred = oracle.mixture_enthalpy(om_ch4, b["T1"][i], b["Y0"][:, i] + dYp[:, i])
+        h_lab = oracle.mixture_enthalpy(om_ch4, b["T1"][i], b["Y1"][:, i])
+        h_0 = oracle.mixture_enthalpy(om_ch4, b["T"][i], b["Y0"][:, i])
+        assert abs(s[i] - (h_pred - h_lab)) <= 1e-9 * max(abs(h_lab), abs(s[i]))
+        assert abs(h_lab - h_0) <= 1e-5 * abs(h_pred - h_lab) + 1e-8 * abs(h_0)
+    terms, _ = ann.physics_terms(b["u"], b["tgt"], b["mu"], b["sd"], b["hT1"], b["href"],
+                                 (1, 1, 1))
+    D = (np.abs(b["hT1"]) * b["sd"][:, None]).sum(axis=0)
+    assert abs(terms[1] - np.mean(np.abs(s) / D)) <= 1e-14 * terms[1]
+
+
+def test_phys_hrr_term_is_the_heat_release(mech_ch4, om_ch4):
+    """The heat-release functional, rho0/dt sum_k h_k(298.15 K) dY_k over a
+    very short reference step, tends to the instantaneous heat release rate
+    sum_k h_k(298.15 K) W_k wdot_k of the mechanism (C oracle rates); it is
+    h(298.15, Y0 + dY) - h(298.15, Y0) by the C oracle's mixture enthalpy."""
+    T, p, Y0 = chemgen.make_states(mech_ch4, "ch4", N=64, seed=63)
+    sel = T > 1400.0
+    T, p, Y0 = T[sel][:6], p[sel][:6], Y0[:, sel][:, :6]
+    # the step average differs from the initial rate by O(dt) (1e-3 at 1e-10 s)
+    dt = 1e-12
+    o = oracle.chem_step(om_ch4, dt, T, p, Y0, opts=oracle.default_opts(rtol=1e-10,
+                                                                          atol_Y=1e-20))
+    dY = o["Y"] - Y0
+    href = ann.species_enthalpy(om_ch4, np.full(T.size, ann.T_REF_HRR))
+    rho0 = ann.density(mech_ch4, T, p, Y0)
+    q_step = rho0 * (href * dY).sum(axis=0) / dt
+    w, _ = oracle.chem_rates(om_ch4, T, p, Y0)
+    q_inst = (href * mech_ch4.W[:, None] * w).sum(axis=0)
+    np.testing.assert_allclose(q_step, q_inst, rtol=1e-4)
+    for i in range(T.size):
+        dh = (oracle.mixture_enthalpy(om_ch4, ann.T_REF_HRR, o["Y"][:, i])
+              - oracle.mixture_enthalpy(om_ch4, ann.T_REF_HRR, Y0[:, i]))
+        # the difference of two mixture enthalpies carries their rounding
+        scale = (np.abs(href[:, i]) * (np.abs(Y0[:, i]) + np.abs(o["Y"][:, i]))).sum()
+        assert abs((href[:, i] * dY[:, i]).sum() - dh) <= 1e-14 * scale
+
+
+def test_phys_mass_term_special_cases(phys_batch):
+    """A prediction whose changes sum to zero has no mass penalty; a uniform
+    shift c of every physical change gives |K c| / sum_k sd_k; a perfect
+    prediction has no energy or heat-release penalty."""
+    b = phys_batch
+    sd, mu = b["sd"], b["mu"]
+    dY = b["u"] * sd[None, :] + mu[None, :]
+    dY[:, 0] -= dY.sum(axis=1)                       # now sums to zero per sample
+    u0 = (dY - mu[None, :]) / sd[None, :]
+    terms, _ = ann.physics_terms(u0, b["tgt"], mu, sd, b["hT1"], b["href"], (1, 0, 0))
+    assert terms[0] <= 1e-13
+    c = 3e-5
+    u1 = (dY + c - mu[None, :]) / sd[None, :]
+    terms, _ = ann.physics_terms(u1, b["tgt"], mu, sd, b["hT1"], b["href"], (1, 0, 0))
+    assert abs(terms[0] - mu.size * c / sd.sum()) <= 1e-9 * terms[0]
+    terms, _ = ann.physics_terms(b["tgt"], b["tgt"], mu, sd, b["hT1"], b["href"], (1, 1, 1))
+    assert terms[1] == 0.0 and terms[2] == 0.0
+
+
+def test_phys_gradient_finite_differences(phys_batch):
+    """d(sum_t w_t terms_t)/du by central differences, and backward_phys on a
+    small network against finite differences of its total loss; with w = 0
+    backward_phys is backward."""
+    b = phys_batch
+    w = (0.7, 1.3, 0.4)
+    args = (b["mu"], b["sd"], b["hT1"], b["href"])
+    terms, g = ann.physics_terms(b["u"], b["tgt"], *args, w)
+    eps = 1e-7
+    u = b["u"].copy()
+    for i, k in ((0, 0), (3, 7), (11, 29), (23, 15)):
+        old = u[i, k]
+        u[i, k] = old + eps
+        tp, _ = ann.physics_terms(u, b["tgt"], *args, w)
+        u[i, k] = old - eps
+        tm, _ = ann.physics_terms(u, b["tgt"], *args, w)
+        u[i, k] = old
+        fd = (np.dot(w, tp) - np.dot(w, tm)) / (2 * eps)
+        # central differences of O(1) terms carry ~1e-16 / 1e-7 of rounding
+        assert abs(fd - g[i, k]) <= 1e-6 * abs(fd) + 3e-9, (i, k)
+    K = b["sd"].size
+    params = ann.init_params([K + 2, 9, 7, 5, K], seed=64)
+    rng = np.random.default_rng(65)
+    X = rng.standard_normal((b["T"].size, K + 2))
+    grads, tot, l1, terms = ann.backward_phys(params, X, b["tgt"], *args, w)
+
+    def total():
+        uu = ann.forward(params, X)
+        t, _ = ann.physics_terms(uu, b["tgt"], *args, w)
+        return ann.l1_loss(uu, b["tgt"]) + np.dot(w, t)
+    assert abs(tot - total()) <= 1e-14 * tot
+    for l, (W, bb) in enumerate(params):
+        for arr, gg in ((W, grads[l][0]), (bb, grads[l][1])):
+            flat = arr.reshape(-1)
+            for idx in range(0, flat.size, max(1, flat.size // 5)):
+                old = flat[idx]
+                flat[idx] = old + eps
+                lp = total()
+                flat[idx] = old - eps
+                lm = total()
+                flat[idx] = old
+                fd = (lp - lm) / (2 * eps)
+                assert abs(fd - gg.reshape(-1)[idx]) <= 1e-6 * max(1.0, abs(fd)), (l, idx)
+    g0, tot0, _, _ = ann.backward_phys(params, X, b["tgt"], *args, (0, 0, 0))
+    g1, l1b = ann.backward(params, X, b["tgt"])
+    assert tot0 == l1b
+    for (a, c), (d, e) in zip(g0, g1):
+        assert np.array_equal(a, d) and np.array_equal(c, e)
