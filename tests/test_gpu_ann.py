@@ -392,20 +392,24 @@ def test_resume_from_file_is_bit_exact(dev, mech, data):
 
 
 def test_residual_fallback_judges_the_network(dev, mech, data):
-    """A network whose output layer is scaled up breaks element conservation
-    in some cells by more than the 1e-6 tolerance: exactly the cells the
-    oracle flags on the network's own residual (up to cells within a factor 2
-    of the threshold) are integrated by the FP64 fallback and then equal the
-    oracle's chem_step; the others equal the oracle's post-processing."""
+    """A network whose output weights are scaled up breaks element
+    conservation in many cells by more than the 1e-6 tolerance: exactly the
+    cells the oracle flags on the network's own residual are integrated by the
+    FP64 fallback and then equal the oracle's chem_step; the others equal the
+    oracle's post-processing.  The oracle post-processes the GPU's own network
+    output, so the two residuals differ only by the FP32 de-normalisation
+    sd u + mu: cells within that rounding of the threshold may go either
+    way."""
     import torch
     import paper_2312_05800_amd as P
     _say("[ann residual fallback]")
     K = mech.K
     om = oracle.OracleMech(mech)
     params = oann.init_params([K + 2, *HID, K], seed=23)
-    # an untrained network scaled by 6 leaves about half of these cells with an
-    # element residual of its own state above 1e-6 (median 1.0e-6 in the oracle)
-    params[3] = (params[3][0] * 6.0, params[3][1] * 6.0)
+    # untrained output weights scaled by 20 (bias unchanged) leave about 70 %
+    # of these cells with an element residual of their own state above 1e-6,
+    # spread from 3e-7 to 3e-6 (oracle, BF16 emulation)
+    params[3] = (params[3][0] * 20.0, params[3][1])
     nm = _norm_from(data)
     m = _model(mech, params, nm)
     gm = P.Mechanism(mech)
@@ -421,12 +425,17 @@ def test_residual_fallback_judges_the_network(dev, mech, data):
     o = oann.post(om, T, p, Y, U.T, _f32(nm["mu_out"]), _f32(nm["sd_out"]), 1e-5,
                   lo=_f32(nm["lo"]), hi=_f32(nm["hi"]))
     fg = flags.cpu().numpy()
-    near = _near_threshold(o)
+    # rounding of the residual sum_k M_ek dY'_k: each dY'_k carries at most two
+    # FP32 roundings of |sd_k u_k| + |mu_k|, and M_ek <= 1
+    sd, mu = _f32(nm["sd_out"]), _f32(nm["mu_out"])
+    rbound = 4 * 2.0 ** -24 * (np.abs(U.T * sd[:, None]) + np.abs(mu)[:, None]).sum(axis=0)
+    r = np.maximum(o["residual"], o["residual_raw"])
+    near = np.abs(r - 1e-6) <= rbound
     assert ((fg & 3) == o["flags"])[~near].all()
     res_only = (o["flags"] == 2) & ~near
     ok = (fg == 0) & (o["flags"] == 0)
     _say(f"  residual-flagged {res_only.sum()}, unflagged {ok.sum()} of {N}; "
-         f"n_fallback {int(nfb.item())}")
+         f"near the threshold {near.sum()}; n_fallback {int(nfb.item())}")
     assert res_only.sum() >= 20 and ok.sum() >= 20
     assert int(nfb.item()) == np.count_nonzero(fg)
     Tg, Yg, RRg = Td.cpu().numpy(), Yd.cpu().numpy(), RR.cpu().numpy()
