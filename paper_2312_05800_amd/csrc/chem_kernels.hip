@@ -66,6 +66,11 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// FP64 add to LDS (ds_add_f64); no return value.
+__device__ __forceinline__ void lds_add(double *p, double v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+
 template <int G>
 __device__ __forceinline__ double grp_sum(double v) {
 #pragma unroll
@@ -82,11 +87,13 @@ __device__ __forceinline__ bool grp_any(bool b) {
 }
 
 // Per-group LDS scratch (doubles): concentrations, h/RT and g/RT of the
-// species, rates of progress, and the Jacobian / Newton matrix (n rows of
-// stride G + 1).  In chem_rates the matrix region holds k_f, k_r instead.
+// species, rates of progress, the Jacobian / Newton matrix (n rows of odd
+// stride) and the LU's pivot order (G ints: the lane whose row is the pivot
+// of step k).  In chem_rates the matrix region holds k_f, k_r instead.
 template <int G>
 struct GLds {
   double *C, *hs, *gs, *qs, *J;
+  int *piv;
   int js;  // row stride of J
   __device__ GLds(double *base, int R, int n) {
     C = base;
@@ -94,14 +101,18 @@ struct GLds {
     gs = hs + G;
     qs = gs + G;
     J = qs + R;
+    piv = (int *)(J + mat(R, n));
     js = stride(n);
   }
   // odd row stride (2 js banks apart: lanes reading one column hit distinct
   // banks) and only the n rows of the n x n matrix
   __host__ __device__ static int stride(int n) { return n | 1; }
-  __host__ __device__ static size_t doubles(int R, int n) {
+  __host__ __device__ static size_t mat(int R, int n) {
     const size_t j = (size_t)n * stride(n), k = 2 * (size_t)R;
-    return 3 * G + (size_t)R + (j > k ? j : k);
+    return j > k ? j : k;
+  }
+  __host__ __device__ static size_t doubles(int R, int n) {
+    return 3 * G + (size_t)R + mat(R, n) + G / 2;
   }
 };
 
@@ -141,6 +152,39 @@ __device__ __forceinline__ Rxn rxn_eval(const DevMech &M, const GLds<G> &L, int 
   return x;
 }
 
+// Adds reaction x's terms of the Jacobian to the LDS matrix (atomic FP64
+// adds: lanes of the group process different reactions that share species).
+// q = k_f prod C^nu' - k_r prod C^nu'', so dq/dC of a slot species is the
+// product of the other factors times the derivative of its own factor.  Per
+// slot species k_a (net coefficient nu_a: - for reactants, + for products)
+// and slot species k_b: row 1 + k_a, column 1 + k_b gets nu_a dq/dC_kb and
+// column 0 gets nu_a dq/dT; row 0, column 1 + k_b gets dH_r dq/dC_kb.
+template <int G>
+__device__ __forceinline__ void jac_scatter(const GLds<G> &L, const Rxn &x, double dqT,
+                                            double dHr) {
+  const double f0 = slot_fac(x.sp.x, x.nu.x, L.C), f1 = slot_fac(x.sp.y, x.nu.y, L.C);
+  const double f2 = slot_fac(x.sp.z, x.nu.z, L.C), f3 = slot_fac(x.sp.w, x.nu.w, L.C);
+  const int sp[4] = {x.sp.x, x.sp.y, x.sp.z, x.sp.w};
+  double dq[4] = {0.0, 0.0, 0.0, 0.0};
+  if (sp[0] >= 0) dq[0] = x.kf * (x.nu.x == 2 ? 2.0 * L.C[sp[0]] : 1.0) * f1;
+  if (sp[1] >= 0) dq[1] = x.kf * f0 * (x.nu.y == 2 ? 2.0 * L.C[sp[1]] : 1.0);
+  if (sp[2] >= 0) dq[2] = -x.kr * (x.nu.z == 2 ? 2.0 * L.C[sp[2]] : 1.0) * f3;
+  if (sp[3] >= 0) dq[3] = -x.kr * f2 * (x.nu.w == 2 ? 2.0 * L.C[sp[3]] : 1.0);
+  const double nu[4] = {-(double)x.nu.x, -(double)x.nu.y, (double)x.nu.z, (double)x.nu.w};
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    if (sp[a] < 0) continue;
+    double *row = L.J + (1 + sp[a]) * L.js;
+    lds_add(row, nu[a] * dqT);
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+      if (sp[b] >= 0) lds_add(row + 1 + sp[b], nu[a] * dq[b]);
+  }
+#pragma unroll
+  for (int b = 0; b < 4; ++b)
+    if (sp[b] >= 0) lds_add(L.J + 1 + sp[b], dHr * dq[b]);
+}
+
 // Right-hand side (and optionally the Jacobian) of one cell.  Lane l holds
 // y_l in yl.  On return lane l holds f_l; species lanes hold wdot_k in wdl.
 // With JAC, LDS row l (l < n) of L.J holds row l of M = I*dg - J.  With KOUT
@@ -177,6 +221,9 @@ __device__ __forceinline__ void eval_cell(const DevMech &M, const GLds<G> &L, in
     L.hs[k] = hRT;
     L.gs[k] = hRT - sR;
   }
+  double *Jrow = L.J + l * L.js;
+  if (JAC && l < n)
+    for (int j = 0; j < n; ++j) Jrow[j] = 0.0;
   wave_sync();
 
   const double lnPRT = log(PREF / (RG * T));
@@ -189,9 +236,12 @@ __device__ __forceinline__ void eval_cell(const DevMech &M, const GLds<G> &L, in
       L.J[R + r] = x.kr;
     }
     if (JAC) {
+      // dq/dT at fixed C: d ln kf/dT = b/T + Ea/(R T^2), d ln Kc/dT = dH_r/(R T^2) - dn/T
       const double dlnkf = M.b[r] * invT + M.EaR[r] * invT * invT;
       const double dlnKc = (x.dH - x.dn) * invT;
-      sumHq += RG * T * x.dH * (x.fwd * dlnkf - x.rev * (dlnkf - dlnKc));
+      const double dqT = x.fwd * dlnkf - x.rev * (dlnkf - dlnKc);
+      sumHq += RG * T * x.dH * dqT;
+      jac_scatter<G>(L, x, dqT, RG * T * x.dH);
     }
   }
   wave_sync();
@@ -208,59 +258,34 @@ __device__ __forceinline__ void eval_cell(const DevMech &M, const GLds<G> &L, in
   if (!JAC) return;
 
   // ---- analytic Jacobian ----
+  // The reaction loop left, per species row k (LDS row 1 + k): d wdot_k/dC_j
+  // at column 1 + j and sum_r nu_kr dq_r/dT at column 0; and in row 0,
+  // column 1 + j: sum_r dH_r dq_r/dC_j.
   const double dcpdT = grp_sum<G>(Yk * RG * dcpR * iWk);
   const double sumCpW = grp_sum<G>(isSp ? RG * cpR * wd : 0.0);
   const double sumHqT = grp_sum<G>(sumHq);
-  double *Jrow = L.J + l * L.js;
-  if (l < n)
-    for (int j = 0; j < n; ++j) Jrow[j] = 0.0;
-  wave_sync();
-  double dwdTC = 0.0, JwT = 0.0;
+  double a = 0.0, dwdTC = 0.0, JwT = 0.0;
   if (isSp) {
-    // row k of d wdot / d C, scattered into LDS row l, and sum_r dH_r dq_r/dC_k;
-    // each species lane evaluates the rate constants of its own reactions
-    const int e1 = M.csr_off[k + 1];
-    for (int e = M.csr_off[k]; e < e1; ++e) {
-      const int r = M.csr_r[e];
-      const double nuk = M.csr_nu[e];
-      const int slot = M.csr_slot[e];
-      const Rxn x = rxn_eval<G>(M, L, r, lnT, invT, lnPRT);
-      const double f0 = slot_fac(x.sp.x, x.nu.x, L.C), f1 = slot_fac(x.sp.y, x.nu.y, L.C);
-      const double f2 = slot_fac(x.sp.z, x.nu.z, L.C), f3 = slot_fac(x.sp.w, x.nu.w, L.C);
-      double dq0 = 0.0, dq1 = 0.0, dq2 = 0.0, dq3 = 0.0;
-      if (x.sp.x >= 0) dq0 = x.kf * (x.nu.x == 2 ? 2.0 * L.C[x.sp.x] : 1.0) * f1;
-      if (x.sp.y >= 0) dq1 = x.kf * f0 * (x.nu.y == 2 ? 2.0 * L.C[x.sp.y] : 1.0);
-      if (x.sp.z >= 0) dq2 = -x.kr * (x.nu.z == 2 ? 2.0 * L.C[x.sp.z] : 1.0) * f3;
-      if (x.sp.w >= 0) dq3 = -x.kr * f2 * (x.nu.w == 2 ? 2.0 * L.C[x.sp.w] : 1.0);
-      if (x.sp.x >= 0) Jrow[1 + x.sp.x] += nuk * dq0;
-      if (x.sp.y >= 0) Jrow[1 + x.sp.y] += nuk * dq1;
-      if (x.sp.z >= 0) Jrow[1 + x.sp.z] += nuk * dq2;
-      if (x.sp.w >= 0) Jrow[1 + x.sp.w] += nuk * dq3;
-      // dq/dT at fixed C: d ln kf/dT = b/T + Ea/(R T^2), d ln Kc/dT = dH_r/(R T^2) - dn/T
-      const double dlnkf = M.b[r] * invT + M.EaR[r] * invT * invT;
-      const double dlnKc = (x.dH - x.dn) * invT;
-      dwdTC += nuk * (x.fwd * dlnkf - x.rev * (dlnkf - dlnKc));
-      const double dqk = slot == 0 ? dq0 : (slot == 1 ? dq1 : (slot == 2 ? dq2 : dq3));
-      JwT += RG * T * x.dH * dqk;
-    }
-  }
-  double a = 0.0;
-  if (isSp)
     for (int j = 0; j < K; ++j) a += Jrow[1 + j] * L.C[j];
+    dwdTC = Jrow[0];
+    JwT = L.J[1 + k];
+  }
   const double aT = grp_sum<G>(isSp ? JwT * Ck : 0.0);
+  wave_sync();
+  // chain rule through C_j(rho(T, Y), Y): dC_j/dY_i = rho d_ij/W_j - C_j/(S W_i),
+  // dC_j/dT = -C_j/T; each entry is written once, as the Newton matrix
+  // M = I/(gamma h) - J
   const double irhocp = irho / cp;
   if (isSp) {
-    // chain rule through C_j(rho(T, Y), Y): dC_j/dY_i = rho d_ij/W_j - C_j/(S W_i), dC_j/dT = -C_j/T
     const double c2 = Wk * (wd - a) * irho / S;
-    for (int i = 0; i < K; ++i) Jrow[1 + i] = (Wk * Jrow[1 + i] + c2) * M.invW[i];
-    Jrow[0] = Wk * irho * (dwdTC + (wd - a) * invT);
-    L.J[1 + k] = -((rho * JwT - aT / S) * iWk) * irhocp - fT * (-iWk / S + RG * cpR * iWk / cp);
+    for (int i = 0; i < K; ++i) {
+      const double Jki = (Wk * Jrow[1 + i] + c2) * M.invW[i];
+      Jrow[1 + i] = ((i == k) ? dg : 0.0) - Jki;
+    }
+    Jrow[0] = -(Wk * irho * (dwdTC + (wd - a) * invT));
+    L.J[1 + k] = ((rho * JwT - aT / S) * iWk) * irhocp + fT * (-iWk / S + RG * cpR * iWk / cp);
   }
-  if (l == 0) L.J[0] = -(sumCpW + sumHqT - aT * invT) * irhocp - fT * (-invT + dcpdT / cp);
-  wave_sync();
-  // the Newton matrix M = I/(gamma h) - J replaces J in place, row l by lane l
-  if (l < n)
-    for (int j = 0; j < n; ++j) Jrow[j] = ((j == l) ? dg : 0.0) - Jrow[j];
+  if (l == 0) L.J[0] = dg - (-(sumCpW + sumHqT - aT * invT) * irhocp - fT * (-invT + dcpdT / cp));
   wave_sync();
 }
 
@@ -268,12 +293,13 @@ __device__ __forceinline__ void eval_cell(const DevMech &M, const GLds<G> &L, in
 // lane l (odd row stride).  Pivot of step k: the not-yet-eliminated row with the
 // largest |a_ik| (NaN counts as largest), ties to the lowest row.  Rows do not
 // move: lane l records the step at which it became pivot (mystep) and the
-// inverse of its diagonal; multipliers overwrite the eliminated entries.
-// Loops stay rolled (the matrix is addressed in LDS, not in registers), which
-// keeps the kernel inside the instruction cache.  Returns false for a zero or
-// non-finite pivot.
+// inverse of its diagonal, piv[k] the lane of step k; multipliers overwrite
+// the eliminated entries.  Loops stay rolled (the matrix is addressed in LDS,
+// not in registers), which keeps the kernel inside the instruction cache.
+// Returns false for a zero or non-finite pivot.
 template <int G>
-__device__ __forceinline__ bool lu_factor(double *A, int l, int n, int &mystep, double &invd) {
+__device__ __forceinline__ bool lu_factor(double *A, int *piv, int l, int n, int &mystep,
+                                          double &invd) {
   const int JS = GLds<G>::stride(n);
   double *row = A + l * JS;
   bool done = (l >= n);
@@ -301,6 +327,7 @@ __device__ __forceinline__ bool lu_factor(double *A, int l, int n, int &mystep, 
       done = true;
       mystep = k;
       invd = inv;
+      piv[k] = idx;
     }
     if (!done) {
       const double mult = row[k] * inv;
@@ -313,31 +340,20 @@ __device__ __forceinline__ bool lu_factor(double *A, int l, int n, int &mystep, 
   return ok;
 }
 
-// Lane that holds pivot step k within the calling lane's group.
-template <int G>
-__device__ __forceinline__ int pivot_lane(int mystep, int k, int gbase) {
-  const unsigned long long mask = __ballot(mystep == k);
-  constexpr unsigned long long seg = (G == 64) ? ~0ull : ((1ull << (G & 63)) - 1ull);
-  const unsigned long long gm = (G == 64) ? mask : ((mask >> gbase) & seg);
-  return __ffsll((long long)gm) - 1;
-}
-
 // Solve M x = b with the factors of lu_factor.  Lane l passes b_l, gets x_l.
 template <int G>
-__device__ __forceinline__ double lu_solve(const double *A, int l, int n, int mystep, double invd,
-                                           int gbase, double b) {
+__device__ __forceinline__ double lu_solve(const double *A, const int *piv, int l, int n,
+                                           int mystep, double invd, double b) {
   const int JS = GLds<G>::stride(n);
   const double *row = A + l * JS;
   const bool real = l < n;  // lanes past n own no row (none is stored for them)
   for (int k = 0; k < n; ++k) {
-    const int src = pivot_lane<G>(mystep, k, gbase);
-    const double zk = __shfl(b, src, G);
+    const double zk = __shfl(b, piv[k], G);
     if (real && mystep > k) b = fma(-row[k], zk, b);
   }
   double x = 0.0;
   for (int k = n - 1; k >= 0; --k) {
-    const int src = pivot_lane<G>(mystep, k, gbase);
-    const double xk = __shfl(b * invd, src, G);
+    const double xk = __shfl(b * invd, piv[k], G);
     if (real && mystep < k) b = fma(-row[k], xk, b);
     if (l == k) x = xk;
   }
@@ -417,7 +433,7 @@ template <int G>
 __global__ __launch_bounds__(64) void k_step(DevMech M, StepArgs A) {
   extern __shared__ double lds[];
   const int lane = threadIdx.x;
-  const int g = lane / G, l = lane % G, gbase = g * G;
+  const int g = lane / G, l = lane % G;
   const int n = M.n;
   GLds<G> L(lds + g * GLds<G>::doubles(M.R, M.n), M.R, M.n);
   const StepOpts &o = A.o;
@@ -525,7 +541,7 @@ __global__ __launch_bounds__(64) void k_step(DevMech M, StepArgs A) {
         eval_cell<G, true, false>(M, L, l, p, yl, F, wd, 1.0 / (GAMMA * h));
         int mystep;
         double invd;
-        const bool ok = lu_factor<G>(L.J, l, n, mystep, invd);
+        const bool ok = lu_factor<G>(L.J, L.piv, l, n, mystep, invd);
         if (!ok) {
           status = CELL_SINGULAR;
           end = true;
@@ -542,7 +558,7 @@ __global__ __launch_bounds__(64) void k_step(DevMech M, StepArgs A) {
               eval_cell<G, false, false>(M, L, l, p, v, F, wd, 0.0);
             }
             const double c = TC_S(s, 0) * K0 + TC_S(s, 1) * K1 + TC_S(s, 2) * K2;
-            const double x = lu_solve<G>(L.J, l, n, mystep, invd, gbase, F + c / h);
+            const double x = lu_solve<G>(L.J, L.piv, l, n, mystep, invd, F + c / h);
             K0 = (s == 0) ? x : K0;
             K1 = (s == 1) ? x : K1;
             K2 = (s == 2) ? x : K2;
