@@ -71,19 +71,146 @@ __device__ __forceinline__ void lds_add(double *p, double v) {
   __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
 }
 
+// Cross-lane exchanges inside a group of G lanes without the LDS crossbar:
+// DPP patterns pair lanes within 16-lane rows (quad_perm [1,0,3,2] and
+// [2,3,0,1], row_half_mirror, row_mirror), v_permlane16_swap pairs rows 0/1
+// and 2/3, v_permlane32_swap the two halves of the wave.  After each stage of
+// an all-reduce every lane of the merged set holds the same bits (the
+// combining operations are commutative).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+template <int CTRL>
+__device__ __forceinline__ int dpp_i32(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xf, 0xf, false);
+}
+__device__ __forceinline__ double mk_f64(unsigned lo, unsigned hi) {
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+// the value of the paired row (16-lane rows 0/1, 2/3) or half (32 lanes)
+__device__ __forceinline__ void swap16(double v, double &a, double &b) {
+  const long long x = __double_as_longlong(v);
+  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)x, (unsigned)x, false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(x >> 32), (unsigned)(x >> 32),
+                                                   false, false);
+  a = mk_f64(lo[0], hi[0]);  // the even row's value, in both rows of the pair
+  b = mk_f64(lo[1], hi[1]);  // the odd row's value
+}
+__device__ __forceinline__ void swap32(double v, double &a, double &b) {
+  const long long x = __double_as_longlong(v);
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)x, (unsigned)x, false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(x >> 32), (unsigned)(x >> 32),
+                                                   false, false);
+  a = mk_f64(lo[0], hi[0]);
+  b = mk_f64(lo[1], hi[1]);
+}
+__device__ __forceinline__ int swap16_min(int v) {
+  const auto r = __builtin_amdgcn_permlane16_swap((unsigned)v, (unsigned)v, false, false);
+  return min((int)r[0], (int)r[1]);
+}
+__device__ __forceinline__ int swap32_min(int v) {
+  const auto r = __builtin_amdgcn_permlane32_swap((unsigned)v, (unsigned)v, false, false);
+  return min((int)r[0], (int)r[1]);
+}
+
 template <int G>
 __device__ __forceinline__ double grp_sum(double v) {
-#pragma unroll
-  for (int off = G / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, G);
+  static_assert(G == 16 || G == 32 || G == 64, "lane groups of 16, 32 or 64");
+  v += dpp_f64<0xB1>(v);
+  v += dpp_f64<0x4E>(v);
+  v += dpp_f64<0x141>(v);
+  v += dpp_f64<0x140>(v);
+  if (G >= 32) {
+    double a, b;
+    swap16(v, a, b);
+    v = a + b;
+  }
+  if (G == 64) {
+    double a, b;
+    swap32(v, a, b);
+    v = a + b;
+  }
+  return v;
+}
+
+template <int G>
+__device__ __forceinline__ double grp_max(double v) {
+  v = fmax(v, dpp_f64<0xB1>(v));
+  v = fmax(v, dpp_f64<0x4E>(v));
+  v = fmax(v, dpp_f64<0x141>(v));
+  v = fmax(v, dpp_f64<0x140>(v));
+  if (G >= 32) {
+    double a, b;
+    swap16(v, a, b);
+    v = fmax(a, b);
+  }
+  if (G == 64) {
+    double a, b;
+    swap32(v, a, b);
+    v = fmax(a, b);
+  }
+  return v;
+}
+
+template <int G>
+__device__ __forceinline__ int grp_min(int v) {
+  v = min(v, dpp_i32<0xB1>(v));
+  v = min(v, dpp_i32<0x4E>(v));
+  v = min(v, dpp_i32<0x141>(v));
+  v = min(v, dpp_i32<0x140>(v));
+  if (G >= 32) v = swap16_min(v);
+  if (G == 64) v = swap32_min(v);
   return v;
 }
 
 template <int G>
 __device__ __forceinline__ bool grp_any(bool b) {
-  int v = b ? 1 : 0;
+  const unsigned long long m = __ballot(b);
+  if (G == 64) return m != 0ull;
+  const int gbase = ((int)threadIdx.x & 63) & ~(G - 1);
+  return ((m >> gbase) & ((1ull << (G & 63)) - 1ull)) != 0ull;
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const long long x = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)x, lane);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(x >> 32), lane);
+  return mk_f64(lo, hi);
+}
+
+// v of lane src_g of the caller's group, where src_g (< G) may differ between
+// the groups of the wave and is held, for group gg, by lane gg*G + k of sel
+// (k wave-uniform).  Every group's source is read with v_readlane.
+template <int G>
+__device__ __forceinline__ double grp_bcast_sel(double v, int sel, int k) {
+  const int g = ((int)threadIdx.x & 63) / G;
+  double out = 0.0;
 #pragma unroll
-  for (int off = G / 2; off >= 1; off >>= 1) v |= __shfl_xor(v, off, G);
-  return v != 0;
+  for (int gg = 0; gg < 64 / G; ++gg) {
+    // a finished group's selector is stale: masking keeps its (unused) read
+    // inside the group
+    const int src = __builtin_amdgcn_readlane(sel, gg * G + k) & (G - 1);
+    const double x = readlane_f64(v, gg * G + src);
+    out = (g == gg) ? x : out;
+  }
+  return out;
+}
+
+// v of lane 0 of the caller's group.
+template <int G>
+__device__ __forceinline__ double grp_first(double v) {
+  const int g = ((int)threadIdx.x & 63) / G;
+  double out = 0.0;
+#pragma unroll
+  for (int gg = 0; gg < 64 / G; ++gg) {
+    const double x = readlane_f64(v, gg * G);
+    out = (g == gg) ? x : out;
+  }
+  return out;
 }
 
 // Per-group LDS scratch (doubles): concentrations, h/RT and g/RT of the
@@ -193,7 +320,7 @@ template <int G, bool JAC, bool KOUT>
 __device__ __forceinline__ void eval_cell(const DevMech &M, const GLds<G> &L, int l, double p,
                                           double yl, double &f, double &wdl, double dg) {
   const int K = M.K, R = M.R, n = M.n;
-  const double T = __shfl(yl, 0, G);
+  const double T = grp_first<G>(yl);
   const double lnT = log(T), invT = 1.0 / T;
   const bool isSp = (l >= 1) && (l <= K);
   const int k = isSp ? l - 1 : 0;
@@ -309,16 +436,8 @@ __device__ __forceinline__ bool lu_factor(double *A, int *piv, int l, int n, int
   for (int k = 0; k < n; ++k) {
     double v = done ? -1.0 : fabs(row[k]);
     if (v != v) v = INFINITY;
-    int idx = l;
-#pragma unroll
-    for (int off = G / 2; off >= 1; off >>= 1) {
-      const double v2 = __shfl_xor(v, off, G);
-      const int i2 = __shfl_xor(idx, off, G);
-      if (v2 > v || (v2 == v && i2 < idx)) {
-        v = v2;
-        idx = i2;
-      }
-    }
+    const double vmax = grp_max<G>(v);
+    const int idx = grp_min<G>(v == vmax ? l : G);
     const double *prow = A + idx * JS;
     const double pv = prow[k];
     if (!(fabs(pv) > 0.0) || !isfinite(pv)) ok = false;
@@ -347,13 +466,14 @@ __device__ __forceinline__ double lu_solve(const double *A, const int *piv, int 
   const int JS = GLds<G>::stride(n);
   const double *row = A + l * JS;
   const bool real = l < n;  // lanes past n own no row (none is stored for them)
+  const int sel = piv[l < n ? l : 0];  // lane k of the group: the lane of pivot step k
   for (int k = 0; k < n; ++k) {
-    const double zk = __shfl(b, piv[k], G);
+    const double zk = grp_bcast_sel<G>(b, sel, k);
     if (real && mystep > k) b = fma(-row[k], zk, b);
   }
   double x = 0.0;
   for (int k = n - 1; k >= 0; --k) {
-    const double xk = __shfl(b * invd, piv[k], G);
+    const double xk = grp_bcast_sel<G>(b * invd, sel, k);
     if (real && mystep < k) b = fma(-row[k], xk, b);
     if (l == k) x = xk;
   }
