@@ -102,7 +102,6 @@ extern "C" chem_status chem_mech_create(const chem_mech_desc *d, chem_mech **out
         return CHEM_EMECH;
       }
   }
-  std::vector<int> cnt(K, 0);
   for (int r = 0; r < R; ++r) {
     const int32_t *sp = d->rsp + 4 * r, *nu = d->rnu + 4 * r;
     if (!(d->A[r] > 0.0) || !isfinite(d->A[r]) || !isfinite(d->b[r]) || !isfinite(d->Ea[r])) {
@@ -125,7 +124,6 @@ extern "C" chem_status chem_mech_create(const chem_mech_desc *d, chem_mech **out
         }
       (s < 2 ? nreac : nprod)++;
       for (int e = 0; e < E; ++e) bal[e] += (s < 2 ? -1 : 1) * (long)nu[s] * d->comp[sp[s] * E + e];
-      cnt[sp[s]]++;
     }
     if (nreac == 0 || nprod == 0) {
       set_error("chem_mech_create: reaction %d needs at least one reactant and one product", r);
@@ -168,21 +166,6 @@ extern "C" chem_status chem_mech_create(const chem_mech_desc *d, chem_mech **out
     sp4[r] = make_int4(s4[0], s4[1], s4[2], s4[3]);
     nu4[r] = make_int4(n4[0], n4[1], n4[2], n4[3]);
   }
-  std::vector<int> off(K + 1, 0);
-  for (int k = 0; k < K; ++k) off[k + 1] = off[k] + cnt[k];
-  const int nnz = off[K];
-  std::vector<int> cr(nnz > 0 ? nnz : 1), cs(nnz > 0 ? nnz : 1);
-  std::vector<double> cn(nnz > 0 ? nnz : 1);
-  std::vector<int> fill(off.begin(), off.end() - 1);
-  for (int r = 0; r < R; ++r)
-    for (int s = 0; s < 4; ++s) {
-      const int k = d->rsp[4 * r + s];
-      if (k < 0) continue;
-      const int e = fill[k]++;
-      cr[e] = r;
-      cs[e] = s;
-      cn[e] = (s < 2 ? -1.0 : 1.0) * d->rnu[4 * r + s];
-    }
   std::vector<double> Mel((size_t)E * K);
   for (int e = 0; e < E; ++e)
     for (int k = 0; k < K; ++k) Mel[(size_t)e * K + k] = d->comp[k * E + e] * d->awt[e] / d->W[k];
@@ -199,25 +182,17 @@ extern "C" chem_status chem_mech_create(const chem_mech_desc *d, chem_mech **out
       e[0] = a[0]; e[1] = a[1]; e[2] = a[2] / 2.0; e[3] = a[3] / 3.0; e[4] = a[4] / 4.0;
       e[5] = a[6]; e[6] = 0.0;
     }
-  // Jacobian pair lists: for species k, every (j, r) with r containing both
-  std::vector<int> poff(K + 1, 0), pcode;
-  for (int k = 0; k < K; ++k) {
-    std::vector<std::pair<long, int>> ent;
-    for (int e = off[k]; e < off[k + 1]; ++e) {
-      const int r = cr[e];
-      const int nuk = (int)cn[e];
-      for (int s2 = 0; s2 < 4; ++s2) {
-        const int j = d->rsp[4 * r + s2];
-        if (j < 0) continue;
-        const int code = r | (s2 << 16) | ((nuk + 8) << 20) | (j << 24);
-        ent.push_back({(long)j * 262144L + (long)r * 4 + s2, code});
+  // the same polynomials coefficient-major, [range][coefficient][species], so
+  // that one coefficient of consecutive species is one contiguous load
+  std::vector<double> cpT(14 * (size_t)K), hT(14 * (size_t)K), sT(14 * (size_t)K);
+  for (int r = 0; r < 2; ++r)
+    for (int i = 0; i < 7; ++i)
+      for (int k = 0; k < K; ++k) {
+        const size_t t = ((size_t)r * 7 + i) * K + k;
+        cpT[t] = (r == 0 ? lo : hi)[7 * k + i];
+        hT[t] = (r == 0 ? nh : nhh)[7 * k + i];
+        sT[t] = (r == 0 ? ns : nsh)[7 * k + i];
       }
-    }
-    std::sort(ent.begin(), ent.end());
-    for (auto &q : ent) pcode.push_back(q.second);
-    poff[k + 1] = (int)pcode.size();
-  }
-  if (pcode.empty()) pcode.push_back(0);
   if (R >= 65536) {
     set_error("chem_mech_create: at most 65535 reactions");
     return CHEM_EUNSUPPORTED;
@@ -229,12 +204,11 @@ extern "C" chem_status chem_mech_create(const chem_mech_desc *d, chem_mech **out
          ohi = pk.add(hi.data(), 7 * K * 8), olnA = pk.add(lnA.data(), R * 8),
          ob = pk.add(bb.data(), R * 8), oEa = pk.add(EaR.data(), R * 8),
          odn = pk.add(dn.data(), R * 8), osp = pk.add(sp4.data(), R * sizeof(int4)),
-         onu = pk.add(nu4.data(), R * sizeof(int4)), ooff = pk.add(off.data(), (K + 1) * 4),
-         ocr = pk.add(cr.data(), cr.size() * 4), ocs = pk.add(cs.data(), cs.size() * 4),
-         ocn = pk.add(cn.data(), cn.size() * 8), oM = pk.add(Mel.data(), Mel.size() * 8),
+         onu = pk.add(nu4.data(), R * sizeof(int4)), oM = pk.add(Mel.data(), Mel.size() * 8),
          onh = pk.add(nh.data(), nh.size() * 8), onhh = pk.add(nhh.data(), nhh.size() * 8),
          ons = pk.add(ns.data(), ns.size() * 8), onsh = pk.add(nsh.data(), nsh.size() * 8),
-         opo = pk.add(poff.data(), poff.size() * 4), opc = pk.add(pcode.data(), pcode.size() * 4);
+         ocpT = pk.add(cpT.data(), cpT.size() * 8), ohT = pk.add(hT.data(), hT.size() * 8),
+         osT = pk.add(sT.data(), sT.size() * 8);
 
   chem_mech *m = new chem_mech();
   m->K = K;
@@ -279,17 +253,14 @@ extern "C" chem_status chem_mech_create(const chem_mech_desc *d, chem_mech **out
   dm.dn = (const double *)(base + odn);
   dm.sp = (const int4 *)(base + osp);
   dm.nu = (const int4 *)(base + onu);
-  dm.csr_off = (const int *)(base + ooff);
-  dm.csr_r = (const int *)(base + ocr);
-  dm.csr_slot = (const int *)(base + ocs);
-  dm.csr_nu = (const double *)(base + ocn);
   dm.Mel = (const double *)(base + oM);
   dm.nasa_h = (const double *)(base + onh);
   dm.nasa_hh = (const double *)(base + onhh);
   dm.nasa_s = (const double *)(base + ons);
   dm.nasa_sh = (const double *)(base + onsh);
-  dm.pair_off = (const int *)(base + opo);
-  dm.pair_code = (const int *)(base + opc);
+  dm.cpT = (const double *)(base + ocpT);
+  dm.hT = (const double *)(base + ohT);
+  dm.sT = (const double *)(base + osT);
   *out = m;
   return CHEM_OK;
 }

@@ -24,24 +24,15 @@ struct DevMech {
   const double *dn;       // [R] sum of product minus reactant coefficients
   const int4 *sp;         // [R] species of slots reactant0, reactant1, product0, product1 (-1 none)
   const int4 *nu;         // [R] their coefficients (0 for empty slots)
-  const int *csr_off;     // [K+1] reactions in which species k takes part ...
-  const int *csr_r;       // [nnz]   ... in ascending order,
-  const int *csr_slot;    // [nnz]   its slot in that reaction,
-  const double *csr_nu;   // [nnz]   and its signed net coefficient
   const double *Mel;      // [E][K] element mass per unit mass fraction, A_e a_ek / W_k
   const double *nasa_h;   // [K][7] low-range h/RT polynomial: a1, a2/2, a3/3, a4/4, a5/5, a6, 0
   const double *nasa_hh;  // [K][7] same for the high range
   const double *nasa_s;   // [K][7] low-range s/R: a1, a2, a3/2, a4/3, a5/4, a7, 0
   const double *nasa_sh;  // [K][7] same for the high range
-  const int *pair_off;    // [K+1] per species k: entries (species j, reaction r, slot of j,
-  const int *pair_code;   //   net coefficient of k) for every r containing k and every j
-                          //   in r, sorted by (j, r); code = r | slot<<16 | (nu+8)<<20 | j<<24
+  const double *cpT;      // [2][7][K] the c_p/R, h/RT and s/R polynomials above,
+  const double *hT;       //   low range then high range, coefficient-major
+  const double *sT;
 };
-
-__host__ __device__ inline int pair_r(int c) { return c & 0xffff; }
-__host__ __device__ inline int pair_slot(int c) { return (c >> 16) & 0xf; }
-__host__ __device__ inline double pair_nu(int c) { return (double)(((c >> 20) & 0xf) - 8); }
-__host__ __device__ inline int pair_j(int c) { return (c >> 24) & 0x7f; }
 
 struct StepOpts {
   double rtol, atol_Y, atol_T, h0, h_min;

@@ -182,24 +182,6 @@ __device__ __forceinline__ double readlane_f64(double v, int lane) {
   return mk_f64(lo, hi);
 }
 
-// v of lane src_g of the caller's group, where src_g (< G) may differ between
-// the groups of the wave and is held, for group gg, by lane gg*G + k of sel
-// (k wave-uniform).  Every group's source is read with v_readlane.
-template <int G>
-__device__ __forceinline__ double grp_bcast_sel(double v, int sel, int k) {
-  const int g = ((int)threadIdx.x & 63) / G;
-  double out = 0.0;
-#pragma unroll
-  for (int gg = 0; gg < 64 / G; ++gg) {
-    // a finished group's selector is stale: masking keeps its (unused) read
-    // inside the group
-    const int src = __builtin_amdgcn_readlane(sel, gg * G + k) & (G - 1);
-    const double x = readlane_f64(v, gg * G + src);
-    out = (g == gg) ? x : out;
-  }
-  return out;
-}
-
 // v of lane 0 of the caller's group.
 template <int G>
 __device__ __forceinline__ double grp_first(double v) {
@@ -214,32 +196,28 @@ __device__ __forceinline__ double grp_first(double v) {
 }
 
 // Per-group LDS scratch (doubles): concentrations, h/RT and g/RT of the
-// species, rates of progress, the Jacobian / Newton matrix (n rows of odd
-// stride) and the LU's pivot order (G ints: the lane whose row is the pivot
-// of step k).  In chem_rates the matrix region holds k_f, k_r instead.
+// species, the net production rates being accumulated, and the Jacobian /
+// Newton matrix (n rows of odd stride).  In chem_rates the matrix region
+// holds k_f, k_r instead; in the solves the concentration slots hold the
+// permuted right-hand side.
 template <int G>
 struct GLds {
-  double *C, *hs, *gs, *qs, *J;
-  int *piv;
+  double *C, *hs, *gs, *wa, *J;
   int js;  // row stride of J
   __device__ GLds(double *base, int R, int n) {
     C = base;
     hs = C + G;
     gs = hs + G;
-    qs = gs + G;
-    J = qs + R;
-    piv = (int *)(J + mat(R, n));
+    wa = gs + G;
+    J = wa + G;
     js = stride(n);
   }
   // odd row stride (2 js banks apart: lanes reading one column hit distinct
   // banks) and only the n rows of the n x n matrix
   __host__ __device__ static int stride(int n) { return n | 1; }
-  __host__ __device__ static size_t mat(int R, int n) {
-    const size_t j = (size_t)n * stride(n), k = 2 * (size_t)R;
-    return j > k ? j : k;
-  }
   __host__ __device__ static size_t doubles(int R, int n) {
-    return 3 * G + (size_t)R + mat(R, n) + G / 2;
+    const size_t j = (size_t)n * stride(n), k = 2 * (size_t)R;
+    return 4 * G + (j > k ? j : k);
   }
 };
 
@@ -329,14 +307,15 @@ __device__ __forceinline__ void eval_cell(const DevMech &M, const GLds<G> &L, in
     Wk = M.W[k];
     iWk = M.invW[k];
     Yk = yl;
-    const bool lo = T <= M.Tmid[k];
-    const double *a = (lo ? M.nasa_lo : M.nasa_hi) + 7 * k;
-    const double *hc = (lo ? M.nasa_h : M.nasa_hh) + 7 * k;
-    const double *sc = (lo ? M.nasa_s : M.nasa_sh) + 7 * k;
-    cpR = a[0] + T * (a[1] + T * (a[2] + T * (a[3] + T * a[4])));
-    hRT = hc[0] + T * (hc[1] + T * (hc[2] + T * (hc[3] + T * hc[4]))) + hc[5] * invT;
-    sR = sc[0] * lnT + T * (sc[1] + T * (sc[2] + T * (sc[3] + T * sc[4]))) + sc[5];
-    if (JAC) dcpR = a[1] + T * (2.0 * a[2] + T * (3.0 * a[3] + T * (4.0 * a[4])));
+    // coefficient i of species k in the range T selects: [i * K] from here
+    const int o = (T <= M.Tmid[k] ? 0 : 7 * K) + k;
+    const double *a = M.cpT + o, *hc = M.hT + o, *sc = M.sT + o;
+    cpR = a[0] + T * (a[K] + T * (a[2 * K] + T * (a[3 * K] + T * a[4 * K])));
+    hRT = hc[0] + T * (hc[K] + T * (hc[2 * K] + T * (hc[3 * K] + T * hc[4 * K]))) +
+          hc[5 * K] * invT;
+    sR = sc[0] * lnT + T * (sc[K] + T * (sc[2 * K] + T * (sc[3 * K] + T * sc[4 * K]))) +
+         sc[5 * K];
+    if (JAC) dcpR = a[K] + T * (2.0 * a[2 * K] + T * (3.0 * a[3 * K] + T * (4.0 * a[4 * K])));
   }
   const double S = grp_sum<G>(Yk * iWk);
   const double rho = p / (RG * T * S);
@@ -348,6 +327,7 @@ __device__ __forceinline__ void eval_cell(const DevMech &M, const GLds<G> &L, in
     L.hs[k] = hRT;
     L.gs[k] = hRT - sR;
   }
+  L.wa[l] = 0.0;
   double *Jrow = L.J + l * L.js;
   if (JAC && l < n)
     for (int j = 0; j < n; ++j) Jrow[j] = 0.0;
@@ -357,7 +337,12 @@ __device__ __forceinline__ void eval_cell(const DevMech &M, const GLds<G> &L, in
   double sumHq = 0.0;
   for (int r = l; r < R; r += G) {
     const Rxn x = rxn_eval<G>(M, L, r, lnT, invT, lnPRT);
-    L.qs[r] = x.fwd - x.rev;
+    // wdot_k = sum_r (nu''_kr - nu'_kr) q_r, added from the reaction's lane
+    const double q = x.fwd - x.rev;
+    if (x.sp.x >= 0) lds_add(L.wa + x.sp.x, -x.nu.x * q);
+    if (x.sp.y >= 0) lds_add(L.wa + x.sp.y, -x.nu.y * q);
+    if (x.sp.z >= 0) lds_add(L.wa + x.sp.z, x.nu.z * q);
+    if (x.sp.w >= 0) lds_add(L.wa + x.sp.w, x.nu.w * q);
     if (KOUT) {
       L.J[r] = x.kf;
       L.J[R + r] = x.kr;
@@ -373,11 +358,7 @@ __device__ __forceinline__ void eval_cell(const DevMech &M, const GLds<G> &L, in
   }
   wave_sync();
 
-  double wd = 0.0;
-  if (isSp) {
-    const int e1 = M.csr_off[k + 1];
-    for (int e = M.csr_off[k]; e < e1; ++e) wd += M.csr_nu[e] * L.qs[M.csr_r[e]];
-  }
+  const double wd = isSp ? L.wa[k] : 0.0;
   wdl = wd;
   const double Q = grp_sum<G>(isSp ? RG * T * hRT * wd : 0.0);
   const double fT = -Q * irho / cp;
@@ -416,17 +397,20 @@ __device__ __forceinline__ void eval_cell(const DevMech &M, const GLds<G> &L, in
   wave_sync();
 }
 
-// LU with partial pivoting of the n x n matrix held in LDS, row l owned by
-// lane l (odd row stride).  Pivot of step k: the not-yet-eliminated row with the
-// largest |a_ik| (NaN counts as largest), ties to the lowest row.  Rows do not
-// move: lane l records the step at which it became pivot (mystep) and the
-// inverse of its diagonal, piv[k] the lane of step k; multipliers overwrite
-// the eliminated entries.  Loops stay rolled (the matrix is addressed in LDS,
-// not in registers), which keeps the kernel inside the instruction cache.
-// Returns false for a zero or non-finite pivot.
+// Gauss-Jordan elimination with partial pivoting of the n x n matrix held in
+// LDS, row l owned by lane l (odd row stride).  Pivot of step k: the
+// not-yet-eliminated row with the largest |a_ik| (NaN counts as largest), ties
+// to the lowest row, as in an LU with partial pivoting.  Rows do not move and
+// pivot rows are not scaled: with p_k the pivot row of step k and
+// m_i = a_ik / a_{p_k k}, every other row i becomes a_i. - m_i a_{p_k}. and
+// its column k holds -m_i, the pivot row's column k holds 1.  Afterwards row
+// p_k holds a_{p_k k} times row k of the inverse with its columns in pivot
+// order (column j belongs to unknown p_j): each solve is then one
+// matrix-vector product instead of two triangular sweeps of n dependent
+// steps.  Lane l records its step (mystep) and 1/a_{l,mystep}.  Returns false
+// for a zero or non-finite pivot.
 template <int G>
-__device__ __forceinline__ bool lu_factor(double *A, int *piv, int l, int n, int &mystep,
-                                          double &invd) {
+__device__ __forceinline__ bool gj_factor(double *A, int l, int n, int &mystep, double &invd) {
   const int JS = GLds<G>::stride(n);
   double *row = A + l * JS;
   bool done = (l >= n);
@@ -442,41 +426,56 @@ __device__ __forceinline__ bool lu_factor(double *A, int *piv, int l, int n, int
     const double pv = prow[k];
     if (!(fabs(pv) > 0.0) || !isfinite(pv)) ok = false;
     const double inv = 1.0 / pv;
-    if (l == idx) {
+    const bool isp = (l == idx);
+    if (isp) {
       done = true;
       mystep = k;
       invd = inv;
-      piv[k] = idx;
     }
-    if (!done) {
-      const double mult = row[k] * inv;
-      row[k] = mult;
-#pragma unroll 4
-      for (int j = k + 1; j < n; ++j) row[j] = fma(-mult, prow[j], row[j]);
+    if (l < n) {
+      // the pivot row itself takes m = 0 and stays unchanged, so lanes
+      // reading it see the same values whatever the order of the stores.
+      // Eight entries are loaded before any is stored (the stores may alias
+      // the pivot row as far as the compiler knows, which would otherwise
+      // cost one LDS round trip per entry).
+      const double m = isp ? 0.0 : row[k] * inv;
+      for (int j0 = 0; j0 < n; j0 += 8) {
+        double pr[8], rr[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (j0 + u < n) {
+            pr[u] = prow[j0 + u];
+            rr[u] = row[j0 + u];
+          }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (j0 + u < n) row[j0 + u] = fma(-m, pr[u], rr[u]);
+      }
+      row[k] = isp ? 1.0 : -m;
     }
     wave_sync();
   }
   return ok;
 }
 
-// Solve M x = b with the factors of lu_factor.  Lane l passes b_l, gets x_l.
+// Solve M x = b with the factors of gj_factor.  Lane l passes b_l, gets x_l.
+// v (G doubles of LDS) carries b in pivot order, then x.
 template <int G>
-__device__ __forceinline__ double lu_solve(const double *A, const int *piv, int l, int n,
-                                           int mystep, double invd, double b) {
+__device__ __forceinline__ double gj_solve(const double *A, double *v, int l, int n, int mystep,
+                                           double invd, double b) {
   const int JS = GLds<G>::stride(n);
   const double *row = A + l * JS;
   const bool real = l < n;  // lanes past n own no row (none is stored for them)
-  const int sel = piv[l < n ? l : 0];  // lane k of the group: the lane of pivot step k
-  for (int k = 0; k < n; ++k) {
-    const double zk = grp_bcast_sel<G>(b, sel, k);
-    if (real && mystep > k) b = fma(-row[k], zk, b);
-  }
-  double x = 0.0;
-  for (int k = n - 1; k >= 0; --k) {
-    const double xk = grp_bcast_sel<G>(b * invd, sel, k);
-    if (real && mystep < k) b = fma(-row[k], xk, b);
-    if (l == k) x = xk;
-  }
+  if (real) v[mystep] = b;
+  wave_sync();
+  double acc = 0.0;
+  if (real)
+    for (int j = 0; j < n; ++j) acc = fma(row[j], v[j], acc);
+  wave_sync();
+  if (real) v[mystep] = acc * invd;
+  wave_sync();
+  const double x = real ? v[l] : 0.0;
+  wave_sync();
   return x;
 }
 
@@ -661,7 +660,7 @@ __global__ __launch_bounds__(64) void k_step(DevMech M, StepArgs A) {
         eval_cell<G, true, false>(M, L, l, p, yl, F, wd, 1.0 / (GAMMA * h));
         int mystep;
         double invd;
-        const bool ok = lu_factor<G>(L.J, L.piv, l, n, mystep, invd);
+        const bool ok = gj_factor<G>(L.J, l, n, mystep, invd);
         if (!ok) {
           status = CELL_SINGULAR;
           end = true;
@@ -678,7 +677,7 @@ __global__ __launch_bounds__(64) void k_step(DevMech M, StepArgs A) {
               eval_cell<G, false, false>(M, L, l, p, v, F, wd, 0.0);
             }
             const double c = TC_S(s, 0) * K0 + TC_S(s, 1) * K1 + TC_S(s, 2) * K2;
-            const double x = lu_solve<G>(L.J, L.piv, l, n, mystep, invd, F + c / h);
+            const double x = gj_solve<G>(L.J, L.C, l, n, mystep, invd, F + c / h);
             K0 = (s == 0) ? x : K0;
             K1 = (s == 1) ? x : K1;
             K2 = (s == 2) ? x : K2;
