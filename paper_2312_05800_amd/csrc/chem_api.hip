@@ -158,7 +158,7 @@ extern "C" chem_status chem_mech_create(const chem_mech_desc *d, chem_mech **out
     int dnn = 0;
     int s4[4], n4[4];
     for (int s = 0; s < 4; ++s) {
-      s4[s] = sp[s] < 0 ? -1 : sp[s];
+      s4[s] = sp[s] < 0 ? K : sp[s];  // empty slot: the dummy species K (see DevMech::sp)
       n4[s] = sp[s] < 0 ? 0 : nu[s];
       dnn += (s < 2 ? -1 : 1) * n4[s];
     }

@@ -22,7 +22,10 @@ struct DevMech {
   const double *b;        // [R]
   const double *EaR;      // [R] Ea / R_gas, K
   const double *dn;       // [R] sum of product minus reactant coefficients
-  const int4 *sp;         // [R] species of slots reactant0, reactant1, product0, product1 (-1 none)
+  const int4 *sp;         // [R] species of slots reactant0, reactant1, product0, product1;
+                          //   an empty slot names the dummy species K (the kernels keep
+                          //   C = 1 and h = g = 0 for it, so it drops out of every product
+                          //   and sum without a branch)
   const int4 *nu;         // [R] their coefficients (0 for empty slots)
   const double *Mel;      // [E][K] element mass per unit mass fraction, A_e a_ek / W_k
   const double *nasa_h;   // [K][7] low-range h/RT polynomial: a1, a2/2, a3/3, a4/4, a5/5, a6, 0

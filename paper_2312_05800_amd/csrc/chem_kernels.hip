@@ -215,14 +215,16 @@ struct GLds {
   // odd row stride (2 js banks apart: lanes reading one column hit distinct
   // banks) and only the n rows of the n x n matrix
   __host__ __device__ static int stride(int n) { return n | 1; }
+  // even, so that every group's slice starts 16-byte aligned
   __host__ __device__ static size_t doubles(int R, int n) {
     const size_t j = (size_t)n * stride(n), k = 2 * (size_t)R;
-    return 4 * G + (j > k ? j : k);
+    return (4 * G + (j > k ? j : k) + 1) & ~(size_t)1;
   }
 };
 
+// C^nu of a reaction slot (nu = 1 or 2; an empty slot names the dummy
+// species, whose C is 1)
 __device__ __forceinline__ double slot_fac(int s, int nu, const double *C) {
-  if (s < 0) return 1.0;
   const double c = C[s];
   return nu == 2 ? c * c : c;
 }
@@ -241,11 +243,17 @@ __device__ __forceinline__ Rxn rxn_eval(const DevMech &M, const GLds<G> &L, int 
   Rxn x;
   x.sp = M.sp[r];
   x.nu = M.nu[r];
+  // empty slots gather the dummy species (g = h = 0, coefficient 0): no branches,
+  // so the twelve LDS reads of a reaction issue together
   double dG = 0.0, dH = 0.0;
-  if (x.sp.x >= 0) { dG -= x.nu.x * L.gs[x.sp.x]; dH -= x.nu.x * L.hs[x.sp.x]; }
-  if (x.sp.y >= 0) { dG -= x.nu.y * L.gs[x.sp.y]; dH -= x.nu.y * L.hs[x.sp.y]; }
-  if (x.sp.z >= 0) { dG += x.nu.z * L.gs[x.sp.z]; dH += x.nu.z * L.hs[x.sp.z]; }
-  if (x.sp.w >= 0) { dG += x.nu.w * L.gs[x.sp.w]; dH += x.nu.w * L.hs[x.sp.w]; }
+  dG -= x.nu.x * L.gs[x.sp.x];
+  dH -= x.nu.x * L.hs[x.sp.x];
+  dG -= x.nu.y * L.gs[x.sp.y];
+  dH -= x.nu.y * L.hs[x.sp.y];
+  dG += x.nu.z * L.gs[x.sp.z];
+  dH += x.nu.z * L.hs[x.sp.z];
+  dG += x.nu.w * L.gs[x.sp.w];
+  dH += x.nu.w * L.hs[x.sp.w];
   x.dH = dH;
   x.dn = M.dn[r];
   const double lnkf = M.lnA[r] + M.b[r] * lnT - M.EaR[r] * invT;
@@ -269,25 +277,28 @@ __device__ __forceinline__ void jac_scatter(const GLds<G> &L, const Rxn &x, doub
                                             double dHr) {
   const double f0 = slot_fac(x.sp.x, x.nu.x, L.C), f1 = slot_fac(x.sp.y, x.nu.y, L.C);
   const double f2 = slot_fac(x.sp.z, x.nu.z, L.C), f3 = slot_fac(x.sp.w, x.nu.w, L.C);
+  // empty slots (coefficient 0) name the dummy species, which has no row or
+  // column in the matrix: they are skipped
   const int sp[4] = {x.sp.x, x.sp.y, x.sp.z, x.sp.w};
-  double dq[4] = {0.0, 0.0, 0.0, 0.0};
-  if (sp[0] >= 0) dq[0] = x.kf * (x.nu.x == 2 ? 2.0 * L.C[sp[0]] : 1.0) * f1;
-  if (sp[1] >= 0) dq[1] = x.kf * f0 * (x.nu.y == 2 ? 2.0 * L.C[sp[1]] : 1.0);
-  if (sp[2] >= 0) dq[2] = -x.kr * (x.nu.z == 2 ? 2.0 * L.C[sp[2]] : 1.0) * f3;
-  if (sp[3] >= 0) dq[3] = -x.kr * f2 * (x.nu.w == 2 ? 2.0 * L.C[sp[3]] : 1.0);
+  const bool has[4] = {x.nu.x > 0, x.nu.y > 0, x.nu.z > 0, x.nu.w > 0};
+  double dq[4];
+  dq[0] = x.kf * (x.nu.x == 2 ? 2.0 * L.C[sp[0]] : 1.0) * f1;
+  dq[1] = x.kf * f0 * (x.nu.y == 2 ? 2.0 * L.C[sp[1]] : 1.0);
+  dq[2] = -x.kr * (x.nu.z == 2 ? 2.0 * L.C[sp[2]] : 1.0) * f3;
+  dq[3] = -x.kr * f2 * (x.nu.w == 2 ? 2.0 * L.C[sp[3]] : 1.0);
   const double nu[4] = {-(double)x.nu.x, -(double)x.nu.y, (double)x.nu.z, (double)x.nu.w};
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
-    if (sp[a] < 0) continue;
+    if (!has[a]) continue;
     double *row = L.J + (1 + sp[a]) * L.js;
     lds_add(row, nu[a] * dqT);
 #pragma unroll
     for (int b = 0; b < 4; ++b)
-      if (sp[b] >= 0) lds_add(row + 1 + sp[b], nu[a] * dq[b]);
+      if (has[b]) lds_add(row + 1 + sp[b], nu[a] * dq[b]);
   }
 #pragma unroll
   for (int b = 0; b < 4; ++b)
-    if (sp[b] >= 0) lds_add(L.J + 1 + sp[b], dHr * dq[b]);
+    if (has[b]) lds_add(L.J + 1 + sp[b], dHr * dq[b]);
 }
 
 // Right-hand side (and optionally the Jacobian) of one cell.  Lane l holds
@@ -327,6 +338,11 @@ __device__ __forceinline__ void eval_cell(const DevMech &M, const GLds<G> &L, in
     L.hs[k] = hRT;
     L.gs[k] = hRT - sR;
   }
+  if (l == 0) {  // the dummy species of empty reaction slots
+    L.C[K] = 1.0;
+    L.hs[K] = 0.0;
+    L.gs[K] = 0.0;
+  }
   L.wa[l] = 0.0;
   double *Jrow = L.J + l * L.js;
   if (JAC && l < n)
@@ -335,14 +351,16 @@ __device__ __forceinline__ void eval_cell(const DevMech &M, const GLds<G> &L, in
 
   const double lnPRT = log(PREF / (RG * T));
   double sumHq = 0.0;
-  for (int r = l; r < R; r += G) {
-    const Rxn x = rxn_eval<G>(M, L, r, lnT, invT, lnPRT);
+  // two reactions per pass: their loads and gathers are independent and
+  // issue together before the adds to LDS
+  auto finish_rxn = [&](const Rxn &x, int r) {
     // wdot_k = sum_r (nu''_kr - nu'_kr) q_r, added from the reaction's lane
+    // (the dummy species of empty slots takes the zero terms)
     const double q = x.fwd - x.rev;
-    if (x.sp.x >= 0) lds_add(L.wa + x.sp.x, -x.nu.x * q);
-    if (x.sp.y >= 0) lds_add(L.wa + x.sp.y, -x.nu.y * q);
-    if (x.sp.z >= 0) lds_add(L.wa + x.sp.z, x.nu.z * q);
-    if (x.sp.w >= 0) lds_add(L.wa + x.sp.w, x.nu.w * q);
+    lds_add(L.wa + x.sp.x, -x.nu.x * q);
+    lds_add(L.wa + x.sp.y, -x.nu.y * q);
+    lds_add(L.wa + x.sp.z, x.nu.z * q);
+    lds_add(L.wa + x.sp.w, x.nu.w * q);
     if (KOUT) {
       L.J[r] = x.kf;
       L.J[R + r] = x.kr;
@@ -355,6 +373,14 @@ __device__ __forceinline__ void eval_cell(const DevMech &M, const GLds<G> &L, in
       sumHq += RG * T * x.dH * dqT;
       jac_scatter<G>(L, x, dqT, RG * T * x.dH);
     }
+  };
+  for (int r0 = l; r0 < R; r0 += 2 * G) {
+    const int r1 = r0 + G;
+    const bool two = r1 < R;
+    const Rxn x0 = rxn_eval<G>(M, L, r0, lnT, invT, lnPRT);
+    const Rxn x1 = rxn_eval<G>(M, L, two ? r1 : r0, lnT, invT, lnPRT);
+    finish_rxn(x0, r0);
+    if (two) finish_rxn(x1, r1);
   }
   wave_sync();
 
@@ -458,6 +484,65 @@ __device__ __forceinline__ bool gj_factor(double *A, int l, int n, int &mystep, 
   return ok;
 }
 
+// gj_factor with each lane's row held in registers (groups of up to 32
+// lanes): slot 0 always holds the column being eliminated (the row is
+// rotated by one slot per step, so every index is a compile-time constant),
+// and the pivot row reaches the other lanes through pbuf (G doubles of LDS)
+// as one broadcast per step; the only LDS round trip left on a step's
+// dependency chain.  Same arithmetic, in the same order, as gj_factor; the
+// factors are written back to the LDS rows at the end.
+template <int G>
+__device__ __forceinline__ bool gj_factor_reg(double *A, double *pbuf, int l, int n, int &mystep,
+                                              double &invd) {
+  static_assert(G <= 32, "the register row holds G doubles");
+  const int JS = GLds<G>::stride(n);
+  double *rowp = A + l * JS;
+  const bool real = l < n;
+  double r[G];
+#pragma unroll
+  for (int i = 0; i < G; ++i) r[i] = (real && i < n) ? rowp[i] : 0.0;
+  bool done = !real;
+  mystep = done ? l : -1;
+  invd = 1.0;
+  bool ok = true;
+  for (int k = 0; k < n; ++k) {
+    double v = done ? -1.0 : fabs(r[0]);
+    if (v != v) v = INFINITY;
+    const double vmax = grp_max<G>(v);
+    const int idx = grp_min<G>(v == vmax ? l : G);
+    const bool isp = (l == idx);
+    if (isp) {
+#pragma unroll
+      for (int i = 0; i < G; ++i) pbuf[i] = r[i];
+    }
+    wave_sync();
+    const double pv = pbuf[0];
+    if (!(fabs(pv) > 0.0) || !isfinite(pv)) ok = false;
+    const double inv = 1.0 / pv;
+    if (isp) {
+      done = true;
+      mystep = k;
+      invd = inv;
+    }
+    const double m = isp ? 0.0 : r[0] * inv;
+#pragma unroll
+    for (int i = 1; i < G; ++i) r[i] = fma(-m, pbuf[i], r[i]);
+    const double c0 = isp ? 1.0 : -m;
+#pragma unroll
+    for (int i = 0; i < G - 1; ++i) r[i] = r[i + 1];
+    r[G - 1] = c0;
+    wave_sync();  // every lane has read pbuf before the next pivot row goes there
+  }
+  // after n rotations slot i holds column (n + i) mod G
+#pragma unroll
+  for (int i = 0; i < G; ++i) {
+    const int c = (n + i) & (G - 1);
+    if (real && c < n) rowp[c] = r[i];
+  }
+  wave_sync();
+  return ok;
+}
+
 // Solve M x = b with the factors of gj_factor.  Lane l passes b_l, gets x_l.
 // v (G doubles of LDS) carries b in pivot order, then x.
 template <int G>
@@ -549,7 +634,7 @@ __global__ __launch_bounds__(64) void k_rates(DevMech M, int64_t N, int64_t ld, 
 }
 
 template <int G>
-__global__ __launch_bounds__(64) void k_step(DevMech M, StepArgs A) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_step(DevMech M, StepArgs A) {
   extern __shared__ double lds[];
   const int lane = threadIdx.x;
   const int g = lane / G, l = lane % G;
@@ -660,7 +745,11 @@ __global__ __launch_bounds__(64) void k_step(DevMech M, StepArgs A) {
         eval_cell<G, true, false>(M, L, l, p, yl, F, wd, 1.0 / (GAMMA * h));
         int mystep;
         double invd;
-        const bool ok = gj_factor<G>(L.J, l, n, mystep, invd);
+        bool ok;
+        if constexpr (G <= 32)
+          ok = gj_factor_reg<G>(L.J, L.wa, l, n, mystep, invd);
+        else
+          ok = gj_factor<G>(L.J, l, n, mystep, invd);
         if (!ok) {
           status = CELL_SINGULAR;
           end = true;
