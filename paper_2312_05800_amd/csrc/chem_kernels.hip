@@ -525,19 +525,32 @@ __device__ __forceinline__ bool gj_factor_reg(double *A, double *pbuf, int l, in
       invd = inv;
     }
     const double m = isp ? 0.0 : r[0] * inv;
+    double pr[G];
 #pragma unroll
-    for (int i = 1; i < G; ++i) r[i] = fma(-m, pbuf[i], r[i]);
+    for (int i = 1; i < G; ++i) pr[i] = pbuf[i];
+    // all reads of the pivot row in flight together, then the updates
+    __builtin_amdgcn_sched_group_barrier(0x100, G / 2, 0);
+    __builtin_amdgcn_sched_group_barrier(0x002, 4 * G, 0);
+#pragma unroll
+    for (int i = 1; i < G; ++i) r[i] = fma(-m, pr[i], r[i]);
     const double c0 = isp ? 1.0 : -m;
 #pragma unroll
     for (int i = 0; i < G - 1; ++i) r[i] = r[i + 1];
     r[G - 1] = c0;
     wave_sync();  // every lane has read pbuf before the next pivot row goes there
   }
-  // after n rotations slot i holds column (n + i) mod G
+  // after n rotations slot i holds column (n + i) mod G: G - n more put
+  // column i back in slot i, so the stores take constant offsets
+  for (int t = n; t < G; ++t) {
+    const double c0 = r[0];
 #pragma unroll
-  for (int i = 0; i < G; ++i) {
-    const int c = (n + i) & (G - 1);
-    if (real && c < n) rowp[c] = r[i];
+    for (int i = 0; i < G - 1; ++i) r[i] = r[i + 1];
+    r[G - 1] = c0;
+  }
+  if (real) {
+#pragma unroll
+    for (int i = 0; i < G; ++i)
+      if (i < n) rowp[i] = r[i];
   }
   wave_sync();
   return ok;
