@@ -239,6 +239,25 @@ chem_status ann_step(ann_model *m, const chem_mech *mech, chem_batch batch, doub
                      int64_t *n_fallback, const ann_step_opts *opts,
                      const chem_step_opts *fb_opts, void *stream);
 
+/* ann_step for callers that cannot allocate device memory: code being
+ * captured into a HIP graph, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same kernels, arguments, results and error behaviour as
+ * ann_step, but the inference workspace and the fallback list live in a
+ * file-scope device array of 64 MiB (one per GPU the library runs on, held
+ * until the process ends); the call makes no hipMalloc, hipFree or other
+ * allocating call.  All cells of a call must fit in it as one chunk: a
+ * batch larger than the network's capacity (7 999 cells for the
+ * 32-1600-800-400-30 network: 64 MiB over its 8.4 KB of per-cell
+ * activations, E4M3 rows and fallback entry) is
+ * rejected with CHEM_EINVAL, and chem_last_error() states the maximum.  The
+ * model and the mechanism must be on the current device.  Calls on one GPU
+ * share the array, so calls that overlap in time (other streams, other
+ * threads) race; calls ordered on one stream do not. */
+chem_status ann_step_noalloc(ann_model *m, const chem_mech *mech, chem_batch batch, double dt,
+                             double *T, const double *p, double *Y, double *RR, uint8_t *flags,
+                             int64_t *n_fallback, const ann_step_opts *opts,
+                             const chem_step_opts *fb_opts, void *stream);
+
 typedef struct {
   float lr, beta1, beta2, eps;
 } ann_train_opts;

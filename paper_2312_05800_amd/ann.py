@@ -43,6 +43,8 @@ def _prototypes(L):
     L.ann_fit_norm.argtypes = [_P, Batch, _P, _P, _P, _P, C.c_float, C.c_double, _P]
     L.ann_forward.argtypes = [_P, Batch, _P, _P, _P, _P, _P]
     L.ann_step.argtypes = [_P, _P, Batch, C.c_double, _P, _P, _P, _P, _P, _P, _P, _P, _P]
+    L.ann_step_noalloc.argtypes = [_P, _P, Batch, C.c_double, _P, _P, _P, _P, _P, _P, _P, _P,
+                                   _P]
     L.ann_train_step.argtypes = [_P, Batch, _P, _P, _P, _P, _P, _P, _P, _P]
     L.ann_num_steps.argtypes = [_P]
     L.ann_num_steps.restype = C.c_int64
@@ -191,9 +193,11 @@ class AnnModel:
         return U
 
     def step(self, mech, dt, T, p, Y, RR=None, flags=None, n_fallback=None, residual_tol=1e-6,
-             ood_margin=0.05, fallback=True, fb_opts=None, stream=None):
+             ood_margin=0.05, fallback=True, fb_opts=None, stream=None, noalloc=False):
         """Surrogate chemistry step, in place on T and Y.  RR ([K, ld] float64),
-        flags ([n] uint8) and n_fallback ([1] int64) are optional outputs."""
+        flags ([n] uint8) and n_fallback ([1] int64) are optional outputs.
+        noalloc=True calls ann_step_noalloc (workspace in the library's static
+        device array; the batch must fit in it)."""
         import torch
         n = T.shape[0]
         ld = _soa(Y, mech.K, n, "Y")
@@ -202,7 +206,8 @@ class AnnModel:
         o = StepOptsANN(float(residual_tol), float(ood_margin), 1 if fallback else 0, 0.0)
         fo = _opts(fb_opts)
         f64 = torch.float64
-        check("ann_step", lib().ann_step(
+        fn = "ann_step_noalloc" if noalloc else "ann_step"
+        check(fn, getattr(lib(), fn)(
             self.handle, mech.handle, Batch(n, ld), float(dt), _vec(T, n, "T", f64),
             _vec(p, n, "p", f64), _dptr(Y, f64, "Y"), _dptr(RR, f64, "RR"),
             _vec(flags, n, "flags", torch.uint8),

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "ann_internal.h"
@@ -99,15 +100,24 @@ int fp8_n2p(const ann_model *m) { return (m->L[1].dout + 31) / 32 * 32; }
 int fp8_kq1(const ann_model *m) { return (m->L[1].dinp + 127) / 128 * 128; }
 int fp8_k3p(const ann_model *m) { return (fp8_n2p(m) + 127) / 128 * 128; }
 
-chem_status grow_infer(ann_model *m, int64_t n) {
-  const int64_t need = n < CHUNK ? n : CHUNK;
-  if (m->wi.cap >= need) return CHEM_OK;
-  if (m->graph_refs > 0) {
-    set_error("ann: the inference workspace is held by a captured step (destroy its graphs "
-              "before a call with more cells)");
-    return CHEM_EINVAL;
-  }
-  const int64_t cap = need;
+// The inference workspace of cap cells: input rows, activations, network
+// output, out-of-distribution bytes, the fallback count and (no-allocation
+// step only) the fallback list.
+struct InferWs {
+  int64_t cap = 0;  // rows between K-blocks of the K-blocked activations
+  u16 *X = nullptr, *H[3] = {};
+  float *U = nullptr;
+  uint8_t *ood = nullptr;
+  unsigned long long *fb_count = nullptr;
+  uint8_t *H1q = nullptr, *H2q = nullptr;  // E4M3 activations, rows padded with zeros
+  size_t q_bytes = 0;                      // bytes from H1q to the end of H2q
+  int32_t *fb_index = nullptr;
+};
+
+// Section offsets of a workspace of cap cells (fb_list: with a fallback list
+// of cap entries).  Returns the bytes needed; with base non-null, fills w.
+size_t infer_layout(const ann_model *m, int64_t cap, bool fb_list, unsigned char *base,
+                    InferWs *w) {
   size_t off = 0;
   auto sect = [&](size_t bytes) {
     size_t o = off;
@@ -122,6 +132,47 @@ chem_status grow_infer(ann_model *m, int64_t n) {
   const size_t oC = sect(64);
   const size_t oQ1 = sect((size_t)cap * fp8_kq1(m));
   const size_t oQ2 = sect((size_t)cap * fp8_k3p(m));
+  const size_t oF = fb_list ? sect((size_t)cap * 4) : 0;
+  if (base && w) {
+    w->cap = cap;
+    w->X = (u16 *)(base + oX);
+    for (int l = 0; l < 3; ++l) w->H[l] = (u16 *)(base + oH[l]);
+    w->U = (float *)(base + oU);
+    w->ood = base + oO;
+    w->fb_count = (unsigned long long *)(base + oC);
+    w->H1q = base + oQ1;
+    w->H2q = base + oQ2;
+    w->q_bytes = oQ2 - oQ1 + (size_t)cap * fp8_k3p(m);
+    w->fb_index = fb_list ? (int32_t *)(base + oF) : nullptr;
+  }
+  return off;
+}
+
+// The model's own (growable) inference workspace as a view.
+InferWs model_ws(const ann_model *m) {
+  InferWs w;
+  w.cap = m->wi.cap;
+  w.X = m->X;
+  for (int l = 0; l < 3; ++l) w.H[l] = m->H[l];
+  w.U = m->U;
+  w.ood = m->ood;
+  w.fb_count = m->fb_count;
+  w.H1q = m->H1q;
+  w.H2q = m->H2q;
+  w.fb_index = m->fb_index;
+  return w;
+}
+
+chem_status grow_infer(ann_model *m, int64_t n) {
+  const int64_t need = n < CHUNK ? n : CHUNK;
+  if (m->wi.cap >= need) return CHEM_OK;
+  if (m->graph_refs > 0) {
+    set_error("ann: the inference workspace is held by a captured step (destroy its graphs "
+              "before a call with more cells)");
+    return CHEM_EINVAL;
+  }
+  const int64_t cap = need;
+  const size_t off = infer_layout(m, cap, false, nullptr, nullptr);
   if (m->wi.base) (void)hipFree(m->wi.base);
   m->wi.base = nullptr;
   m->wi.cap = 0;
@@ -129,17 +180,18 @@ chem_status grow_infer(ann_model *m, int64_t n) {
     set_error("ann: cannot allocate %zu bytes of inference workspace", off);
     return CHEM_ENOMEM;
   }
-  unsigned char *b = (unsigned char *)m->wi.base;
-  m->X = (u16 *)(b + oX);
-  for (int l = 0; l < 3; ++l) m->H[l] = (u16 *)(b + oH[l]);
-  m->U = (float *)(b + oU);
-  m->ood = (uint8_t *)(b + oO);
-  m->fb_count = (unsigned long long *)(b + oC);
-  m->H1q = (uint8_t *)(b + oQ1);
-  m->H2q = (uint8_t *)(b + oQ2);
+  InferWs w;
+  infer_layout(m, cap, false, (unsigned char *)m->wi.base, &w);
+  m->X = w.X;
+  for (int l = 0; l < 3; ++l) m->H[l] = w.H[l];
+  m->U = w.U;
+  m->ood = w.ood;
+  m->fb_count = w.fb_count;
+  m->H1q = w.H1q;
+  m->H2q = w.H2q;
   // the E4M3 activation rows are padded to multiples of 128 bytes; the
   // padding is never written and must read as zero
-  if (hipMemset(b + oQ1, 0, oQ2 - oQ1 + (size_t)cap * fp8_k3p(m)) != hipSuccess) {
+  if (hipMemset(w.H1q, 0, w.q_bytes) != hipSuccess) {
     set_error("ann: cannot clear the E4M3 activation workspace");
     return CHEM_EHIP;
   }
@@ -560,15 +612,15 @@ bool tiled_path(const ann_model *m, int64_t n) {
 // keep_h1: write the first two layers' activations row-major to H[0], H[1]
 // (no fused first two layers, no K-blocked layouts), for the FP8 calibration
 // that reads their first n rows
-chem_status forward_chunk(ann_model *m, int64_t n, int64_t ld, const double *T, const double *p,
-                          const double *Y, float *U, int ldu, uint8_t *ood, float ood_margin,
-                          hipStream_t s, bool keep_h1 = false) {
+chem_status forward_chunk(ann_model *m, const InferWs &w, int64_t n, int64_t ld, const double *T,
+                          const double *p, const double *Y, float *U, int ldu, uint8_t *ood,
+                          float ood_margin, hipStream_t s, bool keep_h1 = false) {
   ann::FeatArgs fa{n, ld, T, p, Y, nullptr, m->n_out, m->L[0].dinp, m->nm.mu_in, m->nm.sd_in,
-                   m->nm.lambda, m->X, ood, m->nm.lo, m->nm.hi, ood_margin};
+                   m->nm.lambda, w.X, ood, m->nm.lo, m->nm.hi, ood_margin};
   chem_status st = ann::features(fa, s);
   if (st != CHEM_OK) return st;
   const bool tl = !keep_h1 && tiled_path(m, n);
-  const long cap = (long)m->wi.cap;  // rows between K-blocks of the activations
+  const long cap = (long)w.cap;  // rows between K-blocks of the activations
   if (!m->use_fp8 && m->wt_stale) {
     for (int l = 1; l <= 2; ++l)
       if ((st = ann::tile_bf16(m->L[l].doutp, m->L[l].dinp, m->Wb[l], m->Wt[l], s)) != CHEM_OK)
@@ -585,12 +637,12 @@ chem_status forward_chunk(ann_model *m, int64_t n, int64_t ld, const double *T, 
     g.M = (int)n;
     g.N = L0.doutp;
     g.K = L0.dinp;
-    g.A = m->X;
+    g.A = w.X;
     g.lda = L0.dinp;
     g.B = m->Wb[0];
     g.ldb = L0.dinp;
     g.bias = m->bm[0];
-    g.Cq = m->H1q;
+    g.Cq = w.H1q;
     g.ldcq = tl ? cap * 128 : m->kq1;
     g.tiled = tl ? ann::TILED_C : 0;
     g.qinv = 1.0f / m->sa[1];
@@ -599,13 +651,13 @@ chem_status forward_chunk(ann_model *m, int64_t n, int64_t ld, const double *T, 
     h.M = (int)n;
     h.N = m->n2p;
     h.K = m->kq1;
-    h.A8 = m->H1q;
+    h.A8 = w.H1q;
     h.lda = tl ? cap * 128 : m->kq1;
     h.B8 = tl ? m->Wq1t : m->Wq1;
     h.ldb = tl ? (long)m->n2p * 128 : m->kq1;
     h.bias = m->bq1;
     h.scale = m->sa[1] * m->sw[1];
-    h.Cq = m->H2q;
+    h.Cq = w.H2q;
     h.ldcq = tl ? cap * 128 : m->k3p;
     h.qinv = 1.0f / m->sa[2];
     h.tiled = tl ? (ann::TILED_A | ann::TILED_B | ann::TILED_C) : 0;
@@ -614,13 +666,13 @@ chem_status forward_chunk(ann_model *m, int64_t n, int64_t ld, const double *T, 
     q.M = (int)n;
     q.N = L2.doutp;
     q.K = m->k3p;
-    q.A8 = m->H2q;
+    q.A8 = w.H2q;
     q.lda = tl ? cap * 128 : m->k3p;
     q.B8 = tl ? m->Wq2t : m->Wq2;
     q.ldb = tl ? (long)L2.doutp * 128 : m->k3p;
     q.bias = m->bm[2];
     q.scale = m->sa[2] * m->sw[2];
-    q.Cb = m->H[2];
+    q.Cb = w.H[2];
     q.ldcb = L2.doutp;
     q.tiled = tl ? (ann::TILED_A | ann::TILED_B) : 0;
     // the output layer rides in the epilogue of the last hidden layer when
@@ -641,7 +693,7 @@ chem_status forward_chunk(ann_model *m, int64_t n, int64_t ld, const double *T, 
     o.M = (int)n;
     o.N = ldu;
     o.K = L3.dinp;
-    o.A = m->H[2];
+    o.A = w.H[2];
     o.lda = L3.dinp;
     o.B = m->Wb[3];
     o.ldb = L3.dinp;
@@ -650,7 +702,7 @@ chem_status forward_chunk(ann_model *m, int64_t n, int64_t ld, const double *T, 
     o.ldcf = ldu;
     return ann::gemm(o, true, true, ann::EPI_F32, s, "mlp_l4");
   }
-  const u16 *in = m->X;
+  const u16 *in = w.X;
   bool in_tiled = false;  // X (K = 32) is one K-block either way
   int l0 = 0;
   {
@@ -661,18 +713,18 @@ chem_status forward_chunk(ann_model *m, int64_t n, int64_t ld, const double *T, 
     f.M = (int)n;
     f.N = L1.doutp;
     f.K = L1.dinp;
-    f.X = m->X;
+    f.X = w.X;
     f.W1 = m->Wb[0];
     f.b1 = m->bm[0];
     f.W2p = m->W2p;
     f.ldw2 = (long)L1.doutp * 32;
     f.b2 = m->bm[1];
-    f.H = m->H[1];
+    f.H = w.H[1];
     f.ldh = tl ? cap * 32 : L1.doutp;
     f.tiled = tl;
     if (!keep_h1 && L0.dinp == 32 && L0.doutp == L1.dinp && ann::mlp12_ok(f)) {
       if ((st = ann::mlp12(f, s, "mlp_l12")) != CHEM_OK) return st;
-      in = m->H[1];
+      in = w.H[1];
       in_tiled = tl;
       l0 = 2;
     }
@@ -711,12 +763,12 @@ chem_status forward_chunk(ann_model *m, int64_t n, int64_t ld, const double *T, 
       // tiled path (L3's output feeds the 32-wide output layer row-major)
       const bool ct = tl && l < 2;
       g.N = L.doutp;
-      g.Cb = m->H[l];
+      g.Cb = w.H[l];
       g.ldcb = ct ? cap * 32 : L.doutp;
       g.tiled |= ct ? ann::TILED_C : 0;
       static const char *lab[3] = {"mlp_l1", "mlp_l2", "mlp_l3"};
       st = ann::gemm(g, true, true, ann::EPI_GELU, s, lab[l]);
-      in = m->H[l];
+      in = w.H[l];
       in_tiled = ct;
     } else {
       g.N = ldu;
@@ -753,8 +805,8 @@ extern "C" chem_status ann_forward(ann_model *m, chem_batch batch, const double 
   hipStream_t s = (hipStream_t)stream;
   for (int64_t c0 = 0; c0 < batch.n; c0 += m->wi.cap) {
     const int64_t nc = (batch.n - c0 < m->wi.cap) ? batch.n - c0 : m->wi.cap;
-    st = forward_chunk(m, nc, batch.ld, T + c0, p + c0, Y + c0, U + c0 * m->n_out, m->n_out,
-                       nullptr, 0.0f, s);
+    st = forward_chunk(m, model_ws(m), nc, batch.ld, T + c0, p + c0, Y + c0, U + c0 * m->n_out,
+                       m->n_out, nullptr, 0.0f, s);
     if (st != CHEM_OK) return st;
   }
   return CHEM_OK;
@@ -794,54 +846,61 @@ __global__ void k_add_counter(const unsigned long long *c, int64_t *total, int f
 }
 }  // namespace
 
-extern "C" chem_status ann_step(ann_model *m, const chem_mech *mech, chem_batch batch, double dt,
-                                double *T, const double *p, double *Y, double *RR,
-                                uint8_t *flags, int64_t *n_fallback, const ann_step_opts *opts,
-                                const chem_step_opts *fb_opts, void *stream) {
+namespace {
+
+// Argument checks shared by the step entry points.
+chem_status step_check(const char *fn, ann_model *m, const chem_mech *mech, chem_batch batch,
+                       double dt, const double *T, const double *p, const double *Y,
+                       const ann_step_opts *opts, ann_step_opts *o) {
   if (opts && opts->audit_fraction != 0.0f) {
-    set_error("ann_step: audit_fraction is reserved and must be 0");
+    set_error("%s: audit_fraction is reserved and must be 0", fn);
     return CHEM_EINVAL;
   }
-  chem_status st = check_model("ann_step", m);
+  chem_status st = check_model(fn, m);
   if (st != CHEM_OK) return st;
   if (!mech) {
-    set_error("ann_step: null mechanism");
+    set_error("%s: null mechanism", fn);
     return CHEM_EINVAL;
   }
   if (!m->has_norm) {
-    set_error("ann_step: normalisation statistics are not set");
+    set_error("%s: normalisation statistics are not set", fn);
     return CHEM_EMODEL;
   }
   if (m->n_out != mech->K || m->n_in != mech->K + 2) {
-    set_error("ann_step: network has %d inputs / %d outputs, mechanism has K=%d", m->n_in,
+    set_error("%s: network has %d inputs / %d outputs, mechanism has K=%d", fn, m->n_in,
               m->n_out, mech->K);
     return CHEM_EMODEL;
   }
   if (batch.n < 0 || batch.ld < batch.n || batch.n > INT32_MAX || !(dt > 0.0) || !isfinite(dt)) {
-    set_error("ann_step: bad batch or dt");
+    set_error("%s: bad batch or dt", fn);
     return CHEM_EINVAL;
   }
-  if (batch.n == 0) return CHEM_OK;
-  if (!T || !p || !Y) {
-    set_error("ann_step: T, p and Y must be non-null");
+  if (batch.n > 0 && (!T || !p || !Y)) {
+    set_error("%s: T, p and Y must be non-null", fn);
     return CHEM_EINVAL;
   }
-  ann_step_opts o{1e-6f, 0.05f, 1, 0.0f};
-  if (opts) o = *opts;
-  if (!(o.residual_tol >= 0.0f) || !(o.ood_margin >= 0.0f)) {
-    set_error("ann_step: residual_tol and ood_margin must be >= 0");
+  *o = ann_step_opts{1e-6f, 0.05f, 1, 0.0f};
+  if (opts) *o = *opts;
+  if (!(o->residual_tol >= 0.0f) || !(o->ood_margin >= 0.0f)) {
+    set_error("%s: residual_tol and ood_margin must be >= 0", fn);
     return CHEM_EINVAL;
   }
-  const StepOpts fo = resolve_opts(fb_opts);
-  st = step_prepare(m, batch.n, o.fallback != 0);
-  if (st != CHEM_OK) return st;
-  hipStream_t s = (hipStream_t)stream;
-  hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, s, m->fb_count);
+  return CHEM_OK;
+}
+
+// The step over batch.n cells in chunks of w.cap, with the fallback list
+// fb_index (n entries, or null without fallback) and count w.fb_count.
+chem_status step_impl(ann_model *m, const chem_mech *mech, chem_batch batch, double dt, double *T,
+                      const double *p, double *Y, double *RR, uint8_t *flags,
+                      int64_t *n_fallback, const ann_step_opts &o, const StepOpts &fo,
+                      const InferWs &w, int32_t *fb_index, hipStream_t s) {
+  chem_status st;
+  hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, s, w.fb_count);
   // a step other than the one the network was trained for: every cell falls back
   const bool dt_mismatch = fabs(dt - m->nm.dt_model) > 1e-6 * m->nm.dt_model;
-  for (int64_t c0 = 0; c0 < batch.n; c0 += m->wi.cap) {
-    const int64_t nc = (batch.n - c0 < m->wi.cap) ? batch.n - c0 : m->wi.cap;
-    st = forward_chunk(m, nc, batch.ld, T + c0, p + c0, Y + c0, m->U, m->L[3].doutp, m->ood,
+  for (int64_t c0 = 0; c0 < batch.n; c0 += w.cap) {
+    const int64_t nc = (batch.n - c0 < w.cap) ? batch.n - c0 : w.cap;
+    st = forward_chunk(m, w, nc, batch.ld, T + c0, p + c0, Y + c0, w.U, m->L[3].doutp, w.ood,
                        o.ood_margin, s);
     if (st != CHEM_OK) return st;
     ann::PostArgs pa{};
@@ -853,29 +912,120 @@ extern "C" chem_status ann_step(ann_model *m, const chem_mech *mech, chem_batch 
     pa.Y = Y + c0;
     pa.RR = RR ? RR + c0 : nullptr;
     pa.flags = flags ? flags + c0 : nullptr;
-    pa.U = m->U;
+    pa.U = w.U;
     pa.doutp = m->L[3].doutp;
     pa.nm = m->nm;
     pa.n_in = m->n_in;
     pa.residual_tol = o.residual_tol;
     pa.ood_margin = o.ood_margin;
-    pa.ood = m->ood;
+    pa.ood = w.ood;
     pa.force_flag = dt_mismatch ? 1 : 0;
-    pa.fb_index = o.fallback ? m->fb_index : nullptr;
-    pa.fb_count = m->fb_count;
+    pa.fb_index = o.fallback ? fb_index : nullptr;
+    pa.fb_count = w.fb_count;
     pa.index_base = c0;
     st = ann::post(mech->d, pa, s);
     if (st != CHEM_OK) return st;
   }
   if (o.fallback) {
     st = launch_step(mech, batch.n, batch.ld, dt, nullptr, T, p, Y, RR, nullptr, nullptr, fo,
-                     m->fb_index, s, m->fb_count, flags);
+                     fb_index, s, w.fb_count, flags);
     if (st != CHEM_OK) return st;
   }
-  if (n_fallback) hipLaunchKernelGGL(k_add_counter, dim3(1), dim3(64), 0, s, m->fb_count,
+  if (n_fallback) hipLaunchKernelGGL(k_add_counter, dim3(1), dim3(64), 0, s, w.fb_count,
                                      n_fallback, 1);
   CHEM_HIP(hipGetLastError());
   return CHEM_OK;
+}
+
+// Workspace of the no-allocation step: one array per GPU, resident for the
+// life of the process.  Host code reaches it only through the address that
+// hipGetSymbolAddress returns on each device (the symbol's name is a host
+// stand-in there, not a device address).
+constexpr size_t SCRATCH_BYTES = (size_t)64 << 20;
+constexpr int SCRATCH_MAXDEV = 64;
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+void *g_scratch[SCRATCH_MAXDEV] = {};
+std::mutex g_scratch_mu;
+
+chem_status scratch_address(int dev, void **out) {
+  if (dev < 0 || dev >= SCRATCH_MAXDEV) {
+    set_error("ann_step_noalloc: device %d beyond the %d supported", dev, SCRATCH_MAXDEV);
+    return CHEM_EUNSUPPORTED;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return hip_fail(e, "ann_step_noalloc: hipGetSymbolAddress");
+    g_scratch[dev] = ptr;
+  }
+  *out = g_scratch[dev];
+  return CHEM_OK;
+}
+
+__global__ void k_fill_zero(unsigned char *p, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+
+}  // namespace
+
+extern "C" chem_status ann_step(ann_model *m, const chem_mech *mech, chem_batch batch, double dt,
+                                double *T, const double *p, double *Y, double *RR,
+                                uint8_t *flags, int64_t *n_fallback, const ann_step_opts *opts,
+                                const chem_step_opts *fb_opts, void *stream) {
+  ann_step_opts o;
+  chem_status st = step_check("ann_step", m, mech, batch, dt, T, p, Y, opts, &o);
+  if (st != CHEM_OK || batch.n == 0) return st;
+  const StepOpts fo = resolve_opts(fb_opts);
+  st = step_prepare(m, batch.n, o.fallback != 0);
+  if (st != CHEM_OK) return st;
+  return step_impl(m, mech, batch, dt, T, p, Y, RR, flags, n_fallback, o, fo, model_ws(m),
+                   m->fb_index, (hipStream_t)stream);
+}
+
+extern "C" chem_status ann_step_noalloc(ann_model *m, const chem_mech *mech, chem_batch batch,
+                                        double dt, double *T, const double *p, double *Y,
+                                        double *RR, uint8_t *flags, int64_t *n_fallback,
+                                        const ann_step_opts *opts,
+                                        const chem_step_opts *fb_opts, void *stream) {
+  ann_step_opts o;
+  chem_status st = step_check("ann_step_noalloc", m, mech, batch, dt, T, p, Y, opts, &o);
+  if (st != CHEM_OK || batch.n == 0) return st;
+  int dev = -1;
+  CHEM_HIP(hipGetDevice(&dev));
+  if (dev != m->device || dev != mech->device) {
+    set_error("ann_step_noalloc: the model (device %d) and mechanism (device %d) must be on "
+              "the current device (%d)", m->device, mech->device, dev);
+    return CHEM_EINVAL;
+  }
+  // the largest chunk whose workspace and fallback list fit in the scratch
+  // array: one chunk, so every cell of the call must fit
+  int64_t cap = 0, hi = (int64_t)(SCRATCH_BYTES / 8);  // layout grows with cap
+  while (hi - cap > 1) {
+    const int64_t mid = cap + (hi - cap) / 2;
+    if (infer_layout(m, mid, true, nullptr, nullptr) <= SCRATCH_BYTES) cap = mid;
+    else hi = mid;
+  }
+  if (batch.n > cap) {
+    set_error("ann_step_noalloc: %lld cells exceed the %lld this network fits in the %zu-byte "
+              "scratch array", (long long)batch.n, (long long)cap, SCRATCH_BYTES);
+    return CHEM_EINVAL;
+  }
+  void *base = nullptr;
+  if ((st = scratch_address(dev, &base)) != CHEM_OK) return st;
+  InferWs w;
+  infer_layout(m, batch.n, true, (unsigned char *)base, &w);
+  hipStream_t s = (hipStream_t)stream;
+  if (m->use_fp8) {
+    // the E4M3 rows' padding must read as zero; earlier calls may have left
+    // other data there
+    hipLaunchKernelGGL(k_fill_zero, dim3(1024), dim3(256), 0, s, w.H1q, w.q_bytes);
+    CHEM_HIP(hipGetLastError());
+  }
+  const StepOpts fo = resolve_opts(fb_opts);
+  return step_impl(m, mech, batch, dt, T, p, Y, RR, flags, n_fallback, o, fo, w, w.fb_index, s);
 }
 
 extern "C" chem_status ann_train_step(ann_model *m, chem_batch batch, const double *T,
@@ -1153,7 +1303,8 @@ extern "C" chem_status ann_quantize_fp8(ann_model *m, chem_batch calib, const do
   if ((st = grow_infer(m, n)) != CHEM_OK) return st;
   const bool prev = m->use_fp8;
   m->use_fp8 = false;  // calibrate on the BF16 activations
-  st = forward_chunk(m, n, calib.ld, T, p, Y, m->U, m->L[3].doutp, nullptr, 0.0f, s, true);
+  st = forward_chunk(m, model_ws(m), n, calib.ld, T, p, Y, m->U, m->L[3].doutp, nullptr, 0.0f, s,
+                     true);
   m->use_fp8 = prev;
   if (st != CHEM_OK) return st;
   m->n2p = fp8_n2p(m);
