@@ -260,19 +260,36 @@ chem_status ann_step_noalloc(ann_model *m, const chem_mech *mech, chem_batch bat
 
 typedef struct {
   float lr, beta1, beta2, eps;
+  /* weights of the physics terms of the loss (Sec. 3.2: mass-fraction sum,
+   * energy and heat release rate); 0 leaves the L1 loss of Eq. (Loss) alone */
+  float w_mass, w_energy, w_hrr;
 } ann_train_opts;
 
 /* One optimisation step on a batch of B state pairs (B a multiple of 32):
  * features and targets from T, p, Y0 and Y1 (Y0 integrated over dt_model),
  * gathered through index (device int64 [B], nullable: cells 0..B-1 with ld);
- * forward pass keeping activations; L1 loss (mean over samples and outputs)
- * written to *loss (device float); backward pass (BF16 operands, FP32
- * accumulation, deterministic bias reductions); Adam with bias correction on
- * the FP32 master weights, refreshing the BF16 copies.  lr = 0 computes the
- * gradients only (no update, step count unchanged). */
-chem_status ann_train_step(ann_model *m, chem_batch batch, const double *T, const double *p,
-                           const double *Y0, const double *Y1, const int64_t *index,
-                           const ann_train_opts *opts, float *loss, void *stream);
+ * forward pass keeping activations; L1 loss (mean over samples and outputs,
+ * Eq. (Loss)) written to *loss (device float); backward pass (BF16 operands,
+ * FP32 accumulation, deterministic bias reductions); Adam with bias
+ * correction on the FP32 master weights, refreshing the BF16 copies.  lr = 0
+ * computes the gradients only (no update, step count unchanged).
+ * Physics terms (Sec. 3.2 names the three principles, not their form; the
+ * reading here): with dY = sd_out u + mu_out the predicted change and
+ * e = (u - u*) sd_out its error, three L1 penalties |s_t| / D_t, averaged
+ * over the batch: s = sum_k dY_k (the mass fractions keep summing to one),
+ * s = sum_k h_k(T1) e_k (the state keeps the reference step's enthalpy at
+ * its final temperature T1) and s = sum_k h_k(298.15 K) e_k (the heat
+ * released over the step equals the reference's), h_k in J/kg from the
+ * mechanism's NASA polynomials and D_t = sum_k |a_tk| sd_out,k the size of
+ * the functional for errors of one standard deviation.  With any weight
+ * non-zero or terms non-null, mech (the network's species) and T1 (device
+ * [ld], gathered like T) are required, *loss becomes the L1 loss plus the
+ * weighted terms and terms (device float [3], nullable) receives the three
+ * unweighted batch means. */
+chem_status ann_train_step(ann_model *m, const chem_mech *mech, chem_batch batch,
+                           const double *T, const double *p, const double *Y0,
+                           const double *Y1, const double *T1, const int64_t *index,
+                           const ann_train_opts *opts, float *loss, float *terms, void *stream);
 int64_t ann_num_steps(const ann_model *m);
 /* FP8 variant of inference: the two hidden-to-hidden layers run on OCP FP8
  * E4M3 MFMA with per-tensor scales amax/448 -- activation scales from a BF16

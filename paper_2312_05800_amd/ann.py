@@ -28,7 +28,8 @@ class StepOptsANN(C.Structure):
 
 class TrainOpts(C.Structure):
     _fields_ = [("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float),
-                ("eps", C.c_float)]
+                ("eps", C.c_float), ("w_mass", C.c_float), ("w_energy", C.c_float),
+                ("w_hrr", C.c_float)]
 
 
 def _prototypes(L):
@@ -45,7 +46,7 @@ def _prototypes(L):
     L.ann_step.argtypes = [_P, _P, Batch, C.c_double, _P, _P, _P, _P, _P, _P, _P, _P, _P]
     L.ann_step_noalloc.argtypes = [_P, _P, Batch, C.c_double, _P, _P, _P, _P, _P, _P, _P, _P,
                                    _P]
-    L.ann_train_step.argtypes = [_P, Batch, _P, _P, _P, _P, _P, _P, _P, _P]
+    L.ann_train_step.argtypes = [_P, _P, Batch, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]
     L.ann_num_steps.argtypes = [_P]
     L.ann_num_steps.restype = C.c_int64
     L.ann_quantize_fp8.argtypes = [_P, Batch, _P, _P, _P, _P]
@@ -236,9 +237,13 @@ class AnnModel:
         return Graph(h, (self, mech, T, p, Y, RR, flags, n_fallback))
 
     def train_step(self, T, p, Y0, Y1, loss, index=None, B=None, lr=1e-3, beta1=0.9,
-                   beta2=0.999, eps=1e-8, stream=None):
+                   beta2=0.999, eps=1e-8, stream=None, mech=None, T1=None, w_phys=(0.0, 0.0, 0.0),
+                   terms=None):
         """One Adam step on B pairs (cells index[0..B) of the [K, ld] arrays, or
-        the first B cells).  loss: device float32 [1] receiving the L1 loss."""
+        the first B cells).  loss: device float32 [1] receiving the loss.
+        w_phys = (mass, energy, heat release) weights of the physics terms;
+        with any non-zero, or terms (device float32 [3]) given, mech and T1
+        (the reference final temperatures, like T) are needed."""
         import torch
         if index is not None:
             # cells are gathered through the index: every array must hold the
@@ -252,9 +257,14 @@ class AnnModel:
             ld = _soa(Y0, Y0.shape[0], B, "Y0")
         if Y1.shape[0] != Y0.shape[0] or _soa(Y1, Y0.shape[0], ncell, "Y1") != ld:
             raise ValueError("Y1 must have the shape and leading dimension of Y0")
-        o = TrainOpts(float(lr), float(beta1), float(beta2), float(eps))
+        wm, we, wh = (float(x) for x in w_phys)
+        o = TrainOpts(float(lr), float(beta1), float(beta2), float(eps), wm, we, wh)
         f64 = torch.float64
         check("ann_train_step", lib().ann_train_step(
-            self.handle, Batch(B, ld), _vec(T, ncell, "T", f64), _vec(p, ncell, "p", f64),
-            _dptr(Y0, f64, "Y0"), _dptr(Y1, f64, "Y1"), _vec(index, B, "index", torch.int64),
-            C.byref(o), _vec(loss, 1, "loss", torch.float32), _stream(stream)))
+            self.handle, None if mech is None else mech.handle, Batch(B, ld),
+            _vec(T, ncell, "T", f64), _vec(p, ncell, "p", f64),
+            _dptr(Y0, f64, "Y0"), _dptr(Y1, f64, "Y1"),
+            None if T1 is None else _vec(T1, ncell, "T1", f64),
+            _vec(index, B, "index", torch.int64),
+            C.byref(o), _vec(loss, 1, "loss", torch.float32),
+            None if terms is None else _vec(terms, 3, "terms", torch.float32), _stream(stream)))

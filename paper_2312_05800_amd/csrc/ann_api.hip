@@ -68,6 +68,7 @@ struct ann_model {
   u16 *tX = nullptr, *tH[3] = {}, *tGb[ann::NLAYER] = {};
   float *tZ[3] = {}, *tU = nullptr, *tUt = nullptr, *tGf[ann::NLAYER] = {};
   double *loss_part = nullptr;
+  double *phys_part = nullptr;  // [PHYS_PARTS][3] partial sums of the physics terms
   double *col_part = nullptr;  // [COLSUM_PARTS][max dout] bias-gradient partials
   float *wg_part = nullptr;    // split-K partial weight gradients
   // FP8 inference of the hidden-to-hidden layers (L2, L3)
@@ -231,6 +232,7 @@ chem_status grow_train(ann_model *m, int64_t B) {
     oGf[l] = sect((size_t)B * m->L[l].doutp * 4);
   }
   const size_t oL = sect(LOSS_PARTS * 8);
+  const size_t oP = sect(ann::PHYS_PARTS * 3 * 8);
   size_t col_n = 0, wg_n = 0;
   for (int l = 0; l < 4; ++l) {
     const ann::Layer &L = m->L[l];
@@ -249,6 +251,7 @@ chem_status grow_train(ann_model *m, int64_t B) {
     return CHEM_ENOMEM;
   }
   unsigned char *b = (unsigned char *)m->wt.base;
+  m->phys_part = (double *)(b + oP);
   m->tX = (u16 *)(b + oX);
   for (int l = 0; l < 3; ++l) {
     m->tH[l] = (u16 *)(b + oH[l]);
@@ -1028,15 +1031,27 @@ extern "C" chem_status ann_step_noalloc(ann_model *m, const chem_mech *mech, che
   return step_impl(m, mech, batch, dt, T, p, Y, RR, flags, n_fallback, o, fo, w, w.fb_index, s);
 }
 
-extern "C" chem_status ann_train_step(ann_model *m, chem_batch batch, const double *T,
-                                      const double *p, const double *Y0, const double *Y1,
-                                      const int64_t *index, const ann_train_opts *opts,
-                                      float *loss, void *stream) {
+extern "C" chem_status ann_train_step(ann_model *m, const chem_mech *mech, chem_batch batch,
+                                      const double *T, const double *p, const double *Y0,
+                                      const double *Y1, const double *T1, const int64_t *index,
+                                      const ann_train_opts *opts, float *loss, float *terms,
+                                      void *stream) {
   chem_status st = check_model("ann_train_step", m);
   if (st != CHEM_OK) return st;
   if (!m->has_norm) {
     set_error("ann_train_step: normalisation statistics are not set");
     return CHEM_EMODEL;
+  }
+  const bool phys = opts && (opts->w_mass != 0.0f || opts->w_energy != 0.0f ||
+                             opts->w_hrr != 0.0f || terms);
+  if (opts && (!(opts->w_mass >= 0.0f) || !(opts->w_energy >= 0.0f) || !(opts->w_hrr >= 0.0f))) {
+    set_error("ann_train_step: physics weights must be >= 0");
+    return CHEM_EINVAL;
+  }
+  if (phys && (!mech || mech->K != m->n_out || !T1)) {
+    set_error("ann_train_step: the physics terms need the mechanism of the network's %d species "
+              "and the reference final temperatures T1", m->n_out);
+    return CHEM_EINVAL;
   }
   const int64_t B = batch.n;
   if (B < 32 || B % 32 != 0 || B > (1 << 24) || (!index && batch.ld < B) || !T || !p || !Y0 ||
@@ -1093,6 +1108,25 @@ extern "C" chem_status ann_train_step(ann_model *m, chem_batch batch, const doub
   st = ann::l1_grad(B, K, m->L[3].doutp, m->tU, m->tUt, m->tGb[3], m->tGf[3], m->loss_part,
                     LOSS_PARTS, loss, s);
   if (st != CHEM_OK) return st;
+  if (phys) {
+    ann::PhysArgs pa{};
+    pa.n = B;
+    pa.ld = batch.ld;
+    pa.K = K;
+    pa.doutp = m->L[3].doutp;
+    pa.U = m->tU;
+    pa.Ut = m->tUt;
+    pa.Gf = m->tGf[3];
+    pa.Gb = m->tGb[3];
+    pa.mu = m->nm.mu_out;
+    pa.sd = m->nm.sd_out;
+    pa.T1 = T1;
+    pa.index = index;
+    pa.w[0] = opts->w_mass;
+    pa.w[1] = opts->w_energy;
+    pa.w[2] = opts->w_hrr;
+    if ((st = ann::phys_grad(pa, mech->d, m->phys_part, loss, terms, s)) != CHEM_OK) return st;
+  }
   // backward: wgrad, bias grad, dgrad (through GELU') per layer
   for (int l = 3; l >= 0; --l) {
     const ann::Layer &L = m->L[l];

@@ -143,6 +143,25 @@ chem_status targets(const TargetArgs &a, hipStream_t s);
 
 chem_status l1_grad(int64_t n, int K, int doutp, const float *U, const float *Ut, u16 *Gb,
                     float *Gf, double *loss_part, int nparts, float *loss, hipStream_t s);
+
+// Physics terms of the training loss (mass-fraction sum, energy at the
+// reference final temperature T1, heat release at 298.15 K): their gradient
+// is added to Gf (and Gb refreshed from it), w-weighted batch means are
+// added to *loss, the unweighted means written to terms[3] (nullable).
+struct PhysArgs {
+  int64_t n, ld;
+  int K, doutp;
+  const float *U, *Ut;  // network output and targets, z-space [n][doutp]
+  float *Gf;
+  u16 *Gb;
+  const float *mu, *sd;  // output statistics
+  const double *T1;      // [ld] reference final temperature, gathered through index
+  const int64_t *index;
+  float w[3];
+};
+constexpr int PHYS_PARTS = 64;
+chem_status phys_grad(const PhysArgs &a, const chem::DevMech &M, double *part, float *loss,
+                      float *terms, hipStream_t s);
 // out[j] = sum over the M rows of X[:, j]; part: COLSUM_PARTS * N doubles
 constexpr int COLSUM_PARTS = 64;
 chem_status colsum(int64_t M, int N, const float *X, long ldx, float *out, double *part,

@@ -1352,6 +1352,82 @@ __global__ void k_l1(int64_t n, int K, int doutp, const float *U, const float *U
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
+// h_k(T) in J/kg from the folded h/RT polynomial of species k's range at T.
+__device__ __forceinline__ double species_h(const chem::DevMech &M, int k, double T) {
+  const double *c = (T <= M.Tmid[k] ? M.nasa_h : M.nasa_hh) + 7 * k;
+  const double hRT = c[0] + T * (c[1] + T * (c[2] + T * (c[3] + T * c[4]))) + c[5] / T;
+  return 8.314462618 * T * hRT * M.invW[k];
+}
+
+// One sample per thread.  With dY = sd u + mu the predicted change and
+// e = (u - u*) sd its error (FP64 from the FP32 u), each term is an L1
+// penalty |s_t| / D_t on a linear functional s_t: the sum of dY (weights 1),
+// sum_k h_k(T1) e_k and sum_k h_k(298.15 K) e_k; D_t = sum_k |a_tk| sd_k is
+// the functional's size for errors of one standard deviation.  d/du_k of
+// w_t |s_t| / (D_t n) is w_t sign(s_t) a_tk sd_k / (D_t n).
+__global__ void k_phys(PhysArgs a, chem::DevMech M, double *part) {
+  __shared__ double red[3][256];
+  constexpr double TREF = 298.15;
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = a.index ? a.index[i] : i;
+    const double T1 = a.T1 ? a.T1[c] : TREF;
+    const float *u = a.U + i * a.doutp, *ut = a.Ut + i * a.doutp;
+    double sm = 0.0, se = 0.0, sh = 0.0, dm = 0.0, de = 0.0, dh = 0.0;
+    for (int k = 0; k < a.K; ++k) {
+      const double sd = a.sd[k], mu = a.mu[k];
+      const double dY = sd * (double)u[k] + mu;
+      const double e = ((double)u[k] - (double)ut[k]) * sd;
+      const double h1 = species_h(M, k, T1), h0 = species_h(M, k, TREF);
+      sm += dY;
+      dm += sd;
+      se += h1 * e;
+      de += fabs(h1) * sd;
+      sh += h0 * e;
+      dh += fabs(h0) * sd;
+    }
+    acc[0] += fabs(sm) / dm;
+    acc[1] += fabs(se) / de;
+    acc[2] += fabs(sh) / dh;
+    const double inv_n = 1.0 / (double)a.n;
+    const double gm = a.w[0] * ((sm > 0.0) - (sm < 0.0)) / dm * inv_n;
+    const double ge = a.w[1] * ((se > 0.0) - (se < 0.0)) / de * inv_n;
+    const double gh = a.w[2] * ((sh > 0.0) - (sh < 0.0)) / dh * inv_n;
+    float *gf = a.Gf + i * a.doutp;
+    u16 *gb = a.Gb + i * a.doutp;
+    for (int k = 0; k < a.K; ++k) {
+      const double sd = a.sd[k];
+      const double g = (gm + ge * species_h(M, k, T1) + gh * species_h(M, k, TREF)) * sd;
+      const float v = gf[k] + (float)g;
+      gf[k] = v;
+      gb[k] = f2bf(v);
+    }
+  }
+  for (int t = 0; t < 3; ++t) red[t][threadIdx.x] = acc[t];
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off)
+      for (int t = 0; t < 3; ++t) red[t][threadIdx.x] += red[t][threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x < 3) part[blockIdx.x * 3 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// Batch means of the three terms (partials added in block order); the
+// weighted sum joins the L1 loss.
+__global__ void k_phys_final(const double *part, int nparts, double inv_n, float w0, float w1,
+                             float w2, float *loss, float *terms) {
+  if (threadIdx.x != 0) return;
+  double t[3] = {0.0, 0.0, 0.0};
+  for (int b = 0; b < nparts; ++b)
+    for (int q = 0; q < 3; ++q) t[q] += part[b * 3 + q];
+  for (int q = 0; q < 3; ++q) t[q] *= inv_n;
+  if (terms)
+    for (int q = 0; q < 3; ++q) terms[q] = (float)t[q];
+  *loss = (float)((double)*loss + w0 * t[0] + w1 * t[1] + w2 * t[2]);
+}
+
 __global__ void k_loss_final(const double *part, int nparts, double scale, float *loss) {
   if (threadIdx.x != 0) return;
   // partials added in order, loaded eight at a time
@@ -1932,6 +2008,16 @@ chem_status features(const FeatArgs &a, hipStream_t s) {
 chem_status targets(const TargetArgs &a, hipStream_t s) {
   if (a.n <= 0) return CHEM_OK;
   hipLaunchKernelGGL(k_targets, dim3(nblk(a.n, 64)), dim3(64), 0, s, a);
+  CHEM_HIP(hipGetLastError());
+  return CHEM_OK;
+}
+
+chem_status phys_grad(const PhysArgs &a, const chem::DevMech &M, double *part, float *loss,
+                      float *terms, hipStream_t s) {
+  if (a.n <= 0) return CHEM_OK;
+  hipLaunchKernelGGL(k_phys, dim3(PHYS_PARTS), dim3(256), 0, s, a, M, part);
+  hipLaunchKernelGGL(k_phys_final, dim3(1), dim3(64), 0, s, part, PHYS_PARTS, 1.0 / (double)a.n,
+                     a.w[0], a.w[1], a.w[2], loss, terms);
   CHEM_HIP(hipGetLastError());
   return CHEM_OK;
 }

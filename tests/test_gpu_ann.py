@@ -241,6 +241,62 @@ def test_gradients_and_adam(dev, mech, data, data8k, B):
         _say(f"  adam step {t}: weights, m, v match the oracle")
 
 
+def test_gradients_with_physics_terms(dev, mech, data):
+    """The physics terms of the loss (mass-fraction sum, energy at T1, heat
+    release at 298.15 K) on the GPU against the oracle's backward_phys: the
+    loss and the three terms, every layer's gradient, and -- to isolate the
+    physics part from the L1 signs -- the change of the output layer's
+    gradient when the terms are switched on."""
+    import torch
+    import paper_2312_05800_amd as P
+    _say("[ann grads, physics terms]")
+    K = mech.K
+    om = oracle.OracleMech(mech)
+    gm = P.Mechanism(mech)
+    params = oann.init_params([K + 2, *HID, K], seed=19)
+    nm = _norm_from(data)
+    m = _model(mech, params, nm)
+    B = 256
+    T, p, Y0, Y1, T1 = (data["T"][:B], data["p"][:B], data["Y0"][:, :B], data["Y1"][:, :B],
+                        data["T1"][:B])
+    w = (0.3, 0.2, 0.1)
+    args = [to_dev(a, dev) for a in (T, p, Y0, Y1)]
+    T1d = to_dev(T1, dev)
+    loss = torch.zeros(1, dtype=torch.float32, device=dev)
+    terms = torch.zeros(3, dtype=torch.float32, device=dev)
+    shapes = [(HID[0], K + 2), (HID[1], HID[0]), (HID[2], HID[1]), (K, HID[2])]
+    m.train_step(*args, loss, lr=0.0)
+    torch.cuda.synchronize()
+    g_plain = m.get_grad(3, shapes[3])[0].astype(np.float64)
+    m.train_step(*args, loss, lr=0.0, mech=gm, T1=T1d, w_phys=w, terms=terms)
+    torch.cuda.synchronize()
+    X = _oracle_inputs(nm, T, p, Y0)
+    mu, sd = _f32(nm["mu_out"]), _f32(nm["sd_out"])
+    tgt = ((oann.targets(Y0, Y1) - mu[:, None]) / sd[:, None]).T
+    h_T1 = oann.species_enthalpy(om, T1)
+    h_ref = np.repeat(oann.species_enthalpy(om, oann.T_REF_HRR), B, axis=1)
+    grads, total, l1, terms_o = oann.backward_phys(_params32(params), X, tgt, mu, sd, h_T1,
+                                                   h_ref, w, prec="bf16")
+    grads0, _ = oann.backward(_params32(params), X, tgt, prec="bf16")
+    tg = terms.cpu().numpy().astype(np.float64)
+    _say(f"  terms gpu {tg} oracle {terms_o}; loss {loss.item():.6f} oracle {total:.6f}")
+    # u differs from the emulation by FP32 accumulation (~1e-3 relative)
+    np.testing.assert_allclose(tg, terms_o, rtol=2e-2)
+    assert abs(loss.item() - total) <= 1e-2 * total
+    for l in range(4):
+        gW, gb = m.get_grad(l, shapes[l])
+        for a, b in ((gW, grads[l][0]), (gb, grads[l][1])):
+            rel = np.linalg.norm(a - b) / np.linalg.norm(b)
+            cos = float(np.sum(a * b) / (np.linalg.norm(a) * np.linalg.norm(b)))
+            _say(f"  layer {l} rel {rel:.2e} cos {cos:.6f}")
+            assert rel <= 1e-2 and cos >= 0.999
+    dg = m.get_grad(3, shapes[3])[0].astype(np.float64) - g_plain
+    do = grads[3][0] - grads0[3][0]
+    rel = np.linalg.norm(dg - do) / np.linalg.norm(do)
+    _say(f"  output-layer gradient of the physics terms: rel {rel:.2e}")
+    assert rel <= 3e-2
+
+
 def test_post_and_fallback(dev, mech, data):
     import torch
     import paper_2312_05800_amd as P
