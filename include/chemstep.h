@@ -224,7 +224,9 @@ typedef struct {
 /* The surrogate chemistry step of every cell (the ANN replacing the
  * reaction-rate integration, Sec. 1-2): Y' = Y0 + sd_out u + mu_out from
  * the network, projected onto element conservation by weighted least
- * squares (weights Y' + 1e-10), clipped at 0; T from h(T, Y) = h(T0, Y0) by
+ * squares (weight of species k: sd_out,k^2 (Y+_k + 1e-10) / (Y+_k + sd_out,k)
+ * with Y+ = max(Y', 0): the expected variance of the network's error in its
+ * change, tapered to zero as the species vanishes), clipped at 0; T from h(T, Y) = h(T0, Y0) by
  * FP64 Newton; RR = rho0 (Y - Y0)/dt.  A cell is flagged (flags [n], nullable)
  * with bit 0 if an input lies outside the widened training range or dt
  * differs from dt_model, bit 1 if the element residual of the network's own
@@ -379,6 +381,13 @@ void chem_graph_destroy(chem_graph *g);
  * label (host char[48]), the number of launches and their total duration in
  * milliseconds since the previous read; returns the number of labels written
  * (at most cap).  Off by default; costs two event records per launch. */
+/* Attainable peaks of this GPU, measured: dense BF16 MFMA, FP8 MFMA
+ * (E4M3 operands, unit block scales) and FP64 vector FMA, each by a launch
+ * of 2048 blocks of 256 threads running eight independent accumulator
+ * chains per wave (one untimed warm-up launch first).  tflops (host [3])
+ * receives TFLOP/s in that order.  Synchronises `stream`; allocates and frees
+ * a small sink buffer. */
+chem_status chem_measure_peaks(double *tflops, void *stream);
 void chem_profile_enable(int32_t on);
 int32_t chem_profile_read(char (*names)[48], int64_t *launches, double *total_ms, int32_t cap);
 

@@ -296,14 +296,24 @@ def element_mass_matrix(mech):
     return mech.comp.T.astype(np.float64) * mech.awt[:, None] / mech.W[None, :]
 
 
-def project(mech, Y0, Yp, floor=1e-10):
+def project(mech, Y0, Yp, sd, floor=1e-10):
     """Weighted least-squares projection of Yp ([K, N]) onto the element
-    conservation constraints M Y = M Y0, with weights D = diag(Yp + floor):
-    Y = Yp + D M^T (M D M^T)^-1 (M Y0 - M Yp)."""
+    conservation constraints M Y = M Y0:
+    Y = Yp + D M^T (M D M^T)^-1 (M Y0 - M Yp), the minimiser of
+    sum_k (Y_k - Yp_k)^2 / d_k under the constraints.  The weight of species k
+    is the expected variance of the network's error in its change, sd_k^2
+    (sd = the training targets' standard deviations), tapered to zero as the
+    species' own mass fraction Y+ = max(Yp, 0) vanishes:
+    d_k = sd_k^2 (Y+_k + floor) / (Y+_k + sd_k).  The paper has no
+    projection; this weighting is the project's reading (a correction spread
+    in proportion to Y itself moved most of an element's residual onto the
+    most abundant species, whatever the accuracy of its predicted change)."""
     M = element_mass_matrix(mech)
+    sd = np.asarray(sd, dtype=np.float64)
     out = np.empty_like(Yp)
     for i in range(Yp.shape[1]):
-        d = np.maximum(Yp[:, i], 0.0) + floor
+        yp = np.maximum(Yp[:, i], 0.0)
+        d = sd * sd * (yp + floor) / (yp + sd)
         A = (M * d[None, :]) @ M.T
         r = M @ Y0[:, i] - M @ Yp[:, i]
         lam = np.linalg.solve(A, r)
@@ -357,7 +367,7 @@ def post(om: OracleMech, T0, p, Y0, u_z, mu_out, sd_out, dt, lo=None, hi=None,
     mech = om.mech
     du = u_z * sd_out[:, None] + mu_out[:, None]
     Yp = Y0 + du
-    Y = project(mech, Y0, Yp)
+    Y = project(mech, Y0, Yp, sd_out)
     Y = np.maximum(Y, 0.0)
     M = element_mass_matrix(mech)
     res_raw = np.abs(M @ Yp - M @ Y0).max(axis=0)

@@ -1352,6 +1352,15 @@ __global__ void k_l1(int64_t n, int K, int doutp, const float *U, const float *U
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
+// Weight of species k in the element projection: the expected variance of
+// the network's error in its change, sd^2 (sd = the target's standard
+// deviation), tapered to zero as the species' own mass fraction vanishes:
+// sd^2 (Y+ + 1e-10) / (Y+ + sd), Y+ = max(Y', 0).
+__device__ __forceinline__ double proj_weight(double y, float sdf) {
+  const double yp = fmax(y, 0.0), sd = (double)sdf;
+  return sd * sd * (yp + 1e-10) / (yp + sd);
+}
+
 // h_k(T) in J/kg from the folded h/RT polynomial of species k's range at T.
 __device__ __forceinline__ double species_h(const chem::DevMech &M, int k, double T) {
   const double *c = (T <= M.Tmid[k] ? M.nasa_h : M.nasa_hh) + 7 * k;
@@ -1609,12 +1618,12 @@ __global__ __launch_bounds__(128, 4) void k_post(chem::DevMech M, PostArgs a) {
         const float du = u4[t] * a.nm.sd_out[k] + a.nm.mu_out[k];
         const double y = y0 + (double)du;  // Y' = Y0 + sd u + mu
         yn[k] = y;
-        const double d = fmax(y, 0.0) + 1e-10;
+        const double d = proj_weight(y, a.nm.sd_out[k]);
         S0 += y0 * M.invW[k];
         double hRT, cpR;
         species_h_cp(M, k, Tp, hRT, cpR);
         h0 += y0 * RG * T0 * hRT * M.invW[k];
-        // weighted least-squares projection onto M Y = M Y0, D = diag(max(Y',0) + 1e-10)
+        // weighted least-squares projection onto M Y = M Y0, D = diag(proj_weight)
 #pragma unroll
         for (int e = 0; e < EP; ++e) {
           if (e < E) {
@@ -1678,7 +1687,7 @@ __global__ __launch_bounds__(128, 4) void k_post(chem::DevMech M, PostArgs a) {
 #pragma unroll
       for (int e = 0; e < EP; ++e)
         if (e < E) corr += M.Mel[e * K + k] * lam[e];
-      const double y = fmax(yn[k] + (fmax(yn[k], 0.0) + 1e-10) * corr, 0.0);
+      const double y = fmax(yn[k] + proj_weight(yn[k], a.nm.sd_out[k]) * corr, 0.0);
       yn[k] = y;
 #pragma unroll
       for (int e = 0; e < EP; ++e)

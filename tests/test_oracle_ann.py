@@ -108,17 +108,20 @@ def test_adam_first_step_closed_form():
 def test_projection_kkt(mech_ch4):
     """The weighted projection equals the solution of the KKT system of
     min sum_k (Y_k - Yp_k)^2 / d_k subject to M Y = M Y0, is idempotent and
-    leaves a conserving input unchanged."""
+    leaves a conserving input unchanged; the correction of a species is in
+    proportion to its weight, so a species with a small spread (or a
+    vanishing mass fraction) barely moves."""
     m = mech_ch4
     T, p, Y0 = chemgen.make_states(m, "ch4", N=6, seed=4)
     rng = np.random.default_rng(2)
     Yp = np.abs(Y0 * (1 + 0.05 * rng.standard_normal(Y0.shape)))
-    Y = ann.project(m, Y0, Yp)
+    sd = 10.0 ** rng.uniform(-7, -3, m.K)
+    Y = ann.project(m, Y0, Yp, sd)
     M = ann.element_mass_matrix(m)
     np.testing.assert_allclose(M @ Y, M @ Y0, atol=1e-14)
     K, E = m.K, m.E
     for i in range(6):
-        d = Yp[:, i] + 1e-10
+        d = sd ** 2 * (Yp[:, i] + 1e-10) / (Yp[:, i] + sd)
         A = np.zeros((K + E, K + E))
         A[:K, :K] = np.diag(1.0 / d)
         A[:K, K:] = M.T
@@ -126,8 +129,15 @@ def test_projection_kkt(mech_ch4):
         rhs = np.concatenate([Yp[:, i] / d, M @ Y0[:, i]])
         sol = np.linalg.solve(A, rhs)
         np.testing.assert_allclose(Y[:, i], sol[:K], rtol=1e-8, atol=1e-14)
-    np.testing.assert_allclose(ann.project(m, Y0, Y), Y, atol=1e-15)
-    np.testing.assert_allclose(ann.project(m, Y0, Y0), Y0, atol=1e-15)
+    np.testing.assert_allclose(ann.project(m, Y0, Y, sd), Y, atol=1e-15)
+    np.testing.assert_allclose(ann.project(m, Y0, Y0, sd), Y0, atol=1e-15)
+    # a species whose spread is 1e6 times smaller than the others' takes no
+    # visible part of the correction
+    sd2 = np.full(m.K, 1e-4)
+    j = int(np.argmax(Y0[:, 0]))
+    sd2[j] = 1e-10
+    Y2 = ann.project(m, Y0[:, :1], Yp[:, :1], sd2)
+    assert abs(Y2[j, 0] - Yp[j, 0]) <= 1e-9 * abs(Y2[:, 0] - Yp[:, 0]).max()
     # element mass fractions sum to one when the species ones do
     np.testing.assert_allclose(M.sum(axis=0), 1.0, rtol=1e-14)
 
