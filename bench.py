@@ -98,13 +98,27 @@ def copy_probe(dev):
     del src, dst
 
 
-def train_model(P, mech, gm, dev, args):
-    """Generate labels with the FP64 GPU integrator and train the network."""
+def _plain(o, path="out"):
+    """The bench record with NumPy scalars and arrays turned into plain
+    Python values (arrays are reported on stderr: they should not occur)."""
     import numpy as np
+    if isinstance(o, dict):
+        return {k: _plain(v, f"{path}.{k}") for k, v in o.items()}
+    if isinstance(o, (list, tuple)):
+        return [_plain(v, f"{path}[{i}]") for i, v in enumerate(o)]
+    if isinstance(o, np.ndarray):
+        log(f"[bench] array at {path} (shape {o.shape})")
+        return o.tolist()
+    if isinstance(o, np.generic):
+        return o.item()
+    return o
+
+
+def make_labels(P, mech, gm, dev, args):
+    """Training pairs: perturbed states integrated over dt by the FP64 GPU
+    integrator (the final temperature T1 kept for the physics terms)."""
     import torch
     import chemgen
-    K = mech.K
-    t0 = time.time()
     cfg = dict(chemgen.STATE_CONFIGS["ch4_train"])
     T, p, Y0 = chemgen.make_states(mech, cfg, N=args.train_cells)
     Td, pd, Y0d = (torch.from_numpy(a).to(dev) for a in (T, p, Y0))
@@ -118,18 +132,31 @@ def train_model(P, mech, gm, dev, args):
     ok = (st[2] == 0)
     nbad = int((~ok).sum().item())
     keep = torch.nonzero(ok).flatten()
-    Td, pd, Y0d, Y1d = Td[keep].contiguous(), pd[keep].contiguous(), \
-        Y0d[:, keep].contiguous(), Y1d[:, keep].contiguous()
-    n = Td.shape[0]
+    lab = dict(T=Td[keep].contiguous(), p=pd[keep].contiguous(), Y0=Y0d[:, keep].contiguous(),
+               Y1=Y1d[:, keep].contiguous(), T1=T1d[keep].contiguous())
     log(f"[train] labels for {T.size} states in {t_label:.2f} s ({nbad} failed)")
+    return lab, dict(states=int(T.size), label_seconds=round(t_label, 3), failed_labels=nbad)
+
+
+def train_model(P, mech, gm, dev, args, lab, w_phys):
+    """Train the network on the labelled pairs (cosine lr decay), with the
+    physics terms of the loss weighted by w_phys (zeros: L1 loss only)."""
+    import numpy as np
+    import torch
+    K = mech.K
+    Td, pd, Y0d, Y1d, T1d = lab["T"], lab["p"], lab["Y0"], lab["Y1"], lab["T1"]
+    n = Td.shape[0]
     m = P.AnnModel(K + 2, K, HIDDEN, seed=args.seed)
     m.fit_norm(Td, pd, Y0d, Y1d, 0.1, 1e-5)
     loss = torch.zeros(1, dtype=torch.float32, device=dev)
+    terms = torch.zeros(3, dtype=torch.float32, device=dev)
+    phys = any(w != 0.0 for w in w_phys)
     rng = np.random.default_rng(args.seed)
     B = args.batch
     perm = None
     pos = n
     hist = []
+    torch.cuda.synchronize()
     tt = time.time()
     for it in range(args.train_steps):
         if pos + B > n:
@@ -139,19 +166,22 @@ def train_model(P, mech, gm, dev, args):
         pos += B
         frac = it / max(1, args.train_steps - 1)
         lr = 1e-5 + 0.5 * (args.lr - 1e-5) * (1 + math.cos(math.pi * frac))
-        m.train_step(Td, pd, Y0d, Y1d, loss, index=idx, lr=lr)
-        if it % 200 == 0 or it == args.train_steps - 1:
+        if phys:
+            m.train_step(Td, pd, Y0d, Y1d, loss, index=idx, lr=lr, mech=gm, T1=T1d,
+                         w_phys=w_phys, terms=terms)
+        else:
+            m.train_step(Td, pd, Y0d, Y1d, loss, index=idx, lr=lr)
+        if it % 500 == 0 or it == args.train_steps - 1:
             hist.append((it, float(loss.item())))
-            log(f"[train] step {it} lr {lr:.2e} loss {hist[-1][1]:.5f}")
+            log(f"[train w={w_phys}] step {it} lr {lr:.2e} loss {hist[-1][1]:.5f}")
     torch.cuda.synchronize()
     t_train = time.time() - tt
-    info = dict(states=int(T.size), label_seconds=round(t_label, 3), failed_labels=nbad,
-                steps=args.train_steps, batch=B, train_seconds=round(t_train, 2),
+    info = dict(steps=args.train_steps, batch=B, w_phys=list(w_phys),
+                train_seconds=round(t_train, 2),
                 ms_per_train_step=round(1e3 * t_train / max(1, args.train_steps), 3),
-                loss_first=hist[0][1] if hist else None, loss_last=hist[-1][1] if hist else None,
-                total_seconds=round(time.time() - t0, 2))
-    if args.save_model:
-        m.save(args.save_model)
+                loss_first=hist[0][1] if hist else None, loss_last=hist[-1][1] if hist else None)
+    if phys:
+        info["physics_terms_last"] = [round(float(v), 6) for v in terms.cpu().numpy()]
     return m, info
 
 
@@ -169,7 +199,7 @@ def timed_loop(run, restore, steps, warmup):
     return time.perf_counter() - t
 
 
-def time_sets(P, mech, gm, dev, args):
+def time_sets(P, mech, gm, dev, args, model=None):
     """Uneven batched workload (independent cell sets of very different size
     and dt): one chem_step launch per set, against all sets on one persistent
     queue (chem_step_sets) and that call replayed as a captured graph.  Each
@@ -215,20 +245,35 @@ def time_sets(P, mech, gm, dev, args):
     t_graph = timed_loop(g.launch, restore, 1, 0)
     eq_graph = same(snapshot(), ref)
     del g
-    # oracle on up to 16 evenly spaced cells of every set
+    # oracle on a stratified sample: every set contributes in proportion to
+    # its size (at least one cell), args.sets_oracle cells in all
     om = oracle.OracleMech(mech)
     err = 0.0
     nchk = 0
     for w, d in zip(ws, live):
         if w["N"] == 0:
             continue
-        ii = np.unique(np.linspace(0, w["N"] - 1, min(16, w["N"])).astype(np.int64))
+        k = max(1, min(w["N"], int(round(args.sets_oracle * w["N"] / total))))
+        ii = np.unique(np.linspace(0, w["N"] - 1, k).astype(np.int64))
         o = oracle.chem_step(om, w["dt"], w["T"][ii], w["p"][ii], w["Y"][:, ii])
         Tg, Yg = d["T"].cpu().numpy()[ii], d["Y"].cpu().numpy()[:, ii]
         big = np.abs(o["Y"]) > 1e-10
         err = max(err, float(np.max(np.abs(Tg - o["T"]) / o["T"])),
                   float(np.max(np.abs(Yg - o["Y"])[big] / np.abs(o["Y"])[big])))
         nchk += ii.size
+    # the surrogate on the same sets, at the step it was trained for (its
+    # accuracy is not claimed for the sets' own dt): one ann_step per set
+    ann_side = None
+    if model is not None:
+        restore()
+
+        def ann_sets():
+            for d in live:
+                if d["T"].shape[0]:
+                    model.step(gm, 1e-5, d["T"], d["p"], d["Y"])
+        t_ann = timed_loop(ann_sets, restore, 1, 1)
+        ann_side = {"dt": 1e-5, "s": round(t_ann, 4), "cells_per_s": round(total / t_ann, 1),
+                    "calls": len([d for d in live if d["T"].shape[0]])}
     sizes = [w["N"] for w in ws]
     out = {"workload": f"{len(ws)} CH4/air cell sets, sizes floor(10^U(3,6)) "
                        f"({min(sizes)}..{max(sizes)}), dt 10^U(-7,-4) s per set, "
@@ -240,7 +285,9 @@ def time_sets(P, mech, gm, dev, args):
            "persistent_queue_graph": {"s": round(t_graph, 3),
                                       "cells_per_s": round(total / t_graph, 1),
                                       "equal_to_per_set": eq_graph},
-           "max_rel_err_vs_oracle": err, "oracle_cells": nchk}
+           "max_rel_err_vs_oracle": err, "oracle_cells": nchk,
+           "oracle_sample": "stratified: each set in proportion to its size",
+           "ann_at_dt_model": ann_side}
     log(f"[sets] per-set {t_naive:.2f} s, queue {t_queue:.2f} s, graph {t_graph:.2f} s")
     return out
 
@@ -261,6 +308,113 @@ def nrmse_table(dY_model, dY_ref, Yref_mean, names, rtol=1e-6):
                        major=abundant and resolved, unresolved=abundant and not resolved)
     majors = [v["nrmse"] for v in out.values() if v["major"]]
     return out, (max(majors) if majors else float("nan"))
+
+
+def big_leg(P, mech, gm, dev, args, model):
+    """Inference at the training-plus-FP8 configuration's size: the BF16 and
+    the FP8 steps on args.big_cells cells, their error against the FP64 GPU
+    integrator on every cell and against the oracle on 2^16 of them."""
+    import numpy as np
+    import torch
+    import chemgen
+    import oracle
+    N = args.big_cells
+    T, p, Y = chemgen.make_states(mech, "ch4", N=N, seed=57)
+    T0d, pd, Y0d = (torch.from_numpy(a).to(dev) for a in (T, p, Y))
+    Td, Yd = T0d.clone(), Y0d.clone()
+    nfb = torch.zeros(1, dtype=torch.int64, device=dev)
+
+    def restore():
+        Td.copy_(T0d)
+        Yd.copy_(Y0d)
+    steps = 3
+    out = {"workload": f"{N} stratified CH4/air cells (seed 57), dt=1e-5 s", "cells": N,
+           "steps": steps}
+    legs = {}
+    for name, prec in (("bf16", 0), ("fp8", 1)):
+        if prec == 1:
+            try:
+                model.set_precision(1)
+            except P.ChemError:
+                continue
+        t = timed_loop(lambda: model.step(gm, 1e-5, Td, pd, Yd, n_fallback=nfb), restore, steps,
+                       1)
+        legs[name] = Yd.cpu().numpy()
+        out[name] = {"cells_per_s": round(N * steps / t, 1),
+                     "ms_per_step": round(1e3 * t / steps, 3),
+                     "fallback_cells": int(nfb.item())}
+        log(f"[large {name}] {N} cells: {1e3 * t / steps:.2f} ms per step")
+    model.set_precision(0)
+    restore()
+    torch.cuda.synchronize()
+    tf = time.time()
+    P.chem_step(gm, 1e-5, Td, pd, Yd)
+    torch.cuda.synchronize()
+    tf = time.time() - tf
+    fp_Y = Yd.cpu().numpy()
+    out["fp64"] = {"cells_per_s": round(N / tf, 1), "s": round(tf, 3)}
+    log(f"[large fp64] {tf:.2f} s")
+    dY_fp = fp_Y - Y
+    fm = fp_Y.mean(axis=1)
+    for name, Yv in legs.items():
+        _, out[name]["nrmse_major_max_vs_gpu_fp64_all_cells"] = nrmse_table(Yv - Y, dY_fp, fm,
+                                                                             mech.species)
+    del dY_fp
+    idx = np.linspace(0, N - 1, 1 << 16).astype(np.int64)
+    o = oracle.chem_step(oracle.OracleMech(mech), 1e-5, T[idx], p[idx], Y[:, idx])
+    dY_ref = o["Y"] - Y[:, idx]
+    for name, Yv in legs.items():
+        _, out[name]["nrmse_major_max_vs_oracle"] = nrmse_table(
+            Yv[:, idx] - Y[:, idx], dY_ref, o["Y"].mean(axis=1), mech.species)
+    big = np.abs(o["Y"]) > 1e-10
+    out["fp64"]["max_rel_err_vs_oracle"] = max(
+        float(np.max(np.abs(fp_Y[:, idx] - o["Y"])[big] / np.abs(o["Y"])[big])), 0.0)
+    out["oracle_sample_cells"] = int(idx.size)
+    return out
+
+
+def n_params(K):
+    dims = [K + 2, *HIDDEN, K]
+    return sum(a * b + b for a, b in zip(dims[:-1], dims[1:]))
+
+
+def train_roofline(info, K):
+    """One Adam step of the batch: forward, data and weight gradients (three
+    times the forward's flops) against the BF16 MFMA peak; the optimiser's
+    bytes (FP32 weights, gradients and two moments read, three of them
+    written, the BF16 copy written: 30 B per parameter) against HBM."""
+    ms = info.get("ms_per_train_step")
+    if not ms:
+        return None
+    B = info["batch"]
+    flops = 3.0 * mlp_flops_per_cell(K) * B
+    ach = flops / (ms * 1e-3)
+    adam_bytes = 30.0 * n_params(K)
+    return {"kernel": "one training step (all launches)", "bound": "mfma",
+            "achieved": round(ach / 1e12, 2), "peak": PEAK_BF16 / 1e12, "unit": "TFLOP/s",
+            "frac": round(ach / PEAK_BF16, 4), "flops_per_step": flops, "batch": B,
+            "ms_per_step": ms, "adam_bytes_per_step": adam_bytes,
+            "adam_bytes_time_at_8TBps_ms": round(adam_bytes / 8e12 * 1e3, 4)}
+
+
+def fp8_roof(prof, K, chunk):
+    """Time-weighted roof of the FP8 network: its BF16 flops (first and last
+    layers) at the BF16 peak plus its FP8 flops (hidden-to-hidden layers) at
+    the FP8 peak, against the measured time of its network kernels."""
+    f_bf16 = 2.0 * ((K + 2) * HIDDEN[0] + HIDDEN[2] * K) * chunk
+    f_fp8 = 2.0 * (HIDDEN[0] * HIDDEN[1] + HIDDEN[1] * HIDDEN[2]) * chunk
+    t_roof = f_bf16 / PEAK_BF16 + f_fp8 / PEAK_FP8
+    labels = ("mlp_l1", "mlp_l2_fp8", "mlp_l3_l4_fp8", "mlp_l3_fp8", "mlp_l4")
+    t_net = 0.0
+    for lab in labels:
+        c, tot = prof.get(lab, (0, 0.0))
+        if c:
+            t_net += tot / c * 1e-3
+    if t_net <= 0.0:
+        return None
+    return {"bf16_flops": f_bf16, "fp8_flops": f_fp8, "roof_ms": round(t_roof * 1e3, 4),
+            "network_ms": round(t_net * 1e3, 4), "frac": round(t_roof / t_net, 4),
+            "kernels": [lab for lab in labels if prof.get(lab, (0, 0))[0]]}
 
 
 def small_config(P, dev, oracle, nthr):
@@ -304,7 +458,7 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--model", default=None, help="load a saved model instead of training")
     ap.add_argument("--save-model", default=None)
-    ap.add_argument("--train-cells", type=int, default=1 << 21)
+    ap.add_argument("--train-cells", type=int, default=1 << 22)
     ap.add_argument("--train-steps", type=int, default=3000)
     ap.add_argument("--batch", type=int, default=8192)
     ap.add_argument("--lr", type=float, default=1e-3)
@@ -312,10 +466,20 @@ def main():
     ap.add_argument("--oracle-sample", type=int, default=1 << 16)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--fp8", type=int, default=1, help="also time FP8 hidden layers (1/0)")
-    ap.add_argument("--sets", type=int, default=0,
-                    help="also time the uneven multi-set FP64 workload with this many sets")
-    ap.add_argument("--sets-max-cells", type=int, default=0,
-                    help="scale the set sizes down to at most this many cells in total")
+    ap.add_argument("--sets", type=int, default=64,
+                    help="time the uneven multi-set workload with this many sets (0: skip)")
+    ap.add_argument("--sets-max-cells", type=int, default=1 << 22,
+                    help="scale the set sizes down to at most this many cells in total "
+                         "(0: the drawn sizes)")
+    ap.add_argument("--sets-oracle", type=int, default=1 << 16,
+                    help="cells of the stratified oracle sample of the sets")
+    ap.add_argument("--w-phys", type=str, default="1.0,0.3,0.3",
+                    help="weights of the loss's mass, energy and heat-release terms")
+    ap.add_argument("--compare-phys", type=int, default=1,
+                    help="also train without the physics terms and report its accuracy")
+    ap.add_argument("--big-cells", type=int, default=1 << 23,
+                    help="cells of the large inference leg (BF16 and FP8; 0: skip)")
+    ap.add_argument("--peaks", type=int, default=1, help="measure attainable peaks (1/0)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the chemistry step has no inter-GPU exchange "
@@ -333,11 +497,24 @@ def main():
     gm = P.Mechanism(mech)
     N = args.cells
 
+    w_phys = tuple(float(x) for x in args.w_phys.split(","))
+    model_plain = None
+    train_plain = None
     if args.model and os.path.exists(args.model):
         model = P.AnnModel.load(args.model)
         train_info = dict(loaded=args.model)
     else:
-        model, train_info = train_model(P, mech, gm, dev, args)
+        t0 = time.time()
+        lab, train_info = make_labels(P, mech, gm, dev, args)
+        model, tinfo = train_model(P, mech, gm, dev, args, lab, w_phys)
+        train_info.update(tinfo)
+        if args.compare_phys and any(w != 0.0 for w in w_phys):
+            model_plain, train_plain = train_model(P, mech, gm, dev, args, lab, (0.0, 0.0, 0.0))
+        train_info["total_seconds"] = round(time.time() - t0, 2)
+        if args.save_model:
+            model.save(args.save_model)
+        del lab
+        torch.cuda.empty_cache()
 
     T, p, Y = chemgen.make_states(mech, "ch4", N=N)
     T0d, pd, Y0d = (torch.from_numpy(a).to(dev) for a in (T, p, Y))
@@ -407,7 +584,15 @@ def main():
 
     ann_cps = N * args.steps / t_ann
     fp64_cps = N * args.fp64_steps / t_fp64
-    sets_out = time_sets(P, mech, gm, dev, args) if args.sets else None
+    sets_out = time_sets(P, mech, gm, dev, args, model=model) if args.sets else None
+
+    # ---- training-plus-FP8 sizes: inference on args.big_cells cells ----
+    large = None
+    if args.big_cells:
+        large = big_leg(P, mech, gm, dev, args, model)
+    peaks = P.measure_peaks() if args.peaks else None
+    if peaks:
+        log(f"[peaks] {peaks}")
 
     # ---- accuracy against the CPU oracle on an evenly spaced sample ----
     copy_probe(dev)
@@ -441,6 +626,29 @@ def main():
     res_raw = np.abs(Mel @ (Yraw - Y[:, idx])).max(axis=0)
     unprojected_flagged = int((res_raw > 1e-6).sum())
     del U, Yraw
+    # the same network trained without the physics terms of the loss
+    phys_cmp = None
+    if model_plain is not None:
+        def sample_step(mdl):
+            Ts, ps, Ys = (T0d[idx_d].contiguous(), pd[idx_d].contiguous(),
+                          Y0d[:, idx_d].contiguous())
+            nf = torch.zeros(1, dtype=torch.int64, device=dev)
+            mdl.step(gm, 1e-5, Ts, ps, Ys, n_fallback=nf)
+            Um = mdl.forward(T0d[idx_d].contiguous(), pd[idx_d].contiguous(),
+                             Y0d[:, idx_d].contiguous(), K).cpu().numpy().astype(np.float64).T
+            nmm = mdl.get_norm(K + 2, K)
+            Yr = np.maximum(Y[:, idx] + Um * nmm["sd_out"][:, None] + nmm["mu_out"][:, None], 0.0)
+            rr = np.abs(Mel @ (Yr - Y[:, idx])).max(axis=0)
+            _, mj = nrmse_table(Ys.cpu().numpy() - Y[:, idx], dY_ref, o["Y"].mean(axis=1),
+                                mech.species)
+            return {"nrmse_major_max": mj, "fallback_cells": int(nf.item()),
+                    "raw_residual_max": float(rr.max()),
+                    "raw_residual_median": float(np.median(rr)),
+                    "raw_residual_flags": int((rr > 1e-6).sum())}
+        phys_cmp = {"sample_cells": int(idx.size),
+                    "with_terms": dict(w_phys=list(w_phys), **sample_step(model)),
+                    "without_terms": sample_step(model_plain),
+                    "training_without_terms": train_plain}
 
     # the same error against the GPU FP64 integrator, on every cell
     dY_fp = fp_Y - Y
@@ -498,11 +706,13 @@ def main():
                                 "unit": "TFLOP/s", "frac": round(ach8 / PEAK_FP8, 4),
                                 "avg_ms": round(t8 * 1e3, 4), "launches": c8},
                    "kernels": {k: dict(launches=v[0], avg_ms=round(v[1] / max(v[0], 1), 4))
-                               for k, v in fp8["prof"].items()}}
+                               for k, v in fp8["prof"].items()},
+                   "time_weighted_roof": fp8_roof(fp8["prof"], K, chunk)}
 
     # ---- CPU baseline: the oracle on a bounded sample of the same cells ----
     nthr = oracle.max_threads()
-    probe_n = 256
+    # the probe keeps every thread busy (dynamic schedule, 64 cells per chunk)
+    probe_n = max(256, 128 * nthr)
     pi = np.linspace(0, N - 1, probe_n).astype(np.int64)
     tp = time.time()
     oracle.chem_step(om, 1e-5, T[pi], p[pi], Y[:, pi])
@@ -537,6 +747,17 @@ def main():
           nmz["sd_in"][:, None].astype(np.float64)).T
     oann.forward(params64, Xa, prec="fp64")
     ta = time.time() - ta
+    # one training step of the batch size on the host: the oracle's FP64
+    # forward and backward (NumPy/BLAS), no optimiser
+    Bt = args.batch
+    bi = np.linspace(0, N - 1, Bt).astype(np.int64)
+    featb = oann.features(T[bi], p[bi], Y[:, bi])
+    Xb = ((featb - nmz["mu_in"][:, None].astype(np.float64)) /
+          nmz["sd_in"][:, None].astype(np.float64)).T
+    tgtb = np.zeros((Bt, K))
+    tb = time.time()
+    oann.backward(params64, Xb, tgtb, prec="fp64")
+    tb = time.time() - tb
     small = small_config(P, dev, oracle, nthr)
 
     out = {
@@ -601,6 +822,17 @@ def main():
         "ann_step_graph": {"ms_per_step": round(1e3 * t_graph / args.steps, 4),
                            "equal_to_eager": graph_equal},
         "fp64_sets": sets_out,
+        "physics_terms_comparison": phys_cmp,
+        "large": large,
+        "attainable_peaks": None if peaks is None else {
+            "measured_tflops": {k: round(v, 1) for k, v in peaks.items()},
+            "spec_tflops": {"bf16_mfma": PEAK_BF16 / 1e12, "fp8_mfma": PEAK_FP8 / 1e12,
+                            "fp64_vector": PEAK_FP64 / 1e12},
+            "roofline_frac_of_measured": round(ach_bf16 / (peaks["bf16_mfma"] * 1e12), 4),
+            "roofline_fp64_frac_of_measured": round(ach_fp64 / (peaks["fp64_vector"] * 1e12), 4),
+            "method": "2048 blocks x 256 threads, 8 independent accumulator chains per wave: "
+                      "v_mfma_f32_16x16x32_bf16, v_mfma_scale_f32_16x16x128_f8f6f4, v_fma_f64"},
+        "roofline_training": train_roofline(train_info, K),
         "fp8": fp8_out,
         "cpu_baseline": {"value": round(cpu_cps, 2), "unit": "cells/s", "cores": nthr,
                          "kind": "oracle",
@@ -610,6 +842,11 @@ def main():
         "cpu_baselines_more": {
             "oracle_one_core": {"value": round(n1 / t1, 2), "unit": "cells/s", "cores": 1,
                                 "sample": f"{n1} evenly spaced cells of the 2^20-cell workload"},
+            "training_step_numpy_fp64": {"value": round(tb * 1e3, 1), "unit": "ms per step",
+                                         "batch": Bt, "threads": os.environ.get(
+                                             "OMP_NUM_THREADS", "library default"),
+                                         "sample": "the oracle's FP64 forward and backward "
+                                                   "(NumPy/BLAS) on one batch, no optimiser"},
             "ann_numpy_fp64": {"value": round(na / ta, 1), "unit": "cells/s",
                                "threads": os.environ.get("OMP_NUM_THREADS", "library default"),
                                "sample": f"{na} evenly spaced cells: features and the FP64 "
@@ -630,7 +867,7 @@ def main():
             "cpu_oracle_cores": nthr,
         },
     }
-    print(json.dumps(out), flush=True)
+    print(json.dumps(_plain(out)), flush=True)
 
 
 if __name__ == "__main__":

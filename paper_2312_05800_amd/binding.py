@@ -80,6 +80,7 @@ def lib():
             L.chem_step_sets_graph_create.argtypes = [_P, C.c_int32, _P, _P, _P, C.POINTER(_P)]
             L.chem_graph_launch.argtypes = [_P, _P]
             L.chem_graph_destroy.argtypes = [_P]
+            L.chem_measure_peaks.argtypes = [_P, _P]
             L.chem_profile_enable.argtypes = [C.c_int32]
             L.chem_profile_read.argtypes = [_P, _P, _P, C.c_int32]
             L.chem_profile_read.restype = C.c_int32
@@ -345,6 +346,13 @@ def chem_step_graph(mech: Mechanism, dt, T, p, Y, dt_cell=None, RR=None, h_hint=
         _vec(h_hint, n, "h_hint", f64), _dptr(stats, torch.int32, "stats"),
         None if o is None else C.byref(o), None, C.byref(h)))
     return Graph(h, (mech, T, p, Y, dt_cell, RR, h_hint, stats))
+
+
+def measure_peaks(stream=None):
+    """Measured TFLOP/s of dense BF16 MFMA, FP8 MFMA and FP64 vector FMA."""
+    out = (C.c_double * 3)()
+    check("chem_measure_peaks", lib().chem_measure_peaks(out, _stream(stream)))
+    return {"bf16_mfma": out[0], "fp8_mfma": out[1], "fp64_vector": out[2]}
 
 
 def profile_enable(on: bool = True):

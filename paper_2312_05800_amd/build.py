@@ -29,7 +29,8 @@ def sources():
 
 # per-source extra flags: the network kernels keep MFMA accumulators in the
 # architectural VGPRs (measured faster than the AGPR form for these tiles)
-EXTRA = {"ann_kernels.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
+EXTRA = {"ann_kernels.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"],
+         "profile.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
 
 
 def _compile(src, jobs_out):
