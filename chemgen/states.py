@@ -162,3 +162,32 @@ def element_matrix(mech: Mech) -> np.ndarray:
     """Atoms of element e per species k, as float64 [E, K] (pure bookkeeping of
     the mechanism's composition table)."""
     return mech.comp.T.astype(np.float64)
+
+
+def hfrd_randoms(K: int, N: int, seed: int, mix_fraction: float = 0.1):
+    """Random numbers of the training-set sampler for N seeds of K species:
+    c [K + 3, N] uniform in [-1, 1] (rows: T, p, N2, then one per species)
+    and s [N]: -1 for a seed that is perturbed, a mixing fraction uniform in
+    [0, 1] for the share mix_fraction of seeds replaced by a mixing-line
+    state."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    c = rng.uniform(-1.0, 1.0, (K + 3, N))
+    s = np.full(N, -1.0)
+    m = rng.uniform(0.0, 1.0, N) < mix_fraction
+    s[m] = rng.uniform(0.0, 1.0, int(m.sum()))
+    return np.ascontiguousarray(c), s
+
+
+def air_state(mech: Mech, T: float = 300.0, p: float = P_ATM):
+    """Ambient air, O2:N2 = 1:3.76 by moles: (T, p, Y[K])."""
+    X = np.zeros((mech.K, 1))
+    X[mech.index("O2")] = 1.0
+    X[mech.index("N2")] = 3.76
+    return T, p, _mass_fractions(mech, X)[:, 0].copy()
+
+
+def burnt_state(mech: Mech, phi: float, T: float, fuel: str = "CH4", p: float = P_ATM):
+    """The recipe's complete-combustion products at equivalence ratio phi and
+    temperature T: (T, p, Y[K])."""
+    Y = _mass_fractions(mech, _moles_burnt(mech, fuel, np.array([phi])))
+    return T, p, Y[:, 0].copy()
