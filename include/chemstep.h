@@ -381,6 +381,40 @@ void chem_graph_destroy(chem_graph *g);
  * label (host char[48]), the number of launches and their total duration in
  * milliseconds since the previous read; returns the number of labels written
  * (at most cap).  Off by default; costs two event records per launch. */
+/* Options of the training-set sampler.  Defaults of Sec. 3.1 and Table 1:
+ * alpha 0.125, beta 10, gamma 0.1, T_min 500 K, H/C in [2.65, 4.67], O/N in
+ * [0.254, 0.32], phi in [0.20, 1.15]. */
+typedef struct {
+  double alpha, beta, gamma; /* Eqs. (Trand)-(Yrand) */
+  double T_min;              /* samples below are dropped */
+  double hc_min, hc_max, on_min, on_max, phi_min, phi_max; /* Table 1 */
+  int32_t n2;                /* species index of N2 */
+  int32_t el_C, el_H, el_O, el_N; /* element indices of C, H, O, N */
+} chem_sample_opts;
+
+/* The random-data generation of the training set (Sec. 3.1), one sample per
+ * seed i.  With s[i] < 0 (or s NULL) the seed (T, p, Y; SoA [K][ld], device)
+ * is perturbed: T' = T + alpha c_T (T_max - T_min), p' = p + beta c_p
+ * (p_max - p_min), y'_N2 = y_N2 + alpha c_N2 (y_N2,max - y_N2,min) with the
+ * extremes over all n seeds, y'_j = y_j^(1 + gamma c_j) for every other
+ * species with y_j > 0 (0 otherwise), and those species rescaled so that
+ * the mass fractions sum to one.  With s[i] >= 0 the sample is the state
+ * (1 - s) end_eq + s end_air on the line between two end states (device
+ * [K + 2] each: T, p, Y_1..K; the paper's ends are the equilibrium of its
+ * leanest mixture, phi = 0.45, and ambient air).  c: device [K + 3][ld]
+ * random numbers in [-1, 1] (rows T, p, N2, then species j at row 3 + j).
+ * keep[i] (device uint8 [n]) is 1 when the sample has T >= T_min, finite
+ * non-negative mass fractions, and molar H/C, O/N and equivalence ratio
+ * (2 n_C + n_H / 2) / n_O inside the limits.  Outputs T_out, p_out (device
+ * [n]) and Y_out (device [K][ld]) are written for every sample.  Argument
+ * errors are detected on the host; the first call allocates a small
+ * range buffer owned by the mechanism handle. */
+chem_status chem_sample_states(const chem_mech *m, chem_batch seeds, const double *T,
+                               const double *p, const double *Y, const double *c,
+                               const double *s, const double *end_eq, const double *end_air,
+                               const chem_sample_opts *opts, double *T_out, double *p_out,
+                               double *Y_out, uint8_t *keep, void *stream);
+
 /* Attainable peaks of this GPU, measured: dense BF16 MFMA, FP8 MFMA
  * (E4M3 operands, unit block scales) and FP64 vector FMA, each by a launch
  * of 2048 blocks of 256 threads running eight independent accumulator

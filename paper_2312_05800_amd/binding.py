@@ -81,6 +81,8 @@ def lib():
             L.chem_graph_launch.argtypes = [_P, _P]
             L.chem_graph_destroy.argtypes = [_P]
             L.chem_measure_peaks.argtypes = [_P, _P]
+            L.chem_sample_states.argtypes = [_P, Batch, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
+                                             _P, _P, _P]
             L.chem_profile_enable.argtypes = [C.c_int32]
             L.chem_profile_read.argtypes = [_P, _P, _P, C.c_int32]
             L.chem_profile_read.restype = C.c_int32
@@ -346,6 +348,43 @@ def chem_step_graph(mech: Mechanism, dt, T, p, Y, dt_cell=None, RR=None, h_hint=
         _vec(h_hint, n, "h_hint", f64), _dptr(stats, torch.int32, "stats"),
         None if o is None else C.byref(o), None, C.byref(h)))
     return Graph(h, (mech, T, p, Y, dt_cell, RR, h_hint, stats))
+
+
+class SampleOpts(C.Structure):
+    _fields_ = [("alpha", C.c_double), ("beta", C.c_double), ("gamma", C.c_double),
+                ("T_min", C.c_double), ("hc_min", C.c_double), ("hc_max", C.c_double),
+                ("on_min", C.c_double), ("on_max", C.c_double), ("phi_min", C.c_double),
+                ("phi_max", C.c_double), ("n2", C.c_int32), ("el_C", C.c_int32),
+                ("el_H", C.c_int32), ("el_O", C.c_int32), ("el_N", C.c_int32)]
+
+
+def sample_states(mech: Mechanism, mech_desc, T, p, Y, c, s=None, end_eq=None, end_air=None,
+                  alpha=0.125, beta=10.0, gamma=0.1, T_min=500.0, hc=(2.65, 4.67),
+                  on=(0.254, 0.32), phi=(0.20, 1.15), stream=None):
+    """Training-set sampler (chem_sample_states): returns (T', p', Y', keep)
+    device tensors.  mech_desc names the N2 species and the C/H/O/N elements
+    (a chemgen.Mech); c: [K+3, ld] draws, s: [n] mixing fractions (< 0:
+    perturb the seed) or None; end_eq / end_air: [K+2] device tensors."""
+    import torch
+    n = T.shape[0]
+    ld = _soa(Y, mech.K, n, "Y")
+    if _soa(c, mech.K + 3, n, "c") != ld:
+        raise ValueError("c must have the leading dimension of Y")
+    el = [mech_desc.elements.index(x) for x in ("C", "H", "O", "N")]
+    o = SampleOpts(alpha, beta, gamma, T_min, hc[0], hc[1], on[0], on[1], phi[0], phi[1],
+                   mech_desc.index("N2"), *el)
+    f64 = torch.float64
+    To = torch.empty(n, dtype=f64, device=T.device)
+    po = torch.empty(n, dtype=f64, device=T.device)
+    Yo = torch.empty((mech.K, ld), dtype=f64, device=T.device)
+    keep = torch.empty(n, dtype=torch.uint8, device=T.device)
+    check("chem_sample_states", lib().chem_sample_states(
+        mech.handle, Batch(n, ld), _vec(T, n, "T", f64), _vec(p, n, "p", f64),
+        _dptr(Y, f64, "Y"), _dptr(c, f64, "c"), _vec(s, n, "s", f64),
+        _vec(end_eq, mech.K + 2, "end_eq", f64), _vec(end_air, mech.K + 2, "end_air", f64),
+        C.byref(o), _dptr(To, f64), _dptr(po, f64), _dptr(Yo, f64), _dptr(keep, torch.uint8),
+        _stream(stream)))
+    return To, po, Yo, keep
 
 
 def measure_peaks(stream=None):

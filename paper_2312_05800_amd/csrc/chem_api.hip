@@ -166,6 +166,9 @@ extern "C" chem_status chem_mech_create(const chem_mech_desc *d, chem_mech **out
     sp4[r] = make_int4(s4[0], s4[1], s4[2], s4[3]);
     nu4[r] = make_int4(n4[0], n4[1], n4[2], n4[3]);
   }
+  std::vector<double> compd((size_t)E * K);
+  for (int e = 0; e < E; ++e)
+    for (int k = 0; k < K; ++k) compd[(size_t)e * K + k] = d->comp[k * E + e];
   std::vector<double> Mel((size_t)E * K);
   for (int e = 0; e < E; ++e)
     for (int k = 0; k < K; ++k) Mel[(size_t)e * K + k] = d->comp[k * E + e] * d->awt[e] / d->W[k];
@@ -208,7 +211,7 @@ extern "C" chem_status chem_mech_create(const chem_mech_desc *d, chem_mech **out
          onh = pk.add(nh.data(), nh.size() * 8), onhh = pk.add(nhh.data(), nhh.size() * 8),
          ons = pk.add(ns.data(), ns.size() * 8), onsh = pk.add(nsh.data(), nsh.size() * 8),
          ocpT = pk.add(cpT.data(), cpT.size() * 8), ohT = pk.add(hT.data(), hT.size() * 8),
-         osT = pk.add(sT.data(), sT.size() * 8);
+         osT = pk.add(sT.data(), sT.size() * 8), ocd = pk.add(compd.data(), compd.size() * 8);
 
   chem_mech *m = new chem_mech();
   m->K = K;
@@ -261,6 +264,7 @@ extern "C" chem_status chem_mech_create(const chem_mech_desc *d, chem_mech **out
   dm.cpT = (const double *)(base + ocpT);
   dm.hT = (const double *)(base + ohT);
   dm.sT = (const double *)(base + osT);
+  dm.compd = (const double *)(base + ocd);
   *out = m;
   return CHEM_OK;
 }
@@ -268,6 +272,7 @@ extern "C" chem_status chem_mech_create(const chem_mech_desc *d, chem_mech **out
 extern "C" void chem_mech_destroy(chem_mech *m) {
   if (!m) return;
   if (m->set_buf) (void)hipFree(m->set_buf);
+  if (m->sample_buf) (void)hipFree(m->sample_buf);
   (void)hipFree(m->blob);
   (void)hipFree(m->counters);
   delete m;

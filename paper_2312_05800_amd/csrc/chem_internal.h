@@ -32,6 +32,7 @@ struct DevMech {
   const double *nasa_hh;  // [K][7] same for the high range
   const double *nasa_s;   // [K][7] low-range s/R: a1, a2, a3/2, a4/3, a5/4, a7, 0
   const double *nasa_sh;  // [K][7] same for the high range
+  const double *compd;    // [E][K] atoms of element e in species k
   const double *cpT;      // [2][7][K] the c_p/R, h/RT and s/R polynomials above,
   const double *hT;       //   low range then high range, coefficient-major
   const double *sT;
@@ -50,6 +51,7 @@ struct chem_mech {
   unsigned long long *counters;    // device work-queue counters
   void *set_buf = nullptr;         // device copy of the last chem_step_sets table
   size_t set_cap = 0;
+  double *sample_buf = nullptr;    // training-set sampler: range partials and ranges
   int device;
   int K, R, E;
   // integrator launch shape (0 = default heuristic), set by chem_autotune or
