@@ -185,6 +185,55 @@ def train_model(P, mech, gm, dev, args, lab, w_phys):
     return m, info
 
 
+def sampled_labels(P, mech, gm, dev, args):
+    """Training pairs from the random-data generation of Sec. 3.1: the
+    recipe's states as seeds, perturbed (or replaced by states on the line
+    between the phi = 0.45 equilibrium and air), filtered by T >= 500 K and
+    Table 1, then integrated over dt by the FP64 GPU integrator."""
+    import numpy as np
+    import torch
+    import chemgen
+    K = mech.K
+    t0 = time.time()
+    T, p, Y = chemgen.make_states(mech, "ch4", N=args.sample_seeds, seed=58)
+    c, s = chemgen.hfrd_randoms(K, T.size, seed=59, mix_fraction=0.1)
+    # the equilibrium end: the recipe's fully burnt phi = 0.45 state after 10 ms
+    Te, pe, Ye = chemgen.burnt_state(mech, 0.45, 2300.0)
+    Ted = torch.tensor([Te], dtype=torch.float64, device=dev)
+    ped = torch.tensor([pe], dtype=torch.float64, device=dev)
+    Yed = torch.from_numpy(Ye[:, None].copy()).to(dev)
+    st = torch.zeros((3, 1), dtype=torch.int32, device=dev)
+    P.chem_step(gm, 1e-2, Ted, ped, Yed, stats=st)
+    Ta, pa, Ya = chemgen.air_state(mech)
+    end_eq = torch.cat([Ted, ped, Yed[:, 0]])
+    end_air = torch.from_numpy(np.concatenate([[Ta, pa], Ya])).to(dev)
+    Td, pd, Yd = (torch.from_numpy(a).to(dev) for a in (T, p, Y))
+    cd, sd = torch.from_numpy(c).to(dev), torch.from_numpy(s).to(dev)
+    To, po, Yo, keep = P.sample_states(gm, mech, Td, pd, Yd, cd, sd, end_eq, end_air)
+    kept = torch.nonzero(keep).flatten()
+    lab = dict(T=To[kept].contiguous(), p=po[kept].contiguous(), Y0=Yo[:, kept].contiguous())
+    del Td, pd, Yd, cd, sd, To, po, Yo
+    T1d, Y1d = lab["T"].clone(), lab["Y0"].clone()
+    stl = torch.zeros((3, T1d.shape[0]), dtype=torch.int32, device=dev)
+    torch.cuda.synchronize()
+    tg = time.time()
+    P.chem_step(gm, 1e-5, T1d, lab["p"], Y1d, stats=stl)
+    torch.cuda.synchronize()
+    t_label = time.time() - tg
+    ok = torch.nonzero(stl[2] == 0).flatten()
+    lab = {k: (v[ok] if v.dim() == 1 else v[:, ok]).contiguous() for k, v in lab.items()}
+    lab["Y1"] = Y1d[:, ok].contiguous()
+    lab["T1"] = T1d[ok].contiguous()
+    info = dict(seeds=int(T.size), kept=int(kept.numel()),
+                kept_fraction=round(kept.numel() / T.size, 4),
+                mixing_samples=int((s >= 0).sum()), equilibrium_end_T=float(Ted.item()),
+                equilibrium_end_status=int(st[2, 0].item()), label_seconds=round(t_label, 3),
+                failed_labels=int(kept.numel() - ok.numel()),
+                seconds=round(time.time() - t0, 2))
+    log(f"[sampler] {info}")
+    return lab, info
+
+
 def timed_loop(run, restore, steps, warmup):
     import torch
     for _ in range(warmup):
@@ -480,6 +529,8 @@ def main():
     ap.add_argument("--big-cells", type=int, default=1 << 23,
                     help="cells of the large inference leg (BF16 and FP8; 0: skip)")
     ap.add_argument("--peaks", type=int, default=1, help="measure attainable peaks (1/0)")
+    ap.add_argument("--sample-seeds", type=int, default=1 << 21,
+                    help="seeds of the Sec. 3.1 sampler leg (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the chemistry step has no inter-GPU exchange "
@@ -500,6 +551,8 @@ def main():
     w_phys = tuple(float(x) for x in args.w_phys.split(","))
     model_plain = None
     train_plain = None
+    model_sampled = None
+    sample_info = None
     if args.model and os.path.exists(args.model):
         model = P.AnnModel.load(args.model)
         train_info = dict(loaded=args.model)
@@ -510,6 +563,12 @@ def main():
         train_info.update(tinfo)
         if args.compare_phys and any(w != 0.0 for w in w_phys):
             model_plain, train_plain = train_model(P, mech, gm, dev, args, lab, (0.0, 0.0, 0.0))
+        if args.sample_seeds:
+            del lab
+            torch.cuda.empty_cache()
+            lab, sample_info = sampled_labels(P, mech, gm, dev, args)
+            model_sampled, tinfo = train_model(P, mech, gm, dev, args, lab, w_phys)
+            sample_info.update(training=tinfo)
         train_info["total_seconds"] = round(time.time() - t0, 2)
         if args.save_model:
             model.save(args.save_model)
@@ -628,7 +687,8 @@ def main():
     del U, Yraw
     # the same network trained without the physics terms of the loss
     phys_cmp = None
-    if model_plain is not None:
+    data_cmp = None
+    if model_plain is not None or model_sampled is not None:
         def sample_step(mdl):
             Ts, ps, Ys = (T0d[idx_d].contiguous(), pd[idx_d].contiguous(),
                           Y0d[:, idx_d].contiguous())
@@ -645,10 +705,15 @@ def main():
                     "raw_residual_max": float(rr.max()),
                     "raw_residual_median": float(np.median(rr)),
                     "raw_residual_flags": int((rr > 1e-6).sum())}
-        phys_cmp = {"sample_cells": int(idx.size),
-                    "with_terms": dict(w_phys=list(w_phys), **sample_step(model)),
-                    "without_terms": sample_step(model_plain),
-                    "training_without_terms": train_plain}
+        if model_plain is not None:
+            phys_cmp = {"sample_cells": int(idx.size),
+                        "with_terms": dict(w_phys=list(w_phys), **sample_step(model)),
+                        "without_terms": sample_step(model_plain),
+                        "training_without_terms": train_plain}
+        if model_sampled is not None:
+            data_cmp = {"sample_cells": int(idx.size),
+                        "perturbed_recipe_states": sample_step(model),
+                        "sec31_sampler": dict(sample_step(model_sampled), data=sample_info)}
 
     # the same error against the GPU FP64 integrator, on every cell
     dY_fp = fp_Y - Y
@@ -823,6 +888,7 @@ def main():
                            "equal_to_eager": graph_equal},
         "fp64_sets": sets_out,
         "physics_terms_comparison": phys_cmp,
+        "training_data_comparison": data_cmp,
         "large": large,
         "attainable_peaks": None if peaks is None else {
             "measured_tflops": {k: round(v, 1) for k, v in peaks.items()},
