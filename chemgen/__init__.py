@@ -13,8 +13,8 @@ reactions, and stratified CH4/air (or H2/air) states at 1 atm.
 """
 from .mech import Mech, make_mechanism, MECH_CONFIGS, isomer_mechanism
 from .states import (make_states, perturb_states, STATE_CONFIGS, multiset_workload,
-                     element_matrix, hfrd_randoms, air_state, burnt_state)
+                     element_matrix, hfrd_randoms, air_state, burnt_state, flow_times)
 
 __all__ = ["Mech", "make_mechanism", "MECH_CONFIGS", "isomer_mechanism",
            "make_states", "perturb_states", "STATE_CONFIGS", "multiset_workload",
-           "element_matrix", "hfrd_randoms", "air_state", "burnt_state"]
+           "element_matrix", "hfrd_randoms", "air_state", "burnt_state", "flow_times"]

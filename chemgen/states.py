@@ -191,3 +191,14 @@ def burnt_state(mech: Mech, phi: float, T: float, fuel: str = "CH4", p: float = 
     temperature T: (T, p, Y[K])."""
     Y = _mass_fractions(mech, _moles_burnt(mech, fuel, np.array([phi])))
     return T, p, Y[:, 0].copy()
+
+
+def flow_times(N: int, seed: int, log_taylor=(-4.0, -2.0), log_kolmogorov=(-5.0, -3.0)):
+    """Per-cell turbulence time scales a flow solver would hand to the
+    chemistry closure: Taylor time 10^U(log_taylor) s and Kolmogorov time
+    10^U(log_kolmogorov) s (magnitudes of a laboratory jet flame's resolved
+    and sub-grid scales).  Returns (tau_taylor[N], tau_kolmogorov[N])."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    tT = 10.0 ** rng.uniform(log_taylor[0], log_taylor[1], N)
+    tK = 10.0 ** rng.uniform(log_kolmogorov[0], log_kolmogorov[1], N)
+    return tT, tK

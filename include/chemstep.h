@@ -374,13 +374,7 @@ chem_status chem_graph_launch(chem_graph *g, void *stream);
 /* Destroy a graph whose replays have finished (synchronise their stream). */
 void chem_graph_destroy(chem_graph *g);
 
-/* ---------------------------------------------------------- launch timing
- * Instrumentation for measurement: when enabled, every kernel launch the
- * library issues is bracketed by HIP events on its own stream.
- * chem_profile_read synchronises on those events and returns, per launch
- * label (host char[48]), the number of launches and their total duration in
- * milliseconds since the previous read; returns the number of labels written
- * (at most cap).  Off by default; costs two event records per launch. */
+/* ------------------------------------------------ training-set sampler */
 /* Options of the training-set sampler.  Defaults of Sec. 3.1 and Table 1:
  * alpha 0.125, beta 10, gamma 0.1, T_min 500 K, H/C in [2.65, 4.67], O/N in
  * [0.254, 0.32], phi in [0.20, 1.15]. */
@@ -422,6 +416,14 @@ chem_status chem_sample_states(const chem_mech *m, chem_batch seeds, const doubl
  * receives TFLOP/s in that order.  Synchronises `stream`; allocates and frees
  * a small sink buffer. */
 chem_status chem_measure_peaks(double *tflops, void *stream);
+
+/* ---------------------------------------------------------- launch timing
+ * Instrumentation for measurement: when enabled, every kernel launch the
+ * library issues is bracketed by HIP events on its own stream.
+ * chem_profile_read synchronises on those events and returns, per launch
+ * label (host char[48]), the number of launches and their total duration in
+ * milliseconds since the previous read; returns the number of labels written
+ * (at most cap).  Off by default; costs two event records per launch. */
 void chem_profile_enable(int32_t on);
 int32_t chem_profile_read(char (*names)[48], int64_t *launches, double *total_ms, int32_t cap);
 
