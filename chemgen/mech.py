@@ -83,6 +83,20 @@ _SPECIES_TABLE: Dict[str, tuple] = {
     "NO2":   ({"N": 1, "O": 2}, True, 33.1, 240.1),
     "N2O":   ({"N": 2, "O": 1}, False, 82.1, 219.9),
     "NH":    ({"N": 1, "H": 1}, True, 376.0, 181.2),
+    "C":     ({"C": 1}, True, 716.7, 158.1),
+    "C2H":   ({"C": 2, "H": 1}, True, 568.0, 207.4),
+    "CH2CO": ({"C": 2, "H": 2, "O": 1}, False, -47.7, 241.8),
+    "HCCO":  ({"C": 2, "H": 1, "O": 1}, True, 177.0, 255.0),
+    "CH3CHO": ({"C": 2, "H": 4, "O": 1}, False, -166.2, 263.8),
+    "C3H8":  ({"C": 3, "H": 8}, False, -104.7, 270.3),
+    "C3H6":  ({"C": 3, "H": 6}, False, 20.0, 266.6),
+    "NH2":   ({"N": 1, "H": 2}, True, 190.0, 194.7),
+    "NH3":   ({"N": 1, "H": 3}, False, -45.9, 192.8),
+    "HNO":   ({"H": 1, "N": 1, "O": 1}, True, 99.6, 220.7),
+    "HCN":   ({"H": 1, "C": 1, "N": 1}, False, 135.1, 201.8),
+    "CN":    ({"C": 1, "N": 1}, True, 438.7, 202.6),
+    "NCO":   ({"N": 1, "C": 1, "O": 1}, True, 131.8, 232.6),
+    "HNCO":  ({"H": 1, "N": 1, "C": 1, "O": 1}, False, -101.7, 238.0),
 }
 _REFERENCE_SPECIES = ("H2", "O2", "N2")
 
@@ -90,6 +104,8 @@ H2_SPECIES = ["H2", "O2", "H2O", "H", "O", "OH", "HO2", "H2O2", "N2"]
 CH4_SPECIES = ["H2", "O2", "H2O", "H", "O", "OH", "HO2", "H2O2", "CH4", "CH3", "CH2", "CH",
                "CH2O", "HCO", "CH3O", "CH2OH", "CH3OH", "CO", "CO2", "C2H6", "C2H5", "C2H4",
                "C2H3", "C2H2", "N2", "N", "NO", "NO2", "N2O", "NH"]
+WIDE_SPECIES = CH4_SPECIES + ["C", "C2H", "CH2CO", "HCCO", "CH3CHO", "C3H8", "C3H6", "NH2",
+                              "NH3", "HNO", "HCN", "CN", "NCO", "HNCO"]
 
 MECH_CONFIGS = {
     # 9 species / 20 reactions over H, O, N (small correctness case)
@@ -98,6 +114,10 @@ MECH_CONFIGS = {
     # 30 species / 150 reactions over C, H, O, N (the full-size case)
     "ch4": dict(species=CH4_SPECIES, elements=["C", "H", "O", "N"], n_reactions=150, seed=2002,
                 logA=(8.0, 14.0), b=(-1.0, 1.0), Ea=(0.0, 150e3)),
+    # 44 species / 220 reactions: above 32 species, so every kernel takes its
+    # widest form (a 64-lane group per cell in the integrator)
+    "wide": dict(species=WIDE_SPECIES, elements=["C", "H", "O", "N"], n_reactions=220,
+                 seed=3003, logA=(8.0, 14.0), b=(-1.0, 1.0), Ea=(0.0, 150e3)),
     # mild kinetics on the small species set, for explicit brute-force checks
     "h2_mild": dict(species=H2_SPECIES, elements=["H", "O", "N"], n_reactions=20, seed=1003,
                     logA=(8.0, 10.0), b=(-1.0, 1.0), Ea=(40e3, 150e3)),

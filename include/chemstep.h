@@ -409,6 +409,36 @@ chem_status chem_sample_states(const chem_mech *m, chem_batch seeds, const doubl
                                const chem_sample_opts *opts, double *T_out, double *p_out,
                                double *Y_out, uint8_t *keep, void *stream);
 
+/* ------------------------------------------------- turbulence closure */
+/* Options of the PaSR closure; NULL selects eta = 1e-3. */
+typedef struct {
+  double eta; /* a species takes part when |RR_k| >= eta max_j |RR_j| (in [0, 1]) */
+} chem_pasr_opts;
+
+/* Partially stirred reactor closure of the chemistry source (Sec. 4.1),
+ * applied to the result of a step (chem_step or ann_step): every rate of a
+ * cell is multiplied by its reacting fraction
+ *   kappa = tau_c / (tau_c + tau_mix),  tau_mix = sqrt(tau_T tau_K),
+ * where tau_T and tau_K are the flow solver's Taylor and Kolmogorov times and
+ * tau_c is the slowest chemical time max_k rho Y_k / |RR_k| over the species
+ * that take part (|RR_k| >= eta max_j |RR_j|, RR_k != 0), with rho the
+ * ideal-gas density of (T, p, Y) and Y clipped at 0.  A cell without such a
+ * species (all rates zero), or with tau_c + tau_mix = 0, has kappa = 1;
+ * otherwise a negative or NaN product tau_T tau_K gives kappa = NaN.
+ *   T [n], p [n]      state after the step (device, read);
+ *   Y [K][ld]         mass fractions after the step (device, read);
+ *   RR [K][ld]        in: the step's rates, kg/m^3/s; out: kappa RR (device);
+ *   tau_taylor [n], tau_kolmogorov [n]  flow time scales, s (device, read);
+ *   kappa [n], tau_c [n]  out (device, nullable; tau_c = +inf without a
+ *                     reacting species).
+ * One thread per cell, asynchronous on `stream`; argument errors (null
+ * arrays, ld < n, eta outside [0, 1]) are detected on the host. */
+chem_status chem_pasr_scale(const chem_mech *m, chem_batch batch, const double *T,
+                            const double *p, const double *Y, double *RR,
+                            const double *tau_taylor, const double *tau_kolmogorov,
+                            const chem_pasr_opts *opts, double *kappa, double *tau_c,
+                            void *stream);
+
 /* Attainable peaks of this GPU, measured: dense BF16 MFMA, FP8 MFMA
  * (E4M3 operands, unit block scales) and FP64 vector FMA, each by a launch
  * of 2048 blocks of 256 threads running eight independent accumulator

@@ -83,6 +83,7 @@ def lib():
             L.chem_measure_peaks.argtypes = [_P, _P]
             L.chem_sample_states.argtypes = [_P, Batch, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
                                              _P, _P, _P]
+            L.chem_pasr_scale.argtypes = [_P, Batch, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]
             L.chem_profile_enable.argtypes = [C.c_int32]
             L.chem_profile_read.argtypes = [_P, _P, _P, C.c_int32]
             L.chem_profile_read.restype = C.c_int32
@@ -385,6 +386,32 @@ def sample_states(mech: Mechanism, mech_desc, T, p, Y, c, s=None, end_eq=None, e
         C.byref(o), _dptr(To, f64), _dptr(po, f64), _dptr(Yo, f64), _dptr(keep, torch.uint8),
         _stream(stream)))
     return To, po, Yo, keep
+
+
+class PasrOpts(C.Structure):
+    _fields_ = [("eta", C.c_double)]
+
+
+def pasr_scale(mech: Mechanism, T, p, Y, RR, tau_taylor, tau_kolmogorov, eta=1e-3,
+               want_tau_c=True, stream=None):
+    """PaSR closure (chem_pasr_scale): RR [K, ld] is scaled in place by each
+    cell's reacting fraction; returns (kappa [n], tau_c [n] or None) device
+    tensors."""
+    import torch
+    n = T.shape[0]
+    ld = _soa(Y, mech.K, n, "Y")
+    if _soa(RR, mech.K, n, "RR") != ld:
+        raise ValueError("RR must have the leading dimension of Y")
+    f64 = torch.float64
+    kappa = torch.empty(n, dtype=f64, device=T.device)
+    tc = torch.empty(n, dtype=f64, device=T.device) if want_tau_c else None
+    o = PasrOpts(eta)
+    check("chem_pasr_scale", lib().chem_pasr_scale(
+        mech.handle, Batch(n, ld), _vec(T, n, "T", f64), _vec(p, n, "p", f64),
+        _dptr(Y, f64, "Y"), _dptr(RR, f64, "RR"), _vec(tau_taylor, n, "tau_taylor", f64),
+        _vec(tau_kolmogorov, n, "tau_kolmogorov", f64), C.byref(o), _dptr(kappa, f64),
+        _dptr(tc, f64), _stream(stream)))
+    return kappa, tc
 
 
 def measure_peaks(stream=None):

@@ -67,9 +67,7 @@ struct SampleArgs {
   chem_sample_opts o;
 };
 
-__global__ void k_sample(DevMech M, SampleArgs a) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= a.n) return;
+__device__ void sample_one(const DevMech &M, const SampleArgs &a, int64_t i) {
   const int K = M.K, n2 = a.o.n2;
   const int64_t ld = a.ld;
   const double s = a.s ? a.s[i] : -1.0;
@@ -125,6 +123,12 @@ __global__ void k_sample(DevMech M, SampleArgs a) {
   ok = ok && isfinite(on) && on >= a.o.on_min && on <= a.o.on_max;
   ok = ok && isfinite(phi) && phi >= a.o.phi_min && phi <= a.o.phi_max;
   a.keep[i] = ok ? 1 : 0;
+}
+
+__global__ void k_sample(DevMech M, SampleArgs a) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    sample_one(M, a, i);
 }
 
 }  // namespace
@@ -190,7 +194,8 @@ extern "C" chem_status chem_sample_states(const chem_mech *m, chem_batch seeds, 
   hipLaunchKernelGGL(k_ranges_fin, dim3(1), dim3(64), 0, st, part, RANGE_BLOCKS, ranges);
   SampleArgs a{n, seeds.ld, T, p, Y, c, s, end_eq, end_air, ranges, T_out, p_out, Y_out,
                keep, o};
-  const int64_t blocks = (n + 255) / 256;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > (1 << 20)) blocks = 1 << 20;  // larger batches loop over the grid
   hipLaunchKernelGGL(k_sample, dim3((unsigned)blocks), dim3(256), 0, st, m->d, a);
   CHEM_HIP(hipGetLastError());
   return CHEM_OK;

@@ -112,3 +112,15 @@ def test_binding_rejects_bad_1d_arrays():
     assert _vec(None, 5, "T") is None
     with pytest.raises(TypeError):
         _vec(torch.zeros(5, dtype=torch.float64), 5, "T")
+
+
+def test_pasr_arguments_rejected_on_host():
+    """chem_pasr_scale rejects a null handle, a bad batch and eta outside
+    [0, 1] before any device call; an empty batch needs no arrays.  The
+    mechanism handle is made on the host alone (its upload needs the GPU), so
+    only the null-handle case runs here."""
+    import paper_2312_05800_amd as P
+    L = P.lib()
+    B = P.binding.Batch
+    assert L.chem_pasr_scale(None, B(1, 1), *([None] * 6), None, None, None, None) == 1
+    assert L.chem_pasr_scale(None, B(0, 0), *([None] * 6), None, None, None, None) == 1

@@ -25,17 +25,24 @@ def dev():
 @pytest.fixture(scope="module")
 def gm(dev):
     import paper_2312_05800_amd as P
-    return {c: P.Mechanism(chemgen.make_mechanism(c)) for c in ("h2", "ch4")}
+    return {c: P.Mechanism(chemgen.make_mechanism(c)) for c in ("h2", "ch4", "wide")}
 
 
-@pytest.mark.parametrize("which,N", [("h2", 4096), ("ch4", 3001), ("h2", 1), ("ch4", 65)])
+def _states(mech, which, N, seed):
+    """The 44-species mechanism takes the CH4/air recipe (its extra species
+    start at zero)."""
+    return chemgen.make_states(mech, "ch4" if which == "wide" else which, N=N, seed=seed)
+
+
+@pytest.mark.parametrize("which,N", [("h2", 4096), ("ch4", 3001), ("h2", 1), ("ch4", 65),
+                                     ("wide", 777)])
 def test_rates_parity(dev, gm, which, N):
     import torch
     import paper_2312_05800_amd as P
     _say(f"[rates] {which} N={N}")
     mech = chemgen.make_mechanism(which)
     om = oracle.OracleMech(mech)
-    T, p, Y = chemgen.make_states(mech, which, N=N, seed=101)
+    T, p, Y = _states(mech, which, N, 101)
     w_o, dT_o, kf_o, kr_o = oracle.chem_rates(om, T, p, Y, want_k=True)
     out = P.chem_rates(gm[which], to_dev(T, dev), to_dev(p, dev), to_dev(Y, dev), kfkr=True)
     torch.cuda.synchronize()
@@ -72,15 +79,17 @@ def _gpu_step(P, gmech, dev, T, p, Y, dt, **kw):
                 stats=st.cpu().numpy(), h_hint=None if hd is None else hd.cpu().numpy())
 
 
-@pytest.mark.parametrize("which,N,dt", [("h2", 4096, 1e-6), ("ch4", 1500, 1e-5)])
+@pytest.mark.parametrize("which,N,dt", [("h2", 4096, 1e-6), ("ch4", 1500, 1e-5),
+                                        ("wide", 1001, 1e-5)])
 def test_step_parity(dev, gm, which, N, dt):
-    """The whole small config (4096 H2/air cells) and a ragged CH4 batch:
-    T and Y_k > 1e-10 within 1e-8 of the oracle, identical step counts."""
+    """The whole small config (4096 H2/air cells), a ragged CH4 batch and a
+    44-species mechanism (one 64-lane group per cell): T and Y_k > 1e-10
+    within 1e-8 of the oracle, identical step counts."""
     import paper_2312_05800_amd as P
     _say(f"[step] {which} N={N} dt={dt}")
     mech = chemgen.make_mechanism(which)
     om = oracle.OracleMech(mech)
-    T, p, Y = chemgen.make_states(mech, which, N=N, seed=202)
+    T, p, Y = _states(mech, which, N, 202)
     o = oracle.chem_step(om, dt, T, p, Y)
     g = _gpu_step(P, gm[which], dev, T, p, Y, dt)
     flips = np.nonzero(np.any(g["stats"][:2] != o["stats"][:2], axis=0))[0]
