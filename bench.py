@@ -26,6 +26,7 @@ METRIC = "chemistry cells/s per step: BF16 ANN vs FP64 stiff integrator, at stat
 PEAK_BF16 = 2500e12   # dense MFMA, FLOP/s
 PEAK_FP64 = 78.6e12   # vector FP64, FLOP/s
 PEAK_FP8 = 5000e12    # dense MFMA, FLOP/s
+PEAK_HBM = 8e12       # HBM3E, bytes/s
 HIDDEN = (1600, 800, 400)
 COPY_PROBE_DOUBLES = 1 << 25   # 256 MiB read + 256 MiB written by one plain copy kernel
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
@@ -597,6 +598,38 @@ def main():
     n_fallback = int(nfb.item())
     log(f"[ann] {args.steps} steps in {t_ann:.3f} s; fallback cells {n_fallback}")
 
+    # ---- PaSR closure of the step's rates (Sec. 4.1) ----
+    tT_np, tK_np = chemgen.flow_times(N, seed=76)
+    tTd, tKd = (torch.from_numpy(a).to(dev) for a in (tT_np, tK_np))
+    RR_ann = RR.clone()  # the network's rates of the last step
+    RRw = RR_ann.clone()
+    # back-to-back closures (each scales the last one's rates again: the same
+    # bytes move), so the host stays ahead of the GPU and the library's
+    # per-launch events time the kernel alone
+    for _ in range(args.warmup):
+        P.pasr_scale(gm, Td, pd, Yd, RRw, tTd, tKd, want_tau_c=False)
+    torch.cuda.synchronize()
+    P.profile_read()
+    t_pasr = time.perf_counter()
+    for _ in range(args.steps):
+        P.pasr_scale(gm, Td, pd, Yd, RRw, tTd, tKd, want_tau_c=False)
+    torch.cuda.synchronize()
+    t_pasr = time.perf_counter() - t_pasr
+    prof_pasr = P.profile_read()
+    RRw.copy_(RR_ann)
+    kap_ann = P.pasr_scale(gm, Td, pd, Yd, RRw, tTd, tKd)[0].cpu().numpy()
+    RRpasr_ann = RRw.cpu().numpy()
+    del RRw
+    # the whole step with the closure: network, fallback, then the closure
+    P.profile_read()
+    t_ann_pasr = timed_loop(lambda: (model.step(gm, 1e-5, Td, pd, Yd, RR=RR, flags=flags,
+                                                n_fallback=nfb),
+                                     P.pasr_scale(gm, Td, pd, Yd, RR, tTd, tKd,
+                                                  want_tau_c=False)),
+                            restore, args.steps, args.warmup)
+    P.profile_read()
+    log(f"[pasr] {args.steps} closures in {t_pasr:.4f} s; step + closure {t_ann_pasr:.3f} s")
+
     # ---- the same step captured as a HIP graph: one launch per step ----
     P.profile_enable(False)
     graph = model.step_graph(gm, 1e-5, Td, pd, Yd, RR=RR, flags=flags, n_fallback=nfb)
@@ -727,6 +760,16 @@ def main():
                  float(np.max(np.abs(fp_Y[:, idx] - o["Y"])[big] / np.abs(o["Y"])[big])))
     ann_Terr = float(np.sqrt(np.mean((ann_T[idx] - o["T"]) ** 2)))
 
+    # the closure under the surrogate: the network's rates against the
+    # oracle's step, both through the oracle's closure and the same flow times
+    from oracle import pasr as opasr
+    k_ref, _, RRp_ref = opasr.scale(mech, o["T"], p[idx], o["Y"], o["RR"], tT_np[idx],
+                                    tK_np[idx])
+    majors = [mech.index(n) for n in ("O2", "H2O", "CH4", "CO", "CO2")]
+    src_err = {mech.species[k]: round(float(np.linalg.norm(RRpasr_ann[k, idx] - RRp_ref[k]) /
+                                            max(np.linalg.norm(RRp_ref[k]), 1e-300)), 5)
+               for k in majors}
+
     # ---- roofline of the dominant kernels, from HIP events on their streams ----
     def avg(prof, label):
         c, tot = prof.get(label, (0, 0.0))
@@ -757,6 +800,10 @@ def main():
     ach_fp64 = step_flops / t_step
     kernels_ann = {k: dict(launches=v[0], avg_ms=round(v[1] / max(v[0], 1), 4))
                    for k, v in prof_ann.items()}
+    t_pk, c_pk = avg(prof_pasr, "pasr_scale")
+    # T, p, tau_T, tau_K, Y and RR in; RR and kappa out (tau_c not asked for)
+    pasr_bytes = 8 * N * (3 * K + 5)
+    pasr_gbs = pasr_bytes / t_pk / 1e9
     fp8_out = None
     if fp8 is not None:
         t8, c8 = avg(fp8["prof"], "mlp_l2_fp8")
@@ -884,6 +931,26 @@ def main():
                           # T, p, Y in; T, Y, stats out (FP64 SoA, int32 stats)
                           "algorithmic_bytes_per_launch": N * (8 + 8 + 8 * K + 8 + 8 * K + 12)},
         "kernels_ann": kernels_ann,
+        "pasr": {"workload": "the BF16 step's rates and state on the same 2^20 cells; Taylor "
+                             "times 10^U(-4,-2) s, Kolmogorov times 10^U(-5,-3) s (seed 76)",
+                 "ms_per_closure": round(1e3 * t_pasr / args.steps, 4),
+                 "ann_step_with_closure": {
+                     "cells_per_s": round(N * args.steps / t_ann_pasr, 1),
+                     "ms_per_step": round(1e3 * t_ann_pasr / args.steps, 4)},
+                 "kappa_quantiles_0_1_50_99": [float(x) for x in
+                                               np.quantile(kap_ann, [0.0, 0.01, 0.5, 0.99])],
+                 "cells_kappa_below_0p99": int((kap_ann < 0.99).sum()),
+                 "vs_oracle": {"sample_cells": int(idx.size),
+                               "kappa_max_abs_err": float(np.max(np.abs(kap_ann[idx] - k_ref))),
+                               "scaled_source_rel_l2_err_major": src_err},
+                 "roofline": {"kernel": "k_pasr (64 cells per block, one species row of "
+                                        "64 cells per wave load, FP64 SoA)",
+                              "bound": "hbm", "achieved": round(pasr_gbs, 1),
+                              "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                              "frac": round(pasr_gbs * 1e9 / PEAK_HBM, 4),
+                              "traffic": measured_traffic("pasr_scale"),
+                              "avg_ms": round(t_pk * 1e3, 4), "launches": c_pk,
+                              "algorithmic_bytes_per_launch": pasr_bytes}},
         "ann_step_graph": {"ms_per_step": round(1e3 * t_graph / args.steps, 4),
                            "equal_to_eager": graph_equal},
         "fp64_sets": sets_out,
