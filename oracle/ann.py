@@ -187,6 +187,32 @@ def backward(params, X, target, prec="fp64"):
     return grads, l1_loss(u, target)
 
 
+# ------------------------------------------- per-species ensemble (Sec. 3.2)
+#
+# Sec. 3.2 trains and runs one network per species: K networks with the same
+# inputs and hidden widths, member k predicting the change of species k
+# alone.  The ensemble's loss is the mean of the members' L1 losses (which
+# equals the L1 mean over samples and species of the single network), so
+# member k's gradient is the gradient of its own loss divided by K.
+
+
+def ensemble_forward(members, X, prec="fp64"):
+    """members: K parameter lists with one output each.  Returns [N, K]."""
+    return np.concatenate([forward(p, X, prec=prec) for p in members], axis=1)
+
+
+def ensemble_backward(members, X, target, prec="fp64"):
+    """Gradients of the ensemble's loss with respect to every member's
+    parameters (a list per member, as backward returns), and the loss."""
+    K = len(members)
+    grads, losses = [], []
+    for k, p in enumerate(members):
+        g, loss = backward(p, X, target[:, k:k + 1], prec=prec)
+        grads.append([(dW / K, db / K) for dW, db in g])
+        losses.append(loss)
+    return grads, float(np.mean(losses))
+
+
 # ------------------------------------------------- physics terms of the loss
 #
 # Sec. 3.2 adds three physical principles to the loss -- conservation of the

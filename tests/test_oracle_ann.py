@@ -459,3 +459,47 @@ def test_phys_gradient_finite_differences(phys_batch):
     assert tot0 == l1b
     for (a, c), (d, e) in zip(g0, g1):
         assert np.array_equal(a, d) and np.array_equal(c, e)
+
+
+def _block_diagonal(members):
+    """One network equal to the ensemble: the members' first layers stacked
+    (they share the input), every later layer block-diagonal."""
+    K = len(members)
+    big = []
+    for l in range(len(members[0])):
+        Ws = [p[l][0] for p in members]
+        bs = np.concatenate([p[l][1] for p in members])
+        if l == 0:
+            W = np.vstack(Ws)
+        else:
+            fo, fi = Ws[0].shape
+            W = np.zeros((K * fo, K * fi))
+            for k in range(K):
+                W[k * fo:(k + 1) * fo, k * fi:(k + 1) * fi] = Ws[k]
+        big.append((W, bs))
+    return big
+
+
+def test_ensemble_is_a_block_diagonal_network():
+    """Five one-output members equal one wide network whose hidden layers are
+    block-diagonal: same outputs, and the diagonal blocks of that network's
+    L1 gradient (mean over samples and its five outputs) are the members'
+    gradients of the ensemble loss."""
+    rng = np.random.default_rng(41)
+    K, sizes = 5, [7, 12, 9, 6, 1]
+    members = [ann.init_params(sizes, 100 + k) for k in range(K)]
+    X = rng.standard_normal((33, sizes[0]))
+    target = rng.standard_normal((33, K))
+    big = _block_diagonal(members)
+    np.testing.assert_allclose(ann.ensemble_forward(members, X), ann.forward(big, X),
+                               rtol=1e-12, atol=1e-14)
+    g_ens, loss_ens = ann.ensemble_backward(members, X, target)
+    g_big, loss_big = ann.backward(big, X, target)
+    np.testing.assert_allclose(loss_ens, loss_big, rtol=1e-13)
+    for l in range(len(sizes) - 1):
+        fo, fi = members[0][l][0].shape
+        for k in range(K):
+            r = slice(k * fo, (k + 1) * fo)
+            c = slice(0, fi) if l == 0 else slice(k * fi, (k + 1) * fi)
+            np.testing.assert_allclose(g_ens[k][l][0], g_big[l][0][r, c], rtol=1e-11, atol=1e-15)
+            np.testing.assert_allclose(g_ens[k][l][1], g_big[l][1][r], rtol=1e-11, atol=1e-15)
