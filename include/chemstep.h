@@ -175,6 +175,11 @@ typedef struct {
   int32_t n_out;      /* K */
   int32_t hidden[3];  /* hidden widths */
   int32_t prec;       /* 0 = BF16 everywhere (the only value this build accepts) */
+  int32_t members;    /* 0 or 1: one network with n_out outputs; n_out: the per-species
+                         ensemble of Sec. 3.2 (one network with the same inputs and hidden
+                         widths and a single output per species; their loss is the mean of
+                         the members' L1 losses).  Every entry point takes either; the
+                         physics terms of the loss and the FP8 variant need one network. */
 } ann_arch;
 
 /* Normalisation and validity statistics (all arrays host, copied). */
@@ -190,7 +195,9 @@ typedef struct {
  * from `seed`, zero Adam state, no statistics.  Owns device memory. */
 chem_status ann_create(const ann_arch *arch, uint64_t seed, ann_model **out);
 void ann_destroy(ann_model *m);
-/* Layer l in 0..3: W (host) [out][in] row-major FP32, b (host) [out]. */
+/* Layer l in 0..3: W (host) [out][in] row-major FP32, b (host) [out].  In an
+ * ensemble, index 4 g + l is layer l of member g (its output layer has one
+ * row). */
 chem_status ann_set_layer(ann_model *m, int32_t layer, const float *W, const float *b);
 chem_status ann_get_layer(const ann_model *m, int32_t layer, float *W, float *b);
 /* Gradients of the loss from the last ann_train_step (host arrays as above). */

@@ -13,7 +13,7 @@ _P = C.c_void_p
 
 class Arch(C.Structure):
     _fields_ = [("n_in", C.c_int32), ("n_out", C.c_int32), ("hidden", C.c_int32 * 3),
-                ("prec", C.c_int32)]
+                ("prec", C.c_int32), ("members", C.c_int32)]
 
 
 class Norm(C.Structure):
@@ -59,15 +59,16 @@ def _prototypes(L):
 
 
 class AnnModel:
-    """Handle of a surrogate network (ann_model)."""
+    """Handle of a surrogate network (ann_model); members = n_out makes the
+    per-species ensemble (layer index 4 g + l addresses member g)."""
 
     def __init__(self, n_in=None, n_out=None, hidden=(1600, 800, 400), seed=0, prec=0,
-                 _handle=None):
+                 members=1, _handle=None):
         lib()
         if _handle is not None:
             self.handle = _handle
         else:
-            a = Arch(int(n_in), int(n_out), (C.c_int32 * 3)(*hidden), int(prec))
+            a = Arch(int(n_in), int(n_out), (C.c_int32 * 3)(*hidden), int(prec), int(members))
             h = _P()
             check("ann_create", lib().ann_create(C.byref(a), C.c_uint64(seed), C.byref(h)))
             self.handle = h

@@ -41,6 +41,9 @@ struct SplitMix {
 struct ann_model {
   int device = 0;
   int n_in = 0, n_out = 0, prec = 0;
+  // networks: 1, or n_out for the per-species ensemble (member g predicts
+  // species g; every per-layer array holds the members one after another)
+  int G = 1;
   ann::Layer L[ann::NLAYER];
   float *Wm[ann::NLAYER] = {}, *bm[ann::NLAYER] = {};  // FP32 master parameters
   u16 *Wb[ann::NLAYER] = {};                           // BF16 copies used by the GEMMs
@@ -60,6 +63,7 @@ struct ann_model {
   Workspace wi;
   u16 *X = nullptr, *H[3] = {};
   float *U = nullptr;
+  float *Um = nullptr;
   int32_t *fb_index = nullptr;  // fallback cell list (own allocation, fb_cap entries)
   int64_t fb_cap = 0;
   unsigned long long *fb_count = nullptr;
@@ -95,6 +99,10 @@ int pad32(int x) { return (x + 31) / 32 * 32; }
 
 size_t layer_elems(const ann::Layer &L) { return (size_t)L.doutp * L.dinp; }
 
+// Row width of the network output U (species padded to 32); one network's
+// output layer width, the assembled ensemble's otherwise.
+int uw(const ann_model *m) { return pad32(m->n_out); }
+
 // E4M3 layout: L2 reads H1q [cells][kq1] and Wq1 [n2p][kq1]; L3 reads H2q
 // [cells][k3p] and Wq2 [L3 outputs][k3p]; K widths padded to 128 with zeros.
 int fp8_n2p(const ann_model *m) { return (m->L[1].dout + 31) / 32 * 32; }
@@ -108,6 +116,7 @@ struct InferWs {
   int64_t cap = 0;  // rows between K-blocks of the K-blocked activations
   u16 *X = nullptr, *H[3] = {};
   float *U = nullptr;
+  float *Um = nullptr;  // one ensemble member's output [cap][32] before its column is taken
   uint8_t *ood = nullptr;
   unsigned long long *fb_count = nullptr;
   uint8_t *H1q = nullptr, *H2q = nullptr;  // E4M3 activations, rows padded with zeros
@@ -128,22 +137,27 @@ size_t infer_layout(const ann_model *m, int64_t cap, bool fb_list, unsigned char
   const size_t oX = sect((size_t)cap * m->L[0].dinp * 2);
   size_t oH[3];
   for (int l = 0; l < 3; ++l) oH[l] = sect((size_t)cap * m->L[l].doutp * 2);
-  const size_t oU = sect((size_t)cap * m->L[3].doutp * 4);
+  const size_t oU = sect((size_t)cap * uw(m) * 4);
+  const size_t oUm = m->G > 1 ? sect((size_t)cap * m->L[3].doutp * 4) : 0;
   const size_t oO = sect((size_t)cap);
   const size_t oC = sect(64);
-  const size_t oQ1 = sect((size_t)cap * fp8_kq1(m));
-  const size_t oQ2 = sect((size_t)cap * fp8_k3p(m));
+  // E4M3 activations (the FP8 variant exists for single networks only)
+  const size_t q1 = m->G > 1 ? 0 : (size_t)cap * fp8_kq1(m);
+  const size_t q2 = m->G > 1 ? 0 : (size_t)cap * fp8_k3p(m);
+  const size_t oQ1 = sect(q1);
+  const size_t oQ2 = sect(q2);
   const size_t oF = fb_list ? sect((size_t)cap * 4) : 0;
   if (base && w) {
     w->cap = cap;
     w->X = (u16 *)(base + oX);
     for (int l = 0; l < 3; ++l) w->H[l] = (u16 *)(base + oH[l]);
     w->U = (float *)(base + oU);
+    w->Um = m->G > 1 ? (float *)(base + oUm) : nullptr;
     w->ood = base + oO;
     w->fb_count = (unsigned long long *)(base + oC);
     w->H1q = base + oQ1;
     w->H2q = base + oQ2;
-    w->q_bytes = oQ2 - oQ1 + (size_t)cap * fp8_k3p(m);
+    w->q_bytes = oQ2 - oQ1 + q2;
     w->fb_index = fb_list ? (int32_t *)(base + oF) : nullptr;
   }
   return off;
@@ -156,6 +170,7 @@ InferWs model_ws(const ann_model *m) {
   w.X = m->X;
   for (int l = 0; l < 3; ++l) w.H[l] = m->H[l];
   w.U = m->U;
+  w.Um = m->Um;
   w.ood = m->ood;
   w.fb_count = m->fb_count;
   w.H1q = m->H1q;
@@ -186,13 +201,14 @@ chem_status grow_infer(ann_model *m, int64_t n) {
   m->X = w.X;
   for (int l = 0; l < 3; ++l) m->H[l] = w.H[l];
   m->U = w.U;
+  m->Um = w.Um;
   m->ood = w.ood;
   m->fb_count = w.fb_count;
   m->H1q = w.H1q;
   m->H2q = w.H2q;
   // the E4M3 activation rows are padded to multiples of 128 bytes; the
   // padding is never written and must read as zero
-  if (hipMemset(w.H1q, 0, w.q_bytes) != hipSuccess) {
+  if (w.q_bytes && hipMemset(w.H1q, 0, w.q_bytes) != hipSuccess) {
     set_error("ann: cannot clear the E4M3 activation workspace");
     return CHEM_EHIP;
   }
@@ -204,8 +220,8 @@ chem_status grow_infer(ann_model *m, int64_t n) {
 // Split-K factor of a weight-gradient GEMM (M x N output, K = batch rows): a
 // power of two that brings the launch to about 1024 blocks of 128 x 128, while
 // every split keeps a multiple of 32 rows.
-int wgrad_splits(int M, int N, int64_t K) {
-  const long tiles = (long)((M + 127) / 128) * ((N + 127) / 128);
+int wgrad_splits(int M, int N, int64_t K, int groups = 1) {
+  const long tiles = (long)((M + 127) / 128) * ((N + 127) / 128) * groups;
   int S = 1;
   while (tiles * S < 1024 && S < 16 && K % (64L * S) == 0) S *= 2;
   return S;
@@ -219,27 +235,30 @@ chem_status grow_train(ann_model *m, int64_t B) {
     off = align256(off + bytes);
     return o;
   };
+  // the input rows and targets are shared by the members of an ensemble;
+  // activations, outputs and gradients are per member
+  const size_t G = (size_t)m->G;
   const size_t oX = sect((size_t)B * m->L[0].dinp * 2);
   size_t oH[3], oZ[3], oGb[4], oGf[4];
   for (int l = 0; l < 3; ++l) {
-    oH[l] = sect((size_t)B * m->L[l].doutp * 2);
-    oZ[l] = sect((size_t)B * m->L[l].doutp * 4);
+    oH[l] = sect(G * B * m->L[l].doutp * 2);
+    oZ[l] = sect(G * B * m->L[l].doutp * 4);
   }
-  const size_t oU = sect((size_t)B * m->L[3].doutp * 4);
-  const size_t oUt = sect((size_t)B * m->L[3].doutp * 4);
+  const size_t oU = sect(G * B * m->L[3].doutp * 4);
+  const size_t oUt = sect((size_t)B * uw(m) * 4);
   for (int l = 0; l < 4; ++l) {
-    oGb[l] = sect((size_t)B * m->L[l].doutp * 2);
-    oGf[l] = sect((size_t)B * m->L[l].doutp * 4);
+    oGb[l] = sect(G * B * m->L[l].doutp * 2);
+    oGf[l] = sect(G * B * m->L[l].doutp * 4);
   }
   const size_t oL = sect(LOSS_PARTS * 8);
   const size_t oP = sect(ann::PHYS_PARTS * 3 * 8);
   size_t col_n = 0, wg_n = 0;
   for (int l = 0; l < 4; ++l) {
     const ann::Layer &L = m->L[l];
-    col_n = std::max(col_n, (size_t)ann::COLSUM_PARTS * L.doutp);
+    col_n = std::max(col_n, G * ann::COLSUM_PARTS * L.doutp);
     // the largest split any batch size can select (K = 2^30 divides by all)
-    const int S = wgrad_splits(L.doutp, L.dinp, 1L << 30);
-    if (S > 1) wg_n = std::max(wg_n, (size_t)S * L.doutp * L.dinp);
+    const int S = wgrad_splits(L.doutp, L.dinp, 1L << 30, m->G);
+    if (S > 1) wg_n = std::max(wg_n, (size_t)S * G * L.doutp * L.dinp);
   }
   const size_t oC = sect(col_n * 8);
   const size_t oW = sect(wg_n * 4);
@@ -272,25 +291,32 @@ chem_status grow_train(ann_model *m, int64_t B) {
 }
 
 // Uploads logical [dout][din] FP32 weights into the padded device layout.
-chem_status upload_layer(ann_model *m, int l, const float *W, const float *b) {
+// Layer index idx = 4 g + l: layer l of member g (g = 0 for one network).
+chem_status upload_layer(ann_model *m, int idx, const float *W, const float *b) {
+  const int l = idx & 3, g = idx >> 2;
   const ann::Layer &L = m->L[l];
+  const size_t ow = (size_t)g * layer_elems(L), ob = (size_t)g * L.doutp;
   std::vector<float> Wp((size_t)L.doutp * L.dinp, 0.0f), bp(L.doutp, 0.0f);
   for (int o = 0; o < L.dout; ++o) {
     for (int i = 0; i < L.din; ++i) Wp[(size_t)o * L.dinp + i] = W[(size_t)o * L.din + i];
     bp[o] = b[o];
   }
-  CHEM_HIP(hipMemcpy(m->Wm[l], Wp.data(), Wp.size() * 4, hipMemcpyHostToDevice));
-  CHEM_HIP(hipMemcpy(m->bm[l], bp.data(), bp.size() * 4, hipMemcpyHostToDevice));
+  CHEM_HIP(hipMemcpy(m->Wm[l] + ow, Wp.data(), Wp.size() * 4, hipMemcpyHostToDevice));
+  CHEM_HIP(hipMemcpy(m->bm[l] + ob, bp.data(), bp.size() * 4, hipMemcpyHostToDevice));
   m->wt_stale = true;
-  chem_status st = ann::to_bf16((int64_t)Wp.size(), m->Wm[l], m->Wb[l], nullptr);
+  chem_status st = ann::to_bf16((int64_t)Wp.size(), m->Wm[l] + ow, m->Wb[l] + ow, nullptr);
   if (st != CHEM_OK) return st;
   CHEM_HIP(hipDeviceSynchronize());
   return CHEM_OK;
 }
 
-chem_status download_pair(const ann_model *m, int l, const float *dW, const float *db, float *W,
+// dW, db: the per-layer arrays of layer idx & 3 (all members); idx = 4 g + l.
+chem_status download_pair(const ann_model *m, int idx, const float *dW, const float *db, float *W,
                           float *b) {
+  const int l = idx & 3, g = idx >> 2;
   const ann::Layer &L = m->L[l];
+  dW += (size_t)g * layer_elems(L);
+  db += (size_t)g * L.doutp;
   std::vector<float> Wp((size_t)L.doutp * L.dinp), bp(L.doutp);
   CHEM_HIP(hipDeviceSynchronize());
   CHEM_HIP(hipMemcpy(Wp.data(), dW, Wp.size() * 4, hipMemcpyDeviceToHost));
@@ -352,12 +378,19 @@ extern "C" chem_status ann_create(const ann_arch *arch, uint64_t seed, ann_model
     set_error("ann_create: only BF16 hidden layers (prec 0) are available in this build");
     return CHEM_EUNSUPPORTED;
   }
+  const int G = arch->members <= 1 ? 1 : arch->members;
+  if (G > 1 && G != arch->n_out) {
+    set_error("ann_create: an ensemble has one member per output (members = n_out = %d, got "
+              "%d)", arch->n_out, arch->members);
+    return CHEM_EINVAL;
+  }
   ann_model *m = new ann_model();
   m->n_in = arch->n_in;
   m->n_out = arch->n_out;
   m->prec = arch->prec;
+  m->G = G;
   const int dims[5] = {arch->n_in, arch->hidden[0], arch->hidden[1], arch->hidden[2],
-                       arch->n_out};
+                       G > 1 ? 1 : arch->n_out};
   for (int l = 0; l < 4; ++l) {
     m->L[l].din = dims[l];
     m->L[l].dout = dims[l + 1];
@@ -371,9 +404,9 @@ extern "C" chem_status ann_create(const ann_arch *arch, uint64_t seed, ann_model
     off = align256(off + bytes);
     return o;
   };
-  const size_t oW2p = sect(layer_elems(m->L[1]) * 2);
+  const size_t oW2p = sect(G * layer_elems(m->L[1]) * 2);
   for (int l = 0; l < 4; ++l) {
-    const size_t e = layer_elems(m->L[l]), nb = m->L[l].doutp;
+    const size_t e = G * layer_elems(m->L[l]), nb = G * m->L[l].doutp;
     oW[l] = sect(e * 4);
     ob[l] = sect(nb * 4);
     oWb[l] = sect(e * 2);
@@ -412,15 +445,15 @@ extern "C" chem_status ann_create(const ann_arch *arch, uint64_t seed, ann_model
     m->gW[l] = (float *)(b + ogW[l]);
     m->gb[l] = (float *)(b + ogb[l]);
   }
-  // W, b ~ U(-1/sqrt(fan_in), +1/sqrt(fan_in))
+  // W, b ~ U(-1/sqrt(fan_in), +1/sqrt(fan_in)), member after member
   SplitMix rng{seed};
-  for (int l = 0; l < 4; ++l) {
-    const ann::Layer &L = m->L[l];
+  for (int idx = 0; idx < 4 * G; ++idx) {
+    const ann::Layer &L = m->L[idx & 3];
     const double bound = 1.0 / sqrt((double)L.din);
     std::vector<float> W((size_t)L.dout * L.din), bb(L.dout);
     for (auto &w : W) w = (float)((2.0 * rng.uniform() - 1.0) * bound);
     for (auto &w : bb) w = (float)((2.0 * rng.uniform() - 1.0) * bound);
-    chem_status st = upload_layer(m, l, W.data(), bb.data());
+    chem_status st = upload_layer(m, idx, W.data(), bb.data());
     if (st != CHEM_OK) {
       ann_destroy(m);
       return st;
@@ -445,7 +478,7 @@ extern "C" chem_status ann_set_layer(ann_model *m, int32_t layer, const float *W
                                      const float *b) {
   chem_status st = check_model("ann_set_layer", m);
   if (st != CHEM_OK) return st;
-  if (layer < 0 || layer >= ann::NLAYER || !W || !b) {
+  if (layer < 0 || layer >= ann::NLAYER * m->G || !W || !b) {
     set_error("ann_set_layer: bad layer index or null array");
     return CHEM_EINVAL;
   }
@@ -455,34 +488,34 @@ extern "C" chem_status ann_set_layer(ann_model *m, int32_t layer, const float *W
 extern "C" chem_status ann_get_layer(const ann_model *m, int32_t layer, float *W, float *b) {
   chem_status st = check_model("ann_get_layer", m);
   if (st != CHEM_OK) return st;
-  if (layer < 0 || layer >= ann::NLAYER) {
+  if (layer < 0 || layer >= ann::NLAYER * m->G) {
     set_error("ann_get_layer: bad layer index");
     return CHEM_EINVAL;
   }
-  return download_pair(m, layer, m->Wm[layer], m->bm[layer], W, b);
+  return download_pair(m, layer, m->Wm[layer & 3], m->bm[layer & 3], W, b);
 }
 
 extern "C" chem_status ann_get_grad(const ann_model *m, int32_t layer, float *dW, float *db) {
   chem_status st = check_model("ann_get_grad", m);
   if (st != CHEM_OK) return st;
-  if (layer < 0 || layer >= ann::NLAYER) {
+  if (layer < 0 || layer >= ann::NLAYER * m->G) {
     set_error("ann_get_grad: bad layer index");
     return CHEM_EINVAL;
   }
-  return download_pair(m, layer, m->gW[layer], m->gb[layer], dW, db);
+  return download_pair(m, layer, m->gW[layer & 3], m->gb[layer & 3], dW, db);
 }
 
 extern "C" chem_status ann_get_moments(const ann_model *m, int32_t layer, float *mW, float *vW,
                                        float *mb, float *vb) {
   chem_status st = check_model("ann_get_moments", m);
   if (st != CHEM_OK) return st;
-  if (layer < 0 || layer >= ann::NLAYER) {
+  if (layer < 0 || layer >= ann::NLAYER * m->G) {
     set_error("ann_get_moments: bad layer index");
     return CHEM_EINVAL;
   }
-  st = download_pair(m, layer, m->mW[layer], m->mb[layer], mW, mb);
+  st = download_pair(m, layer, m->mW[layer & 3], m->mb[layer & 3], mW, mb);
   if (st != CHEM_OK) return st;
-  return download_pair(m, layer, m->vW[layer], m->vb[layer], vW, vb);
+  return download_pair(m, layer, m->vW[layer & 3], m->vb[layer & 3], vW, vb);
 }
 
 extern "C" chem_status ann_set_norm(ann_model *m, const ann_norm *nm) {
@@ -612,6 +645,118 @@ bool tiled_path(const ann_model *m, int64_t n) {
   return b.doutp % 400 == 0 && (c.doutp % 416 == 0 || c.doutp % 400 == 0);
 }
 
+// The per-species ensemble: the shared input rows once, then each member's
+// four layers on the single network's kernels (its weights at the member's
+// offset), its one output written to U's column g.  Members run one after
+// another: at inference sizes every launch fills the GPU on its own.
+chem_status forward_members(ann_model *m, const InferWs &w, int64_t n, float *U, int ldu,
+                            hipStream_t s) {
+  chem_status st;
+  const bool tl = tiled_path(m, n);
+  const long cap = (long)w.cap;
+  const int G = m->G;
+  if (m->wt_stale) {
+    for (int g = 0; g < G; ++g) {
+      for (int l = 1; l <= 2; ++l) {
+        const size_t o = (size_t)g * layer_elems(m->L[l]);
+        if ((st = ann::tile_bf16(m->L[l].doutp, m->L[l].dinp, m->Wb[l] + o, m->Wt[l] + o, s)) !=
+            CHEM_OK)
+          return st;
+      }
+      const size_t o1 = (size_t)g * layer_elems(m->L[1]);
+      if ((st = ann::tile_bf16(m->L[1].doutp, m->L[1].dinp, m->Wb[1] + o1, m->W2p + o1, s,
+                               true)) != CHEM_OK)
+        return st;
+    }
+    m->wt_stale = false;
+  }
+  const int uo = m->L[3].doutp;  // a member's padded output width
+  for (int g = 0; g < G; ++g) {
+    size_t ow[4], ob[4];
+    for (int l = 0; l < 4; ++l) {
+      ow[l] = (size_t)g * layer_elems(m->L[l]);
+      ob[l] = (size_t)g * m->L[l].doutp;
+    }
+    const u16 *in = w.X;
+    bool in_tiled = false;
+    int l0 = 0;
+    {
+      const ann::Layer &L0 = m->L[0], &L1 = m->L[1];
+      ann::Mlp12Args f{};
+      f.M = (int)n;
+      f.N = L1.doutp;
+      f.K = L1.dinp;
+      f.X = w.X;
+      f.W1 = m->Wb[0] + ow[0];
+      f.b1 = m->bm[0] + ob[0];
+      f.W2p = m->W2p + ow[1];
+      f.ldw2 = (long)L1.doutp * 32;
+      f.b2 = m->bm[1] + ob[1];
+      f.H = w.H[1];
+      f.ldh = tl ? cap * 32 : L1.doutp;
+      f.tiled = tl;
+      if (L0.dinp == 32 && L0.doutp == L1.dinp && ann::mlp12_ok(f)) {
+        if ((st = ann::mlp12(f, s, "mlp_l12")) != CHEM_OK) return st;
+        in = w.H[1];
+        in_tiled = tl;
+        l0 = 2;
+      }
+    }
+    bool done = false;
+    for (int l = l0; l < 4 && !done; ++l) {
+      const ann::Layer &L = m->L[l];
+      ann::GemmArgs a{};
+      a.M = (int)n;
+      a.K = L.dinp;
+      a.A = in;
+      a.lda = in_tiled ? cap * 32 : L.dinp;
+      const bool wt = tl && (l == 1 || l == 2);
+      a.B = (wt ? m->Wt[l] : m->Wb[l]) + ow[l];
+      a.ldb = wt ? (long)L.doutp * 32 : L.dinp;
+      a.bias = m->bm[l] + ob[l];
+      a.tiled = (in_tiled ? ann::TILED_A : 0) | (wt ? ann::TILED_B : 0);
+      if (l == 2) {
+        a.N = L.doutp;
+        a.B2 = m->Wb[3] + ow[3];
+        a.bias2 = m->bm[3] + ob[3];
+        a.N2 = uo;
+        a.Cf = w.Um;
+        a.ldcf = uo;
+        if (ann::gemm_fuses_next(a)) {
+          if ((st = ann::gemm(a, true, true, ann::EPI_GELU_NEXT, s, "mlp_l3_l4")) != CHEM_OK)
+            return st;
+          done = true;
+          break;
+        }
+        a.B2 = nullptr;
+        a.bias2 = nullptr;
+        a.N2 = 0;
+        a.Cf = nullptr;
+        a.ldcf = 0;
+      }
+      if (l < 3) {
+        const bool ct = tl && l < 2;
+        a.N = L.doutp;
+        a.Cb = w.H[l];
+        a.ldcb = ct ? cap * 32 : L.doutp;
+        a.tiled |= ct ? ann::TILED_C : 0;
+        static const char *lab[3] = {"mlp_l1", "mlp_l2", "mlp_l3"};
+        st = ann::gemm(a, true, true, ann::EPI_GELU, s, lab[l]);
+        in = w.H[l];
+        in_tiled = ct;
+      } else {
+        a.N = uo;
+        a.Cf = w.Um;
+        a.ldcf = uo;
+        st = ann::gemm(a, true, true, ann::EPI_F32, s, "mlp_l4");
+      }
+      if (st != CHEM_OK) return st;
+    }
+    if ((st = ann::take_col(n, w.Um, uo, U + g, ldu, s)) != CHEM_OK) return st;
+  }
+  return CHEM_OK;
+}
+
 // keep_h1: write the first two layers' activations row-major to H[0], H[1]
 // (no fused first two layers, no K-blocked layouts), for the FP8 calibration
 // that reads their first n rows
@@ -622,6 +767,7 @@ chem_status forward_chunk(ann_model *m, const InferWs &w, int64_t n, int64_t ld,
                    m->nm.lambda, w.X, ood, m->nm.lo, m->nm.hi, ood_margin};
   chem_status st = ann::features(fa, s);
   if (st != CHEM_OK) return st;
+  if (m->G > 1) return forward_members(m, w, n, U, ldu, s);
   const bool tl = !keep_h1 && tiled_path(m, n);
   const long cap = (long)w.cap;  // rows between K-blocks of the activations
   if (!m->use_fp8 && m->wt_stale) {
@@ -903,7 +1049,7 @@ chem_status step_impl(ann_model *m, const chem_mech *mech, chem_batch batch, dou
   const bool dt_mismatch = fabs(dt - m->nm.dt_model) > 1e-6 * m->nm.dt_model;
   for (int64_t c0 = 0; c0 < batch.n; c0 += w.cap) {
     const int64_t nc = (batch.n - c0 < w.cap) ? batch.n - c0 : w.cap;
-    st = forward_chunk(m, w, nc, batch.ld, T + c0, p + c0, Y + c0, w.U, m->L[3].doutp, w.ood,
+    st = forward_chunk(m, w, nc, batch.ld, T + c0, p + c0, Y + c0, w.U, uw(m), w.ood,
                        o.ood_margin, s);
     if (st != CHEM_OK) return st;
     ann::PostArgs pa{};
@@ -916,7 +1062,7 @@ chem_status step_impl(ann_model *m, const chem_mech *mech, chem_batch batch, dou
     pa.RR = RR ? RR + c0 : nullptr;
     pa.flags = flags ? flags + c0 : nullptr;
     pa.U = w.U;
-    pa.doutp = m->L[3].doutp;
+    pa.doutp = uw(m);
     pa.nm = m->nm;
     pa.n_in = m->n_in;
     pa.residual_tol = o.residual_tol;
@@ -1048,6 +1194,11 @@ extern "C" chem_status ann_train_step(ann_model *m, const chem_mech *mech, chem_
     set_error("ann_train_step: physics weights must be >= 0");
     return CHEM_EINVAL;
   }
+  if (phys && m->G > 1) {
+    set_error("ann_train_step: the physics terms act on the whole predicted change; the members "
+              "of a per-species ensemble each see one species");
+    return CHEM_EINVAL;
+  }
   if (phys && (!mech || mech->K != m->n_out || !T1)) {
     set_error("ann_train_step: the physics terms need the mechanism of the network's %d species "
               "and the reference final temperatures T1", m->n_out);
@@ -1075,10 +1226,13 @@ extern "C" chem_status ann_train_step(ann_model *m, const chem_mech *mech, chem_
   ann::FeatArgs fa{B, batch.ld, T, p, Y0, index, K, m->L[0].dinp, m->nm.mu_in, m->nm.sd_in,
                    m->nm.lambda, m->tX, nullptr, nullptr, nullptr, 0.0f};
   if ((st = ann::features(fa, s)) != CHEM_OK) return st;
-  ann::TargetArgs ta{B, batch.ld, Y0, Y1, index, K, m->L[3].doutp, m->nm.mu_out, m->nm.sd_out,
+  ann::TargetArgs ta{B, batch.ld, Y0, Y1, index, K, uw(m), m->nm.mu_out, m->nm.sd_out,
                      m->nm.lambda, m->tUt};
   if ((st = ann::targets(ta, s)) != CHEM_OK) return st;
-  // forward, keeping pre-activations (FP32) and activations (BF16)
+  // forward, keeping pre-activations (FP32) and activations (BF16); an
+  // ensemble's members are the groups of each product (the first layer reads
+  // the shared input rows)
+  const int G = m->G;
   const u16 *in = m->tX;
   for (int l = 0; l < 4; ++l) {
     const ann::Layer &L = m->L[l];
@@ -1091,6 +1245,11 @@ extern "C" chem_status ann_train_step(ann_model *m, const chem_mech *mech, chem_
     g.B = m->Wb[l];
     g.ldb = L.dinp;
     g.bias = m->bm[l];
+    g.groups = G;
+    g.gA = l == 0 ? 0 : (long)B * L.dinp;
+    g.gB = (long)layer_elems(L);
+    g.gbias = L.doutp;
+    g.gcb = g.gcf = g.gz = (long)B * L.doutp;
     if (l < 3) {
       g.Cb = m->tH[l];
       g.ldcb = L.doutp;
@@ -1105,8 +1264,12 @@ extern "C" chem_status ann_train_step(ann_model *m, const chem_mech *mech, chem_
     }
     if (st != CHEM_OK) return st;
   }
-  st = ann::l1_grad(B, K, m->L[3].doutp, m->tU, m->tUt, m->tGb[3], m->tGf[3], m->loss_part,
-                    LOSS_PARTS, loss, s);
+  if (G > 1)
+    st = ann::l1_grad_members(B, G, m->L[3].doutp, (long)B * m->L[3].doutp, m->tU, m->tUt, uw(m),
+                              m->tGb[3], m->tGf[3], m->loss_part, LOSS_PARTS, loss, s);
+  else
+    st = ann::l1_grad(B, K, m->L[3].doutp, m->tU, m->tUt, m->tGb[3], m->tGf[3], m->loss_part,
+                      LOSS_PARTS, loss, s);
   if (st != CHEM_OK) return st;
   if (phys) {
     ann::PhysArgs pa{};
@@ -1139,15 +1302,22 @@ extern "C" chem_status ann_train_step(ann_model *m, const chem_mech *mech, chem_
     w.B = l > 0 ? m->tH[l - 1] : m->tX;
     w.ldb = L.dinp;
     w.ldcf = L.dinp;
-    const int S = wgrad_splits(L.doutp, L.dinp, B);
+    const int S = wgrad_splits(L.doutp, L.dinp, B, G);
     const long wn = (long)L.doutp * L.dinp;
+    // split-K partials [S][G][wn]: split q of member z at q G wn + z wn
     w.Cf = S > 1 ? m->wg_part : m->gW[l];
     w.ksplit = S;
-    w.split_stride = wn;
+    w.split_stride = (long)G * wn;
+    w.groups = G;
+    w.gA = (long)B * L.doutp;
+    w.gB = l > 0 ? (long)B * L.dinp : 0;
+    w.gcf = wn;
     if ((st = ann::gemm(w, false, false, ann::EPI_F32, s, "train_wgrad")) != CHEM_OK) return st;
-    if (S > 1 && (st = ann::sum_splits(wn, S, m->wg_part, wn, m->gW[l], s)) != CHEM_OK)
+    if (S > 1 && (st = ann::sum_splits((long)G * wn, S, m->wg_part, (long)G * wn, m->gW[l], s)) !=
+                     CHEM_OK)
       return st;
-    if ((st = ann::colsum(B, L.doutp, m->tGf[l], L.doutp, m->gb[l], m->col_part, s)) != CHEM_OK)
+    if ((st = ann::colsum(B, L.doutp, m->tGf[l], L.doutp, m->gb[l], m->col_part, s, G,
+                          (long)B * L.doutp, L.doutp)) != CHEM_OK)
       return st;
     if (l > 0) {
       const ann::Layer &P = m->L[l - 1];
@@ -1165,6 +1335,10 @@ extern "C" chem_status ann_train_step(ann_model *m, const chem_mech *mech, chem_
       d.ldcb = P.doutp;
       d.Cf = m->tGf[l - 1];
       d.ldcf = P.doutp;
+      d.groups = G;
+      d.gA = (long)B * L.doutp;
+      d.gB = (long)layer_elems(L);
+      d.gz = d.gcb = d.gcf = (long)B * P.doutp;
       if ((st = ann::gemm(d, true, false, ann::EPI_GELUGRAD, s, "train_dgrad")) != CHEM_OK)
         return st;
     }
@@ -1176,11 +1350,12 @@ extern "C" chem_status ann_train_step(ann_model *m, const chem_mech *mech, chem_
     const double bc2 = 1.0 - pow((double)opts->beta2, (double)m->step);
     for (int l = 0; l < 4; ++l) {
       const ann::Layer &L = m->L[l];
-      st = ann::adam((int64_t)layer_elems(L), m->Wm[l], m->gW[l], m->mW[l], m->vW[l], m->Wb[l],
-                     opts->lr, opts->beta1, opts->beta2, opts->eps, (float)bc1, (float)bc2, s);
+      st = ann::adam((int64_t)G * layer_elems(L), m->Wm[l], m->gW[l], m->mW[l], m->vW[l],
+                     m->Wb[l], opts->lr, opts->beta1, opts->beta2, opts->eps, (float)bc1,
+                     (float)bc2, s);
       if (st != CHEM_OK) return st;
-      st = ann::adam(L.doutp, m->bm[l], m->gb[l], m->mb[l], m->vb[l], nullptr, opts->lr,
-                     opts->beta1, opts->beta2, opts->eps, (float)bc1, (float)bc2, s);
+      st = ann::adam((int64_t)G * L.doutp, m->bm[l], m->gb[l], m->mb[l], m->vb[l], nullptr,
+                     opts->lr, opts->beta1, opts->beta2, opts->eps, (float)bc1, (float)bc2, s);
       if (st != CHEM_OK) return st;
     }
   }
@@ -1190,7 +1365,9 @@ extern "C" chem_status ann_train_step(ann_model *m, const chem_mech *mech, chem_
 extern "C" int64_t ann_num_steps(const ann_model *m) { return m ? m->step : -1; }
 
 namespace {
+// file versions: 1 = one network; 2 adds the member count after the header
 const char MAGIC[8] = {'C', 'H', 'E', 'M', 'A', 'N', 'N', '1'};
+const char MAGIC2[8] = {'C', 'H', 'E', 'M', 'A', 'N', 'N', '2'};
 
 bool wr(FILE *f, const void *p, size_t n) { return fwrite(p, 1, n, f) == n; }
 bool rd(FILE *f, void *p, size_t n) { return fread(p, 1, n, f) == n; }
@@ -1208,21 +1385,23 @@ extern "C" chem_status ann_save(const ann_model *m, const char *path) {
     set_error("ann_save: cannot open %s", path);
     return CHEM_EINVAL;
   }
-  bool ok = wr(f, MAGIC, 8);
+  bool ok = wr(f, m->G > 1 ? MAGIC2 : MAGIC, 8);
   int32_t hdr[7] = {m->n_in, m->n_out, m->L[0].dout, m->L[1].dout, m->L[2].dout, m->prec,
                     m->has_norm ? 1 : 0};
-  ok = ok && wr(f, hdr, sizeof(hdr)) && wr(f, &m->step, 8) && wr(f, &m->nm.lambda, 4) &&
-       wr(f, &m->nm.dt_model, 8);
+  const int32_t members = m->G;
+  ok = ok && wr(f, hdr, sizeof(hdr)) && (m->G == 1 || wr(f, &members, 4)) &&
+       wr(f, &m->step, 8) && wr(f, &m->nm.lambda, 4) && wr(f, &m->nm.dt_model, 8);
   if (m->has_norm)
     for (auto *v : {&m->h_mu_in, &m->h_sd_in, &m->h_lo, &m->h_hi, &m->h_mu_out, &m->h_sd_out})
       ok = ok && wr(f, v->data(), v->size() * 4);
-  for (int l = 0; l < 4 && ok; ++l) {
+  for (int idx = 0; idx < 4 * m->G && ok; ++idx) {
+    const int l = idx & 3;
     const ann::Layer &L = m->L[l];
     std::vector<float> W((size_t)L.dout * L.din), b(L.dout);
     const float *srcW[3] = {m->Wm[l], m->mW[l], m->vW[l]};
     const float *srcb[3] = {m->bm[l], m->mb[l], m->vb[l]};
     for (int q = 0; q < 3 && ok; ++q) {
-      st = download_pair(m, l, srcW[q], srcb[q], W.data(), b.data());
+      st = download_pair(m, idx, srcW[q], srcb[q], W.data(), b.data());
       if (st != CHEM_OK) {
         fclose(f);
         return st;
@@ -1251,17 +1430,20 @@ extern "C" chem_status ann_load(const char *path, ann_model **out) {
   }
   char mg[8];
   int32_t hdr[7];
+  int32_t members = 1;
   int64_t step = 0;
   float lambda = 0;
   double dtm = 0;
-  bool ok = rd(f, mg, 8) && memcmp(mg, MAGIC, 8) == 0 && rd(f, hdr, sizeof(hdr)) &&
-            rd(f, &step, 8) && rd(f, &lambda, 4) && rd(f, &dtm, 8);
+  bool ok = rd(f, mg, 8);
+  const bool v2 = ok && memcmp(mg, MAGIC2, 8) == 0;
+  ok = ok && (v2 || memcmp(mg, MAGIC, 8) == 0) && rd(f, hdr, sizeof(hdr)) &&
+       (!v2 || rd(f, &members, 4)) && rd(f, &step, 8) && rd(f, &lambda, 4) && rd(f, &dtm, 8);
   if (!ok) {
     fclose(f);
     set_error("ann_load: %s is not a model file", path);
     return CHEM_EMODEL;
   }
-  ann_arch arch{hdr[0], hdr[1], {hdr[2], hdr[3], hdr[4]}, hdr[5]};
+  ann_arch arch{hdr[0], hdr[1], {hdr[2], hdr[3], hdr[4]}, hdr[5], members};
   ann_model *m = nullptr;
   chem_status st = ann_create(&arch, 0, &m);
   if (st != CHEM_OK) {
@@ -1282,11 +1464,13 @@ extern "C" chem_status ann_load(const char *path, ann_model **out) {
       ok = st == CHEM_OK;
     }
   }
-  for (int l = 0; l < 4 && ok; ++l) {
+  for (int idx = 0; idx < 4 * m->G && ok; ++idx) {
+    const int l = idx & 3;
     const ann::Layer &L = m->L[l];
+    const size_t ow = (size_t)(idx >> 2) * layer_elems(L), ob = (size_t)(idx >> 2) * L.doutp;
     std::vector<float> W((size_t)L.dout * L.din), b(L.dout);
-    float *dstW[3] = {m->Wm[l], m->mW[l], m->vW[l]};
-    float *dstb[3] = {m->bm[l], m->mb[l], m->vb[l]};
+    float *dstW[3] = {m->Wm[l] + ow, m->mW[l] + ow, m->vW[l] + ow};
+    float *dstb[3] = {m->bm[l] + ob, m->mb[l] + ob, m->vb[l] + ob};
     for (int q = 0; q < 3 && ok; ++q) {
       ok = rd(f, W.data(), W.size() * 4) && rd(f, b.data(), b.size() * 4);
       if (!ok) break;
@@ -1298,7 +1482,9 @@ extern "C" chem_status ann_load(const char *path, ann_model **out) {
       ok = hipMemcpy(dstW[q], Wp.data(), Wp.size() * 4, hipMemcpyHostToDevice) == hipSuccess &&
            hipMemcpy(dstb[q], bp.data(), bp.size() * 4, hipMemcpyHostToDevice) == hipSuccess;
     }
-    if (ok) ok = ann::to_bf16((int64_t)layer_elems(L), m->Wm[l], m->Wb[l], nullptr) == CHEM_OK;
+    if (ok)
+      ok = ann::to_bf16((int64_t)layer_elems(L), m->Wm[l] + ow, m->Wb[l] + ow, nullptr) ==
+           CHEM_OK;
     m->wt_stale = true;
   }
   fclose(f);
@@ -1324,6 +1510,10 @@ extern "C" chem_status ann_quantize_fp8(ann_model *m, chem_batch calib, const do
                                         const double *p, const double *Y, void *stream) {
   chem_status st = check_model("ann_quantize_fp8", m);
   if (st != CHEM_OK) return st;
+  if (m->G > 1) {
+    set_error("ann_quantize_fp8: the FP8 variant is built for the single network only");
+    return CHEM_EUNSUPPORTED;
+  }
   if (!m->has_norm || m->n_in != m->n_out + 2) {
     set_error("ann_quantize_fp8: statistics not set or n_in != n_out + 2");
     return CHEM_EMODEL;

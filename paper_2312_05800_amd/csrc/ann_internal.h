@@ -64,6 +64,12 @@ struct GemmArgs {
   // (E4M3), so the rows of one K-step are contiguous; ld is then the stride
   // between K-blocks.  Only the direct-to-LDS kernels accept it.
   int tiled;
+  // grouped product (the networks of a per-species ensemble, one per
+  // blockIdx.z): group z reads A + z gA, B + z gB, bias + z gbias and writes
+  // Cb + z gcb, Cf + z gcf, Z + z gz (element strides; 0 = shared operand).
+  // Only the generic tiling (training products) accepts groups > 1.
+  int groups;
+  long gA, gB, gbias, gcb, gcf, gz;
 };
 enum { TILED_A = 1, TILED_B = 2, TILED_C = 4 };
 
@@ -162,10 +168,22 @@ struct PhysArgs {
 constexpr int PHYS_PARTS = 64;
 chem_status phys_grad(const PhysArgs &a, const chem::DevMech &M, double *part, float *loss,
                       float *terms, hipStream_t s);
-// out[j] = sum over the M rows of X[:, j]; part: COLSUM_PARTS * N doubles
+// out[j] = sum over the M rows of X[:, j]; part: COLSUM_PARTS * N doubles.
+// With groups > 1, group z sums X + z gx into out + z gout (part: groups
+// times as many doubles).
 constexpr int COLSUM_PARTS = 64;
 chem_status colsum(int64_t M, int N, const float *X, long ldx, float *out, double *part,
-                   hipStream_t s);
+                   hipStream_t s, int groups = 1, long gx = 0, long gout = 0);
+// Per-species ensemble: member g's output is column 0 of U + g gu (row
+// stride ldu) and its target column g of Ut (row stride ldt); the gradient
+// sign(u - u*) / (n G) goes to column 0 of Gb/Gf + g gu (every other column
+// 0), and *loss is the mean of |u - u*| over samples and members.
+chem_status l1_grad_members(int64_t n, int G, int ldu, long gu, const float *U, const float *Ut,
+                            int ldt, u16 *Gb, float *Gf, double *loss_part, int nparts,
+                            float *loss, hipStream_t s);
+// dst[i * ldd] = src[i * lds] for i < n (one output column of an ensemble
+// member into the ensemble's output)
+chem_status take_col(int64_t n, const float *src, int lds, float *dst, int ldd, hipStream_t s);
 // out[i] = sum_{s < S} part[s * stride + i], in order of s
 chem_status sum_splits(int64_t n, int S, const float *part, long stride, float *out,
                        hipStream_t s);

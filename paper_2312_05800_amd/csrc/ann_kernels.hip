@@ -113,6 +113,16 @@ __device__ __forceinline__ unsigned e4m3x4(float a, float b, float c, float d) {
 // when the K range of a block allows it.
 template <int WM, int WN, int TM, int TN, bool AK, bool BKC, int EPI, int BK = 32>
 __global__ __launch_bounds__(WM *WN * 64) void k_gemm(GemmArgs g) {
+  if (g.groups > 1) {
+    // this block's member of a grouped product
+    const long z = blockIdx.z;
+    g.A += z * g.gA;
+    g.B += z * g.gB;
+    if (g.bias) g.bias += z * g.gbias;
+    if (g.Cb) g.Cb += z * g.gcb;
+    if (g.Cf) g.Cf += z * g.gcf;
+    if (g.Z) g.Z += z * g.gz;
+  }
   constexpr int BM = WM * TM * 32, BN = WN * TN * 32, LK = BK + 8;
   constexpr int NT = WM * WN * 64;
   __shared__ __attribute__((aligned(16))) u16 As[2][BM * LK];
@@ -834,12 +844,13 @@ template <int WM, int WN, int TM, int TN>
 chem_status gemm_cfg(const GemmArgs &g, bool AK, bool BKC, int epi, hipStream_t s) {
   constexpr int BM = WM * TM * 32, BN = WN * TN * 32;
   const long total = (long)((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
-  dim3 grid((unsigned)(((total + 7) / 8) * 8), g.ksplit > 1 ? g.ksplit : 1);
+  dim3 grid((unsigned)(((total + 7) / 8) * 8), g.ksplit > 1 ? g.ksplit : 1,
+            g.groups > 1 ? g.groups : 1);
   dim3 block(WM * WN * 64);
   // 64-wide K-steps for launches of up to 1024 blocks (the training batch);
   // larger grids keep the smaller LDS footprint and more blocks per CU
   const int kper = g.ksplit > 1 ? g.K / g.ksplit : g.K;
-  if (kper >= 64 && (long)grid.x * grid.y <= 1024)
+  if (kper >= 64 && (long)grid.x * grid.y * grid.z <= 1024)
     return gemm_launch<WM, WN, TM, TN, 64>(g, AK, BKC, epi, grid, block, s);
   return gemm_launch<WM, WN, TM, TN, 32>(g, AK, BKC, epi, grid, block, s);
 }
@@ -1352,6 +1363,42 @@ __global__ void k_l1(int64_t n, int K, int doutp, const float *U, const float *U
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
+// Per-species ensemble: member g's single output is column 0 of its [n][ldu]
+// block; g = sign(u - u*) / (n G) there, 0 on the padding columns.
+__global__ void k_l1_members(int64_t n, int G, int ldu, long gu, const float *U, const float *Ut,
+                             int ldt, u16 *Gb, float *Gf, double *part) {
+  __shared__ double red[256];
+  const double scale = 1.0 / ((double)n * G);
+  double s = 0.0;
+  const int64_t per = n * ldu, total = per * G;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t g = e / per, r = (e % per) / ldu;
+    const int c = (int)(e % ldu);
+    const int64_t at = g * gu + r * ldu + c;
+    float gv = 0.0f;
+    if (c == 0) {
+      const float d = U[at] - Ut[r * ldt + g];
+      s += fabs((double)d);
+      gv = (float)(((d > 0.0f) - (d < 0.0f)) * scale);
+    }
+    Gb[at] = f2bf(gv);
+    Gf[at] = gv;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void k_take_col(int64_t n, const float *src, int lds, float *dst, int ldd) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i * ldd] = src[i * lds];
+}
+
 // Weight of species k in the element projection: the expected variance of
 // the network's error in its change, sd^2 (sd = the target's standard
 // deviation), tapered to zero as the species' own mass fraction vanishes:
@@ -1460,9 +1507,12 @@ __global__ void k_loss_final(const double *part, int nparts, double scale, float
 // running sum (the same order as one load at a time).
 constexpr int COLSUM_BATCH = 16;
 
-__global__ void k_colsum_part(int64_t M, int N, const float *X, long ldx, double *part) {
+__global__ void k_colsum_part(int64_t M, int N, const float *X, long ldx, double *part,
+                              long gx) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= N) return;
+  X += (long)blockIdx.z * gx;                       // member of a grouped sum
+  part += (long)blockIdx.z * gridDim.y * (long)N;
   const int P = gridDim.y, q = blockIdx.y;
   const int64_t m0 = M * q / P, m1 = M * (q + 1) / P;
   double s = 0.0;
@@ -1478,9 +1528,11 @@ __global__ void k_colsum_part(int64_t M, int N, const float *X, long ldx, double
   part[(int64_t)q * N + j] = s;
 }
 
-__global__ void k_colsum_fin(int N, int P, const double *part, float *out) {
+__global__ void k_colsum_fin(int N, int P, const double *part, float *out, long gout) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= N) return;
+  part += (long)blockIdx.z * P * (long)N;
+  out += (long)blockIdx.z * gout;
   double s = 0.0;
   int q = 0;
   for (; q + COLSUM_BATCH <= P; q += COLSUM_BATCH) {
@@ -1876,6 +1928,14 @@ chem_status gemm(const GemmArgs &g, bool AK, bool BK, int epi, hipStream_t s,
     chem::set_error("gemm: split-K needs K a multiple of 32 ksplit, FP32 output, no bias");
     return CHEM_EINVAL;
   }
+  if (g.groups > 1) {
+    if (g.tiled || epi == EPI_GELU_NEXT || epi == EPI_GELU_Q8 || g.groups > 65535) {
+      chem::set_error("gemm: grouped products take the generic tiling only");
+      return CHEM_EUNSUPPORTED;
+    }
+    if (g.N <= 32) return gemm_cfg<4, 1, 1, 1>(g, AK, BK, epi, s);
+    return gemm_cfg<2, 2, 2, 2>(g, AK, BK, epi, s);
+  }
   if (epi == EPI_GELU_NEXT) {
     if (!AK || !BK || !gemm_fuses_next(g)) {
       chem::set_error("gemm: the fused output layer needs the 256 x 416 tiling");
@@ -2040,6 +2100,24 @@ chem_status l1_grad(int64_t n, int K, int doutp, const float *U, const float *Ut
   return CHEM_OK;
 }
 
+chem_status l1_grad_members(int64_t n, int G, int ldu, long gu, const float *U, const float *Ut,
+                            int ldt, u16 *Gb, float *Gf, double *loss_part, int nparts,
+                            float *loss, hipStream_t s) {
+  hipLaunchKernelGGL(k_l1_members, dim3(nparts), dim3(256), 0, s, n, G, ldu, gu, U, Ut, ldt, Gb,
+                     Gf, loss_part);
+  hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, s, loss_part, nparts,
+                     1.0 / ((double)n * G), loss);
+  CHEM_HIP(hipGetLastError());
+  return CHEM_OK;
+}
+
+chem_status take_col(int64_t n, const float *src, int lds, float *dst, int ldd, hipStream_t s) {
+  if (n <= 0) return CHEM_OK;
+  hipLaunchKernelGGL(k_take_col, dim3(nblk(n, 256)), dim3(256), 0, s, n, src, lds, dst, ldd);
+  CHEM_HIP(hipGetLastError());
+  return CHEM_OK;
+}
+
 chem_status tile_bf16(int N, int K, const u16 *src, u16 *dst, hipStream_t s, bool permute) {
   if (K % 32 != 0) {
     chem::set_error("tile_bf16: K must be a multiple of 32");
@@ -2067,10 +2145,13 @@ chem_status tile_e4m3(int rows_p, int cols_p, const uint8_t *src, uint8_t *dst, 
 }
 
 chem_status colsum(int64_t M, int N, const float *X, long ldx, float *out, double *part,
-                   hipStream_t s) {
+                   hipStream_t s, int groups, long gx, long gout) {
   const int P = (int)(M < COLSUM_PARTS ? (M > 0 ? M : 1) : COLSUM_PARTS);
-  hipLaunchKernelGGL(k_colsum_part, dim3(nblk(N, 64), P), dim3(64), 0, s, M, N, X, ldx, part);
-  hipLaunchKernelGGL(k_colsum_fin, dim3(nblk(N, 256)), dim3(256), 0, s, N, P, part, out);
+  const unsigned G = groups > 1 ? (unsigned)groups : 1u;
+  hipLaunchKernelGGL(k_colsum_part, dim3(nblk(N, 64), P, G), dim3(64), 0, s, M, N, X, ldx, part,
+                     gx);
+  hipLaunchKernelGGL(k_colsum_fin, dim3(nblk(N, 256), 1, G), dim3(256), 0, s, N, P, part, out,
+                     gout);
   CHEM_HIP(hipGetLastError());
   return CHEM_OK;
 }
