@@ -139,15 +139,16 @@ def make_labels(P, mech, gm, dev, args):
     return lab, dict(states=int(T.size), label_seconds=round(t_label, 3), failed_labels=nbad)
 
 
-def train_model(P, mech, gm, dev, args, lab, w_phys):
-    """Train the network on the labelled pairs (cosine lr decay), with the
-    physics terms of the loss weighted by w_phys (zeros: L1 loss only)."""
+def train_model(P, mech, gm, dev, args, lab, w_phys, members=1):
+    """Train the network (members = K: the per-species ensemble) on the
+    labelled pairs (cosine lr decay), with the physics terms of the loss
+    weighted by w_phys (zeros: L1 loss only)."""
     import numpy as np
     import torch
     K = mech.K
     Td, pd, Y0d, Y1d, T1d = lab["T"], lab["p"], lab["Y0"], lab["Y1"], lab["T1"]
     n = Td.shape[0]
-    m = P.AnnModel(K + 2, K, HIDDEN, seed=args.seed)
+    m = P.AnnModel(K + 2, K, HIDDEN, seed=args.seed, members=members)
     m.fit_norm(Td, pd, Y0d, Y1d, 0.1, 1e-5)
     loss = torch.zeros(1, dtype=torch.float32, device=dev)
     terms = torch.zeros(3, dtype=torch.float32, device=dev)
@@ -177,7 +178,7 @@ def train_model(P, mech, gm, dev, args, lab, w_phys):
             log(f"[train w={w_phys}] step {it} lr {lr:.2e} loss {hist[-1][1]:.5f}")
     torch.cuda.synchronize()
     t_train = time.time() - tt
-    info = dict(steps=args.train_steps, batch=B, w_phys=list(w_phys),
+    info = dict(steps=args.train_steps, batch=B, w_phys=list(w_phys), members=members,
                 train_seconds=round(t_train, 2),
                 ms_per_train_step=round(1e3 * t_train / max(1, args.train_steps), 3),
                 loss_first=hist[0][1] if hist else None, loss_last=hist[-1][1] if hist else None)
@@ -437,10 +438,19 @@ def train_roofline(info, K):
     if not ms:
         return None
     B = info["batch"]
-    flops = 3.0 * mlp_flops_per_cell(K) * B
+    G = info.get("members", 1)
+    if G > 1:
+        # K single-output members, every product of the step one grouped launch
+        per_cell = G * sum(2 * a * b for a, b in zip([K + 2, *HIDDEN], [*HIDDEN, 1]))
+        params = G * sum((a + 1) * b for a, b in zip([K + 2, *HIDDEN], [*HIDDEN, 1]))
+    else:
+        per_cell = mlp_flops_per_cell(K)
+        params = n_params(K)
+    flops = 3.0 * per_cell * B
     ach = flops / (ms * 1e-3)
-    adam_bytes = 30.0 * n_params(K)
-    return {"kernel": "one training step (all launches)", "bound": "mfma",
+    adam_bytes = 30.0 * params
+    return {"kernel": "one training step (all launches)" if G == 1 else
+            f"one training step of the {G}-member ensemble (grouped launches)", "bound": "mfma",
             "achieved": round(ach / 1e12, 2), "peak": PEAK_BF16 / 1e12, "unit": "TFLOP/s",
             "frac": round(ach / PEAK_BF16, 4), "flops_per_step": flops, "batch": B,
             "ms_per_step": ms, "adam_bytes_per_step": adam_bytes,
@@ -530,6 +540,8 @@ def main():
     ap.add_argument("--big-cells", type=int, default=1 << 23,
                     help="cells of the large inference leg (BF16 and FP8; 0: skip)")
     ap.add_argument("--peaks", type=int, default=1, help="measure attainable peaks (1/0)")
+    ap.add_argument("--ensemble", type=int, default=1,
+                    help="also train and time the per-species ensemble of Sec. 3.2 (1/0)")
     ap.add_argument("--sample-seeds", type=int, default=1 << 21,
                     help="seeds of the Sec. 3.1 sampler leg (0: skip)")
     args = ap.parse_args()
@@ -554,6 +566,8 @@ def main():
     train_plain = None
     model_sampled = None
     sample_info = None
+    model_ens = None
+    train_ens = None
     if args.model and os.path.exists(args.model):
         model = P.AnnModel.load(args.model)
         train_info = dict(loaded=args.model)
@@ -564,6 +578,11 @@ def main():
         train_info.update(tinfo)
         if args.compare_phys and any(w != 0.0 for w in w_phys):
             model_plain, train_plain = train_model(P, mech, gm, dev, args, lab, (0.0, 0.0, 0.0))
+        if args.ensemble:
+            # one network per species on the same pairs; the members each see
+            # one species, so the loss is the L1 loss alone
+            model_ens, train_ens = train_model(P, mech, gm, dev, args, lab, (0.0, 0.0, 0.0),
+                                               members=K)
         if args.sample_seeds:
             del lab
             torch.cuda.empty_cache()
@@ -656,6 +675,18 @@ def main():
         model.set_precision(0)
         log(f"[fp8] {args.steps} steps in {t_fp8:.3f} s; fallback cells {fp8['fallback']}")
 
+    # ---- the per-species ensemble (Sec. 3.2): the same step with K networks ----
+    ens = None
+    if model_ens is not None:
+        steps_e = max(1, min(args.steps, 3))
+        P.profile_read()
+        t_ens = timed_loop(lambda: model_ens.step(gm, 1e-5, Td, pd, Yd, RR=RR, flags=flags,
+                                                  n_fallback=nfb),
+                           restore, steps_e, 1)
+        prof_ens = P.profile_read()
+        ens = dict(t=t_ens, steps=steps_e, fallback=int(nfb.item()), prof=prof_ens)
+        log(f"[ensemble] {steps_e} steps in {t_ens:.3f} s; fallback cells {ens['fallback']}")
+
     # ---- FP64 integrator step, launch shape from the autotuner ----
     tune_default = P.chem_get_tuning(gm)
     si = torch.from_numpy(np.linspace(0, N - 1, 1 << 15).astype(np.int64)).to(dev)
@@ -721,32 +752,52 @@ def main():
     # the same network trained without the physics terms of the loss
     phys_cmp = None
     data_cmp = None
-    if model_plain is not None or model_sampled is not None:
-        def sample_step(mdl):
-            Ts, ps, Ys = (T0d[idx_d].contiguous(), pd[idx_d].contiguous(),
-                          Y0d[:, idx_d].contiguous())
-            nf = torch.zeros(1, dtype=torch.int64, device=dev)
-            mdl.step(gm, 1e-5, Ts, ps, Ys, n_fallback=nf)
-            Um = mdl.forward(T0d[idx_d].contiguous(), pd[idx_d].contiguous(),
-                             Y0d[:, idx_d].contiguous(), K).cpu().numpy().astype(np.float64).T
-            nmm = mdl.get_norm(K + 2, K)
-            Yr = np.maximum(Y[:, idx] + Um * nmm["sd_out"][:, None] + nmm["mu_out"][:, None], 0.0)
-            rr = np.abs(Mel @ (Yr - Y[:, idx])).max(axis=0)
-            _, mj = nrmse_table(Ys.cpu().numpy() - Y[:, idx], dY_ref, o["Y"].mean(axis=1),
-                                mech.species)
-            return {"nrmse_major_max": mj, "fallback_cells": int(nf.item()),
-                    "raw_residual_max": float(rr.max()),
-                    "raw_residual_median": float(np.median(rr)),
-                    "raw_residual_flags": int((rr > 1e-6).sum())}
-        if model_plain is not None:
-            phys_cmp = {"sample_cells": int(idx.size),
-                        "with_terms": dict(w_phys=list(w_phys), **sample_step(model)),
-                        "without_terms": sample_step(model_plain),
-                        "training_without_terms": train_plain}
-        if model_sampled is not None:
-            data_cmp = {"sample_cells": int(idx.size),
-                        "perturbed_recipe_states": sample_step(model),
-                        "sec31_sampler": dict(sample_step(model_sampled), data=sample_info)}
+    ens_cmp = None
+
+    def sample_step(mdl):
+        Ts, ps, Ys = (T0d[idx_d].contiguous(), pd[idx_d].contiguous(),
+                      Y0d[:, idx_d].contiguous())
+        nf = torch.zeros(1, dtype=torch.int64, device=dev)
+        mdl.step(gm, 1e-5, Ts, ps, Ys, n_fallback=nf)
+        Um = mdl.forward(T0d[idx_d].contiguous(), pd[idx_d].contiguous(),
+                         Y0d[:, idx_d].contiguous(), K).cpu().numpy().astype(np.float64).T
+        nmm = mdl.get_norm(K + 2, K)
+        Yr = np.maximum(Y[:, idx] + Um * nmm["sd_out"][:, None] + nmm["mu_out"][:, None], 0.0)
+        rr = np.abs(Mel @ (Yr - Y[:, idx])).max(axis=0)
+        _, mj = nrmse_table(Ys.cpu().numpy() - Y[:, idx], dY_ref, o["Y"].mean(axis=1),
+                            mech.species)
+        return {"nrmse_major_max": mj, "fallback_cells": int(nf.item()),
+                "raw_residual_max": float(rr.max()),
+                "raw_residual_median": float(np.median(rr)),
+                "raw_residual_flags": int((rr > 1e-6).sum())}
+    if model_plain is not None:
+        phys_cmp = {"sample_cells": int(idx.size),
+                    "with_terms": dict(w_phys=list(w_phys), **sample_step(model)),
+                    "without_terms": sample_step(model_plain),
+                    "training_without_terms": train_plain}
+    if model_sampled is not None:
+        data_cmp = {"sample_cells": int(idx.size),
+                    "perturbed_recipe_states": sample_step(model),
+                    "sec31_sampler": dict(sample_step(model_sampled), data=sample_info)}
+    if ens is not None:
+        fl_single = mlp_flops_per_cell(K)
+        fl_member = sum(2 * a * b for a, b in zip([K + 2, *HIDDEN], [*HIDDEN, 1]))
+        ens_cmp = {
+            "members": K,
+            "sample_cells": int(idx.size),
+            "ensemble": sample_step(model_ens),
+            "single_network_same_loss": None if model_plain is None else
+            sample_step(model_plain),
+            "single_network_with_physics_terms": sample_step(model),
+            "step": {"cells_per_s": round(N * ens["steps"] / ens["t"], 1),
+                     "ms_per_step": round(1e3 * ens["t"] / ens["steps"], 3),
+                     "steps": ens["steps"], "fallback_cells": ens["fallback"],
+                     "kernels": {k: dict(launches=v[0], avg_ms=round(v[1] / max(v[0], 1), 4))
+                                 for k, v in ens["prof"].items()}},
+            "training": train_ens,
+            "roofline_training": train_roofline(train_ens, K),
+            "mlp_flops_per_cell": {"ensemble": K * fl_member, "single": fl_single,
+                                   "ratio": round(K * fl_member / fl_single, 2)}}
 
     # the same error against the GPU FP64 integrator, on every cell
     dY_fp = fp_Y - Y
@@ -956,6 +1007,7 @@ def main():
         "fp64_sets": sets_out,
         "physics_terms_comparison": phys_cmp,
         "training_data_comparison": data_cmp,
+        "ensemble_comparison": ens_cmp,
         "large": large,
         "attainable_peaks": None if peaks is None else {
             "measured_tflops": {k: round(v, 1) for k, v in peaks.items()},
