@@ -150,6 +150,9 @@ def train_model(P, mech, gm, dev, args, lab, w_phys, members=1):
     n = Td.shape[0]
     m = P.AnnModel(K + 2, K, HIDDEN, seed=args.seed, members=members)
     m.fit_norm(Td, pd, Y0d, Y1d, 0.1, 1e-5)
+    # tilings of the step's products for this batch, by measurement
+    tuning = m.autotune_train(args.batch)
+    log(f"[train] autotuned products: {tuning}")
     loss = torch.zeros(1, dtype=torch.float32, device=dev)
     terms = torch.zeros(3, dtype=torch.float32, device=dev)
     phys = any(w != 0.0 for w in w_phys)
@@ -179,6 +182,7 @@ def train_model(P, mech, gm, dev, args, lab, w_phys, members=1):
     torch.cuda.synchronize()
     t_train = time.time() - tt
     info = dict(steps=args.train_steps, batch=B, w_phys=list(w_phys), members=members,
+                autotuned_products_ms={k: round(v, 4) for k, v in tuning.items()},
                 train_seconds=round(t_train, 2),
                 ms_per_train_step=round(1e3 * t_train / max(1, args.train_steps), 3),
                 loss_first=hist[0][1] if hist else None, loss_last=hist[-1][1] if hist else None)

@@ -300,6 +300,22 @@ chem_status ann_train_step(ann_model *m, const chem_mech *mech, chem_batch batch
                            const double *Y1, const double *T1, const int64_t *index,
                            const ann_train_opts *opts, float *loss, float *terms, void *stream);
 int64_t ann_num_steps(const ann_model *m);
+/* Block and tile shapes of the training step, picked by measurement (the
+ * step is launch- and latency-bound at training batches, so the best tiling
+ * differs from the inference rule): each of the eleven products of a step at
+ * batch B (forward, weight gradient and data gradient of every layer; an
+ * ensemble's members grouped) is timed with every generic tiling (128 x 128,
+ * 128 x 32, 64 x 64, 128 x 64 blocks; 32- or 64-wide K-steps) and, for the
+ * weight gradients, every split along the batch the workspace holds (1..16),
+ * on the model's training workspace; the fastest stays in the model for later
+ * ann_train_step calls at batch B (other batches keep the built-in rules).
+ * ms_default / ms_tuned (host, nullable) receive the summed product times
+ * with the built-in rules and the chosen tilings.  With CHEM_AUTOTUNE_CACHE
+ * naming a file, a result stored there for this device, network and batch
+ * is taken without timing, and new results are stored.  Overwrites the last
+ * step's gradients; synchronises `stream`. */
+chem_status ann_autotune_train(ann_model *m, int64_t B, double *ms_default, double *ms_tuned,
+                               void *stream);
 /* FP8 variant of inference: the two hidden-to-hidden layers run on OCP FP8
  * E4M3 MFMA with per-tensor scales amax/448 -- activation scales from a BF16
  * forward pass over the calibration cells (at most 2^21 of them), weight
@@ -336,7 +352,10 @@ typedef struct {
  * modified), keeps the fastest in the mechanism handle for later chem_step,
  * chem_step_sets and fallback launches, and returns it (host, nullable).
  * Allocates and frees its scratch copies and synchronises `stream`; must not
- * run concurrently with other calls on the same handle. */
+ * run concurrently with other calls on the same handle.  With the environment
+ * variable CHEM_AUTOTUNE_CACHE naming a file, a shape stored there for this
+ * device, mechanism, dt and tolerances is applied without timing, and a new
+ * measurement is stored ("key = value" text lines). */
 chem_status chem_autotune(chem_mech *m, chem_batch sample, double dt, const double *T,
                           const double *p, const double *Y, const chem_step_opts *opts,
                           void *stream, chem_tuning *best);

@@ -48,6 +48,7 @@ def _prototypes(L):
                                    _P]
     L.ann_train_step.argtypes = [_P, _P, Batch, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]
     L.ann_num_steps.argtypes = [_P]
+    L.ann_autotune_train.argtypes = [_P, C.c_int64, _P, _P, _P]
     L.ann_num_steps.restype = C.c_int64
     L.ann_quantize_fp8.argtypes = [_P, Batch, _P, _P, _P, _P]
     L.ann_set_precision.argtypes = [_P, C.c_int32]
@@ -91,6 +92,15 @@ class AnnModel:
             except Exception:
                 pass
             self.handle = None
+
+    def autotune_train(self, B, stream=None):
+        """Pick the training products' tilings for batch B by measurement
+        (ann_autotune_train); returns the summed product times in ms with the
+        built-in rules and with the chosen tilings."""
+        d0, d1 = C.c_double(), C.c_double()
+        check("ann_autotune_train", lib().ann_autotune_train(
+            self.handle, C.c_int64(int(B)), C.byref(d0), C.byref(d1), _stream(stream)))
+        return {"products_ms_default": d0.value, "products_ms_tuned": d1.value}
 
     @property
     def num_steps(self):

@@ -6,7 +6,10 @@
 #include <string.h>
 
 #include <algorithm>
+#include <iomanip>
 #include <mutex>
+#include <sstream>
+#include <string>
 #include <vector>
 
 #include "ann_internal.h"
@@ -75,6 +78,7 @@ struct ann_model {
   double *phys_part = nullptr;  // [PHYS_PARTS][3] partial sums of the physics terms
   double *col_part = nullptr;  // [COLSUM_PARTS][max dout] bias-gradient partials
   float *wg_part = nullptr;    // split-K partial weight gradients
+  size_t wg_cap = 0;           // floats in wg_part
   // FP8 inference of the hidden-to-hidden layers (L2, L3)
   bool fp8_ready = false, use_fp8 = false;
   float sa[3] = {1, 1, 1}, sw[3] = {1, 1, 1};  // per-tensor scales of layers 1, 2
@@ -86,6 +90,10 @@ struct ann_model {
   uint8_t *H1q = nullptr, *H2q = nullptr;  // inference workspace (E4M3 activations)
   uint8_t *ood = nullptr;                  // per-cell out-of-distribution bits
   int graph_refs = 0;  // live captured steps that use the inference workspace
+  // tilings of the eleven training products at batch tt_B, from
+  // ann_autotune_train (tt_B = 0: the built-in rules)
+  int64_t tt_B = 0;
+  int tt_tile[11] = {}, tt_bk[11] = {}, tt_split[4] = {};
 };
 
 using namespace chem;
@@ -285,6 +293,7 @@ chem_status grow_train(ann_model *m, int64_t B) {
   m->loss_part = (double *)(b + oL);
   m->col_part = (double *)(b + oC);
   m->wg_part = (float *)(b + oW);
+  m->wg_cap = wg_n;
   m->wt.cap = B;
   m->wt.bytes = off;
   return CHEM_OK;
@@ -1177,6 +1186,118 @@ extern "C" chem_status ann_step_noalloc(ann_model *m, const chem_mech *mech, che
   return step_impl(m, mech, batch, dt, T, p, Y, RR, flags, n_fallback, o, fo, w, w.fb_index, s);
 }
 
+namespace {
+
+// The eleven GEMMs of a training step at batch B: p = 0..3 the forward of
+// layer p, 4..7 the weight gradient of layer p - 4 (split S ways along the
+// batch, partials [S][members][weights]), 8..10 the data gradient into layer
+// p - 8 (through GELU').  An ensemble's members are the groups of each product.
+struct TrainProduct {
+  ann::GemmArgs g;
+  bool AK, BK;
+  int epi;
+  const char *label;
+};
+
+TrainProduct train_product(const ann_model *m, int64_t B, int p, int S) {
+  TrainProduct t{};
+  ann::GemmArgs &g = t.g;
+  const int G = m->G;
+  g.groups = G;
+  if (p < 4) {
+    const int l = p;
+    const ann::Layer &L = m->L[l];
+    g.M = (int)B;
+    g.N = L.doutp;
+    g.K = L.dinp;
+    g.A = l == 0 ? m->tX : m->tH[l - 1];
+    g.lda = L.dinp;
+    g.B = m->Wb[l];
+    g.ldb = L.dinp;
+    g.bias = m->bm[l];
+    g.gA = l == 0 ? 0 : (long)B * L.dinp;
+    g.gB = (long)layer_elems(L);
+    g.gbias = L.doutp;
+    g.gcb = g.gcf = g.gz = (long)B * L.doutp;
+    if (l < 3) {
+      g.Cb = m->tH[l];
+      g.ldcb = L.doutp;
+      g.Z = m->tZ[l];
+      g.ldz = L.doutp;
+      t.epi = ann::EPI_GELU;
+    } else {
+      g.Cf = m->tU;
+      g.ldcf = L.doutp;
+      t.epi = ann::EPI_F32;
+    }
+    t.AK = t.BK = true;
+    t.label = "train_fwd";
+  } else if (p < 8) {
+    const int l = p - 4;
+    const ann::Layer &L = m->L[l];
+    const long wn = (long)L.doutp * L.dinp;
+    g.M = L.doutp;
+    g.N = L.dinp;
+    g.K = (int)B;
+    g.A = m->tGb[l];
+    g.lda = L.doutp;
+    g.B = l > 0 ? m->tH[l - 1] : m->tX;
+    g.ldb = L.dinp;
+    g.ldcf = L.dinp;
+    g.Cf = S > 1 ? m->wg_part : m->gW[l];
+    g.ksplit = S;
+    g.split_stride = (long)G * wn;
+    g.gA = (long)B * L.doutp;
+    g.gB = l > 0 ? (long)B * L.dinp : 0;
+    g.gcf = wn;
+    t.AK = t.BK = false;
+    t.epi = ann::EPI_F32;
+    t.label = "train_wgrad";
+  } else {
+    const int l = p - 7;  // the layer whose input gradient this is
+    const ann::Layer &L = m->L[l], &P = m->L[l - 1];
+    g.M = (int)B;
+    g.N = L.dinp;
+    g.K = L.doutp;
+    g.A = m->tGb[l];
+    g.lda = L.doutp;
+    g.B = m->Wb[l];
+    g.ldb = L.dinp;
+    g.Z = m->tZ[l - 1];
+    g.ldz = P.doutp;
+    g.Cb = m->tGb[l - 1];
+    g.ldcb = P.doutp;
+    g.Cf = m->tGf[l - 1];
+    g.ldcf = P.doutp;
+    g.gA = (long)B * L.doutp;
+    g.gB = (long)layer_elems(L);
+    g.gz = g.gcb = g.gcf = (long)B * P.doutp;
+    t.AK = true;
+    t.BK = false;
+    t.epi = ann::EPI_GELUGRAD;
+    t.label = "train_dgrad";
+  }
+  return t;
+}
+
+// Split factor of layer l's weight gradient: the tuned one at the tuned
+// batch, else the built-in rule.
+int train_split(const ann_model *m, int64_t B, int l) {
+  if (m->tt_B == B && m->tt_split[l] > 0) return m->tt_split[l];
+  return wgrad_splits(m->L[l].doutp, m->L[l].dinp, B, m->G);
+}
+
+chem_status run_product(const ann_model *m, int64_t B, int p, int S, hipStream_t s) {
+  TrainProduct t = train_product(m, B, p, S);
+  if (m->tt_B == B) {
+    t.g.tile = m->tt_tile[p];
+    t.g.bk = m->tt_bk[p];
+  }
+  return ann::gemm(t.g, t.AK, t.BK, t.epi, s, t.label);
+}
+
+}  // namespace
+
 extern "C" chem_status ann_train_step(ann_model *m, const chem_mech *mech, chem_batch batch,
                                       const double *T, const double *p, const double *Y0,
                                       const double *Y1, const double *T1, const int64_t *index,
@@ -1233,37 +1354,8 @@ extern "C" chem_status ann_train_step(ann_model *m, const chem_mech *mech, chem_
   // ensemble's members are the groups of each product (the first layer reads
   // the shared input rows)
   const int G = m->G;
-  const u16 *in = m->tX;
-  for (int l = 0; l < 4; ++l) {
-    const ann::Layer &L = m->L[l];
-    ann::GemmArgs g{};
-    g.M = (int)B;
-    g.N = L.doutp;
-    g.K = L.dinp;
-    g.A = in;
-    g.lda = L.dinp;
-    g.B = m->Wb[l];
-    g.ldb = L.dinp;
-    g.bias = m->bm[l];
-    g.groups = G;
-    g.gA = l == 0 ? 0 : (long)B * L.dinp;
-    g.gB = (long)layer_elems(L);
-    g.gbias = L.doutp;
-    g.gcb = g.gcf = g.gz = (long)B * L.doutp;
-    if (l < 3) {
-      g.Cb = m->tH[l];
-      g.ldcb = L.doutp;
-      g.Z = m->tZ[l];
-      g.ldz = L.doutp;
-      st = ann::gemm(g, true, true, ann::EPI_GELU, s, "train_fwd");
-      in = m->tH[l];
-    } else {
-      g.Cf = m->tU;
-      g.ldcf = L.doutp;
-      st = ann::gemm(g, true, true, ann::EPI_F32, s, "train_fwd");
-    }
-    if (st != CHEM_OK) return st;
-  }
+  for (int l = 0; l < 4; ++l)
+    if ((st = run_product(m, B, l, 1, s)) != CHEM_OK) return st;
   if (G > 1)
     st = ann::l1_grad_members(B, G, m->L[3].doutp, (long)B * m->L[3].doutp, m->tU, m->tUt, uw(m),
                               m->tGb[3], m->tGf[3], m->loss_part, LOSS_PARTS, loss, s);
@@ -1293,55 +1385,16 @@ extern "C" chem_status ann_train_step(ann_model *m, const chem_mech *mech, chem_
   // backward: wgrad, bias grad, dgrad (through GELU') per layer
   for (int l = 3; l >= 0; --l) {
     const ann::Layer &L = m->L[l];
-    ann::GemmArgs w{};
-    w.M = L.doutp;
-    w.N = L.dinp;
-    w.K = (int)B;
-    w.A = m->tGb[l];
-    w.lda = L.doutp;
-    w.B = l > 0 ? m->tH[l - 1] : m->tX;
-    w.ldb = L.dinp;
-    w.ldcf = L.dinp;
-    const int S = wgrad_splits(L.doutp, L.dinp, B, G);
+    const int S = train_split(m, B, l);
     const long wn = (long)L.doutp * L.dinp;
-    // split-K partials [S][G][wn]: split q of member z at q G wn + z wn
-    w.Cf = S > 1 ? m->wg_part : m->gW[l];
-    w.ksplit = S;
-    w.split_stride = (long)G * wn;
-    w.groups = G;
-    w.gA = (long)B * L.doutp;
-    w.gB = l > 0 ? (long)B * L.dinp : 0;
-    w.gcf = wn;
-    if ((st = ann::gemm(w, false, false, ann::EPI_F32, s, "train_wgrad")) != CHEM_OK) return st;
+    if ((st = run_product(m, B, 4 + l, S, s)) != CHEM_OK) return st;
     if (S > 1 && (st = ann::sum_splits((long)G * wn, S, m->wg_part, (long)G * wn, m->gW[l], s)) !=
                      CHEM_OK)
       return st;
     if ((st = ann::colsum(B, L.doutp, m->tGf[l], L.doutp, m->gb[l], m->col_part, s, G,
                           (long)B * L.doutp, L.doutp)) != CHEM_OK)
       return st;
-    if (l > 0) {
-      const ann::Layer &P = m->L[l - 1];
-      ann::GemmArgs d{};
-      d.M = (int)B;
-      d.N = L.dinp;
-      d.K = L.doutp;
-      d.A = m->tGb[l];
-      d.lda = L.doutp;
-      d.B = m->Wb[l];
-      d.ldb = L.dinp;
-      d.Z = m->tZ[l - 1];
-      d.ldz = P.doutp;
-      d.Cb = m->tGb[l - 1];
-      d.ldcb = P.doutp;
-      d.Cf = m->tGf[l - 1];
-      d.ldcf = P.doutp;
-      d.groups = G;
-      d.gA = (long)B * L.doutp;
-      d.gB = (long)layer_elems(L);
-      d.gz = d.gcb = d.gcf = (long)B * P.doutp;
-      if ((st = ann::gemm(d, true, false, ann::EPI_GELUGRAD, s, "train_dgrad")) != CHEM_OK)
-        return st;
-    }
+    if (l > 0 && (st = run_product(m, B, 7 + l, 1, s)) != CHEM_OK) return st;
   }
   if (opts->lr > 0.0f) {
     m->step += 1;
@@ -1363,6 +1416,134 @@ extern "C" chem_status ann_train_step(ann_model *m, const chem_mech *mech, chem_
 }
 
 extern "C" int64_t ann_num_steps(const ann_model *m) { return m ? m->step : -1; }
+
+extern "C" chem_status ann_autotune_train(ann_model *m, int64_t B, double *ms_default,
+                                          double *ms_tuned, void *stream) {
+  chem_status st = check_model("ann_autotune_train", m);
+  if (st != CHEM_OK) return st;
+  if (B < 32 || B % 32 != 0 || B > (1 << 24)) {
+    set_error("ann_autotune_train: the batch must be a positive multiple of 32 (<= 2^24)");
+    return CHEM_EINVAL;
+  }
+  if ((st = grow_train(m, B)) != CHEM_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  char kb[256];
+  snprintf(kb, sizeof(kb), "ann_train %s in=%d hidden=%d,%d,%d out=%d members=%d B=%lld",
+           tune_device_key().c_str(), m->n_in, m->L[0].dout, m->L[1].dout, m->L[2].dout,
+           m->n_out, m->G, (long long)B);
+  std::string cached;
+  if (tune_cache_get(kb, &cached)) {
+    int tl[11], bk[11], sp[4];
+    double d0 = 0, d1 = 0;
+    std::istringstream in(cached);
+    bool ok = true;
+    for (int p = 0; p < 11 && ok; ++p) ok = (bool)(in >> tl[p] >> bk[p]);
+    for (int l = 0; l < 4 && ok; ++l) ok = (bool)(in >> sp[l]);
+    ok = ok && (bool)(in >> d0 >> d1);
+    for (int p = 0; p < 11 && ok; ++p)
+      ok = tl[p] >= 0 && tl[p] <= ann::GEMM_TILES && (bk[p] == 0 || bk[p] == 32 || bk[p] == 64);
+    for (int l = 0; l < 4 && ok; ++l) {
+      const long wn = (long)m->L[l].doutp * m->L[l].dinp;
+      ok = sp[l] >= 1 && sp[l] <= 16 && B % (32L * sp[l]) == 0 &&
+           (sp[l] == 1 || (size_t)sp[l] * m->G * wn <= m->wg_cap);
+    }
+    if (ok) {
+      std::copy(tl, tl + 11, m->tt_tile);
+      std::copy(bk, bk + 11, m->tt_bk);
+      std::copy(sp, sp + 4, m->tt_split);
+      m->tt_B = B;
+      if (ms_default) *ms_default = d0;
+      if (ms_tuned) *ms_tuned = d1;
+      return CHEM_OK;
+    }
+  }
+  // the products' times do not depend on the values: run them on a cleared
+  // workspace (the last step's gradients are overwritten)
+  CHEM_HIP(hipMemsetAsync(m->wt.base, 0, m->wt.bytes, s));
+  hipEvent_t ea = nullptr, eb = nullptr;
+  if (hipEventCreate(&ea) != hipSuccess || hipEventCreate(&eb) != hipSuccess) {
+    if (ea) (void)hipEventDestroy(ea);
+    set_error("ann_autotune_train: hipEventCreate failed");
+    return CHEM_EHIP;
+  }
+  const int G = m->G;
+  constexpr int REPS = 4;
+  // one product (and its split-K reduction) with the given tiling: its
+  // average over REPS launches after a warm-up, or infinity if it cannot run
+  auto timed = [&](int p, int tile, int bkv, int S) -> float {
+    TrainProduct t = train_product(m, B, p, S);
+    t.g.tile = tile;
+    t.g.bk = bkv;
+    const int l = p - 4;
+    const long wn = p >= 4 && p < 8 ? (long)m->L[l].doutp * m->L[l].dinp : 0;
+    auto once = [&]() -> chem_status {
+      chem_status r = ann::gemm(t.g, t.AK, t.BK, t.epi, s, "autotune");
+      if (r == CHEM_OK && S > 1)
+        r = ann::sum_splits((long)G * wn, S, m->wg_part, (long)G * wn, m->gW[l], s);
+      return r;
+    };
+    if (once() != CHEM_OK) return INFINITY;
+    if (hipEventRecord(ea, s) != hipSuccess) return INFINITY;
+    for (int r = 0; r < REPS; ++r)
+      if (once() != CHEM_OK) return INFINITY;
+    float ms = 0.0f;
+    if (hipEventRecord(eb, s) != hipSuccess || hipEventSynchronize(eb) != hipSuccess ||
+        hipEventElapsedTime(&ms, ea, eb) != hipSuccess)
+      return INFINITY;
+    return ms / REPS;
+  };
+  double tot0 = 0.0, tot1 = 0.0;
+  int tl[11], bk[11], sp[4];
+  for (int p = 0; p < 11; ++p) {
+    const bool wg = p >= 4 && p < 8;
+    const int l = wg ? p - 4 : 0;
+    const int S0 = wg ? wgrad_splits(m->L[l].doutp, m->L[l].dinp, B, G) : 1;
+    const float t0 = timed(p, 0, 0, S0);
+    if (!(t0 < INFINITY)) {
+      (void)hipEventDestroy(ea);
+      (void)hipEventDestroy(eb);
+      set_error("ann_autotune_train: the built-in tiling of product %d failed to run", p);
+      return CHEM_EHIP;
+    }
+    float best = t0;
+    int bt = 0, bb = 0, bs = S0;
+    for (int S = 1; S <= (wg ? 16 : 1); S *= 2) {
+      if (wg) {
+        const long wn = (long)m->L[l].doutp * m->L[l].dinp;
+        if (B % (32L * S) != 0 || (S > 1 && (size_t)S * G * wn > m->wg_cap)) continue;
+      }
+      for (int tile = 1; tile <= ann::GEMM_TILES; ++tile)
+        for (int bkv : {32, 64}) {
+          const float t = timed(p, tile, bkv, S);
+          if (t < best) {
+            best = t;
+            bt = tile;
+            bb = bkv;
+            bs = S;
+          }
+        }
+    }
+    tl[p] = bt;
+    bk[p] = bb;
+    if (wg) sp[l] = bs;
+    tot0 += t0;
+    tot1 += best;
+  }
+  (void)hipEventDestroy(ea);
+  (void)hipEventDestroy(eb);
+  std::copy(tl, tl + 11, m->tt_tile);
+  std::copy(bk, bk + 11, m->tt_bk);
+  std::copy(sp, sp + 4, m->tt_split);
+  m->tt_B = B;
+  if (ms_default) *ms_default = tot0;
+  if (ms_tuned) *ms_tuned = tot1;
+  std::ostringstream v;
+  for (int p = 0; p < 11; ++p) v << tl[p] << " " << bk[p] << " ";
+  for (int l = 0; l < 4; ++l) v << sp[l] << " ";
+  v << std::setprecision(17) << tot0 << " " << tot1;
+  tune_cache_put(kb, v.str());
+  return CHEM_OK;
+}
 
 namespace {
 // file versions: 1 = one network; 2 adds the member count after the header

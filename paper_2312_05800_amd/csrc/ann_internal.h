@@ -70,7 +70,14 @@ struct GemmArgs {
   // Only the generic tiling (training products) accepts groups > 1.
   int groups;
   long gA, gB, gbias, gcb, gcf, gz;
+  // tiling of the generic kernel chosen by the autotuner: tile 0 = the
+  // built-in rule, 1..GEMM_TILES = gemm_tile_shape(tile); bk 0 = the built-in
+  // rule, else the K-step (32 or 64).  The direct-to-LDS paths ignore them.
+  int tile, bk;
 };
+constexpr int GEMM_TILES = 4;
+// Block shape (rows x columns of C) of generic tiling t in 1..GEMM_TILES.
+void gemm_tile_shape(int t, int *bm, int *bn);
 enum { TILED_A = 1, TILED_B = 2, TILED_C = 4 };
 
 // C = epi(A * op(B)); AK: A is [M][K] row-major (else [K][M]); BK: B is [N][K]

@@ -849,10 +849,26 @@ chem_status gemm_cfg(const GemmArgs &g, bool AK, bool BKC, int epi, hipStream_t 
   dim3 block(WM * WN * 64);
   // 64-wide K-steps for launches of up to 1024 blocks (the training batch);
   // larger grids keep the smaller LDS footprint and more blocks per CU
+  // (unless the autotuner chose)
   const int kper = g.ksplit > 1 ? g.K / g.ksplit : g.K;
-  if (kper >= 64 && (long)grid.x * grid.y * grid.z <= 1024)
-    return gemm_launch<WM, WN, TM, TN, 64>(g, AK, BKC, epi, grid, block, s);
+  const bool bk64 = g.bk ? (g.bk == 64 && kper >= 64)
+                         : (kper >= 64 && (long)grid.x * grid.y * grid.z <= 1024);
+  if (bk64) return gemm_launch<WM, WN, TM, TN, 64>(g, AK, BKC, epi, grid, block, s);
   return gemm_launch<WM, WN, TM, TN, 32>(g, AK, BKC, epi, grid, block, s);
+}
+
+// The generic tilings the autotuner chooses from: 128 x 128, 128 x 32,
+// 64 x 64 and 128 x 64 blocks of C (waves x 32 x 32 MFMA tiles per wave).
+chem_status gemm_tiled(const GemmArgs &g, bool AK, bool BKC, int epi, hipStream_t s) {
+  switch (g.tile) {
+    case 1: return gemm_cfg<2, 2, 2, 2>(g, AK, BKC, epi, s);
+    case 2: return gemm_cfg<4, 1, 1, 1>(g, AK, BKC, epi, s);
+    case 3: return gemm_cfg<2, 2, 1, 1>(g, AK, BKC, epi, s);
+    case 4: return gemm_cfg<4, 2, 1, 1>(g, AK, BKC, epi, s);
+    default: break;
+  }
+  if (g.N <= 32) return gemm_cfg<4, 1, 1, 1>(g, AK, BKC, epi, s);
+  return gemm_cfg<2, 2, 2, 2>(g, AK, BKC, epi, s);
 }
 
 // ------------------------------------------------------------ FP8 GEMM
@@ -1933,8 +1949,7 @@ chem_status gemm(const GemmArgs &g, bool AK, bool BK, int epi, hipStream_t s,
       chem::set_error("gemm: grouped products take the generic tiling only");
       return CHEM_EUNSUPPORTED;
     }
-    if (g.N <= 32) return gemm_cfg<4, 1, 1, 1>(g, AK, BK, epi, s);
-    return gemm_cfg<2, 2, 2, 2>(g, AK, BK, epi, s);
+    return gemm_tiled(g, AK, BK, epi, s);
   }
   if (epi == EPI_GELU_NEXT) {
     if (!AK || !BK || !gemm_fuses_next(g)) {
@@ -1958,7 +1973,7 @@ chem_status gemm(const GemmArgs &g, bool AK, bool BK, int epi, hipStream_t s,
     chem::set_error("gemm: no direct-to-LDS tiling for this K-blocked shape");
     return CHEM_EUNSUPPORTED;
   }
-  if (AK && BK && epi != EPI_GELUGRAD && dma16_ok(g)) {
+  if (AK && BK && epi != EPI_GELUGRAD && !g.tile && dma16_ok(g)) {
     // forward layers through the direct-to-LDS ring when the launch has at
     // least two blocks per CU of work: K = 32 (first layer) in 64 x 320
     // single-stage tiles; 256 x 400 (or x 416) tiles; 256 x 32 for the
@@ -1970,8 +1985,15 @@ chem_status gemm(const GemmArgs &g, bool AK, bool BK, int epi, hipStream_t s,
     if (g.N % 416 == 0 && mt * (g.N / 416) >= 512) return gemm_dma16_cfg<8, 2, 26>(g, epi, s);
     if (g.N <= 32 && mt >= 512) return gemm_dma16_cfg<4, 4, 2>(g, epi, s);
   }
-  if (g.N <= 32) return gemm_cfg<4, 1, 1, 1>(g, AK, BK, epi, s);
-  return gemm_cfg<2, 2, 2, 2>(g, AK, BK, epi, s);
+  return gemm_tiled(g, AK, BK, epi, s);
+}
+
+void gemm_tile_shape(int t, int *bm, int *bn) {
+  static const int shape[GEMM_TILES + 1][2] = {{0, 0}, {128, 128}, {128, 32}, {64, 64},
+                                               {128, 64}};
+  const int i = t >= 1 && t <= GEMM_TILES ? t : 0;
+  *bm = shape[i][0];
+  *bn = shape[i][1];
 }
 
 bool mlp12_ok(const Mlp12Args &g) {

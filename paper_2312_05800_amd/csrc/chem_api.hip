@@ -6,7 +6,11 @@
 #include <string.h>
 
 #include <algorithm>
+#include <fstream>
+#include <mutex>
+#include <sstream>
 #include <utility>
+#include <vector>
 #include <vector>
 
 #include "chem_internal.h"
@@ -231,6 +235,7 @@ extern "C" chem_status chem_mech_create(const chem_mech_desc *d, chem_mech **out
     set_error("chem_mech_create: device allocation: %s", hipGetErrorString(e));
     return CHEM_ENOMEM;
   }
+  m->digest = fnv1a(pk.buf.data(), pk.buf.size());
   e = hipMemcpy(m->blob, pk.buf.data(), pk.buf.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(m->counters, 0, 64 * sizeof(unsigned long long));
   if (e != hipSuccess) {
@@ -483,6 +488,30 @@ extern "C" chem_status chem_autotune(chem_mech *m, chem_batch sample, double dt,
   hipStream_t s = (hipStream_t)stream;
   const int64_t n = sample.n;
   const int K = m->K;
+  // a shape measured before for this device, mechanism, step and controls
+  // (CHEM_AUTOTUNE_CACHE) is taken without timing
+  char kb[256];
+  snprintf(kb, sizeof(kb), "chem_step %s K=%d R=%d mech=%016llx dt=%.6g rtol=%.3g atol=%.3g",
+           tune_device_key().c_str(), K, m->R, (unsigned long long)m->digest, dt, o.rtol,
+           o.atol_Y);
+  std::string cached;
+  if (tune_cache_get(kb, &cached)) {
+    int cg = 0, cw = 0;
+    double ccps = 0.0;
+    if (sscanf(cached.c_str(), "%d %d %lf", &cg, &cw, &ccps) == 3 && cg >= group_size(m->d.n) &&
+        cg <= 64 && (cg & (cg - 1)) == 0 && cw >= 1 &&
+        cw <= max_waves_per_cu(step_lds_bytes(m, cg))) {
+      m->tune_G = cg;
+      m->tune_waves = cw;
+      m->tune_cps = ccps;
+      if (best) {
+        best->lanes_per_cell = cg;
+        best->waves_per_cu = resolved_waves(m, cg);
+        best->cells_per_s = ccps;
+      }
+      return CHEM_OK;
+    }
+  }
   // candidates: every usable lane group, and 1/4 .. 4/4 of the waves per CU
   // its LDS allows
   struct Cand {
@@ -567,6 +596,11 @@ extern "C" chem_status chem_autotune(chem_mech *m, chem_batch sample, double dt,
   m->tune_G = bc.G;
   m->tune_waves = bc.w;
   m->tune_cps = (double)n / (best_ms * 1e-3);
+  {
+    char vb[96];
+    snprintf(vb, sizeof(vb), "%d %d %.17g", bc.G, bc.w, m->tune_cps);
+    tune_cache_put(kb, vb);
+  }
   if (best) {
     best->lanes_per_cell = bc.G;
     best->waves_per_cu = resolved_waves(m, bc.G);
@@ -653,3 +687,78 @@ extern "C" void chem_graph_destroy(chem_graph *g) {
   if (g->release) g->release(g->owner);
   delete g;
 }
+
+// ------------------------------------------------------------ tuning cache
+namespace chem {
+
+uint64_t fnv1a(const void *p, size_t n, uint64_t h) {
+  const unsigned char *c = (const unsigned char *)p;
+  for (size_t i = 0; i < n; ++i) {
+    h ^= c[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+namespace {
+std::mutex g_cache_mu;
+
+const char *cache_path() {
+  const char *p = getenv("CHEM_AUTOTUNE_CACHE");
+  return p && *p ? p : nullptr;
+}
+
+// every "key = value" line of the file, in order
+std::vector<std::pair<std::string, std::string>> cache_read(const char *path) {
+  std::vector<std::pair<std::string, std::string>> out;
+  std::ifstream in(path);
+  std::string line;
+  while (std::getline(in, line)) {
+    const size_t eq = line.find(" = ");
+    if (eq == std::string::npos) continue;
+    out.emplace_back(line.substr(0, eq), line.substr(eq + 3));
+  }
+  return out;
+}
+}  // namespace
+
+bool tune_cache_get(const std::string &key, std::string *value) {
+  const char *path = cache_path();
+  if (!path) return false;
+  std::lock_guard<std::mutex> lock(g_cache_mu);
+  bool found = false;
+  for (auto &kv : cache_read(path))
+    if (kv.first == key) {
+      *value = kv.second;
+      found = true;
+    }
+  return found;
+}
+
+void tune_cache_put(const std::string &key, const std::string &value) {
+  const char *path = cache_path();
+  if (!path) return;
+  std::lock_guard<std::mutex> lock(g_cache_mu);
+  auto all = cache_read(path);
+  bool replaced = false;
+  for (auto &kv : all)
+    if (kv.first == key) {
+      kv.second = value;
+      replaced = true;
+    }
+  if (!replaced) all.emplace_back(key, value);
+  std::ofstream out(path, std::ios::trunc);
+  for (auto &kv : all) out << kv.first << " = " << kv.second << "\n";
+}
+
+std::string tune_device_key() {
+  int dev = 0;
+  hipDeviceProp_t prop{};
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+    return "unknown";
+  std::ostringstream k;
+  k << prop.gcnArchName << ":" << prop.multiProcessorCount;
+  return k.str();
+}
+
+}  // namespace chem

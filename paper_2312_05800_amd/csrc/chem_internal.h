@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
+
 #include "chemstep.h"
 
 namespace chem {
@@ -58,6 +60,7 @@ struct chem_mech {
   // chem_set_tuning
   int tune_G = 0, tune_waves = 0;
   double tune_cps = 0.0;
+  uint64_t digest = 0;  // FNV-1a of the packed tables (keys the tuning cache)
 };
 
 // A captured step: the graph, its executable and the stream it was captured
@@ -90,6 +93,15 @@ class ProfScope {
 };
 
 void set_error(const char *fmt, ...);
+
+// Tuning results kept between runs in the text file named by the environment
+// variable CHEM_AUTOTUNE_CACHE (no file: nothing is kept): one line
+// "key = value" per tuned problem, the last write of a key winning.
+bool tune_cache_get(const std::string &key, std::string *value);
+void tune_cache_put(const std::string &key, const std::string &value);
+// The current device's architecture name and compute-unit count, for keys.
+std::string tune_device_key();
+uint64_t fnv1a(const void *p, size_t n, uint64_t h = 1469598103934665603ull);
 
 // ProfScope is a no-op while suspended (graph capture).
 void profile_suspend(bool on);
