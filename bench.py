@@ -300,6 +300,10 @@ def time_sets(P, mech, gm, dev, args, model=None):
     t_graph = timed_loop(g.launch, restore, 1, 0)
     eq_graph = same(snapshot(), ref)
     del g
+    # the table already on the device: offsets and count formed on the GPU
+    table, nt = P.set_table_device(gm, live, device=dev)
+    t_dev = timed_loop(lambda: P.chem_step_sets_device(gm, table, nt), restore, 1, 0)
+    eq_dev = same(snapshot(), ref)
     # oracle on a stratified sample: every set contributes in proportion to
     # its size (at least one cell), args.sets_oracle cells in all
     om = oracle.OracleMech(mech)
@@ -340,6 +344,9 @@ def time_sets(P, mech, gm, dev, args, model=None):
            "persistent_queue_graph": {"s": round(t_graph, 3),
                                       "cells_per_s": round(total / t_graph, 1),
                                       "equal_to_per_set": eq_graph},
+           "persistent_queue_device_table": {"s": round(t_dev, 3),
+                                             "cells_per_s": round(total / t_dev, 1),
+                                             "equal_to_per_set": eq_dev},
            "max_rel_err_vs_oracle": err, "oracle_cells": nchk,
            "oracle_sample": "stratified: each set in proportion to its size",
            "ann_at_dt_model": ann_side}

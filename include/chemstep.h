@@ -158,6 +158,19 @@ typedef struct {
  * with the set's dt. */
 chem_status chem_step_sets(const chem_mech *m, int32_t n_sets, const chem_set *sets,
                            const chem_step_opts *opts, void *stream);
+/* chem_step_sets with the table of n_sets descriptors already in device
+ * memory (`sets`: device array, its pointers device pointers), for callers
+ * that keep the step on the GPU without host round trips (Sec. 2): the set
+ * offsets and the cell count are formed on the device, the launch is a full
+ * persistent grid whose waves stop at that count, and nothing synchronises.
+ * A set with n < 0, ld < n, null T, p or Y, or a dt that is not finite and
+ * positive is skipped (its arrays untouched) and counted in *n_bad (device
+ * int32, nullable).  The handle keeps the offsets: the first call with more
+ * sets than before allocates (and so cannot be captured), and calls on one
+ * handle must be ordered.  Host-side errors: null handle or table, more than
+ * 2^20 sets, invalid options. */
+chem_status chem_step_sets_device(const chem_mech *m, int32_t n_sets, const chem_set *sets,
+                                  const chem_step_opts *opts, int32_t *n_bad, void *stream);
 
 /* ------------------------------------------------------------ surrogate
  * The ANN of Sec. 3.2 that stands in for the integration: inputs

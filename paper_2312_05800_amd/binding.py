@@ -78,6 +78,7 @@ def lib():
             L.chem_step_graph_create.argtypes = [_P, Batch, C.c_double, _P, _P, _P, _P, _P, _P,
                                                  _P, _P, _P, C.POINTER(_P)]
             L.chem_step_sets_graph_create.argtypes = [_P, C.c_int32, _P, _P, _P, C.POINTER(_P)]
+            L.chem_step_sets_device.argtypes = [_P, C.c_int32, _P, _P, _P, _P]
             L.chem_graph_launch.argtypes = [_P, _P]
             L.chem_graph_destroy.argtypes = [_P]
             L.chem_measure_peaks.argtypes = [_P, _P]
@@ -269,6 +270,30 @@ def chem_step_sets(mech: Mechanism, sets, opts=None, stream=None):
     check("chem_step_sets", lib().chem_step_sets(mech.handle, len(sets), C.addressof(arr),
                                                  None if o is None else C.byref(o),
                                                  _stream(stream)))
+
+
+def set_table_device(mech: Mechanism, sets, device=None):
+    """The chem_set table of ``sets`` (as for chem_step_sets) copied into a
+    device uint8 tensor, for chem_step_sets_device.  Returns (table, n)."""
+    import torch
+    arr = _set_table(mech, sets)
+    host = torch.frombuffer(bytearray(C.string_at(C.addressof(arr), C.sizeof(arr))),
+                            dtype=torch.uint8)
+    dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
+    return host.to(dev), len(sets)
+
+
+def chem_step_sets_device(mech: Mechanism, table, n_sets, opts=None, n_bad=None, stream=None):
+    """chem_step_sets on a table already in device memory (set_table_device);
+    n_bad: optional device int32 [1] receiving the number of skipped sets."""
+    import torch
+    if not isinstance(table, torch.Tensor) or not table.is_cuda or \
+            table.numel() < n_sets * C.sizeof(ChemSet):
+        raise ValueError("table must be a device tensor holding n_sets chem_set descriptors")
+    o = _opts(opts)
+    check("chem_step_sets_device", lib().chem_step_sets_device(
+        mech.handle, int(n_sets), table.data_ptr(), None if o is None else C.byref(o),
+        _vec(n_bad, 1, "n_bad", torch.int32), _stream(stream)))
 
 
 def chem_step_sets_graph(mech: Mechanism, sets, opts=None, stream=None):

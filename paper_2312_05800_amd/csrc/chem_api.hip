@@ -277,6 +277,7 @@ extern "C" chem_status chem_mech_create(const chem_mech_desc *d, chem_mech **out
 extern "C" void chem_mech_destroy(chem_mech *m) {
   if (!m) return;
   if (m->set_buf) (void)hipFree(m->set_buf);
+  if (m->dset_buf) (void)hipFree(m->dset_buf);
   if (m->sample_buf) (void)hipFree(m->sample_buf);
   (void)hipFree(m->blob);
   (void)hipFree(m->counters);
@@ -633,6 +634,38 @@ extern "C" chem_status chem_step_graph_create(const chem_mech *m, chem_batch bat
 namespace {
 void free_device(void *p) { (void)hipFree(p); }
 }  // namespace
+
+extern "C" chem_status chem_step_sets_device(const chem_mech *m, int32_t n_sets,
+                                             const chem_set *sets, const chem_step_opts *opts,
+                                             int32_t *n_bad, void *stream) {
+  StepOpts o;
+  chem_status st = check_sets_call("chem_step_sets_device", m, n_sets, sets, opts, &o);
+  if (st != CHEM_OK) return st;
+  if (n_sets == 0) return CHEM_OK;
+  chem_mech *mm = const_cast<chem_mech *>(m);
+  hipStream_t s = (hipStream_t)stream;
+  // offsets [n_sets + 1] and the total count, in memory the handle owns
+  const size_t need = ((size_t)(n_sets + 1) * 8 + 255) / 256 * 256 + 256;
+  if (mm->dset_cap < need) {
+    if (mm->dset_buf) (void)hipFree(mm->dset_buf);
+    mm->dset_buf = nullptr;
+    mm->dset_cap = 0;
+    if (hipMalloc(&mm->dset_buf, need) != hipSuccess) {
+      mm->dset_buf = nullptr;
+      set_error("chem_step_sets_device: cannot allocate the set offsets");
+      return CHEM_ENOMEM;
+    }
+    mm->dset_cap = need;
+  }
+  int64_t *off = (int64_t *)mm->dset_buf;
+  unsigned long long *total =
+      (unsigned long long *)((unsigned char *)mm->dset_buf + need - 256);
+  if ((st = launch_set_offsets(sets, n_sets, off, total, n_bad, s)) != CHEM_OK) return st;
+  // the cell count stays on the device: a full persistent grid whose waves
+  // stop at the count
+  return launch_step(m, INT64_MAX / 4, 0, 0.0, nullptr, nullptr, nullptr, nullptr, nullptr,
+                     nullptr, nullptr, o, nullptr, s, total, nullptr, sets, off, n_sets);
+}
 
 extern "C" chem_status chem_step_sets_graph_create(const chem_mech *m, int32_t n_sets,
                                                    const chem_set *sets,

@@ -53,6 +53,8 @@ struct chem_mech {
   unsigned long long *counters;    // device work-queue counters
   void *set_buf = nullptr;         // device copy of the last chem_step_sets table
   size_t set_cap = 0;
+  void *dset_buf = nullptr;        // offsets and count of chem_step_sets_device's table
+  size_t dset_cap = 0;
   double *sample_buf = nullptr;    // training-set sampler: range partials and ranges
   int device;
   int K, R, E;
@@ -175,5 +177,8 @@ chem_status launch_step(const chem_mech *m, int64_t n, int64_t ld, double dt,
                         const unsigned long long *n_dev = nullptr, uint8_t *flags = nullptr,
                         const chem_set *sets = nullptr, const int64_t *set_off = nullptr,
                         int n_sets = 0);
+// Offsets and total cell count of a device set table (see k_set_offsets).
+chem_status launch_set_offsets(const chem_set *sets, int n_sets, int64_t *off,
+                               unsigned long long *total, int32_t *n_bad, hipStream_t s);
 
 }  // namespace chem

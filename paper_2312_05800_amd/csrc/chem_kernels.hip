@@ -894,6 +894,69 @@ chem_status launch_rates(const chem_mech *m, int64_t N, int64_t ld, const double
   return CHEM_OK;
 }
 
+// Offsets of a device set table: off[s] = cells of the valid sets before s,
+// off[n_sets] and *total = all of them; a set with bad sizes, null arrays or
+// a bad dt counts as empty and is counted in *n_bad.  One block: each thread
+// sums a contiguous run of sets, a scan over the runs, then each thread
+// writes its run's offsets.
+constexpr int SETOFF_THREADS = 1024;
+
+__device__ __forceinline__ int64_t valid_cells(const chem_set &c, int *bad) {
+  const bool ok = c.n >= 0 && c.ld >= c.n &&
+                  (c.n == 0 || (c.T && c.p && c.Y && c.dt > 0.0 && isfinite(c.dt)));
+  *bad = ok ? 0 : 1;
+  return ok ? c.n : 0;
+}
+
+__global__ __launch_bounds__(SETOFF_THREADS) void k_set_offsets(const chem_set *sets, int n_sets,
+                                                                 int64_t *off,
+                                                                 unsigned long long *total,
+                                                                 int32_t *n_bad) {
+  __shared__ int64_t run[SETOFF_THREADS];
+  __shared__ int bads[SETOFF_THREADS];
+  const int t = threadIdx.x;
+  const int per = (n_sets + SETOFF_THREADS - 1) / SETOFF_THREADS;
+  const int s0 = t * per, s1 = s0 + per < n_sets ? s0 + per : n_sets;
+  int64_t sum = 0;
+  int nb = 0;
+  for (int i = s0; i < s1; ++i) {
+    int b = 0;
+    sum += valid_cells(sets[i], &b);
+    nb += b;
+  }
+  run[t] = sum;
+  bads[t] = nb;
+  __syncthreads();
+  if (t == 0) {  // exclusive scan of the runs, in order
+    int64_t acc = 0;
+    int nbad = 0;
+    for (int q = 0; q < SETOFF_THREADS; ++q) {
+      const int64_t v = run[q];
+      run[q] = acc;
+      acc += v;
+      nbad += bads[q];
+    }
+    off[n_sets] = acc;
+    *total = (unsigned long long)acc;
+    if (n_bad) *n_bad = nbad;
+  }
+  __syncthreads();
+  int64_t acc = run[t];
+  for (int i = s0; i < s1; ++i) {
+    off[i] = acc;
+    int b = 0;
+    acc += valid_cells(sets[i], &b);
+  }
+}
+
+chem_status launch_set_offsets(const chem_set *sets, int n_sets, int64_t *off,
+                               unsigned long long *total, int32_t *n_bad, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_offsets, dim3(1), dim3(SETOFF_THREADS), 0, s, sets, n_sets, off,
+                     total, n_bad);
+  CHEM_HIP(hipGetLastError());
+  return CHEM_OK;
+}
+
 chem_status launch_step(const chem_mech *m, int64_t N, int64_t ld, double dt,
                         const double *dt_cell, double *T, const double *p, double *Y, double *RR,
                         double *h_hint, int32_t *stats, const StepOpts &o, const int32_t *index,

@@ -230,3 +230,52 @@ def test_step_sets_uneven(dev, gm):
         assert res["ok"], res
         np.testing.assert_allclose(d["RR"].cpu().numpy(), o["RR"], rtol=1e-6,
                                    atol=1e-8 * np.abs(o["RR"]).max())
+
+
+def test_step_sets_device_table(dev, gm):
+    """chem_step_sets_device (table in device memory, offsets and count formed
+    on the GPU) equals chem_step_sets bit for bit on uneven sets; sets with a
+    bad dt or leading dimension are skipped, left untouched and counted."""
+    import torch
+    import paper_2312_05800_amd as P
+    _say("[step sets, device table]")
+    mech = chemgen.make_mechanism("ch4")
+    sizes = [0, 1, 37, 300, 900, 50, 64]
+    dts = [1e-6, 3e-7, 1e-5, 2e-6, 4e-5, -1.0, 1e-6]
+    host = []
+    for i, (nc, dt) in enumerate(zip(sizes, dts)):
+        T, p, Y = chemgen.make_states(mech, dict(fuel="CH4", phi=(0.5, 1.3),
+                                                 T=("uniform", 300.0, 2500.0), N=nc),
+                                      seed=600 + i)
+        host.append((T, p, Y, dt))
+
+    def make():
+        out = []
+        for T, p, Y, dt in host:
+            nc = T.size
+            out.append(dict(dt=dt, T=to_dev(T, dev), p=to_dev(p, dev), Y=to_dev(Y, dev),
+                            RR=torch.zeros((mech.K, nc), dtype=torch.float64, device=dev),
+                            stats=torch.zeros((3, nc), dtype=torch.int32, device=dev)))
+        return out
+    a, b = make(), make()
+    valid = [i for i, (T, p, Y, dt) in enumerate(host) if dt > 0]
+    P.chem_step_sets(gm["ch4"], [a[i] for i in valid])
+    table, n = P.set_table_device(gm["ch4"], b, device=dev)
+    # set 6 claims a leading dimension below its size: skipped like the bad dt
+    import ctypes as C
+    raw = bytearray(table.cpu().numpy().tobytes())
+    sz = C.sizeof(P.binding.ChemSet)
+    st6 = P.binding.ChemSet.from_buffer(raw, 6 * sz)
+    st6.ld = st6.n - 1
+    table = torch.frombuffer(raw, dtype=torch.uint8).to(dev)
+    n_bad = torch.full((1,), -1, dtype=torch.int32, device=dev)
+    P.chem_step_sets_device(gm["ch4"], table, n, n_bad=n_bad)
+    torch.cuda.synchronize()
+    assert int(n_bad.item()) == 2
+    for i in valid[:-1]:
+        for k in ("T", "Y", "RR", "stats"):
+            assert torch.equal(a[i][k], b[i][k]), (i, k)
+    for i in (5, 6):  # skipped: arrays as given
+        assert torch.equal(b[i]["T"], to_dev(host[i][0], dev))
+        assert torch.equal(b[i]["Y"], to_dev(host[i][2], dev))
+        assert not b[i]["stats"].any()
