@@ -299,3 +299,67 @@ def test_ensemble_refusals(dev, mech, data):
     with pytest.raises(P.ChemError):
         m.get_layer(4 * K, (1, HID[2]))
     torch.cuda.synchronize()
+
+
+def test_ensemble_full_size_ch4(dev):
+    """The benchmarked configuration: 30 members on 2^20 CH4/air cells (every
+    member on the fused, K-blocked inference path), sampled cells against the
+    oracle's ensemble."""
+    import torch
+    mech = chemgen.make_mechanism("ch4")
+    K = mech.K
+    N = 1 << 20
+    _say(f"[ensemble forward] ch4, {K} members, N={N}")
+    om = oracle.OracleMech(mech)
+    T0, p0, Y0 = chemgen.make_states(mech, "ch4", N=2048, seed=81)
+    o = oracle.chem_step(om, 1e-5, T0, p0, Y0)
+    nm = _norm_from(dict(T=T0, p=p0, Y0=Y0, Y1=o["Y"]))
+    members = _members(K, 90)
+    m = _model(K, members, nm)
+    T, p, Y = chemgen.make_states(mech, "ch4")
+    U = m.forward(to_dev(T, dev), to_dev(p, dev), to_dev(Y, dev), K)
+    torch.cuda.synchronize()
+    idx = np.linspace(0, N - 1, 97).astype(np.int64)
+    Ug = U[torch.from_numpy(idx).to(dev)].cpu().numpy().astype(np.float64)
+    Uo = oann.ensemble_forward(_p32(members), _x(nm, T[idx], p[idx], Y[:, idx]), prec="bf16")
+    _check_u(Ug, Uo)
+    assert torch.isfinite(U).all()
+
+
+def test_ensemble_step_graph_and_noalloc(dev, mech, data):
+    """The ensemble's step replayed as a captured graph (three replays, with
+    eager work between them) and through the no-allocation entry point gives
+    the eager step's T, Y, RR and flags bit for bit, fallback included."""
+    import torch
+    import paper_2312_05800_amd as P
+    K = mech.K
+    members = _members(K, 100)
+    for p_ in members:
+        p_[3] = (p_[3][0] * 0.02, p_[3][1] * 0.02)
+    m = _model(K, members, _norm_from(data))
+    gm = P.Mechanism(mech)
+    N = 700
+    T, p, Y = chemgen.make_states(mech, "h2", N=N, seed=101)
+
+    def fresh():
+        return (to_dev(T, dev), to_dev(p, dev), to_dev(Y, dev),
+                torch.zeros((K, N), dtype=torch.float64, device=dev),
+                torch.zeros(N, dtype=torch.uint8, device=dev))
+    Te, pe, Ye, Re, fe = fresh()
+    m.step(gm, DT, Te, pe, Ye, RR=Re, flags=fe)
+    Tn, pn, Yn, Rn, fn = fresh()
+    m.step(gm, DT, Tn, pn, Yn, RR=Rn, flags=fn, noalloc=True)
+    torch.cuda.synchronize()
+    assert int(fe.ne(0).sum()) > 0  # untrained members: the fallback path runs
+    for a, b in ((Te, Tn), (Ye, Yn), (Re, Rn), (fe, fn)):
+        assert torch.equal(a, b)
+    Tg, pg, Yg, Rg, fg = fresh()
+    g = m.step_graph(gm, DT, Tg, pg, Yg, RR=Rg, flags=fg)
+    for _ in range(3):
+        Tg.copy_(to_dev(T, dev))
+        Yg.copy_(to_dev(Y, dev))
+        g.launch()
+        torch.cuda.synchronize()
+        for a, b in ((Te, Tg), (Ye, Yg), (Re, Rg), (fe, fg)):
+            assert torch.equal(a, b)
+    del g
