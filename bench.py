@@ -660,6 +660,15 @@ def main():
     P.profile_read()
     log(f"[pasr] {args.steps} closures in {t_pasr:.4f} s; step + closure {t_ann_pasr:.3f} s")
 
+    # ---- the audit: the integrator judging the network inside the step ----
+    aud = torch.zeros(3 + 3 * K, dtype=torch.float64, device=dev)
+    aud_frac = 1.0 / 64
+    t_aud = timed_loop(lambda: model.step(gm, 1e-5, Td, pd, Yd, RR=RR, flags=flags,
+                                          n_fallback=nfb, audit_fraction=aud_frac, audit=aud),
+                       restore, 3, 1)
+    aud_np = aud.cpu().numpy()
+    log(f"[audit] 3 audited steps in {t_aud:.3f} s; compared {int(aud_np[0])} cells")
+
     # ---- the same step captured as a HIP graph: one launch per step ----
     P.profile_enable(False)
     graph = model.step_graph(gm, 1e-5, Td, pd, Yd, RR=RR, flags=flags, n_fallback=nfb)
@@ -832,6 +841,21 @@ def main():
                                             max(np.linalg.norm(RRp_ref[k]), 1e-300)), 5)
                for k in majors}
 
+    # the in-step audit's per-species normalised RMSE (its reference is the GPU
+    # integrator on every 64th cell) next to the oracle's figure on its sample
+    aud_nrmse = {}
+    for k, nm_ in enumerate(mech.species):
+        if table[nm_]["major"] and aud_np[0] > 0:
+            rng_ = aud_np[5 + 3 * k] - aud_np[4 + 3 * k]
+            aud_nrmse[nm_] = round(float(np.sqrt(aud_np[3 + 3 * k] / aud_np[0]) / rng_), 5)
+    audit_out = {"fraction": aud_frac, "cells_compared": int(aud_np[0]),
+                 "cells_not_compared": int(aud_np[1]),
+                 "ms_per_audited_step": round(1e3 * t_aud / 3, 3),
+                 "T_max_abs_err_K": float(aud_np[2]),
+                 "nrmse_major": aud_nrmse,
+                 "nrmse_major_max": max(aud_nrmse.values()) if aud_nrmse else None,
+                 "oracle_sample_nrmse_major_max": ann_major}
+
     # ---- roofline of the dominant kernels, from HIP events on their streams ----
     def avg(prof, label):
         c, tot = prof.get(label, (0, 0.0))
@@ -993,6 +1017,7 @@ def main():
                           # T, p, Y in; T, Y, stats out (FP64 SoA, int32 stats)
                           "algorithmic_bytes_per_launch": N * (8 + 8 + 8 * K + 8 + 8 * K + 12)},
         "kernels_ann": kernels_ann,
+        "audit": audit_out,
         "pasr": {"workload": "the BF16 step's rates and state on the same 2^20 cells; Taylor "
                              "times 10^U(-4,-2) s, Kolmogorov times 10^U(-5,-3) s (seed 76)",
                  "ms_per_closure": round(1e3 * t_pasr / args.steps, 4),

@@ -238,7 +238,10 @@ typedef struct {
   float residual_tol;   /* [1e-6] max |element mass fraction change| allowed */
   float ood_margin;     /* [0.05] widening of the training range, fraction of its span */
   int32_t fallback;     /* [1] integrate flagged cells with chem_step */
-  float audit_fraction; /* reserved: must be 0 (any other value is CHEM_EINVAL) */
+  float audit_fraction; /* [0] share of the cells also integrated by chem_step to judge the
+                           network (in [0, 1]; see ann_step) */
+  double *audit;        /* device [3 + 3K] doubles, out: the audit (needed when
+                           audit_fraction > 0, else ignored) */
 } ann_step_opts;
 
 /* The surrogate chemistry step of every cell (the ANN replacing the
@@ -255,7 +258,20 @@ typedef struct {
  * flagged cells keep their input state and, with fallback on, are integrated
  * by chem_step (fb_opts) on the same stream without a host round trip; bit 2
  * marks a failed fallback.  n_fallback (device int64, nullable) receives the
- * number of flagged cells.  Workspace grows on the first call with a larger n. */
+ * number of flagged cells.  Workspace grows on the first call with a larger n.
+ * Audit (the integrator judging the network inside the step): with
+ * audit_fraction f > 0, every s-th cell (s the integer nearest 1/f; cells 0,
+ * s, 2s, ... of the batch)
+ * is also integrated from its input state by chem_step (fb_opts), and
+ * opts->audit receives, for this call: [0] the audited cells the network
+ * handled, [1] the audited cells not compared (flagged by the network, or
+ * whose reference integration failed), [2] the largest |T - T_ref|, and per
+ * species k: [3 + 3k] the sum over the compared cells of (Y_k - Y_ref,k)^2,
+ * [4 + 3k] and [5 + 3k] the smallest and largest reference change
+ * Y_ref,k - Y0,k (so that the normalised RMSE of species k is
+ * sqrt([3 + 3k] / [0]) / ([5 + 3k] - [4 + 3k])).  The sums use atomics: their
+ * last bits vary from run to run.  The audited cells' reference integration
+ * is one more chem_step launch per chunk of cells. */
 chem_status ann_step(ann_model *m, const chem_mech *mech, chem_batch batch, double dt, double *T,
                      const double *p, double *Y, double *RR, uint8_t *flags,
                      int64_t *n_fallback, const ann_step_opts *opts,
@@ -274,7 +290,8 @@ chem_status ann_step(ann_model *m, const chem_mech *mech, chem_batch batch, doub
  * rejected with CHEM_EINVAL, and chem_last_error() states the maximum.  The
  * model and the mechanism must be on the current device.  Calls on one GPU
  * share the array, so calls that overlap in time (other streams, other
- * threads) race; calls ordered on one stream do not. */
+ * threads) race; calls ordered on one stream do not.  The audit needs its
+ * own workspace: audit_fraction must be 0 here. */
 chem_status ann_step_noalloc(ann_model *m, const chem_mech *mech, chem_batch batch, double dt,
                              double *T, const double *p, double *Y, double *RR, uint8_t *flags,
                              int64_t *n_fallback, const ann_step_opts *opts,

@@ -23,7 +23,7 @@ class Norm(C.Structure):
 
 class StepOptsANN(C.Structure):
     _fields_ = [("residual_tol", C.c_float), ("ood_margin", C.c_float), ("fallback", C.c_int32),
-                ("audit_fraction", C.c_float)]
+                ("audit_fraction", C.c_float), ("audit", _P)]
 
 
 class TrainOpts(C.Structure):
@@ -205,17 +205,22 @@ class AnnModel:
         return U
 
     def step(self, mech, dt, T, p, Y, RR=None, flags=None, n_fallback=None, residual_tol=1e-6,
-             ood_margin=0.05, fallback=True, fb_opts=None, stream=None, noalloc=False):
+             ood_margin=0.05, fallback=True, fb_opts=None, stream=None, noalloc=False,
+             audit_fraction=0.0, audit=None):
         """Surrogate chemistry step, in place on T and Y.  RR ([K, ld] float64),
         flags ([n] uint8) and n_fallback ([1] int64) are optional outputs.
         noalloc=True calls ann_step_noalloc (workspace in the library's static
-        device array; the batch must fit in it)."""
+        device array; the batch must fit in it).  audit_fraction > 0 with
+        audit ([3 + 3K] float64 device tensor): the integrator also runs on
+        that share of the cells and judges the network (see ann_step)."""
         import torch
         n = T.shape[0]
         ld = _soa(Y, mech.K, n, "Y")
         if RR is not None and _soa(RR, mech.K, n, "RR") != ld:
             raise ValueError("RR must have the leading dimension of Y")
-        o = StepOptsANN(float(residual_tol), float(ood_margin), 1 if fallback else 0, 0.0)
+        o = StepOptsANN(float(residual_tol), float(ood_margin), 1 if fallback else 0,
+                        float(audit_fraction),
+                        _vec(audit, 3 + 3 * mech.K, "audit", torch.float64))
         fo = _opts(fb_opts)
         f64 = torch.float64
         fn = "ann_step_noalloc" if noalloc else "ann_step"
@@ -227,7 +232,8 @@ class AnnModel:
             C.byref(o), None if fo is None else C.byref(fo), _stream(stream)))
 
     def step_graph(self, mech, dt, T, p, Y, RR=None, flags=None, n_fallback=None,
-                   residual_tol=1e-6, ood_margin=0.05, fallback=True, fb_opts=None):
+                   residual_tol=1e-6, ood_margin=0.05, fallback=True, fb_opts=None,
+                   audit_fraction=0.0, audit=None):
         """ann_step captured as a graph on these arrays (see step)."""
         import torch
         from .binding import Graph
@@ -235,7 +241,9 @@ class AnnModel:
         ld = _soa(Y, mech.K, n, "Y")
         if RR is not None and _soa(RR, mech.K, n, "RR") != ld:
             raise ValueError("RR must have the leading dimension of Y")
-        o = StepOptsANN(float(residual_tol), float(ood_margin), 1 if fallback else 0, 0.0)
+        o = StepOptsANN(float(residual_tol), float(ood_margin), 1 if fallback else 0,
+                        float(audit_fraction),
+                        _vec(audit, 3 + 3 * mech.K, "audit", torch.float64))
         fo = _opts(fb_opts)
         f64 = torch.float64
         h = _P()

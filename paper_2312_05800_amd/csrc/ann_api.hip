@@ -94,6 +94,13 @@ struct ann_model {
   // ann_autotune_train (tt_B = 0: the built-in rules)
   int64_t tt_B = 0;
   int tt_tile[11] = {}, tt_bk[11] = {}, tt_split[4] = {};
+  // audit workspace of ann_step: copies of the audited cells of one chunk and
+  // a flags row for callers that pass none
+  void *aud_buf = nullptr;
+  int64_t aud_cells = 0, aud_flag_cap = 0;
+  double *aud_T = nullptr, *aud_p = nullptr, *aud_Y = nullptr, *aud_Y0 = nullptr;
+  int32_t *aud_stats = nullptr;
+  uint8_t *aud_flags = nullptr;
 };
 
 using namespace chem;
@@ -480,6 +487,7 @@ extern "C" void ann_destroy(ann_model *m) {
   if (m->wi.base) (void)hipFree(m->wi.base);
   if (m->wt.base) (void)hipFree(m->wt.base);
   if (m->fb_index) (void)hipFree(m->fb_index);
+  if (m->aud_buf) (void)hipFree(m->aud_buf);
   delete m;
 }
 
@@ -1010,8 +1018,9 @@ namespace {
 chem_status step_check(const char *fn, ann_model *m, const chem_mech *mech, chem_batch batch,
                        double dt, const double *T, const double *p, const double *Y,
                        const ann_step_opts *opts, ann_step_opts *o) {
-  if (opts && opts->audit_fraction != 0.0f) {
-    set_error("%s: audit_fraction is reserved and must be 0", fn);
+  if (opts && (!(opts->audit_fraction >= 0.0f && opts->audit_fraction <= 1.0f) ||
+               (opts->audit_fraction > 0.0f && !opts->audit))) {
+    set_error("%s: audit_fraction must be in [0, 1], with an audit array when above 0", fn);
     return CHEM_EINVAL;
   }
   chem_status st = check_model(fn, m);
@@ -1037,12 +1046,56 @@ chem_status step_check(const char *fn, ann_model *m, const chem_mech *mech, chem
     set_error("%s: T, p and Y must be non-null", fn);
     return CHEM_EINVAL;
   }
-  *o = ann_step_opts{1e-6f, 0.05f, 1, 0.0f};
+  *o = ann_step_opts{1e-6f, 0.05f, 1, 0.0f, nullptr};
   if (opts) *o = *opts;
   if (!(o->residual_tol >= 0.0f) || !(o->ood_margin >= 0.0f)) {
     set_error("%s: residual_tol and ood_margin must be >= 0", fn);
     return CHEM_EINVAL;
   }
+  return CHEM_OK;
+}
+
+// Stride of the audited cells: every s-th cell, s the integer nearest 1 / f.
+int64_t audit_stride(float f) {
+  const double s = floor(1.0 / (double)f + 0.5);
+  return s < 1.0 ? 1 : (s > 1e15 ? (int64_t)1e15 : (int64_t)s);
+}
+
+// The audit workspace for chunks of up to cap cells (allocates when it grows).
+chem_status audit_prepare(ann_model *m, int64_t cap, float f) {
+  const int64_t na = (cap + audit_stride(f) - 1) / audit_stride(f);
+  if (m->aud_cells >= na && m->aud_flag_cap >= cap) return CHEM_OK;
+  if (m->graph_refs > 0) {
+    set_error("ann_step: the audit workspace is held by a captured step");
+    return CHEM_EINVAL;
+  }
+  const int K = m->n_out;
+  size_t off = 0;
+  auto sect = [&](size_t bytes) {
+    size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  const size_t oT = sect((size_t)na * 8), oP = sect((size_t)na * 8);
+  const size_t oY = sect((size_t)na * K * 8), oY0 = sect((size_t)na * K * 8);
+  const size_t oS = sect((size_t)na * 3 * 4), oF = sect((size_t)cap);
+  if (m->aud_buf) (void)hipFree(m->aud_buf);
+  m->aud_buf = nullptr;
+  m->aud_cells = m->aud_flag_cap = 0;
+  if (hipMalloc(&m->aud_buf, off) != hipSuccess) {
+    m->aud_buf = nullptr;
+    set_error("ann_step: cannot allocate the audit workspace");
+    return CHEM_ENOMEM;
+  }
+  unsigned char *b = (unsigned char *)m->aud_buf;
+  m->aud_T = (double *)(b + oT);
+  m->aud_p = (double *)(b + oP);
+  m->aud_Y = (double *)(b + oY);
+  m->aud_Y0 = (double *)(b + oY0);
+  m->aud_stats = (int32_t *)(b + oS);
+  m->aud_flags = b + oF;
+  m->aud_cells = na;
+  m->aud_flag_cap = cap;
   return CHEM_OK;
 }
 
@@ -1056,8 +1109,23 @@ chem_status step_impl(ann_model *m, const chem_mech *mech, chem_batch batch, dou
   hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, s, w.fb_count);
   // a step other than the one the network was trained for: every cell falls back
   const bool dt_mismatch = fabs(dt - m->nm.dt_model) > 1e-6 * m->nm.dt_model;
+  const bool audit = o.audit_fraction > 0.0f;
+  const int64_t astride = audit ? audit_stride(o.audit_fraction) : 1;
+  if (audit && (st = ann::audit_init(o.audit, m->n_out, s)) != CHEM_OK) return st;
   for (int64_t c0 = 0; c0 < batch.n; c0 += w.cap) {
     const int64_t nc = (batch.n - c0 < w.cap) ? batch.n - c0 : w.cap;
+    ann::AuditArgs aa{};
+    if (audit) {
+      // the audited cells (global indices 0, s, 2s, ...) of this chunk: their
+      // inputs, before the network overwrites them
+      const int64_t first = (astride - c0 % astride) % astride;
+      const int64_t na = first < nc ? (nc - first + astride - 1) / astride : 0;
+      uint8_t *fl = (flags ? flags + c0 : m->aud_flags) + first;
+      aa = ann::AuditArgs{na, astride, batch.ld, m->n_out, T + c0 + first, p + c0 + first,
+                          Y + c0 + first, fl, m->aud_T, m->aud_p, m->aud_Y, m->aud_Y0,
+                          m->aud_stats, o.audit};
+      if ((st = ann::audit_gather(aa, s)) != CHEM_OK) return st;
+    }
     st = forward_chunk(m, w, nc, batch.ld, T + c0, p + c0, Y + c0, w.U, uw(m), w.ood,
                        o.ood_margin, s);
     if (st != CHEM_OK) return st;
@@ -1069,7 +1137,7 @@ chem_status step_impl(ann_model *m, const chem_mech *mech, chem_batch batch, dou
     pa.p = p + c0;
     pa.Y = Y + c0;
     pa.RR = RR ? RR + c0 : nullptr;
-    pa.flags = flags ? flags + c0 : nullptr;
+    pa.flags = flags ? flags + c0 : (audit ? m->aud_flags : nullptr);
     pa.U = w.U;
     pa.doutp = uw(m);
     pa.nm = m->nm;
@@ -1083,6 +1151,15 @@ chem_status step_impl(ann_model *m, const chem_mech *mech, chem_batch batch, dou
     pa.index_base = c0;
     st = ann::post(mech->d, pa, s);
     if (st != CHEM_OK) return st;
+    if (audit) {
+      // the reference: the plain step on the copies, then the comparison
+      if (aa.na > 0) {
+        st = launch_step(mech, aa.na, aa.na, dt, nullptr, m->aud_T, m->aud_p, m->aud_Y, nullptr,
+                         nullptr, m->aud_stats, fo, nullptr, s);
+        if (st != CHEM_OK) return st;
+      }
+      if ((st = ann::audit_compare(aa, s)) != CHEM_OK) return st;
+    }
   }
   if (o.fallback) {
     st = launch_step(mech, batch.n, batch.ld, dt, nullptr, T, p, Y, RR, nullptr, nullptr, fo,
@@ -1139,6 +1216,8 @@ extern "C" chem_status ann_step(ann_model *m, const chem_mech *mech, chem_batch 
   const StepOpts fo = resolve_opts(fb_opts);
   st = step_prepare(m, batch.n, o.fallback != 0);
   if (st != CHEM_OK) return st;
+  if (o.audit_fraction > 0.0f && (st = audit_prepare(m, m->wi.cap, o.audit_fraction)) != CHEM_OK)
+    return st;
   return step_impl(m, mech, batch, dt, T, p, Y, RR, flags, n_fallback, o, fo, model_ws(m),
                    m->fb_index, (hipStream_t)stream);
 }
@@ -1151,6 +1230,10 @@ extern "C" chem_status ann_step_noalloc(ann_model *m, const chem_mech *mech, che
   ann_step_opts o;
   chem_status st = step_check("ann_step_noalloc", m, mech, batch, dt, T, p, Y, opts, &o);
   if (st != CHEM_OK || batch.n == 0) return st;
+  if (o.audit_fraction > 0.0f) {
+    set_error("ann_step_noalloc: the audit needs its own workspace (audit_fraction must be 0)");
+    return CHEM_EINVAL;
+  }
   int dev = -1;
   CHEM_HIP(hipGetDevice(&dev));
   if (dev != m->device || dev != mech->device) {
@@ -1817,6 +1900,9 @@ extern "C" chem_status ann_step_graph_create(ann_model *m, const chem_mech *mech
   // rebuilt from the BF16 copies (so replays follow weight updates)
   st = step_prepare(m, batch.n, !opts || opts->fallback != 0);
   if (st != CHEM_OK) return st;
+  if (opts && opts->audit_fraction > 0.0f &&
+      (st = audit_prepare(m, m->wi.cap, opts->audit_fraction)) != CHEM_OK)
+    return st;
   m->wt_stale = true;
   st = capture_graph(
       [&](hipStream_t cs) {

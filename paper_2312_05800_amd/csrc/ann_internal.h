@@ -224,6 +224,23 @@ struct PostArgs {
 };
 chem_status post(const chem::DevMech &M, const PostArgs &a, hipStream_t s);
 
+// The audit of a chunk: cells 0, stride, 2 stride, ... of the chunk's arrays
+// (T, p, Y with leading dimension ld; flags as post wrote them) against their
+// copies Ta, pa, Ya (integrated by the plain step; Y0a keeps the inputs),
+// na cells, stats_a [3][na] the reference integration's rows.
+struct AuditArgs {
+  int64_t na, stride, ld;
+  int K;
+  const double *T, *p, *Y;
+  const uint8_t *flags;
+  double *Ta, *pa, *Ya, *Y0a;
+  const int32_t *stats_a;
+  double *audit;
+};
+chem_status audit_init(double *audit, int K, hipStream_t s);
+chem_status audit_gather(const AuditArgs &a, hipStream_t s);
+chem_status audit_compare(const AuditArgs &a, hipStream_t s);
+
 struct StatArgs {
   int64_t n, ld;
   const double *T, *p, *Y0, *Y1;

@@ -1858,6 +1858,72 @@ __global__ __launch_bounds__(128, 4) void k_post(chem::DevMech M, PostArgs a) {
 }
 
 
+// ------------------------------------------------------------- audit
+// The integrator judging the network: the audited cells (every s-th of a
+// chunk) are copied before the network runs, integrated by the plain step
+// afterwards, and compared with what the network left in the caller's arrays.
+
+__global__ void k_audit_init(double *audit, int K) {
+  for (int q = threadIdx.x; q < 3 + 3 * K; q += blockDim.x) {
+    const int r = q < 3 ? 0 : (q - 3) % 3;
+    audit[q] = q < 3 ? 0.0 : (r == 0 ? 0.0 : (r == 1 ? INFINITY : -INFINITY));
+  }
+}
+
+__global__ void k_audit_gather(AuditArgs a) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= a.na) return;
+  const int64_t i = j * a.stride;
+  a.Ta[j] = a.T[i];
+  a.pa[j] = a.p[i];
+  for (int k = 0; k < a.K; ++k) {
+    const double y = a.Y[(int64_t)k * a.ld + i];
+    a.Ya[(int64_t)k * a.na + j] = y;
+    a.Y0a[(int64_t)k * a.na + j] = y;
+  }
+}
+
+__device__ __forceinline__ void atomic_min_f64(double *p, double v) {
+  unsigned long long *u = (unsigned long long *)p;
+  unsigned long long old = *u;
+  while (v < __longlong_as_double(old)) {
+    const unsigned long long seen = atomicCAS(u, old, __double_as_longlong(v));
+    if (seen == old) break;
+    old = seen;
+  }
+}
+__device__ __forceinline__ void atomic_max_f64(double *p, double v) {
+  unsigned long long *u = (unsigned long long *)p;
+  unsigned long long old = *u;
+  while (v > __longlong_as_double(old)) {
+    const unsigned long long seen = atomicCAS(u, old, __double_as_longlong(v));
+    if (seen == old) break;
+    old = seen;
+  }
+}
+
+__global__ void k_audit_compare(AuditArgs a) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= a.na) return;
+  const int64_t i = j * a.stride;
+  const bool flagged = a.flags[i] != 0;
+  const bool ref_ok = a.stats_a[2 * a.na + j] == 0;
+  if (flagged || !ref_ok) {
+    atomicAdd(&a.audit[1], 1.0);
+    return;
+  }
+  atomicAdd(&a.audit[0], 1.0);
+  atomic_max_f64(&a.audit[2], fabs(a.T[i] - a.Ta[j]));
+  for (int k = 0; k < a.K; ++k) {
+    const double yr = a.Ya[(int64_t)k * a.na + j];
+    const double d = a.Y[(int64_t)k * a.ld + i] - yr;
+    const double dref = yr - a.Y0a[(int64_t)k * a.na + j];
+    atomicAdd(&a.audit[3 + 3 * k], d * d);
+    atomic_min_f64(&a.audit[4 + 3 * k], dref);
+    atomic_max_f64(&a.audit[5 + 3 * k], dref);
+  }
+}
+
 // ---------------------------------------------------------- statistics
 
 // Partial statistics of the training features: block (b, f) covers feature f
@@ -2224,5 +2290,26 @@ chem_status stats_partial(const StatArgs &a, hipStream_t s) {
   CHEM_HIP(hipGetLastError());
   return CHEM_OK;
 }
+
+chem_status audit_init(double *audit, int K, hipStream_t s) {
+  hipLaunchKernelGGL(k_audit_init, dim3(1), dim3(256), 0, s, audit, K);
+  CHEM_HIP(hipGetLastError());
+  return CHEM_OK;
+}
+
+chem_status audit_gather(const AuditArgs &a, hipStream_t s) {
+  if (a.na <= 0) return CHEM_OK;
+  hipLaunchKernelGGL(k_audit_gather, dim3(nblk(a.na, 256)), dim3(256), 0, s, a);
+  CHEM_HIP(hipGetLastError());
+  return CHEM_OK;
+}
+
+chem_status audit_compare(const AuditArgs &a, hipStream_t s) {
+  if (a.na <= 0) return CHEM_OK;
+  hipLaunchKernelGGL(k_audit_compare, dim3(nblk(a.na, 256)), dim3(256), 0, s, a);
+  CHEM_HIP(hipGetLastError());
+  return CHEM_OK;
+}
+
 
 }  // namespace ann

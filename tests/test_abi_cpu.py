@@ -73,18 +73,19 @@ def test_tuning_and_graph_arguments_rejected_on_host():
     assert not h.value
 
 
-def test_reserved_audit_fraction_rejected_on_host():
-    """ann_step rejects a non-zero audit_fraction (reserved) before anything
-    else, so the check needs no model and no GPU."""
+def test_audit_arguments_rejected_on_host():
+    """ann_step rejects an audit fraction outside [0, 1], or above 0 without
+    an audit array, before anything else (no model or GPU needed)."""
     import ctypes as C
     import paper_2312_05800_amd as P
     from paper_2312_05800_amd.ann import StepOptsANN
     L = P.lib()
-    o = StepOptsANN(1e-6, 0.05, 1, 0.25)
-    assert L.ann_step(None, None, P.binding.Batch(1, 1), 1e-5, None, None, None, None, None,
-                      None, C.byref(o), None, None) == 1
-    assert b"audit_fraction" in L.chem_last_error()
-    o = StepOptsANN(1e-6, 0.05, 1, 0.0)
+    for f, arr in ((1.5, 1), (-0.1, 1), (float("nan"), 1), (0.25, None)):
+        o = StepOptsANN(1e-6, 0.05, 1, f, arr)
+        assert L.ann_step(None, None, P.binding.Batch(1, 1), 1e-5, None, None, None, None, None,
+                          None, C.byref(o), None, None) == 1
+        assert b"audit_fraction" in L.chem_last_error()
+    o = StepOptsANN(1e-6, 0.05, 1, 0.0, None)
     assert L.ann_step(None, None, P.binding.Batch(1, 1), 1e-5, None, None, None, None, None,
                       None, C.byref(o), None, None) == 1
     assert b"null model" in L.chem_last_error()

@@ -737,3 +737,47 @@ def test_large_tile_paths_ragged(dev, mech, data):
     Yg8 = Yd[:, it].cpu().numpy()
     _check_post(Yg8, Td[it].cpu().numpy(), RR8[:, it].cpu().numpy(), o8, Y[:, idx],
                 U8full[idx], nm, ok8)
+
+
+@pytest.mark.parametrize("N,frac", [(3001, 0.01), ((1 << 21) + 4097, 1.0 / 3000)])
+def test_step_audit(dev, mech, data, N, frac):
+    """The audit inside ann_step (the integrator judging the network): every
+    s-th cell (s the integer nearest 1/f, counted over the whole batch, across the
+    2^21-cell chunks) is integrated from its input and compared with what the
+    network left.  Against the oracle's step on the same cells and the GPU's
+    own outputs: the counts exactly, the largest |T - T_ref|, the per-species
+    sums of squared differences and the range of the reference change (the
+    GPU's reference integrator agrees with the oracle to ~1e-12)."""
+    import torch
+    import paper_2312_05800_amd as P
+    _say(f"[ann step audit] N={N} f={frac:.5f}")
+    K = mech.K
+    om = oracle.OracleMech(mech)
+    params = oann.init_params([K + 2, *HID, K], seed=31)
+    params[3] = (params[3][0] * 0.02, params[3][1] * 0.02)
+    nm = _norm_from(data)
+    m = _model(mech, params, nm)
+    gm = P.Mechanism(mech)
+    T, p, Y = chemgen.make_states(mech, "ch4", N=N, seed=32)
+    Td, pd, Yd = to_dev(T, dev), to_dev(p, dev), to_dev(Y, dev)
+    flags = torch.zeros(N, dtype=torch.uint8, device=dev)
+    audit = torch.full((3 + 3 * K,), -7.0, dtype=torch.float64, device=dev)
+    m.step(gm, 1e-5, Td, pd, Yd, flags=flags, residual_tol=1e-2, audit_fraction=frac,
+           audit=audit)
+    torch.cuda.synchronize()
+    s = int(np.floor(1.0 / np.float64(np.float32(frac)) + 0.5))
+    idx = np.arange(0, N, s)
+    o = oracle.chem_step(om, 1e-5, T[idx], p[idx], Y[:, idx])
+    fg = flags.cpu().numpy()[idx]
+    ok = (fg == 0) & (o["stats"][2] == 0)
+    Tg, Yg = Td.cpu().numpy()[idx], Yd.cpu().numpy()[:, idx]
+    a = audit.cpu().numpy()
+    _say(f"  audited {idx.size}: compared {int(a[0])}, not compared {int(a[1])}")
+    assert a[0] == ok.sum() and a[1] == idx.size - ok.sum() and ok.sum() > idx.size // 2
+    np.testing.assert_allclose(a[2], np.abs(Tg - o["T"])[ok].max(), rtol=1e-6)
+    d = Yg[:, ok] - o["Y"][:, ok]
+    dref = o["Y"][:, ok] - Y[:, idx][:, ok]
+    sums = (d ** 2).sum(axis=1)
+    np.testing.assert_allclose(a[3::3], sums, rtol=1e-6, atol=1e-30)
+    np.testing.assert_allclose(a[4::3], dref.min(axis=1), rtol=1e-9, atol=1e-18)
+    np.testing.assert_allclose(a[5::3], dref.max(axis=1), rtol=1e-9, atol=1e-18)
