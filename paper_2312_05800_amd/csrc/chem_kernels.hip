@@ -484,13 +484,93 @@ __device__ __forceinline__ bool gj_factor(double *A, int l, int n, int &mystep, 
   return ok;
 }
 
+// Largest of 32-bit integer values over the caller's group (one DPP max per
+// stage, as in grp_max).
+template <int G>
+__device__ __forceinline__ int grp_max_i32(int v) {
+  v = max(v, dpp_i32<0xB1>(v));
+  v = max(v, dpp_i32<0x4E>(v));
+  v = max(v, dpp_i32<0x141>(v));
+  v = max(v, dpp_i32<0x140>(v));
+  if (G >= 32) {
+    const auto r = __builtin_amdgcn_permlane16_swap((unsigned)v, (unsigned)v, false, false);
+    v = max((int)r[0], (int)r[1]);
+  }
+  if (G == 64) {
+    const auto r = __builtin_amdgcn_permlane32_swap((unsigned)v, (unsigned)v, false, false);
+    v = max((int)r[0], (int)r[1]);
+  }
+  return v;
+}
+template <int G>
+__device__ __forceinline__ unsigned grp_max_u32(unsigned v) {
+  v = max(v, (unsigned)dpp_i32<0xB1>((int)v));
+  v = max(v, (unsigned)dpp_i32<0x4E>((int)v));
+  v = max(v, (unsigned)dpp_i32<0x141>((int)v));
+  v = max(v, (unsigned)dpp_i32<0x140>((int)v));
+  if (G >= 32) {
+    const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    v = max((unsigned)r[0], (unsigned)r[1]);
+  }
+  if (G == 64) {
+    const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    v = max((unsigned)r[0], (unsigned)r[1]);
+  }
+  return v;
+}
+
+// Lowest lane (index within the caller's group) whose b is set; G if none.
+template <int G>
+__device__ __forceinline__ int grp_first_lane(bool b) {
+  const unsigned long long m = __ballot(b);
+  if (G == 64) return m ? __builtin_ctzll(m) : G;
+  const int g = ((int)threadIdx.x & 63) / G;
+  int out = G;
+#pragma unroll
+  for (int gg = 0; gg < 64 / G; ++gg) {
+    // bit G stands in for "no lane"
+    const unsigned long long part =
+        ((m >> (gg * G)) & ((1ull << (G & 63)) - 1ull)) | (1ull << (G & 63));
+    const int f = __builtin_ctzll(part);
+    out = (g == gg) ? f : out;
+  }
+  return out;
+}
+
+// Pivot lane of an elimination step: the lane with the largest v in the
+// group, the lowest lane among equal values.  v is +0 ... +inf (a candidate
+// row's |entry|) or -1 (a row already used), never NaN; on these values the
+// order of the doubles is the order of the pair (high word as a signed
+// integer, low word as an unsigned one), so the search runs on 32-bit words
+// and ends in a ballot of the lanes holding the maximum.
+template <int G>
+__device__ __forceinline__ int grp_argmax(double v) {
+  const long long b = __double_as_longlong(v);
+  const int hi = (int)(b >> 32);
+  const unsigned lo = (unsigned)b;
+  const int mh = grp_max_i32<G>(hi);
+  const unsigned ml = grp_max_u32<G>(hi == mh ? lo : 0u);
+  return grp_first_lane<G>(hi == mh && lo == ml);
+}
+
+// c - m a as a three-address FMA: its result may go to another register than
+// c, so the rotation of the register row below costs no copies.
+__device__ __forceinline__ double fma_nm(double m, double a, double c) {
+  double d;
+  asm("v_fma_f64 %0, -%1, %2, %3" : "=v"(d) : "v"(m), "v"(a), "v"(c));
+  return d;
+}
+
 // gj_factor with each lane's row held in registers (groups of up to 32
 // lanes): slot 0 always holds the column being eliminated (the row is
 // rotated by one slot per step, so every index is a compile-time constant),
 // and the pivot row reaches the other lanes through pbuf (G doubles of LDS)
 // as one broadcast per step; the only LDS round trip left on a step's
-// dependency chain.  Same arithmetic, in the same order, as gj_factor; the
-// factors are written back to the LDS rows at the end.
+// dependency chain.  Every lane forms the reciprocal of its own candidate
+// pivot while the pivot is searched for, and the pivot lane sends its
+// reciprocal in place of the pivot (slot 0): the division leaves the chain.
+// Same arithmetic, in the same order, as gj_factor; the factors are written
+// back to the LDS rows at the end.
 template <int G>
 __device__ __forceinline__ bool gj_factor_reg(double *A, double *pbuf, int l, int n, int &mystep,
                                               double &invd) {
@@ -504,38 +584,38 @@ __device__ __forceinline__ bool gj_factor_reg(double *A, double *pbuf, int l, in
   bool done = !real;
   mystep = done ? l : -1;
   invd = 1.0;
-  bool ok = true;
+  bool ok = true;  // this lane's pivot (if it was one) is finite and non-zero
+  // the reciprocal of slot 0, formed as soon as the slot is (at the end of
+  // the previous step)
+  double rinv = 1.0 / r[0];
   for (int k = 0; k < n; ++k) {
     double v = done ? -1.0 : fabs(r[0]);
     if (v != v) v = INFINITY;
-    const double vmax = grp_max<G>(v);
-    const int idx = grp_min<G>(v == vmax ? l : G);
+    const int idx = grp_argmax<G>(v);
     const bool isp = (l == idx);
     if (isp) {
+      pbuf[0] = rinv;
 #pragma unroll
-      for (int i = 0; i < G; ++i) pbuf[i] = r[i];
-    }
-    wave_sync();
-    const double pv = pbuf[0];
-    if (!(fabs(pv) > 0.0) || !isfinite(pv)) ok = false;
-    const double inv = 1.0 / pv;
-    if (isp) {
+      for (int i = 1; i < G; ++i) pbuf[i] = r[i];
+      if (!(fabs(r[0]) > 0.0) || !isfinite(r[0])) ok = false;
       done = true;
       mystep = k;
-      invd = inv;
+      invd = rinv;
     }
+    wave_sync();
+    const double inv = pbuf[0];
     const double m = isp ? 0.0 : r[0] * inv;
     double pr[G];
 #pragma unroll
     for (int i = 1; i < G; ++i) pr[i] = pbuf[i];
-    // all reads of the pivot row in flight together, then the updates
-    __builtin_amdgcn_sched_group_barrier(0x100, G / 2, 0);
-    __builtin_amdgcn_sched_group_barrier(0x002, 4 * G, 0);
-#pragma unroll
-    for (int i = 1; i < G; ++i) r[i] = fma(-m, pr[i], r[i]);
     const double c0 = isp ? 1.0 : -m;
+    // the next step's column first, so that its reciprocal (formed here by
+    // every lane, not sunk into the pivot's branch) overlaps the other updates
+    r[0] = fma_nm(m, pr[1], r[1]);
+    rinv = 1.0 / r[0];
+    asm volatile("" : "+v"(rinv));
 #pragma unroll
-    for (int i = 0; i < G - 1; ++i) r[i] = r[i + 1];
+    for (int i = 1; i < G - 1; ++i) r[i] = fma_nm(m, pr[i + 1], r[i + 1]);
     r[G - 1] = c0;
     wave_sync();  // every lane has read pbuf before the next pivot row goes there
   }
@@ -553,7 +633,7 @@ __device__ __forceinline__ bool gj_factor_reg(double *A, double *pbuf, int l, in
       if (i < n) rowp[i] = r[i];
   }
   wave_sync();
-  return ok;
+  return !grp_any<G>(!ok);
 }
 
 // Solve M x = b with the factors of gj_factor.  Lane l passes b_l, gets x_l.
