@@ -301,6 +301,38 @@ __device__ __forceinline__ void jac_scatter(const GLds<G> &L, const Rxn &x, doub
     if (has[b]) lds_add(L.J + 1 + sp[b], dHr * dq[b]);
 }
 
+// sum_j x[j] y[j] over j < n (LDS arrays), one FMA per term in index order.
+// The operands are read eight at a time, so a chunk costs one LDS round trip
+// instead of one per term; the last chunk reads with its indices clamped to
+// n - 1 and adds only its terms below n.
+__device__ __forceinline__ double dot_lds(const double *x, const double *y, int n) {
+  double acc = 0.0;
+  int j0 = 0;
+  for (; j0 + 8 <= n; j0 += 8) {
+    double a[8], c[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      a[u] = x[j0 + u];
+      c[u] = y[j0 + u];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc = fma(a[u], c[u], acc);
+  }
+  if (j0 < n) {
+    double a[8], c[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int j = min(j0 + u, n - 1);
+      a[u] = x[j];
+      c[u] = y[j];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (j0 + u < n) acc = fma(a[u], c[u], acc);
+  }
+  return acc;
+}
+
 // Right-hand side (and optionally the Jacobian) of one cell.  Lane l holds
 // y_l in yl.  On return lane l holds f_l; species lanes hold wdot_k in wdl.
 // With JAC, LDS row l (l < n) of L.J holds row l of M = I*dg - J.  With KOUT
@@ -400,7 +432,7 @@ __device__ __forceinline__ void eval_cell(const DevMech &M, const GLds<G> &L, in
   const double sumHqT = grp_sum<G>(sumHq);
   double a = 0.0, dwdTC = 0.0, JwT = 0.0;
   if (isSp) {
-    for (int j = 0; j < K; ++j) a += Jrow[1 + j] * L.C[j];
+    a = dot_lds(Jrow + 1, L.C, K);
     dwdTC = Jrow[0];
     JwT = L.J[1 + k];
   }
@@ -646,9 +678,7 @@ __device__ __forceinline__ double gj_solve(const double *A, double *v, int l, in
   const bool real = l < n;  // lanes past n own no row (none is stored for them)
   if (real) v[mystep] = b;
   wave_sync();
-  double acc = 0.0;
-  if (real)
-    for (int j = 0; j < n; ++j) acc = fma(row[j], v[j], acc);
+  const double acc = real ? dot_lds(row, v, n) : 0.0;
   wave_sync();
   if (real) v[mystep] = acc * invd;
   wave_sync();
