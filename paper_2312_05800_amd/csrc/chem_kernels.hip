@@ -444,9 +444,24 @@ __device__ __forceinline__ void eval_cell(const DevMech &M, const GLds<G> &L, in
   const double irhocp = irho / cp;
   if (isSp) {
     const double c2 = Wk * (wd - a) * irho / S;
-    for (int i = 0; i < K; ++i) {
-      const double Jki = (Wk * Jrow[1 + i] + c2) * M.invW[i];
-      Jrow[1 + i] = ((i == k) ? dg : 0.0) - Jki;
+    // eight entries of the row read, then eight written: one LDS round trip
+    // per chunk (the last chunk reads with its indices clamped to K - 1)
+    for (int i0 = 0; i0 < K; i0 += 8) {
+      double jr[8], iw[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int i = min(i0 + u, K - 1);
+        jr[u] = Jrow[1 + i];
+        iw[u] = M.invW[i];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int i = i0 + u;
+        if (i < K) {
+          const double Jki = (Wk * jr[u] + c2) * iw[u];
+          Jrow[1 + i] = ((i == k) ? dg : 0.0) - Jki;
+        }
+      }
     }
     Jrow[0] = -(Wk * irho * (dwdTC + (wd - a) * invT));
     L.J[1 + k] = ((rho * JwT - aT / S) * iWk) * irhocp + fT * (-iWk / S + RG * cpR * iWk / cp);
@@ -625,21 +640,26 @@ __device__ __forceinline__ bool gj_factor_reg(double *A, double *pbuf, int l, in
     if (v != v) v = INFINITY;
     const int idx = grp_argmax<G>(v);
     const bool isp = (l == idx);
+    // pbuf is 16-byte aligned: the row moves as G / 2 pairs (b128 accesses)
+    double2 *const pb2 = (double2 *)pbuf;
     if (isp) {
-      pbuf[0] = rinv;
+      pb2[0] = make_double2(rinv, r[1]);
 #pragma unroll
-      for (int i = 1; i < G; ++i) pbuf[i] = r[i];
+      for (int i = 1; i < G / 2; ++i) pb2[i] = make_double2(r[2 * i], r[2 * i + 1]);
       if (!(fabs(r[0]) > 0.0) || !isfinite(r[0])) ok = false;
       done = true;
       mystep = k;
       invd = rinv;
     }
     wave_sync();
-    const double inv = pbuf[0];
+    double2 q[G / 2];
+#pragma unroll
+    for (int i = 0; i < G / 2; ++i) q[i] = pb2[i];
+    const double inv = q[0].x;
     const double m = isp ? 0.0 : r[0] * inv;
     double pr[G];
 #pragma unroll
-    for (int i = 1; i < G; ++i) pr[i] = pbuf[i];
+    for (int i = 1; i < G; ++i) pr[i] = (i & 1) ? q[i / 2].y : q[i / 2].x;
     const double c0 = isp ? 1.0 : -m;
     // the next step's column first, so that its reciprocal (formed here by
     // every lane, not sunk into the pivot's branch) overlaps the other updates
