@@ -195,20 +195,21 @@ __device__ __forceinline__ double grp_first(double v) {
   return out;
 }
 
-// Per-group LDS scratch (doubles): concentrations, h/RT and g/RT of the
-// species, the net production rates being accumulated, and the Jacobian /
-// Newton matrix (n rows of odd stride).  In chem_rates the matrix region
-// holds k_f, k_r instead; in the solves the concentration slots hold the
-// permuted right-hand side.
+// Per-group LDS scratch (doubles): concentrations, (g/RT, h/RT) pairs of the
+// species (one 16-byte gather per reaction slot), the net production rates
+// being accumulated, and the Jacobian / Newton matrix (n rows of odd
+// stride).  In chem_rates the matrix region holds k_f, k_r instead; in the
+// solves the concentration slots hold the permuted right-hand side.
 template <int G>
 struct GLds {
-  double *C, *hs, *gs, *wa, *J;
+  double *C;
+  double2 *gh;  // 16-byte aligned: the slice starts so, and C holds G doubles
+  double *wa, *J;
   int js;  // row stride of J
   __device__ GLds(double *base, int R, int n) {
     C = base;
-    hs = C + G;
-    gs = hs + G;
-    wa = gs + G;
+    gh = (double2 *)(C + G);
+    wa = C + 3 * G;
     J = wa + G;
     js = stride(n);
   }
@@ -244,16 +245,18 @@ __device__ __forceinline__ Rxn rxn_eval(const DevMech &M, const GLds<G> &L, int 
   x.sp = M.sp[r];
   x.nu = M.nu[r];
   // empty slots gather the dummy species (g = h = 0, coefficient 0): no branches,
-  // so the twelve LDS reads of a reaction issue together
+  // so the eight LDS reads of a reaction (four (g, h) pairs, four
+  // concentrations) issue together
   double dG = 0.0, dH = 0.0;
-  dG -= x.nu.x * L.gs[x.sp.x];
-  dH -= x.nu.x * L.hs[x.sp.x];
-  dG -= x.nu.y * L.gs[x.sp.y];
-  dH -= x.nu.y * L.hs[x.sp.y];
-  dG += x.nu.z * L.gs[x.sp.z];
-  dH += x.nu.z * L.hs[x.sp.z];
-  dG += x.nu.w * L.gs[x.sp.w];
-  dH += x.nu.w * L.hs[x.sp.w];
+  const double2 a0 = L.gh[x.sp.x], a1 = L.gh[x.sp.y], a2 = L.gh[x.sp.z], a3 = L.gh[x.sp.w];
+  dG -= x.nu.x * a0.x;
+  dH -= x.nu.x * a0.y;
+  dG -= x.nu.y * a1.x;
+  dH -= x.nu.y * a1.y;
+  dG += x.nu.z * a2.x;
+  dH += x.nu.z * a2.y;
+  dG += x.nu.w * a3.x;
+  dH += x.nu.w * a3.y;
   x.dH = dH;
   x.dn = M.dn[r];
   const double lnkf = M.lnA[r] + M.b[r] * lnT - M.EaR[r] * invT;
@@ -367,13 +370,11 @@ __device__ __forceinline__ void eval_cell(const DevMech &M, const GLds<G> &L, in
   const double cp = grp_sum<G>(Yk * RG * cpR * iWk);
   if (isSp) {
     L.C[k] = Ck;
-    L.hs[k] = hRT;
-    L.gs[k] = hRT - sR;
+    L.gh[k] = make_double2(hRT - sR, hRT);
   }
   if (l == 0) {  // the dummy species of empty reaction slots
     L.C[K] = 1.0;
-    L.hs[K] = 0.0;
-    L.gs[K] = 0.0;
+    L.gh[K] = make_double2(0.0, 0.0);
   }
   L.wa[l] = 0.0;
   double *Jrow = L.J + l * L.js;
