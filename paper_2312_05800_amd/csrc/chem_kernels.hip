@@ -592,13 +592,22 @@ __device__ __forceinline__ int grp_first_lane(bool b) {
 // integer, low word as an unsigned one), so the search runs on 32-bit words
 // and ends in a ballot of the lanes holding the maximum.
 template <int G>
-__device__ __forceinline__ int grp_argmax(double v) {
+__device__ __forceinline__ bool grp_is_max(double v) {
   const long long b = __double_as_longlong(v);
   const int hi = (int)(b >> 32);
   const unsigned lo = (unsigned)b;
   const int mh = grp_max_i32<G>(hi);
   const unsigned ml = grp_max_u32<G>(hi == mh ? lo : 0u);
-  return grp_first_lane<G>(hi == mh && lo == ml);
+  return hi == mh && lo == ml;
+}
+template <int G>
+__device__ __forceinline__ int grp_argmax(double v) {
+  return grp_first_lane<G>(grp_is_max<G>(v));
+}
+// the wave's ballot of the lanes holding their group's maximum
+template <int G>
+__device__ __forceinline__ unsigned long long grp_argmax_mask(double v) {
+  return __ballot(grp_is_max<G>(v));
 }
 
 // c - m a as a three-address FMA: its result may go to another register than
@@ -608,6 +617,9 @@ __device__ __forceinline__ double fma_nm(double m, double a, double c) {
   asm("v_fma_f64 %0, -%1, %2, %3" : "=v"(d) : "v"(m), "v"(a), "v"(c));
   return d;
 }
+
+// pairs of the pivot row broadcast by v_readlane instead of LDS (G = 32)
+constexpr int GJ_RL = 2;
 
 // gj_factor with each lane's row held in registers (groups of up to 32
 // lanes): slot 0 always holds the column being eliminated (the row is
@@ -639,14 +651,31 @@ __device__ __forceinline__ bool gj_factor_reg(double *A, double *pbuf, int l, in
   for (int k = 0; k < n; ++k) {
     double v = done ? -1.0 : fabs(r[0]);
     if (v != v) v = INFINITY;
-    const int idx = grp_argmax<G>(v);
+    // the first GJ_RL pairs of the pivot row (slot 0 carrying the
+    // reciprocal) reach the other lanes by v_readlane from the pivot lanes of
+    // the wave's two groups, the rest through LDS: the LDS pipe, shared by
+    // every wave of the CU, is the integrator's busiest unit, and moving two
+    // of the sixteen pairs to the VALU was the fastest split measured
+    constexpr int RP = (G == 32) ? GJ_RL : 0;
+    int idx, q0 = 0, q1 = 0;
+    if constexpr (RP > 0) {
+      const unsigned long long bm = grp_argmax_mask<G>(v);
+      q0 = __builtin_ctzll((bm & 0xffffffffull) | (1ull << 32));
+      q1 = __builtin_ctzll((bm >> 32) | (1ull << 32));
+      idx = (((int)threadIdx.x & 63) < 32) ? q0 : q1;
+      q0 &= 31;
+      q1 = 32 + (q1 & 31);
+    } else {
+      idx = grp_argmax<G>(v);
+    }
     const bool isp = (l == idx);
     // pbuf is 16-byte aligned: the row moves as G / 2 pairs (b128 accesses)
     double2 *const pb2 = (double2 *)pbuf;
     if (isp) {
-      pb2[0] = make_double2(rinv, r[1]);
+      if (RP == 0) pb2[0] = make_double2(rinv, r[1]);
 #pragma unroll
-      for (int i = 1; i < G / 2; ++i) pb2[i] = make_double2(r[2 * i], r[2 * i + 1]);
+      for (int i = (RP > 0 ? RP : 1); i < G / 2; ++i)
+        pb2[i] = make_double2(r[2 * i], r[2 * i + 1]);
       if (!(fabs(r[0]) > 0.0) || !isfinite(r[0])) ok = false;
       done = true;
       mystep = k;
@@ -655,7 +684,17 @@ __device__ __forceinline__ bool gj_factor_reg(double *A, double *pbuf, int l, in
     wave_sync();
     double2 q[G / 2];
 #pragma unroll
-    for (int i = 0; i < G / 2; ++i) q[i] = pb2[i];
+    for (int i = RP; i < G / 2; ++i) q[i] = pb2[i];
+    if constexpr (RP > 0) {
+      const bool g0 = ((int)threadIdx.x & 63) < 32;
+#pragma unroll
+      for (int i = 0; i < RP; ++i) {
+        const double e0 = (i == 0) ? rinv : r[2 * i], e1 = r[2 * i + 1];
+        const double a0 = readlane_f64(e0, q0), b0 = readlane_f64(e0, q1);
+        const double a1 = readlane_f64(e1, q0), b1 = readlane_f64(e1, q1);
+        q[i] = make_double2(g0 ? a0 : b0, g0 ? a1 : b1);
+      }
+    }
     const double inv = q[0].x;
     const double m = isp ? 0.0 : r[0] * inv;
     double pr[G];
