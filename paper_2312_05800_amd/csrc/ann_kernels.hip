@@ -313,10 +313,16 @@ __global__ __launch_bounds__(WM *WN * 64) void k_gemm(GemmArgs g) {
 // Operand tiles are streamed into LDS by direct global->LDS loads
 // (global_load_lds_dwordx4: lane i's 16 bytes land at M0 + 16 i), so no
 // registers stage them.  A tile row holds 32 K values (64 bytes, four 16-byte
-// chunks); chunk c of row r is stored at position c ^ swz(r), which makes the
-// 16-lane phases of the 16-byte fragment reads hit distinct banks of the
-// 64-bank LDS (rows r..r+15 read one chunk each).
-__device__ __forceinline__ int swz(int r) { return (r >> 2) & 3; }
+// chunks); chunk c of row r is stored at position c ^ swz(r).  A fragment
+// read has rows r..r+15 (r a multiple of 16) read one chunk each; the
+// swizzle puts any 8 consecutive of those lanes on distinct 4-byte banks of
+// a 32-bank window, and all 16 on distinct banks of a 64-bank one (row r
+// starts at bank 16 r: rows of equal parity within an octet, and rows equal
+// mod 4 within the 16, get distinct positions).  It depends on r mod 16 only.
+// (The earlier (r >> 2) & 3 met the 64-bank condition alone; the LDS
+// bank-conflict counter put half of the fragment reads' LDS cycles in
+// conflicts with it.)
+__device__ __forceinline__ int swz(int r) { return ((r >> 1) ^ ((r >> 3) & 1)) & 3; }
 
 // One direct load of 16 bytes per lane: wave-uniform 64-bit base in SGPRs, a
 // 32-bit per-lane byte offset, destination M0 = lds_addr (wave-uniform).
@@ -693,11 +699,11 @@ __device__ __forceinline__ void mlp12_tile(const Mlp12Args &g, u16 *S, float *b1
   // DMA rows: the first R1 rows of a stage are the first layer's weights of
   // the next K-step, then BN rows of the second layer's (all valid: N is a
   // multiple of BN).  A 16-row group starts at a multiple of 16, so the
-  // swizzle of row 16 gi + l / 4 is (l / 16) & 3 for every group: one
+  // swizzle of row 16 gi + l / 4 is swz(l / 4) for every group: one
   // per-lane byte offset serves all of them, the rest is wave-uniform.
   const u16 *const sB = g.W2p + n0 * BK;
   const unsigned loff =
-      (unsigned)((lane >> 2) * BK * 2 + (((lane & 3) ^ ((lane >> 4) & 3)) * 16));
+      (unsigned)((lane >> 2) * BK * 2 + (((lane & 3) ^ swz(lane >> 2)) * 16));
   const unsigned lds0 =
       (unsigned)(uintptr_t)(__attribute__((address_space(3))) u16 *)(S);
   auto issue = [&](int stage, int kt) __attribute__((always_inline)) {
@@ -814,6 +820,211 @@ __global__ __launch_bounds__(MLP12_WM * 64) void k_mlp12(Mlp12Args g) {
     mlp12_tile<TN16, true>(g, S, b1_s, bias_s, wave);
   else
     mlp12_tile<TN16, false>(g, S, b1_s, bias_s, wave);
+}
+
+// ------------------------------------ fused first two layers, paired halves
+// The same computation as k_mlp12 on a 128-cell x 800-feature tile: wave w
+// takes cells 32 (w & 3) .. + 31 and second-layer features 400 (w >> 2) ..
+// + 399, so the two waves of a SIMD (w and w + 4) share their cells.  Each
+// produces one of the two 16-feature halves of the next K-step's first layer
+// (one MFMA and eight GELUs per cell tile instead of two and sixteen: the
+// first layer is computed once per cell, not once per 400 features) and
+// leaves it in LDS (8 bytes per lane and tile); after the step's barrier the
+// partner's half completes the MFMA operand, in the order k_mlp12 builds it.
+// The 832-row stage (the first layer's 32 rows, the second's 800) allows a
+// ring of two, so each K-step prefetches only the next one.
+template <int TN16>
+struct Mlp12PTile {
+  static constexpr int WM = 8, TM16 = 2, BK = 32, STAGES = 2, RW = 4;
+  static constexpr int BM = RW * TM16 * 16, BNH = TN16 * 16, BN = 2 * BNH;
+  static constexpr int R1 = 32;
+  static constexpr int ROWS = R1 + BN;
+  // exchange buffer: [2 steps][RW][TM16][2 halves][64 lanes] of 8 bytes
+  static constexpr int XB = 2 * RW * TM16 * 2 * 64;
+};
+
+// CW: the wave's feature half (waves 4..7: 1), which also multiplies first
+template <int TN16, int CW>
+__device__ __forceinline__ void mlp12p_tile(const Mlp12Args &g, u16 *S, float *b1_s,
+                                            float *bias_s, uint2 *xb, int wave) {
+  constexpr bool MULFIRST = CW == 1;
+  constexpr int cw = CW;
+  using TL = Mlp12PTile<TN16>;
+  constexpr int WM = TL::WM, TM16 = TL::TM16, BK = TL::BK, STAGES = TL::STAGES;
+  constexpr int BM = TL::BM, BNH = TL::BNH, BN = TL::BN, R1 = TL::R1, ROWS = TL::ROWS;
+  constexpr int NI = ROWS / 16;
+  constexpr int NPW = (NI + WM - 1) / WM;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int rw = wave & 3;
+  const int ntn = g.N / BN;
+  const int ntm = (g.M + BM - 1) / BM;
+  const int total = ntn * ntm;
+  const int per_xcd = (total + 7) / 8;
+  const int logical = (int)(blockIdx.x % 8) * per_xcd + (int)(blockIdx.x / 8);
+  if (logical >= total) return;  // uniform over the block: no barrier is skipped by part of it
+  const long m0 = (long)(logical / ntn) * BM, n0 = (long)(logical % ntn) * BN;
+  for (int c = tid; c < BN / 4; c += WM * 64)
+    *(float4 *)&bias_s[4 * c] = *(const float4 *)(g.b2 + n0 + 4 * c);
+  for (int c = tid; c < g.K / 4; c += WM * 64) *(float4 *)&b1_s[4 * c] = *(const float4 *)(g.b1 + 4 * c);
+
+  // the wave's 32 cells as the first layer's B operand (rows past M clamped)
+  const int cc = lane >> 4, hf = 4 * cc;
+  bf16x8 xin[TM16];
+#pragma unroll
+  for (int i = 0; i < TM16; ++i) {
+    long row = m0 + rw * TM16 * 16 + i * 16 + (lane & 15);
+    if (row >= g.M) row = g.M - 1;
+    xin[i] = *(const bf16x8 *)(g.X + row * 32 + cc * 8);
+  }
+  __syncthreads();  // b1_s, bias_s
+
+  // this wave's half (features 16 cw .. 16 cw + 15) of K-step kt's first
+  // layer: lane l gets features 16 cw + 4 (l / 16) .. + 3 of cell l % 16
+  auto layer1h = [&](const bf16x8 &w1, int kt, uint2(&hh)[TM16]) __attribute__((always_inline)) {
+    const float4 c = *(const float4 *)&b1_s[kt * 32 + 16 * cw + hf];
+#pragma unroll
+    for (int i = 0; i < TM16; ++i) {
+      f32x4 z = (f32x4){c.x, c.y, c.z, c.w};
+      z = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1, xin[i], z, 0, 0, 0);
+      const bf16x2 a = __builtin_convertvector((f32x2){gelu(z[0]), gelu(z[1])}, bf16x2);
+      const bf16x2 b = __builtin_convertvector((f32x2){gelu(z[2]), gelu(z[3])}, bf16x2);
+      hh[i] = make_uint2(__builtin_bit_cast(unsigned, a), __builtin_bit_cast(unsigned, b));
+    }
+  };
+  // slot of (step parity, tile i, half) for this wave's cells
+  auto xslot = [&](int par, int i, int half) __attribute__((always_inline)) {
+    return xb + (((par * TL::RW + rw) * TM16 + i) * 2 + half) * 64 + lane;
+  };
+
+  // K-step 0 of the first layer straight from global memory
+  const int nk = g.K / BK;
+  uint2 hh[TM16];
+  {
+    const bf16x8 w1 = *(const bf16x8 *)(g.W1 + (16 * cw + (lane & 15)) * 32 + cc * 8);
+    layer1h(w1, 0, hh);
+#pragma unroll
+    for (int i = 0; i < TM16; ++i) *xslot(0, i, cw) = hh[i];
+  }
+
+  // DMA rows as in k_mlp12: the first R1 rows of a stage are the first
+  // layer's weights of the next K-step, then the BN rows of the second's
+  const u16 *const sB = g.W2p + n0 * BK;
+  const unsigned loff =
+      (unsigned)((lane >> 2) * BK * 2 + (((lane & 3) ^ swz(lane >> 2)) * 16));
+  const unsigned lds0 =
+      (unsigned)(uintptr_t)(__attribute__((address_space(3))) u16 *)(S);
+  auto issue = [&](int stage, int kt) __attribute__((always_inline)) {
+    const int k1 = kt + 1 < nk ? kt + 1 : nk - 1;
+#pragma unroll
+    for (int i = 0; i < NPW; ++i) {
+      const int gi = i * WM + wave;
+      if (gi < NI)
+        lds_dma16s(gi * 16 < R1 ? g.W1 + ((long)k1 * R1 + gi * 16) * BK
+                                : sB + kt * g.ldw2 + (long)(gi * 16 - R1) * BK,
+                   loff, lds0 + (unsigned)((stage * ROWS + gi * 16) * BK * 2));
+    }
+  };
+
+  f32x4 acc[TM16][TN16];
+#pragma unroll
+  for (int i = 0; i < TM16; ++i)
+#pragma unroll
+    for (int j = 0; j < TN16; ++j) acc[i][j] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
+
+  issue(0, 0);
+  for (int kt = 0; kt < nk; ++kt) {
+    // this wave's loads of stage kt and its half of step kt's first layer
+    // done; the barrier publishes every wave's
+    asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" : : : "memory");
+    if (kt + 1 < nk) issue((kt + 1) % STAGES, kt + 1);
+    const u16 *T = S + (kt % STAGES) * ROWS * BK;
+    // step kt's operand: the z0 half (features 4g..) then the z1 half (16 + 4g..)
+    bf16x8 h[TM16];
+#pragma unroll
+    for (int i = 0; i < TM16; ++i) {
+      const uint2 o = *xslot(kt & 1, i, cw ^ 1);
+      const uint2 lo = CW == 0 ? hh[i] : o, hi = CW == 0 ? o : hh[i];
+      const unsigned v[4] = {lo.x, lo.y, hi.x, hi.y};
+      h[i] = __builtin_bit_cast(bf16x8, v);
+    }
+    uint2 hn[TM16];
+    auto produce = [&]() __attribute__((always_inline)) {
+      const int row = 16 * cw + (lane & 15);
+      const bf16x8 w1 = *(const bf16x8 *)&T[row * BK + ((cc ^ swz(row)) * 8)];
+      layer1h(w1, kt + 1 < nk ? kt + 1 : kt, hn);
+#pragma unroll
+      for (int i = 0; i < TM16; ++i) *xslot((kt + 1) & 1, i, cw) = hn[i];
+    };
+    auto bfrag = [&](int j) __attribute__((always_inline)) {
+      const int row = R1 + cw * BNH + j * 16 + (lane & 15);
+      return *(const bf16x8 *)&T[row * BK + ((cc ^ swz(row)) * 8)];
+    };
+    auto multiply = [&]() __attribute__((always_inline)) {
+      bf16x8 wq[MLP12_PF];
+#pragma unroll
+      for (int q = 0; q < MLP12_PF; ++q) wq[q] = bfrag(q);
+#pragma unroll
+      for (int j = 0; j < TN16; ++j) {
+        const bf16x8 w = wq[j % MLP12_PF];
+        if (j + MLP12_PF < TN16) wq[j % MLP12_PF] = bfrag(j + MLP12_PF);
+#pragma unroll
+        for (int i = 0; i < TM16; ++i)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, h[i], acc[i][j], 0, 0, 0);
+      }
+    };
+    if (MULFIRST) {
+      multiply();
+      produce();
+    } else {
+      produce();
+      multiply();
+    }
+#pragma unroll
+    for (int i = 0; i < TM16; ++i) hh[i] = hn[i];
+  }
+
+  // epilogue: bias + GELU, BF16 (lane: 4 consecutive features of one cell)
+  long rb[TM16];
+  bool live[TM16];
+#pragma unroll
+  for (int i = 0; i < TM16; ++i) {
+    rb[i] = m0 + rw * TM16 * 16 + i * 16 + (lane & 15);
+    live[i] = rb[i] < g.M;
+  }
+#pragma unroll
+  for (int j = 0; j < TN16; ++j) {
+    const long cj = n0 + cw * BNH + j * 16;  // uniform
+    const float4 b = *(const float4 *)&bias_s[cw * BNH + j * 16 + hf];
+#pragma unroll
+    for (int i = 0; i < TM16; ++i) {
+      if (!live[i]) continue;
+      const long row = rb[i];
+      const bf16x2 lo = __builtin_convertvector(
+          (f32x2){gelu(acc[i][j][0] + b.x), gelu(acc[i][j][1] + b.y)}, bf16x2);
+      const bf16x2 hi = __builtin_convertvector(
+          (f32x2){gelu(acc[i][j][2] + b.z), gelu(acc[i][j][3] + b.w)}, bf16x2);
+      uint2 o;
+      o.x = __builtin_bit_cast(unsigned, lo);
+      o.y = __builtin_bit_cast(unsigned, hi);
+      u16 *const at = g.tiled ? g.H + (row * 32 + hf) + ((cj / 32) * g.ldh + cj % 32)
+                              : g.H + (row * g.ldh + hf) + cj;
+      *(uint2 *)at = o;
+    }
+  }
+}
+
+template <int TN16>
+__global__ __launch_bounds__(8 * 64) void k_mlp12p(Mlp12Args g) {
+  using TL = Mlp12PTile<TN16>;
+  __shared__ __attribute__((aligned(1024))) u16 S[TL::STAGES * TL::ROWS * TL::BK];
+  __shared__ __attribute__((aligned(16))) float b1_s[MLP12_KMAX];
+  __shared__ __attribute__((aligned(16))) float bias_s[TL::BN];
+  __shared__ __attribute__((aligned(16))) uint2 xb[TL::XB];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (wave & PHASE)
+    mlp12p_tile<TN16, 1>(g, S, b1_s, bias_s, xb, wave);
+  else
+    mlp12p_tile<TN16, 0>(g, S, b1_s, bias_s, xb, wave);
 }
 
 template <int WM, int WN, int TM, int TN, int BK>
@@ -2077,10 +2288,18 @@ chem_status mlp12(const Mlp12Args &g, hipStream_t s, const char *label) {
     chem::set_error("mlp12: unsupported shape or misaligned operand");
     return CHEM_EUNSUPPORTED;
   }
-  constexpr int BM = Mlp12Tile<25>::BM;
-  const long total = (long)((g.M + BM - 1) / BM) * (g.N / 400);
-  hipLaunchKernelGGL((k_mlp12<25>), dim3((unsigned)(((total + 7) / 8) * 8)), dim3(MLP12_WM * 64),
-                     0, s, g);
+  if (g.N % 800 == 0) {
+    // paired halves: the first layer once per cell
+    constexpr int BM = Mlp12PTile<25>::BM;
+    const long total = (long)((g.M + BM - 1) / BM) * (g.N / 800);
+    hipLaunchKernelGGL((k_mlp12p<25>), dim3((unsigned)(((total + 7) / 8) * 8)), dim3(8 * 64), 0,
+                       s, g);
+  } else {
+    constexpr int BM = Mlp12Tile<25>::BM;
+    const long total = (long)((g.M + BM - 1) / BM) * (g.N / 400);
+    hipLaunchKernelGGL((k_mlp12<25>), dim3((unsigned)(((total + 7) / 8) * 8)),
+                       dim3(MLP12_WM * 64), 0, s, g);
+  }
   CHEM_HIP(hipGetLastError());
   return CHEM_OK;
 }
