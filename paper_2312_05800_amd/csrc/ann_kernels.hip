@@ -318,10 +318,8 @@ __global__ __launch_bounds__(WM *WN * 64) void k_gemm(GemmArgs g) {
 // swizzle puts any 8 consecutive of those lanes on distinct 4-byte banks of
 // a 32-bank window, and all 16 on distinct banks of a 64-bank one (row r
 // starts at bank 16 r: rows of equal parity within an octet, and rows equal
-// mod 4 within the 16, get distinct positions).  It depends on r mod 16 only.
-// (The earlier (r >> 2) & 3 met the 64-bank condition alone; the LDS
-// bank-conflict counter put half of the fragment reads' LDS cycles in
-// conflicts with it.)
+// mod 4 within the 16, get distinct positions), whichever way the LDS splits
+// a 16-byte read into phases.  It depends on r mod 16 only.
 __device__ __forceinline__ int swz(int r) { return ((r >> 1) ^ ((r >> 3) & 1)) & 3; }
 
 // One direct load of 16 bytes per lane: wave-uniform 64-bit base in SGPRs, a
