@@ -2111,25 +2111,63 @@ __device__ __forceinline__ void atomic_max_f64(double *p, double v) {
   }
 }
 
-__global__ void k_audit_compare(AuditArgs a) {
+// The block's cells are reduced first (wave shuffles, then the four waves'
+// partials in LDS), so each of the audit's sums, minima and maxima takes one
+// atomic per block instead of one per cell.
+constexpr int AUDIT_THREADS = 256;
+__global__ __launch_bounds__(AUDIT_THREADS) void k_audit_compare(AuditArgs a) {
+  __shared__ double part[AUDIT_THREADS / 64][3];
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= a.na) return;
-  const int64_t i = j * a.stride;
-  const bool flagged = a.flags[i] != 0;
-  const bool ref_ok = a.stats_a[2 * a.na + j] == 0;
-  if (flagged || !ref_ok) {
-    atomicAdd(&a.audit[1], 1.0);
-    return;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const bool in = j < a.na;
+  const int64_t i = in ? j * a.stride : 0;
+  bool cmp = false;
+  if (in) cmp = a.flags[i] == 0 && a.stats_a[2 * a.na + j] == 0;
+  const int n_cmp = __syncthreads_count(cmp);
+  const int n_in = __syncthreads_count(in);
+  if (threadIdx.x == 0) {
+    if (n_cmp) atomicAdd(&a.audit[0], (double)n_cmp);
+    if (n_in > n_cmp) atomicAdd(&a.audit[1], (double)(n_in - n_cmp));
   }
-  atomicAdd(&a.audit[0], 1.0);
-  atomic_max_f64(&a.audit[2], fabs(a.T[i] - a.Ta[j]));
+  if (n_cmp == 0) return;  // uniform over the block
+  // sum, min and max of three values over the block, then one atomic each
+  auto reduce3 = [&](double s0, double lo, double hi, double *ps, double *pl, double *ph) {
+    for (int o = 32; o > 0; o >>= 1) {
+      s0 += __shfl_xor(s0, o);
+      lo = fmin(lo, __shfl_xor(lo, o));
+      hi = fmax(hi, __shfl_xor(hi, o));
+    }
+    if (lane == 0) {
+      part[w][0] = s0;
+      part[w][1] = lo;
+      part[w][2] = hi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0, l = INFINITY, h = -INFINITY;
+      for (int v = 0; v < AUDIT_THREADS / 64; ++v) {
+        t += part[v][0];
+        l = fmin(l, part[v][1]);
+        h = fmax(h, part[v][2]);
+      }
+      if (ps) atomicAdd(ps, t);
+      if (pl) atomic_min_f64(pl, l);
+      if (ph) atomic_max_f64(ph, h);
+    }
+    __syncthreads();
+  };
+  reduce3(0.0, INFINITY, cmp ? fabs(a.T[i] - a.Ta[j]) : -INFINITY, nullptr, nullptr,
+          &a.audit[2]);
   for (int k = 0; k < a.K; ++k) {
-    const double yr = a.Ya[(int64_t)k * a.na + j];
-    const double d = a.Y[(int64_t)k * a.ld + i] - yr;
-    const double dref = yr - a.Y0a[(int64_t)k * a.na + j];
-    atomicAdd(&a.audit[3 + 3 * k], d * d);
-    atomic_min_f64(&a.audit[4 + 3 * k], dref);
-    atomic_max_f64(&a.audit[5 + 3 * k], dref);
+    double d2 = 0.0, dl = INFINITY, dh = -INFINITY;
+    if (cmp) {
+      const double yr = a.Ya[(int64_t)k * a.na + j];
+      const double d = a.Y[(int64_t)k * a.ld + i] - yr;
+      const double dref = yr - a.Y0a[(int64_t)k * a.na + j];
+      d2 = d * d;
+      dl = dh = dref;
+    }
+    reduce3(d2, dl, dh, &a.audit[3 + 3 * k], &a.audit[4 + 3 * k], &a.audit[5 + 3 * k]);
   }
 }
 
@@ -2523,7 +2561,8 @@ chem_status audit_gather(const AuditArgs &a, hipStream_t s) {
 
 chem_status audit_compare(const AuditArgs &a, hipStream_t s) {
   if (a.na <= 0) return CHEM_OK;
-  hipLaunchKernelGGL(k_audit_compare, dim3(nblk(a.na, 256)), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_audit_compare, dim3(nblk(a.na, AUDIT_THREADS)), dim3(AUDIT_THREADS), 0, s,
+                     a);
   CHEM_HIP(hipGetLastError());
   return CHEM_OK;
 }
