@@ -127,6 +127,32 @@ def test_forward_parity(dev, mech, data, N):
     assert np.sqrt((err ** 2).mean()) < np.sqrt((e64 ** 2).mean())
 
 
+@pytest.mark.parametrize("hid", [(1600, 400, 400), (1600, 1200, 400)])
+def test_forward_parity_400_wide_tiles(dev, mech, data, hid):
+    """Second-layer widths that are a multiple of 400 but not of 800 take the
+    fused kernel with 400-feature tiles (the first layer recomputed per
+    tile) instead of the paired-halves one; same parity bar."""
+    import torch
+    import paper_2312_05800_amd as P
+    N = 3001
+    _say(f"[ann forward] hidden={hid} N={N}")
+    K = mech.K
+    params = oann.init_params([K + 2, *hid, K], seed=9)
+    nm = _norm_from(data)
+    m = P.AnnModel(K + 2, K, hid, seed=1)
+    for l, (W, b) in enumerate(params):
+        m.set_layer(l, W, b)
+    m.set_norm(0.1, 1e-5, nm["mu_in"], nm["sd_in"], nm["lo"], nm["hi"], nm["mu_out"], nm["sd_out"])
+    T, p, Y = chemgen.make_states(mech, "ch4", N=N, seed=607)
+    U = m.forward(to_dev(T, dev), to_dev(p, dev), to_dev(Y, dev), K)
+    torch.cuda.synchronize()
+    Ug = U.cpu().numpy().astype(np.float64)
+    Uo = oann.forward(_params32(params), _oracle_inputs(nm, T, p, Y), prec="bf16")
+    err = np.abs(Ug - Uo)
+    _say(f"  max abs {err.max():.3e} rms {np.sqrt((err ** 2).mean()):.3e}")
+    assert err.max() <= 2e-2 and np.sqrt((err ** 2).mean()) <= 2e-3
+
+
 def test_forward_full_size_sampled(dev, mech, data):
     import torch
     N = 1 << 20
