@@ -865,10 +865,12 @@ def main():
     n_in = K + 2
     if "mlp_l12" in prof_ann:
         # first two layers in one kernel: useful flops of both layers (the
-        # per-tile recomputation of the first is not counted); X in and H2
-        # out (BF16), W1, b1, W2, b2 once
+        # paired-halves kernel computes the first once per cell; a per-tile
+        # recomputation would not be counted); X in and H2 out (BF16), W1,
+        # b1, W2, b2 once
         dom = "mlp_l12"
-        dom_desc = "mlp_l12 (32->1600->800 BF16, first layer produced on chip per K-step, bias+GELU)"
+        dom_desc = ("mlp_l12 (32->1600->800 BF16, first layer produced on chip per K-step "
+                    "once per cell, bias+GELU)")
         dom_flops = 2.0 * chunk * (n_in * HIDDEN[0] + HIDDEN[0] * HIDDEN[1])
         dom_bytes = (2 * chunk * (n_in + HIDDEN[1]) + 2 * (n_in * HIDDEN[0] + HIDDEN[0] * HIDDEN[1])
                      + 4 * (HIDDEN[0] + HIDDEN[1]))
