@@ -1484,16 +1484,31 @@ extern "C" chem_status ann_train_step(ann_model *m, const chem_mech *mech, chem_
     m->wt_stale = true;
     const double bc1 = 1.0 - pow((double)opts->beta1, (double)m->step);
     const double bc2 = 1.0 - pow((double)opts->beta2, (double)m->step);
+    // the four weight tensors and the four biases in one launch
+    ann::AdamTable at{};
+    at.count = 8;
+    int64_t o = 0;
     for (int l = 0; l < 4; ++l) {
       const ann::Layer &L = m->L[l];
-      st = ann::adam((int64_t)G * layer_elems(L), m->Wm[l], m->gW[l], m->mW[l], m->vW[l],
-                     m->Wb[l], opts->lr, opts->beta1, opts->beta2, opts->eps, (float)bc1,
-                     (float)bc2, s);
-      if (st != CHEM_OK) return st;
-      st = ann::adam((int64_t)G * L.doutp, m->bm[l], m->gb[l], m->mb[l], m->vb[l], nullptr,
-                     opts->lr, opts->beta1, opts->beta2, opts->eps, (float)bc1, (float)bc2, s);
-      if (st != CHEM_OK) return st;
+      at.start[2 * l] = o;
+      at.W[2 * l] = m->Wm[l];
+      at.g[2 * l] = m->gW[l];
+      at.m[2 * l] = m->mW[l];
+      at.v[2 * l] = m->vW[l];
+      at.Wb[2 * l] = m->Wb[l];
+      o += (int64_t)G * layer_elems(L);
+      at.start[2 * l + 1] = o;
+      at.W[2 * l + 1] = m->bm[l];
+      at.g[2 * l + 1] = m->gb[l];
+      at.m[2 * l + 1] = m->mb[l];
+      at.v[2 * l + 1] = m->vb[l];
+      at.Wb[2 * l + 1] = nullptr;
+      o += (int64_t)G * L.doutp;
     }
+    at.start[8] = o;
+    st = ann::adam_multi(at, opts->lr, opts->beta1, opts->beta2, opts->eps, (float)bc1,
+                         (float)bc2, s);
+    if (st != CHEM_OK) return st;
   }
   return CHEM_OK;
 }

@@ -194,8 +194,20 @@ chem_status take_col(int64_t n, const float *src, int lds, float *dst, int ldd, 
 // out[i] = sum_{s < S} part[s * stride + i], in order of s
 chem_status sum_splits(int64_t n, int S, const float *part, long stride, float *out,
                        hipStream_t s);
-chem_status adam(int64_t n, float *W, const float *g, float *m, float *v, u16 *Wb, float lr,
-                 float b1, float b2, float eps, float bc1, float bc2, hipStream_t s);
+// Adam over several tensors in one launch: tensor k holds elements
+// start[k] .. start[k + 1] - 1 of the concatenation (start[0] = 0).
+constexpr int ADAM_MAX = 8;
+struct AdamTable {
+  int count;
+  int64_t start[ADAM_MAX + 1];
+  float *W[ADAM_MAX];
+  const float *g[ADAM_MAX];
+  float *m[ADAM_MAX];
+  float *v[ADAM_MAX];
+  u16 *Wb[ADAM_MAX];  // BF16 copy of W, or null
+};
+chem_status adam_multi(const AdamTable &t, float lr, float b1, float b2, float eps, float bc1,
+                       float bc2, hipStream_t s);
 chem_status to_bf16(int64_t n, const float *src, u16 *dst, hipStream_t s);
 // dst [K/32][N][32] from src [N][K] (BF16, K a multiple of 32); with permute,
 // element k % 32 of each block goes to position mlp12_slot(k % 32) (the K

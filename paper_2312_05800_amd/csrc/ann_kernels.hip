@@ -1779,10 +1779,9 @@ __global__ void k_sum_splits(int64_t n, int S, const float *part, long stride, f
   out[i] = s;
 }
 
-__global__ void k_adam(int64_t n, float *W, const float *g, float *m, float *v, u16 *Wb, float lr,
-                       float b1, float b2, float eps, float bc1, float bc2) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+__device__ __forceinline__ void adam_elem(int64_t i, float *W, const float *g, float *m, float *v,
+                                          u16 *Wb, float lr, float b1, float b2, float eps,
+                                          float bc1, float bc2) {
   const float gi = g[i];
   const float mi = b1 * m[i] + (1.0f - b1) * gi;
   const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
@@ -1791,6 +1790,20 @@ __global__ void k_adam(int64_t n, float *W, const float *g, float *m, float *v, 
   const float w = W[i] - lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
   W[i] = w;
   if (Wb) Wb[i] = f2bf(w);
+}
+
+// Adam over up to ADAM_MAX tensors in one launch (a training step's weights
+// and biases): element i of the concatenation belongs to the last tensor
+// whose start is <= i.
+__global__ void k_adam_multi(AdamTable t, float lr, float b1, float b2, float eps, float bc1,
+                             float bc2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= t.start[t.count]) return;
+  int k = 0;
+#pragma unroll
+  for (int q = 1; q < ADAM_MAX; ++q)
+    if (q < t.count && i >= t.start[q]) k = q;
+  adam_elem(i - t.start[k], t.W[k], t.g[k], t.m[k], t.v[k], t.Wb[k], lr, b1, b2, eps, bc1, bc2);
 }
 
 __global__ void k_to_bf16(int64_t n, const float *src, u16 *dst) {
@@ -2506,10 +2519,16 @@ chem_status sum_splits(int64_t n, int S, const float *part, long stride, float *
   return CHEM_OK;
 }
 
-chem_status adam(int64_t n, float *W, const float *g, float *m, float *v, u16 *Wb, float lr,
-                 float b1, float b2, float eps, float bc1, float bc2, hipStream_t s) {
-  hipLaunchKernelGGL(k_adam, dim3(nblk(n, 256)), dim3(256), 0, s, n, W, g, m, v, Wb, lr, b1, b2,
-                     eps, bc1, bc2);
+chem_status adam_multi(const AdamTable &t, float lr, float b1, float b2, float eps, float bc1,
+                       float bc2, hipStream_t s) {
+  if (t.count < 1 || t.count > ADAM_MAX) {
+    chem::set_error("adam_multi: 1..%d tensors", ADAM_MAX);
+    return CHEM_EINVAL;
+  }
+  const int64_t n = t.start[t.count];
+  if (n <= 0) return CHEM_OK;
+  hipLaunchKernelGGL(k_adam_multi, dim3(nblk(n, 256)), dim3(256), 0, s, t, lr, b1, b2, eps, bc1,
+                     bc2);
   CHEM_HIP(hipGetLastError());
   return CHEM_OK;
 }
