@@ -558,7 +558,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the chemistry step has no inter-GPU exchange "
-              "and this build runs on a single MI355X; use --gpus 1", file=sys.stderr)
+              "and this benchmark runs on a single MI355X; use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -42,7 +42,7 @@ typedef enum {
   CHEM_EHIP = 3,         /* a HIP runtime call failed */
   CHEM_EMECH = 4,        /* inconsistent mechanism description */
   CHEM_EMODEL = 5,       /* inconsistent network / model file */
-  CHEM_EUNSUPPORTED = 6  /* valid but beyond this build's limits (e.g. K > 63) */
+  CHEM_EUNSUPPORTED = 6  /* valid but beyond the library's limits (e.g. K > 63) */
 } chem_status;
 
 /* Per-cell status codes written to stats[2][i] by chem_step. */
@@ -187,7 +187,7 @@ typedef struct {
   int32_t n_in;       /* K + 2 for a mechanism with K species */
   int32_t n_out;      /* K */
   int32_t hidden[3];  /* hidden widths */
-  int32_t prec;       /* 0 = BF16 everywhere (the only value this build accepts) */
+  int32_t prec;       /* 0 = BF16 everywhere (the only value the library accepts) */
   int32_t members;    /* 0 or 1: one network with n_out outputs; n_out: the per-species
                          ensemble of Sec. 3.2 (one network with the same inputs and hidden
                          widths and a single output per species; their loss is the mean of

@@ -391,7 +391,7 @@ extern "C" chem_status ann_create(const ann_arch *arch, uint64_t seed, ann_model
       return CHEM_EINVAL;
     }
   if (arch->prec != 0) {
-    set_error("ann_create: only BF16 hidden layers (prec 0) are available in this build");
+    set_error("ann_create: only BF16 hidden layers (prec 0) are available in this library");
     return CHEM_EUNSUPPORTED;
   }
   const int G = arch->members <= 1 ? 1 : arch->members;
