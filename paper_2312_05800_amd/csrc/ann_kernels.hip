@@ -1883,29 +1883,38 @@ __global__ __launch_bounds__(128, 4) void k_post(chem::DevMech M, PostArgs a) {
   double S0 = 0.0, h0 = 0.0, Tp[5];
   tpowers(T0, Tp);
   const bool vec = a.doutp % 4 == 0;
+  // Species in chunks of CH: the chunk's Y0 and U loads are issued together
+  // (indices past the last species are clamped into range and their values
+  // unused), ahead of the per-species branches that would otherwise hold
+  // each load back until the previous species is done.  All of a cell's U
+  // (one row of doutp floats) is then read while its lines are in cache.
+  constexpr int CH = 8;
 #pragma unroll
-  for (int k4 = 0; k4 < KP; k4 += 4) {
-    float u4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  for (int k0 = 0; k0 < KP; k0 += CH) {
+    double y0c[CH];
+    float uc[CH];
+#pragma unroll
+    for (int t = 0; t < CH; ++t) y0c[t] = a.Y[(int64_t)min(k0 + t, K - 1) * a.ld + i];
     if (vec) {
-      if (k4 < a.doutp) {
-        const float4 v = *(const float4 *)(a.U + i * a.doutp + k4);
-        u4[0] = v.x;
-        u4[1] = v.y;
-        u4[2] = v.z;
-        u4[3] = v.w;
+#pragma unroll
+      for (int q = 0; q < CH; q += 4) {
+        const float4 v = *(const float4 *)(a.U + i * a.doutp + min(k0 + q, a.doutp - 4));
+        uc[q] = v.x;
+        uc[q + 1] = v.y;
+        uc[q + 2] = v.z;
+        uc[q + 3] = v.w;
       }
     } else {
 #pragma unroll
-      for (int t = 0; t < 4; ++t)
-        if (k4 + t < K) u4[t] = a.U[i * a.doutp + k4 + t];
+      for (int t = 0; t < CH; ++t) uc[t] = a.U[i * a.doutp + min(k0 + t, K - 1)];
     }
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int k = k4 + t;
+    for (int t = 0; t < CH; ++t) {
+      const int k = k0 + t;
       yn[k] = 0.0;
       if (k < K) {
-        const double y0 = a.Y[(int64_t)k * a.ld + i];
-        const float du = u4[t] * a.nm.sd_out[k] + a.nm.mu_out[k];
+        const double y0 = y0c[t];
+        const float du = uc[t] * a.nm.sd_out[k] + a.nm.mu_out[k];
         const double y = y0 + (double)du;  // Y' = Y0 + sd u + mu
         yn[k] = y;
         const double d = proj_weight(y, a.nm.sd_out[k]);
