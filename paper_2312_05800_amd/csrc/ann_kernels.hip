@@ -357,7 +357,8 @@ __global__ __launch_bounds__(WM * 64) void k_gemm_dma16(GemmArgs g) {
   constexpr int NPW = (NI + WM - 1) / WM;
   constexpr int NMIN = NI / WM;
   static_assert(BM % 16 == 0 && BN % 16 == 0, "tile rows must be multiples of 16");
-  static_assert(STAGES == 1 || STAGES == 3, "ring of 3 stages, or 1 for a single K-step");
+  static_assert(STAGES == 1 || STAGES == 2 || STAGES == 3,
+                "ring of 2 or 3 stages, or 1 for a single K-step");
   __shared__ __attribute__((aligned(1024))) u16 S[STAGES * ROWS * BK];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -424,7 +425,8 @@ __global__ __launch_bounds__(WM * 64) void k_gemm_dma16(GemmArgs g) {
   const int nk = g.K / BK;
   const int cc = lane >> 4;
   // STAGES - 1 K-steps in flight ahead of the one being multiplied (a single
-  // stage serves layers with one K-step only)
+  // stage serves layers with one K-step only; two stages leave the CU room
+  // for a second block, whose work covers this one's waits)
   issue(0, 0);
   if (STAGES == 3 && nk > 1) issue(1, 1);
   for (int kt = 0; kt < nk; ++kt) {
@@ -437,6 +439,8 @@ __global__ __launch_bounds__(WM * 64) void k_gemm_dma16(GemmArgs g) {
     // STAGES = 3: the ring slot of stage kt + 2 was last read in iteration
     // kt - 1, which every wave finished before the barrier above
     if (STAGES == 3 && kt + 2 < nk) issue((kt + 2) % STAGES, kt + 2);
+    // STAGES = 2: the slot of stage kt + 1 was last read in iteration kt - 1
+    if (STAGES == 2 && kt + 1 < nk) issue((kt + 1) % STAGES, kt + 1);
     const u16 *T = S + (kt % STAGES) * ROWS * BK;
     bf16x8 x[TM16];
 #pragma unroll
@@ -616,6 +620,9 @@ constexpr int MLP12_KMAX = 2048;
 constexpr int MLP12_WM = 8, MLP12_TM16 = 2;
 // second-layer weight fragments in flight ahead of their MFMAs
 constexpr int MLP12_PF = 2;
+// k_mlp12p: the first tile, and the spacing in tiles, of the first layer's
+// GELUs among the second layer's MFMAs (8 GELUs over 25 tiles)
+constexpr int MLP12P_GSTART = 2, MLP12P_GSTEP = 3;
 constexpr int PHASE = 4;
 
 template <int TN16>
@@ -829,7 +836,8 @@ __global__ __launch_bounds__(MLP12_WM * 64) void k_mlp12(Mlp12Args g) {
 // first layer is computed once per cell, not once per 400 features) and
 // leaves it in LDS (8 bytes per lane and tile); after the step's barrier the
 // partner's half completes the MFMA operand, in the order k_mlp12 builds it.
-// The 832-row stage (the first layer's 32 rows, the second's 800) allows a
+// Within a K-step the first layer's GELUs sit between the second layer's
+// MFMAs of the same wave.  The 832-row stage (the first layer's 32 rows, the second's 800) allows a
 // ring of two, so each K-step prefetches only the next one.
 template <int TN16>
 struct Mlp12PTile {
@@ -841,11 +849,10 @@ struct Mlp12PTile {
   static constexpr int XB = 2 * RW * TM16 * 2 * 64;
 };
 
-// CW: the wave's feature half (waves 4..7: 1), which also multiplies first
+// CW: the wave's feature half (waves 4..7: 1)
 template <int TN16, int CW>
 __device__ __forceinline__ void mlp12p_tile(const Mlp12Args &g, u16 *S, float *b1_s,
                                             float *bias_s, uint2 *xb, int wave) {
-  constexpr bool MULFIRST = CW == 1;
   constexpr int cw = CW;
   using TL = Mlp12PTile<TN16>;
   constexpr int WM = TL::WM, TM16 = TL::TM16, BK = TL::BK, STAGES = TL::STAGES;
@@ -946,21 +953,32 @@ __device__ __forceinline__ void mlp12p_tile(const Mlp12Args &g, u16 *S, float *b
       h[i] = __builtin_bit_cast(bf16x8, v);
     }
     uint2 hn[TM16];
-    auto produce = [&]() __attribute__((always_inline)) {
+    // step kt + 1's first-layer products go first; their eight GELUs are
+    // then spread between the second layer's MFMAs of step kt, one every
+    // MLP12P_GSTEP feature tiles from tile MLP12P_GSTART, each tile fenced
+    // off from the scheduler so that the VALU work stays between the MFMAs
+    f32x4 z[TM16];
+    {
       const int row = 16 * cw + (lane & 15);
       const bf16x8 w1 = *(const bf16x8 *)&T[row * BK + ((cc ^ swz(row)) * 8)];
-      layer1h(w1, kt + 1 < nk ? kt + 1 : kt, hn);
+      const int k1 = kt + 1 < nk ? kt + 1 : kt;
+      const float4 c = *(const float4 *)&b1_s[k1 * 32 + 16 * cw + hf];
 #pragma unroll
-      for (int i = 0; i < TM16; ++i) *xslot((kt + 1) & 1, i, cw) = hn[i];
-    };
+      for (int i = 0; i < TM16; ++i) {
+        z[i] = (f32x4){c.x, c.y, c.z, c.w};
+        z[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1, xin[i], z[i], 0, 0, 0);
+      }
+    }
     auto bfrag = [&](int j) __attribute__((always_inline)) {
       const int row = R1 + cw * BNH + j * 16 + (lane & 15);
       return *(const bf16x8 *)&T[row * BK + ((cc ^ swz(row)) * 8)];
     };
-    auto multiply = [&]() __attribute__((always_inline)) {
+    {
+      float gz[TM16 * 4];
       bf16x8 wq[MLP12_PF];
 #pragma unroll
       for (int q = 0; q < MLP12_PF; ++q) wq[q] = bfrag(q);
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int j = 0; j < TN16; ++j) {
         const bf16x8 w = wq[j % MLP12_PF];
@@ -968,15 +986,22 @@ __device__ __forceinline__ void mlp12p_tile(const Mlp12Args &g, u16 *S, float *b
 #pragma unroll
         for (int i = 0; i < TM16; ++i)
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, h[i], acc[i][j], 0, 0, 0);
+        if (j >= MLP12P_GSTART && (j - MLP12P_GSTART) % MLP12P_GSTEP == 0 &&
+            (j - MLP12P_GSTART) / MLP12P_GSTEP < TM16 * 4) {
+          const int q = (j - MLP12P_GSTART) / MLP12P_GSTEP;
+          gz[q] = gelu(z[q / 4][q % 4]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
       }
-    };
-    if (MULFIRST) {
-      multiply();
-      produce();
-    } else {
-      produce();
-      multiply();
+#pragma unroll
+      for (int i = 0; i < TM16; ++i) {
+        const bf16x2 lo = __builtin_convertvector((f32x2){gz[4 * i], gz[4 * i + 1]}, bf16x2);
+        const bf16x2 hi = __builtin_convertvector((f32x2){gz[4 * i + 2], gz[4 * i + 3]}, bf16x2);
+        hn[i] = make_uint2(__builtin_bit_cast(unsigned, lo), __builtin_bit_cast(unsigned, hi));
+      }
     }
+#pragma unroll
+    for (int i = 0; i < TM16; ++i) *xslot((kt + 1) & 1, i, cw) = hn[i];
 #pragma unroll
     for (int i = 0; i < TM16; ++i) hh[i] = hn[i];
   }
@@ -2263,7 +2288,7 @@ bool dma16_ok(const GemmArgs &g) {
 
 bool gemm_fuses_next(const GemmArgs &g) {
   return dma16_ok(g) && g.N == 416 && (long)((g.M + 255) / 256) >= 512 && g.N2 == 32 &&
-         g.N2 <= g.ldcf && g.N2 * (416 + 4) <= 3 * (256 + 416) * 32 && g.B2 &&
+         g.N2 <= g.ldcf && g.N2 * (416 + 4) <= 2 * (128 + 416) * 32 && g.B2 &&
          g.bias && g.bias2 && ((uintptr_t)g.B2 & 7) == 0;
 }
 
@@ -2288,10 +2313,13 @@ chem_status gemm(const GemmArgs &g, bool AK, bool BK, int epi, hipStream_t s,
   }
   if (epi == EPI_GELU_NEXT) {
     if (!AK || !BK || !gemm_fuses_next(g)) {
-      chem::set_error("gemm: the fused output layer needs the 256 x 416 tiling");
+      chem::set_error("gemm: the fused output layer needs the 128 x 416 tiling");
       return CHEM_EUNSUPPORTED;
     }
-    return gemm_dma16_cfg<8, 2, 26>(g, epi, s);
+    // 128 x 416 tiles on a two-stage ring (71 KB of LDS): two blocks per CU,
+    // so one block's epilogue (GELU, output layer) runs beside the other's
+    // main loop
+    return gemm_dma16_cfg<4, 2, 26, 2>(g, epi, s);
   }
   if (g.tiled) {
     // K-blocked operands exist only on the direct-to-LDS path, whose launch
