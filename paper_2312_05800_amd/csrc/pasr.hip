@@ -60,6 +60,12 @@ __device__ __forceinline__ void pasr_cells(const DevMech &M, const PasrArgs &a, 
   const unsigned t = threadIdx.x & 63u;
   const unsigned off = t * 8u;
   const int live = (int)(a.n - c0 < PASR_CELLS ? a.n - c0 : PASR_CELLS);
+  // every load of the cells goes out first: the per-cell inputs do not
+  // wait behind the block's two reductions
+  const double T = row_load(row_rsrc(a.T + c0, live), off);
+  const double p = row_load(row_rsrc(a.p + c0, live), off);
+  const double tT = row_load(row_rsrc(a.tau_t + c0, live), off);
+  const double tK = row_load(row_rsrc(a.tau_k + c0, live), off);
   double y[J], r[J];
 #pragma unroll
   for (int j = 0; j < J; ++j) {
@@ -86,8 +92,6 @@ __device__ __forceinline__ void pasr_cells(const DevMech &M, const PasrArgs &a, 
   __syncthreads();
   s = (red[0][t] + red[1][t]) + (red[2][t] + red[3][t]);
   amax = fmax(fmax(red[4][t], red[5][t]), fmax(red[6][t], red[7][t]));
-  const double T = row_load(row_rsrc(a.T + c0, live), off);
-  const double p = row_load(row_rsrc(a.p + c0, live), off);
   const double rho = p / (RG * T * s);
   // the slowest time rho Y_k / |RR_k| among species with |RR_k| >= eta max
   // (-inf while none qualifies)
@@ -102,8 +106,6 @@ __device__ __forceinline__ void pasr_cells(const DevMech &M, const PasrArgs &a, 
   __syncthreads();
   tc = fmax(fmax(red[8][t], red[9][t]), fmax(red[10][t], red[11][t]));
   if (tc == -INFINITY) tc = INFINITY;  // no reacting species
-  const double tT = row_load(row_rsrc(a.tau_t + c0, live), off);
-  const double tK = row_load(row_rsrc(a.tau_k + c0, live), off);
   const double tmix = sqrt(tT * tK);
   const double den = tc + tmix;
   const double kap = tc == INFINITY || den == 0.0 ? 1.0 : tc / den;
