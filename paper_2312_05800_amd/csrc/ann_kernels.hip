@@ -974,6 +974,8 @@ __device__ __forceinline__ void mlp12p_tile(const Mlp12Args &g, u16 *S, float *b
       return *(const bf16x8 *)&T[row * BK + ((cc ^ swz(row)) * 8)];
     };
     {
+      static_assert(MLP12P_GSTART + (TM16 * 4 - 1) * MLP12P_GSTEP < TN16,
+                    "each first-layer GELU needs a feature tile of its own");
       float gz[TM16 * 4];
       bf16x8 wq[MLP12_PF];
 #pragma unroll
